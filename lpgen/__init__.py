@@ -1,0 +1,235 @@
+"""Seeded synthetic LP instances shaped like the workloads of the PDCS LP path.
+
+This module only draws random data and assembles it into CSR arrays; it holds
+none of the solver's arithmetic.  Both the FP64 CPU oracle (under ``oracle/``)
+and the HIP solver consume what it returns, so the two sides see identical
+inputs without sharing any code.
+
+Every instance is the LP of the paper's conic form (Section 1.1, eq. prob_cp)
+restricted to box-bounded variables and zero / nonnegative row cones:
+
+    min c^T x   s.t.  (G x - h)[:m_zero] = 0,  (G x - h)[m_zero:] >= 0,  l <= x <= u.
+
+Random streams use ``numpy.random.default_rng([15504, config_id, instance_id])``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "LPInstance",
+    "csr_from_columns",
+    "planted_lp",
+    "c0_instance",
+    "c1_instance",
+    "c2_batch",
+    "c3_family_base",
+    "c3_perturb",
+    "c4_instance",
+    "zipf_row_lengths",
+    "rng_for",
+]
+
+
+@dataclass
+class LPInstance:
+    """LP data in CSR form (row_ptr int64[m+1], col_idx int32[nnz], val f64[nnz])."""
+
+    m: int
+    n: int
+    m_zero: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    val: np.ndarray
+    h: np.ndarray
+    c: np.ndarray
+    l: np.ndarray
+    u: np.ndarray
+    name: str = "lp"
+    x_planted: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def m_nonneg(self) -> int:
+        return self.m - self.m_zero
+
+    def scipy_csr(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix((self.val, self.col_idx, self.row_ptr), shape=(self.m, self.n))
+
+
+def rng_for(config_id: int, instance_id: int = 0) -> np.random.Generator:
+    return np.random.default_rng([15504, int(config_id), int(instance_id)])
+
+
+def _distinct_rows_per_column(rng, m: int, n: int, k) -> tuple[np.ndarray, np.ndarray]:
+    """For column j draw k[j] distinct row indices, uniform over [0, m).
+
+    Duplicates inside a column are redrawn until none remain, so the result is a
+    uniform draw of a k[j]-subset per column.  Returns (row, col) entry lists.
+    """
+    k = np.broadcast_to(np.asarray(k, dtype=np.int64), (n,))
+    if np.any(k > m):
+        raise ValueError("more nonzeros per column than rows")
+    col = np.repeat(np.arange(n, dtype=np.int64), k)
+    row = rng.integers(0, m, size=col.size, dtype=np.int64)
+    while True:
+        key = col * m + row
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        dup = np.nonzero(ks[1:] == ks[:-1])[0] + 1
+        if dup.size == 0:
+            break
+        idx = order[dup]
+        row[idx] = rng.integers(0, m, size=idx.size, dtype=np.int64)
+    return row, col
+
+
+def _distinct_cols_per_row(rng, m: int, n: int, lengths: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """For row i draw lengths[i] distinct columns, uniform over [0, n)."""
+    row = np.repeat(np.arange(m, dtype=np.int64), lengths)
+    col = rng.integers(0, n, size=row.size, dtype=np.int64)
+    while True:
+        key = row * n + col
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        dup = np.nonzero(ks[1:] == ks[:-1])[0] + 1
+        if dup.size == 0:
+            break
+        idx = order[dup]
+        col[idx] = rng.integers(0, n, size=idx.size, dtype=np.int64)
+    return row, col
+
+
+def csr_from_columns(m: int, n: int, row: np.ndarray, col: np.ndarray, val: np.ndarray):
+    """Sort (row, col, val) triplets into CSR order (rows, then columns ascending)."""
+    key = row.astype(np.int64) * n + col.astype(np.int64)
+    order = np.argsort(key, kind="stable")
+    r = row[order]
+    counts = np.bincount(r, minlength=m).astype(np.int64)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return row_ptr, col[order].astype(np.int32), np.ascontiguousarray(val[order], dtype=np.float64)
+
+
+def _csr_matvec(row_ptr, col_idx, val, x):
+    """Plain CSR product used only to plant a feasible right-hand side b = A x0."""
+    import scipy.sparse as sp
+
+    m = row_ptr.size - 1
+    n = x.size
+    return sp.csr_matrix((val, col_idx, row_ptr), shape=(m, n)) @ x
+
+
+def planted_lp(
+    rng,
+    m: int,
+    n: int,
+    per_col=None,
+    row_lengths=None,
+    m_zero: int | None = None,
+    row_scale=None,
+    col_scale=None,
+    upper: float = 10.0,
+    name: str = "lp",
+) -> LPInstance:
+    """Random LP with a planted interior point (the shared recipe of all configs).
+
+    A has either ``per_col`` distinct uniform rows per column or ``row_lengths``
+    distinct uniform columns per row, values N(0,1), optionally scaled as
+    diag(row_scale) A diag(col_scale).  x0 ~ U[0,5]^n, h = A x0, c ~ U[0,1]^n,
+    0 <= x <= upper.  Rows are equalities unless ``m_zero`` < m, in which case
+    the remaining rows are ">=" rows (still satisfied with equality by x0).
+    """
+    if row_lengths is not None:
+        row, col = _distinct_cols_per_row(rng, m, n, np.asarray(row_lengths, dtype=np.int64))
+    else:
+        row, col = _distinct_rows_per_column(rng, m, n, per_col)
+    val = rng.standard_normal(row.size)
+    if row_scale is not None:
+        val = val * np.asarray(row_scale)[row]
+    if col_scale is not None:
+        val = val * np.asarray(col_scale)[col]
+    row_ptr, col_idx, val = csr_from_columns(m, n, row, col, val)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    h = _csr_matvec(row_ptr, col_idx, val, x0)
+    c = rng.uniform(0.0, 1.0, size=n)
+    l = np.zeros(n)
+    u = np.full(n, float(upper))
+    mz = m if m_zero is None else int(m_zero)
+    return LPInstance(m, n, mz, row_ptr, col_idx, val, h, c, l, u, name=name, x_planted=x0)
+
+
+def c0_instance(seed: int = 0, m: int = 200, n: int = 500, per_col: int = 5) -> LPInstance:
+    """Plain single LP: m=200, n=500, 5 nonzeros per column (nnz = 2500)."""
+    return planted_lp(rng_for(0, seed), m, n, per_col=per_col, name=f"c0_m{m}_n{n}_s{seed}")
+
+
+def zipf_row_lengths(rng, m: int, s: float = 1.5, max_len: int = 5000) -> np.ndarray:
+    """Row lengths from a Zipf(s) law truncated to [1, max_len], by inverse CDF."""
+    k = np.arange(1, max_len + 1, dtype=np.float64)
+    p = k ** (-s)
+    cdf = np.cumsum(p)
+    cdf /= cdf[-1]
+    u = rng.random(m)
+    return (np.searchsorted(cdf, u, side="left") + 1).astype(np.int64)
+
+
+def c1_instance(seed: int = 0, m: int = 1_000_000, n: int = 2_000_000, s: float = 1.5,
+                max_len: int = 5000) -> LPInstance:
+    """Single large LP: power-law (truncated Zipf) row lengths, m=1e6, n=2e6."""
+    rng = rng_for(1, seed)
+    lengths = np.minimum(zipf_row_lengths(rng, m, s, max_len), n)
+    inst = planted_lp(rng, m, n, row_lengths=lengths, name=f"c1_m{m}_n{n}_zipf{s}_s{seed}")
+    inst.meta["zipf_s"] = s
+    return inst
+
+
+def c2_batch(count: int = 512, m_lo: int = 1000, m_hi: int = 50_000, per_col: int = 8,
+             seed: int = 0) -> list[LPInstance]:
+    """Batch of independent LPs, m log-uniform in [m_lo, m_hi], n = 2m, 8 nnz/col."""
+    out = []
+    for b in range(count):
+        rng = rng_for(2, seed * 100_000 + b)
+        m = int(round(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi)))))
+        out.append(planted_lp(rng, m, 2 * m, per_col=per_col, name=f"c2_{b}"))
+    return out
+
+
+def c3_family_base(m: int = 20_000, n: int = 40_000, seed: int = 0) -> LPInstance:
+    """Shared-pattern base LP for the warm-start family (nnz = 7.5 * n exactly).
+
+    After a random permutation the first n/2 columns get 8 rows, the rest 7.
+    """
+    rng = rng_for(3, seed)
+    perm = rng.permutation(n)
+    k = np.empty(n, dtype=np.int64)
+    k[perm[: n // 2]] = 8
+    k[perm[n // 2:]] = 7
+    return planted_lp(rng, m, n, per_col=k, name=f"c3base_m{m}_n{n}")
+
+
+def c3_perturb(base: LPInstance, k: int, rel: float = 0.1) -> LPInstance:
+    """Family member k: h and c multiplied elementwise by (1 + rel * N(0,1))."""
+    rng = rng_for(30, k)
+    xi = rng.standard_normal(base.m)
+    zeta = rng.standard_normal(base.n)
+    return LPInstance(base.m, base.n, base.m_zero, base.row_ptr, base.col_idx, base.val,
+                      base.h * (1.0 + rel * xi), base.c * (1.0 + rel * zeta), base.l, base.u,
+                      name=f"{base.name}_k{k}")
+
+
+def c4_instance(seed: int = 0, m: int = 200_000, n: int = 500_000, per_col: int = 10) -> LPInstance:
+    """Ill-conditioned LP: A = R A0 C, R_ii = 10^U[-3,3], C_jj = 10^U[-2,2]."""
+    rng = rng_for(4, seed)
+    rs = 10.0 ** rng.uniform(-3.0, 3.0, size=m)
+    cs = 10.0 ** rng.uniform(-2.0, 2.0, size=n)
+    return planted_lp(rng, m, n, per_col=per_col, row_scale=rs, col_scale=cs,
+                      name=f"c4_m{m}_n{n}_s{seed}")

@@ -1,0 +1,649 @@
+"""Plain FP64 CPU oracle for the PDCS method on linear programs.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+this module: it is used by ``tests/``, by ``__graft_entry__.smoke()`` (to check
+one small GPU solve) and by the CPU-baseline leg of ``bench.py``.  It shares no
+code with the HIP solver; the two sides only share the seeded input generators
+in ``lpgen``.
+
+What it computes (paper: "A Technical Note on the Implementation and Use of
+PDCS", arXiv 2603.15504):
+
+* the LP restriction of the conic problem of Section 1.1 (eq. prob_cp): every
+  variable is box-bounded (n2 = 0), rows are zero-cone (equality) rows followed
+  by nonnegative-cone (>=) rows, so K_d* = {0}^m_zero x R+^m_nonneg and
+  K_d = R^m_zero x R+^m_nonneg;
+* Algorithm "PDCS with preconditioning" (Section 2.6): diagonal rescaling, the
+  PDCS loop of Algorithm 1 (Section 2) on the rescaled data, then unscaling;
+* inside it: OnePDHG (eq. PDHG, Section 1.2), AdaptiveStepPDHG (Function 2,
+  eq. adaptive_step_size, Section 2.1), the reflection parameter (eq.
+  adaptive_reflection / tolerance / tolerance-2, Section 2.2), the reflected
+  Halpern and averaging updates (Algorithm 1), GetRestartCandidate and the
+  three restart conditions with the KKT_omega fallback (Section 2.3), the
+  bisection for the normalized duality gap (Algorithm 3, eq. compute_rho,
+  compute_zt, compute_zt_2, Section 2.4), the primal weight (Section 2.5) and
+  the termination errors of Section 3 (eq. PDCS_terminate_tolerance_abs/rel).
+
+Everything is float64; products with G use scipy.sparse CSR.  Steps follow the
+paper's order and notation; nothing is fused or reordered.  Where the paper is
+silent or ambiguous the reading taken is stated at the point of use.
+
+Every function here is pinned by the CPU tests (HiGHS optimum, vertex brute
+force, closed forms, invariants).  The full trajectory (iteration counts after
+the first restart check) is parity unpinned: restart decisions are
+discontinuous in rounding.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+# Restart thresholds (Section 2.3) and primal-weight constants (Section 2.5).
+BETA_SUFFICIENT = 0.4
+BETA_NECESSARY = 0.8
+BETA_ARTIFICIAL = 0.223
+THETA = 0.5
+OMEGA_MIN, OMEGA_MAX = 1e-5, 1e5
+TINY = 1e-10
+
+EXIT_OPTIMAL = 0
+EXIT_MAX_ITER = 1
+EXIT_TIME_LIMIT = 6
+EXIT_CONTINUE = 7
+EXIT_NUMERICAL_ERROR = 8
+
+
+# --------------------------------------------------------------------------
+# Problem data
+# --------------------------------------------------------------------------
+@dataclass
+class LPData:
+    """min c^T x  s.t.  Gx - h in K_d*,  l <= x <= u   (eq. prob_cp, LP case)."""
+
+    G: sp.csr_matrix
+    h: np.ndarray
+    c: np.ndarray
+    l: np.ndarray
+    u: np.ndarray
+    m_zero: int
+
+    @property
+    def m(self) -> int:
+        return self.G.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.G.shape[1]
+
+
+def lpdata_from_arrays(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u) -> LPData:
+    G = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col_idx), np.asarray(row_ptr)),
+                      shape=(int(m), int(n)))
+    return LPData(G, np.asarray(h, np.float64), np.asarray(c, np.float64),
+                  np.asarray(l, np.float64), np.asarray(u, np.float64), int(m_zero))
+
+
+def lpdata_from_instance(inst) -> LPData:
+    return lpdata_from_arrays(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx,
+                              inst.val, inst.h, inst.c, inst.l, inst.u)
+
+
+# --------------------------------------------------------------------------
+# Projections (Section 1.1, eq. defn_Lambda1; Section 1.2)
+# --------------------------------------------------------------------------
+def proj_box(x, l, u):
+    """Projection onto [l, u] (componentwise clip; +-inf bounds allowed)."""
+    return np.minimum(np.maximum(x, l), u)
+
+
+def proj_Kd(y, m_zero):
+    """Projection onto K_d = R^m_zero x R+^m_nonneg (dual variables of the rows)."""
+    out = np.array(y, dtype=np.float64, copy=True)
+    out[m_zero:] = np.maximum(out[m_zero:], 0.0)
+    return out
+
+
+def proj_Kd_star(v, m_zero):
+    """Projection onto K_d* = {0}^m_zero x R+^m_nonneg."""
+    out = np.array(v, dtype=np.float64, copy=True)
+    out[:m_zero] = 0.0
+    out[m_zero:] = np.maximum(out[m_zero:], 0.0)
+    return out
+
+
+def proj_Lambda(lam, l, u):
+    """Projection onto Lambda of eq. defn_Lambda1.
+
+    Lambda_i = {0} if both bounds are infinite, R- if only u is finite, R+ if
+    only l is finite, R if both are finite.
+    """
+    lf = np.isfinite(l)
+    uf = np.isfinite(u)
+    out = np.array(lam, dtype=np.float64, copy=True)
+    both_inf = ~lf & ~uf
+    only_u = ~lf & uf
+    only_l = lf & ~uf
+    out[both_inf] = 0.0
+    out[only_u] = np.minimum(out[only_u], 0.0)
+    out[only_l] = np.maximum(out[only_l], 0.0)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Diagonal rescaling (Section 2.6, eq. rescaled_prob, Algorithm 4)
+# --------------------------------------------------------------------------
+def ruiz_l2_scaling(G: sp.csr_matrix, ruiz_iters: int = 10, l2_pass: bool = True):
+    """Return positive diagonals (D1, D2) with G_hat = D1 G D2.
+
+    The paper does not say how D1, D2 are chosen.  Reading taken: Ruiz
+    equilibration (each pass divides row i by sqrt(max_j |G_hat_ij|) and column
+    j by sqrt(max_i |G_hat_ij|), both taken from the same current matrix) for
+    ``ruiz_iters`` passes, then one pass dividing rows and columns by the square
+    roots of their Euclidean norms.  Empty rows or columns keep factor 1.
+    """
+    m, n = G.shape
+    A = abs(G).tocsr()
+    D1 = np.ones(m)
+    D2 = np.ones(n)
+
+    def current():
+        return sp.diags(D1) @ A @ sp.diags(D2)
+
+    for _ in range(ruiz_iters):
+        M = current()
+        rmax = np.asarray(M.max(axis=1).todense()).ravel()
+        cmax = np.asarray(M.max(axis=0).todense()).ravel()
+        r = np.where(rmax > 0, np.sqrt(rmax), 1.0)
+        s = np.where(cmax > 0, np.sqrt(cmax), 1.0)
+        D1 = D1 / r
+        D2 = D2 / s
+    if l2_pass:
+        M = current()
+        M2 = M.multiply(M)
+        rn = np.sqrt(np.asarray(M2.sum(axis=1)).ravel())
+        cn = np.sqrt(np.asarray(M2.sum(axis=0)).ravel())
+        r = np.where(rn > 0, np.sqrt(rn), 1.0)
+        s = np.where(cn > 0, np.sqrt(cn), 1.0)
+        D1 = D1 / r
+        D2 = D2 / s
+    return D1, D2
+
+
+def rescale(lp: LPData, D1, D2) -> LPData:
+    """Rescaled data of eq. rescaled_prob: G^=D1 G D2, c^=D2 c, h^=D1 h, l^=l/D2, u^=u/D2."""
+    Gs = (sp.diags(D1) @ lp.G @ sp.diags(D2)).tocsr()
+    return LPData(Gs, D1 * lp.h, D2 * lp.c, lp.l / D2, lp.u / D2, lp.m_zero)
+
+
+# --------------------------------------------------------------------------
+# One PDHG step (Section 1.2, eq. PDHG)
+# --------------------------------------------------------------------------
+def one_pdhg(lp: LPData, x, y, tau, sigma):
+    xh = proj_box(x - tau * (lp.c - lp.G.T @ y), lp.l, lp.u)
+    yh = proj_Kd(y + sigma * (lp.h - lp.G @ (2.0 * xh - x)), lp.m_zero)
+    return xh, yh
+
+
+# --------------------------------------------------------------------------
+# Error metrics
+# --------------------------------------------------------------------------
+def dual_objective(lp: LPData, y, lam):
+    """<y, h> + l^T lam+ - u^T lam-  (eq. dual_conic).
+
+    Reading: 0 * inf is taken as 0, i.e. the bound terms sum over finite bounds
+    only; lam+ = max(lam, 0), lam- = max(-lam, 0).
+    """
+    lf = np.isfinite(lp.l)
+    uf = np.isfinite(lp.u)
+    lp_term = np.dot(lp.l[lf], np.maximum(lam[lf], 0.0))
+    um_term = np.dot(lp.u[uf], np.maximum(-lam[uf], 0.0))
+    return float(np.dot(y, lp.h) + lp_term - um_term)
+
+
+def abs_errors_l2(lp: LPData, x, y):
+    """Absolute errors of eq. tolerance-3 (Euclidean norms) with lam = c - G^T y.
+
+    Returns (err_p, err_d, err_gap, pobj, dobj).
+    """
+    r = lp.G @ x - lp.h
+    err_p = float(np.linalg.norm(r - proj_Kd_star(r, lp.m_zero)))
+    lam = lp.c - lp.G.T @ y
+    err_d = float(np.linalg.norm(lam - proj_Lambda(lam, lp.l, lp.u)))
+    pobj = float(np.dot(lp.c, x))
+    dobj = dual_objective(lp, y, lam)
+    return err_p, err_d, abs(pobj - dobj), pobj, dobj
+
+
+def rel_errors_l2(lp: LPData, x, y):
+    """Relative errors of eq. tolerance-2: L2 numerators, 1+||h||_1, 1+||c||_1, 1+|pobj|+|dobj|."""
+    ep, ed, eg, pobj, dobj = abs_errors_l2(lp, x, y)
+    rp = ep / (1.0 + np.sum(np.abs(lp.h)))
+    rd = ed / (1.0 + np.sum(np.abs(lp.c)))
+    rg = eg / (1.0 + abs(pobj) + abs(dobj))
+    return rp, rd, rg
+
+
+def max_err(lp: LPData, x, y) -> float:
+    """maxErr of eq. tolerance."""
+    return float(max(rel_errors_l2(lp, x, y)))
+
+
+def reflection_parameter(maxerr: float) -> float:
+    """AdaptiveReflectionParameter (eq. adaptive_reflection): Proj_[0,1](-0.1 log10(maxErr) + 0.2).
+
+    Reading: maxErr = 0 gives beta = 1 (the limit of the formula).
+    """
+    if maxerr <= 0.0:
+        return 1.0
+    return float(min(1.0, max(0.0, -0.1 * math.log10(maxerr) + 0.2)))
+
+
+def kkt_omega(err_p, err_d, err_gap, omega):
+    """Weighted KKT error of Section 2.3 (used when the bisection fails)."""
+    return math.sqrt(omega ** 2 * err_p ** 2 + err_d ** 2 / omega ** 2 + err_gap ** 2)
+
+
+def termination_errors(lp: LPData, x, y):
+    """Unscaled errors of eq. PDCS_terminate_tolerance_abs and _rel (infinity norms).
+
+    Returns a dict with abs_p, abs_d, abs_gap, rel_p, rel_d, rel_gap, pobj, dobj.
+    """
+    Gx = lp.G @ x
+    r = Gx - lp.h
+    pr = proj_Kd_star(r, lp.m_zero)
+    abs_p = float(np.max(np.abs(r - pr), initial=0.0))
+    GTy = lp.G.T @ y
+    lam = lp.c - GTy
+    abs_d = float(np.max(np.abs(lam - proj_Lambda(lam, lp.l, lp.u)), initial=0.0))
+    pobj = float(np.dot(lp.c, x))
+    dobj = dual_objective(lp, y, lam)
+    abs_gap = abs(pobj - dobj)
+    inf = lambda v: float(np.max(np.abs(v), initial=0.0))
+    rel_p = abs_p / (1.0 + max(inf(lp.h), inf(Gx), inf(pr)))
+    rel_d = abs_d / (1.0 + max(inf(lp.c), inf(GTy)))
+    rel_gap = abs_gap / (1.0 + max(abs(pobj), abs(dobj)))
+    return dict(abs_p=abs_p, abs_d=abs_d, abs_gap=abs_gap, rel_p=rel_p, rel_d=rel_d,
+                rel_gap=rel_gap, pobj=pobj, dobj=dobj)
+
+
+def is_optimal(err: dict, rel_tol: float, abs_tol: float) -> bool:
+    """Reading: optimal when all three absolute errors are within abs_tol, or all three
+    relative errors are within rel_tol (Section 3 lists both tolerances)."""
+    a = max(err["abs_p"], err["abs_d"], err["abs_gap"]) <= abs_tol
+    r = max(err["rel_p"], err["rel_d"], err["rel_gap"]) <= rel_tol
+    return bool(a or r)
+
+
+# --------------------------------------------------------------------------
+# Adaptive step size (Section 2.1, Function 2)
+# --------------------------------------------------------------------------
+def eta_bar(lp: LPData, dx, dy, omega):
+    """Step-size limit: (1/2) ||(dx, dy)||_omega^2 / |dy^T G dx|, +inf when the
+    denominator vanishes (reading: such a step is always accepted)."""
+    num = 0.5 * (omega * np.dot(dx, dx) + np.dot(dy, dy) / omega)
+    den = abs(float(np.dot(dy, lp.G @ dx)))
+    if den == 0.0:
+        return math.inf
+    return float(num / den)
+
+
+def eta_next(etabar, eta, kbar):
+    """eta' = min((1-(kbar+1)^-0.3) eta_bar, (1+(kbar+1)^-0.6) eta)."""
+    return min((1.0 - (kbar + 1) ** -0.3) * etabar, (1.0 + (kbar + 1) ** -0.6) * eta)
+
+
+def adaptive_step_pdhg(lp: LPData, x, y, omega, eta, kbar, trace=None, max_kbar=1 << 62):
+    """AdaptiveStepPDHG (Function 2).
+
+    Reading of the trial counter: kbar counts every trial, accepted or not, and
+    is incremented at the top of each trial, so the first trial of a solve uses
+    kbar = 1 (with kbar = 0 the first factor of eta' would be zero).
+    Returns (x_hat, y_hat, eta, eta', kbar, n_trials); x_hat is None when the
+    trial budget ``max_kbar`` ran out on a rejected trial.
+    """
+    trials = 0
+    while True:
+        kbar += 1
+        trials += 1
+        tau = eta / omega
+        sigma = eta * omega
+        xh, yh = one_pdhg(lp, x, y, tau, sigma)
+        eb = eta_bar(lp, xh - x, yh - y, omega)
+        ep = eta_next(eb, eta, kbar)
+        acc = eta < eb
+        if trace is not None:
+            trace.append(dict(kbar=kbar, eta=eta, eta_bar=eb, eta_next=ep, accepted=bool(acc)))
+        if acc:
+            return xh, yh, eta, ep, kbar, trials
+        if not math.isfinite(ep) or ep <= 0.0:
+            raise FloatingPointError("step size collapsed")
+        eta = ep
+        if kbar >= max_kbar:
+            return None, None, eta, ep, kbar, trials
+
+
+# --------------------------------------------------------------------------
+# Normalized duality gap (Sections 2.3-2.4, Algorithm 3)
+# --------------------------------------------------------------------------
+def z_of_t(lp: LPData, x, y, b1, b2, tau, sigma, t):
+    """z(t) of eq. compute_zt_2: (Proj_X(x + t tau b1), Proj_Y(y + t sigma b2))."""
+    return proj_box(x + t * tau * b1, lp.l, lp.u), proj_Kd(y + t * sigma * b2, lp.m_zero)
+
+
+def n_norm(dx, dy, tau, sigma):
+    """||(dx, dy)||_N with N = diag(I/tau, I/sigma)."""
+    return math.sqrt(float(np.dot(dx, dx)) / tau + float(np.dot(dy, dy)) / sigma)
+
+
+def gap_direction(lp: LPData, x, y):
+    """b = (G^T y - c, h - G x) of eq. compute_rho."""
+    return lp.G.T @ y - lp.c, lp.h - lp.G @ x
+
+
+def normalized_gap(lp: LPData, x, y, tau, sigma, r, rel_eps=1e-6, max_doublings=64,
+                   b=None):
+    """rho^N(r; z) by Algorithm 3 (exponential search, then bisection on t).
+
+    Readings (the algorithm leaves t0, eps and the returned point open):
+    * t0 = r / sqrt(tau ||b1||^2 + sigma ||b2||^2): without projection this t
+      gives ||z - z(t)||_N = r, and projection is nonexpansive, so z(t0) lies in
+      the ball;
+    * the search doubles t at most ``max_doublings`` times; if a doubling does
+      not move the distance (every coordinate sits on a bound) the value at the
+      current t is returned;
+    * bisection stops when t_right - t_left <= rel_eps * t_right, and the value
+      is taken at t_left (a point inside the ball);
+    * r <= 0 or non-finite r returns NaN (treated by the caller as a numerical
+      issue); b = 0 returns 0.
+    """
+    if not (r > 0.0) or not math.isfinite(r):
+        return math.nan
+    b1, b2 = gap_direction(lp, x, y) if b is None else b
+
+    def dist(t):
+        xt, yt = z_of_t(lp, x, y, b1, b2, tau, sigma, t)
+        return n_norm(xt - x, yt - y, tau, sigma), xt, yt
+
+    def value(xt, yt):
+        return (float(np.dot(b1, xt - x)) + float(np.dot(b2, yt - y))) / r
+
+    scale = math.sqrt(tau * float(np.dot(b1, b1)) + sigma * float(np.dot(b2, b2)))
+    if scale == 0.0:
+        return 0.0
+    t0 = r / scale
+    d0, x0, y0 = dist(t0)
+    if d0 > r:
+        t_left, t_right = 0.0, t0
+    else:
+        t_prev, d_prev, xp, yp = t0, d0, x0, y0
+        bracket = False
+        for _ in range(max_doublings):
+            t = 2.0 * t_prev
+            d, xt, yt = dist(t)
+            if d > r:
+                t_left, t_right = t_prev, t
+                bracket = True
+                break
+            if d <= d_prev:  # saturated: z(2t) = z(t)
+                return value(xp, yp)
+            t_prev, d_prev, xp, yp = t, d, xt, yt
+        if not bracket:
+            return value(xp, yp)
+    while t_right - t_left > rel_eps * t_right:
+        t_mid = 0.5 * (t_left + t_right)
+        d, _, _ = dist(t_mid)
+        if d < r:
+            t_left = t_mid
+        else:
+            t_right = t_mid
+    _, xt, yt = dist(t_left)
+    return value(xt, yt)
+
+
+# --------------------------------------------------------------------------
+# Primal weight (Section 2.5)
+# --------------------------------------------------------------------------
+def primal_weight_init(c, h):
+    nc = float(np.linalg.norm(c))
+    nh = float(np.linalg.norm(h))
+    if nc > TINY and nh > TINY:
+        return nc / nh
+    return 1.0
+
+
+def primal_weight_update(dx, dy, omega_prev, omega0):
+    """PrimalWeightUpdate with theta = 0.5, then the reset to the initial weight when
+    omega leaves [1e-5, 1e5]."""
+    if dx > TINY and dy > TINY:
+        omega = math.exp(THETA * math.log(dy / dx) + (1.0 - THETA) * math.log(omega_prev))
+    else:
+        omega = omega_prev
+    if omega > OMEGA_MAX or omega < OMEGA_MIN:
+        omega = omega0
+    return omega
+
+
+# --------------------------------------------------------------------------
+# Restart logic (Section 2.3)
+# --------------------------------------------------------------------------
+def restart_decision(t, k, kbar, metric_c, metric_anchor, metric_prev):
+    """Restart conditions 1-3 with beta_sufficient/necessary/artificial = 0.4/0.8/0.223.
+
+    Readings: in the first interval (t = 0) the anchor has no predecessor, so
+    conditions 1 and 2 are off; condition 2 compares with the candidate of the
+    previous check in the same interval and is off at the interval's first check.
+    """
+    if k >= BETA_ARTIFICIAL * kbar:
+        return True, 3
+    if t == 0 or metric_anchor is None:
+        return False, 0
+    if metric_c <= BETA_SUFFICIENT * metric_anchor:
+        return True, 1
+    if metric_prev is not None and metric_c > metric_prev and metric_c <= BETA_NECESSARY * metric_anchor:
+        return True, 2
+    return False, 0
+
+
+def _valid_rho(v):
+    return v is not None and math.isfinite(v) and v >= 0.0
+
+
+# --------------------------------------------------------------------------
+# The solver (Algorithm 4 around Algorithm 1)
+# --------------------------------------------------------------------------
+@dataclass
+class Options:
+    rel_tol: float = 1e-6
+    abs_tol: float = 1e-6
+    max_iter: int = 1 << 62          # trial budget (exit code 1)
+    time_limit: float = 1000.0       # seconds (exit code 6)
+    use_preconditioner: bool = True
+    ruiz_iters: int = 10
+    l2_pass: bool = True
+    method: str = "auto"             # auto | average | halpern (candidate rule)
+    check_every: int = 64            # restart / termination check period, in trials
+    bisect_rel_eps: float = 1e-6
+    max_doublings: int = 64
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    y: np.ndarray
+    lam: np.ndarray
+    exit_code: int
+    pobj: float
+    dobj: float
+    errors: dict
+    iters: int                     # kbar: all trials
+    accepted: int
+    restarts: int
+    checks: int
+    time_sec: float
+    D1: np.ndarray
+    D2: np.ndarray
+    state: dict = field(default_factory=dict)
+    trace: list = field(default_factory=list)
+    checks_log: list = field(default_factory=list)
+
+
+def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool = False) -> Result:
+    """PDCS with preconditioning (Algorithm 4) on an LP.
+
+    Readings fixed here (all stated in the design notes):
+    * the restart/termination check runs after an accepted trial whose trial
+      count kbar is a multiple of ``check_every`` (the paper's options check every
+      duality_gap_restart_freq iterations);
+    * the restart candidates are the PDHG output z_hat^{t,k+1} and the eta-weighted
+      average of the PDHG outputs of the interval; both lie in X x Y, which the
+      normalized duality gap requires;
+    * tau, sigma inside N are eta_hat/omega and eta_hat*omega at the check;
+    * the anchor's metric is the candidate's value at the check that restarted;
+    * termination is evaluated on the unscaled candidate at each check (and on
+      the start point); the returned point is that candidate.
+    """
+    opts = opts or Options()
+    t_start = time.perf_counter()
+    m, n = lp.m, lp.n
+    if opts.use_preconditioner:
+        D1, D2 = ruiz_l2_scaling(lp.G, opts.ruiz_iters, opts.l2_pass)
+    else:
+        D1, D2 = np.ones(m), np.ones(n)
+    sl = rescale(lp, D1, D2)
+
+    def unscale(xs, ys):
+        return D2 * xs, D1 * ys
+
+    # Start point (reading: 0 when none is given), mapped to the scaled space and projected.
+    xs = np.zeros(n) if x0 is None else np.asarray(x0, np.float64) / D2
+    ys = np.zeros(m) if y0 is None else np.asarray(y0, np.float64) / D1
+    x = proj_box(xs, sl.l, sl.u)
+    y = proj_Kd(ys, sl.m_zero)
+
+    gmax = float(np.max(np.abs(sl.G.data), initial=0.0))
+    eta_hat = 1.0 / gmax if gmax > 0 else 1.0
+    omega0 = primal_weight_init(sl.c, sl.h)
+    omega = omega0
+    kbar = 0
+    accepted = 0
+    restarts = 0
+    checks = 0
+    t = 0
+    k = 0
+    xa, ya = x.copy(), y.copy()
+    Sx, Sy, SH = np.zeros(n), np.zeros(m), 0.0
+    xh, yh = x.copy(), y.copy()
+    metric_anchor = None
+    metric_prev = None
+    trial_log = [] if trace else None
+    checks_log = []
+
+    def finish(code, xs_, ys_):
+        xu, yu = unscale(xs_, ys_)
+        err = termination_errors(lp, xu, yu)
+        lam = lp.c - lp.G.T @ yu
+        return Result(xu, yu, lam, code, err["pobj"], err["dobj"], err, kbar, accepted,
+                      restarts, checks, time.perf_counter() - t_start, D1, D2,
+                      state=dict(x=x.copy(), y=y.copy(), x_hat=xh.copy(), y_hat=yh.copy(),
+                                 x_anchor=xa.copy(), y_anchor=ya.copy(), Sx=Sx.copy(),
+                                 Sy=Sy.copy(), SH=SH, omega=omega, omega0=omega0,
+                                 eta_hat=eta_hat, kbar=kbar, k=k, t=t),
+                      trace=trial_log or [], checks_log=checks_log)
+
+    # Termination test of the start point.
+    xu, yu = unscale(x, y)
+    if is_optimal(termination_errors(lp, xu, yu), opts.rel_tol, opts.abs_tol):
+        return finish(EXIT_OPTIMAL, x, y)
+
+    while True:
+        # ---- AdaptiveStepPDHG (Algorithm 1, line 4) ----
+        out = adaptive_step_pdhg(sl, x, y, omega, eta_hat, kbar, trial_log, opts.max_iter)
+        xh_new, yh_new, eta_k, eta_p, kbar, _ = out
+        if xh_new is None:  # trial budget ran out during rejections
+            return finish(EXIT_MAX_ITER, xh, yh)
+        if not (np.all(np.isfinite(xh_new)) and np.all(np.isfinite(yh_new))):
+            return finish(EXIT_NUMERICAL_ERROR, xh, yh)
+        xh, yh = xh_new, yh_new
+        eta_hat = eta_p
+        accepted += 1
+        # ---- beta at z_hat (line 5) ----
+        beta = reflection_parameter(max_err(sl, xh, yh))
+        if trial_log is not None:
+            trial_log[-1]["beta"] = beta
+        # ---- reflected Halpern (line 6) ----
+        a = (k + 1.0) / (k + 2.0)
+        bcoef = 1.0 / (k + 2.0)
+        x = a * ((1.0 + beta) * xh - beta * x) + bcoef * xa
+        y = a * ((1.0 + beta) * yh - beta * y) + bcoef * ya
+        # ---- eta-weighted average of the PDHG outputs (line 7) ----
+        Sx = Sx + eta_k * xh
+        Sy = Sy + eta_k * yh
+        SH += eta_k
+        k += 1
+
+        if kbar % opts.check_every == 0:
+            checks += 1
+            tau_c = eta_hat / omega
+            sig_c = eta_hat * omega
+            cands = {}
+            if opts.method in ("auto", "halpern"):
+                cands["cur"] = (xh, yh)
+            if opts.method in ("auto", "average"):
+                cands["avg"] = (Sx / SH, Sy / SH)
+            info = {}
+            for name, (cx, cy) in cands.items():
+                r = n_norm(cx - xa, cy - ya, tau_c, sig_c)
+                rho = normalized_gap(sl, cx, cy, tau_c, sig_c, r, opts.bisect_rel_eps,
+                                     opts.max_doublings)
+                ep, ed, eg, _, _ = abs_errors_l2(sl, cx, cy)
+                info[name] = dict(rho=rho, kkt=kkt_omega(ep, ed, eg, omega), err=(ep, ed, eg))
+            # Numerical issue (Section 2.3): any gap value of this check, of the
+            # anchor or of the previous candidate that is negative, NaN or has
+            # r = 0 switches every comparison of this check to KKT_omega.
+            stored = [d["rho"] for d in (metric_anchor, metric_prev) if d is not None]
+            use_kkt = not all(_valid_rho(v) for v in [i["rho"] for i in info.values()] + stored)
+            key = "kkt" if use_kkt else "rho"
+            if "cur" in info and "avg" in info:
+                chosen = "cur" if info["cur"][key] <= info["avg"][key] else "avg"
+            else:
+                chosen = next(iter(info))
+            cx, cy = cands[chosen]
+            mc = info[chosen][key]
+            m_anchor = None if metric_anchor is None else metric_anchor[key]
+            m_prev = None if metric_prev is None else metric_prev[key]
+            restart, rule = restart_decision(t, k, kbar, mc, m_anchor, m_prev)
+            xu, yu = unscale(cx, cy)
+            err = termination_errors(lp, xu, yu)
+            done = is_optimal(err, opts.rel_tol, opts.abs_tol)
+            checks_log.append(dict(kbar=kbar, k=k, t=t, chosen=chosen, use_kkt=use_kkt,
+                                   rho={nm: v["rho"] for nm, v in info.items()},
+                                   restart=bool(restart or done), rule=rule, omega=omega,
+                                   rel=max(err["rel_p"], err["rel_d"], err["rel_gap"])))
+            if done:
+                x, y = cx.copy(), cy.copy()
+                xh, yh = cx.copy(), cy.copy()
+                return finish(EXIT_OPTIMAL, cx, cy)
+            if restart:
+                # PrimalWeightUpdate(z^{t+1,0}, z^{t,0}, omega^t) and the new anchor.
+                dxn = float(np.linalg.norm(cx - xa))
+                dyn = float(np.linalg.norm(cy - ya))
+                omega = primal_weight_update(dxn, dyn, omega, omega0)
+                ep, ed, eg = info[chosen]["err"]
+                metric_anchor = dict(rho=info[chosen]["rho"], kkt=kkt_omega(ep, ed, eg, omega))
+                metric_prev = None
+                xa, ya = cx.copy(), cy.copy()
+                x, y = cx.copy(), cy.copy()
+                Sx, Sy, SH = np.zeros(n), np.zeros(m), 0.0
+                k = 0
+                t += 1
+                restarts += 1
+            else:
+                metric_prev = dict(rho=info[chosen]["rho"], kkt=info[chosen]["kkt"])
+        if kbar >= opts.max_iter:
+            return finish(EXIT_MAX_ITER, xh, yh)
+        if time.perf_counter() - t_start > opts.time_limit:
+            return finish(EXIT_TIME_LIMIT, xh, yh)
