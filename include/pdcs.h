@@ -1,0 +1,238 @@
+/*
+ * pdcs.h -- C ABI of the MI355X (gfx950) PDCS linear-programming solver.
+ *
+ * Problem solved (Section 1.1, eq. prob_cp, restricted to linear programs):
+ *
+ *     min  c^T x   s.t.  (G x - h)_i  = 0   for i <  m_zero      (zero cone)
+ *                        (G x - h)_i >= 0   for i >= m_zero      (nonnegative cone)
+ *                        l <= x <= u                            (box, +-inf allowed)
+ *
+ * with its dual (eq. dual_conic): max h^T y + l^T lam+ - u^T lam-, lam = c - G^T y.
+ * The method is "PDCS with preconditioning" (Section 2.6): diagonal rescaling,
+ * then the restarted, line-searched, reflected-Halpern PDHG loop of Algorithm 1
+ * (Function 2 for the step size, Section 2.2 for the reflection parameter,
+ * Section 2.3 / Algorithm 3 for restarts, Section 2.5 for the primal weight),
+ * then unscaling.  Every step of the loop runs in HIP kernels on the GPU.
+ *
+ * Conventions
+ *  - Every function returns an int status: PDCS_OK (0) or a negative PDCS_ERR_*.
+ *    Solver outcomes are NOT errors; they are the exit codes of the paper's
+ *    exit-code table (Section 3), reported in pdcs_info.exit_code.
+ *  - Host input arrays are copied during the call; the caller keeps ownership.
+ *  - Handles (problem, result, batch, mlp) are owned by the library until the
+ *    matching *_destroy call.  A handle must not be used from two threads at once.
+ *  - +-infinity bounds are IEEE infinities.  NaN anywhere in the data is an error.
+ *  - "stream" arguments are a hipStream_t passed as void* (NULL = the library's
+ *    own stream).  Solve calls are synchronous: they return with results on host.
+ *  - pdcs_last_error() returns a static string describing the last failure of
+ *    the calling thread.
+ */
+#ifndef PDCS_H
+#define PDCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define PDCS_OK               0
+#define PDCS_ERR_INVALID_ARG (-1)  /* null pointer, malformed CSR, NaN, l > u, bad sizes */
+#define PDCS_ERR_UNSUPPORTED (-2)  /* cone types other than zero / nonnegative rows     */
+#define PDCS_ERR_OOM         (-3)  /* device or host allocation failed                  */
+#define PDCS_ERR_HIP         (-4)  /* a HIP runtime call failed                          */
+#define PDCS_ERR_SIZE        (-5)  /* problem too large for 32-bit device indexing       */
+#define PDCS_ERR_STATE       (-6)  /* handle used in a state that does not allow the call */
+
+/* ---- exit codes: exit-code table of Section 3 --------------------------- */
+#define PDCS_EXIT_OPTIMAL                   0
+#define PDCS_EXIT_MAX_ITER                  1
+#define PDCS_EXIT_PRIMAL_INFEASIBLE_LOW_ACC 2
+#define PDCS_EXIT_PRIMAL_INFEASIBLE_HIGH_ACC 3
+#define PDCS_EXIT_DUAL_INFEASIBLE_LOW_ACC   4
+#define PDCS_EXIT_DUAL_INFEASIBLE_HIGH_ACC  5
+#define PDCS_EXIT_TIME_LIMIT                6
+#define PDCS_EXIT_CONTINUE                  7
+#define PDCS_EXIT_NUMERICAL_ERROR           8
+
+/* ---- candidate rule ("method" option of Section 3) ---------------------- */
+#define PDCS_METHOD_AUTO    0   /* smaller normalized duality gap (Section 2.3) */
+#define PDCS_METHOD_AVERAGE 1   /* eta-weighted average of the interval          */
+#define PDCS_METHOD_HALPERN 2   /* latest PDHG output                            */
+
+/* ---- precision ---------------------------------------------------------- */
+#define PDCS_PRECISION_FP64  0  /* FP64 values and iterates throughout              */
+#define PDCS_PRECISION_MIXED 1  /* FP32 values, iterates and SpMV; FP64 reductions,
+                                   scalars, restart decisions, termination checks
+                                   (FP64 values) and an FP64 polish phase           */
+
+typedef struct pdcs_problem_s* pdcs_problem;
+typedef struct pdcs_result_s*  pdcs_result;
+typedef struct pdcs_batch_s*   pdcs_batch;
+typedef struct pdcs_mlp_s*     pdcs_mlp;
+
+/* Solver options.  Defaults (pdcs_options_default) follow the option list of
+ * Section 3 where the paper gives one. All fields are 8 bytes wide. */
+typedef struct {
+  double  rel_tol;            /* 1e-6: eq. PDCS_terminate_tolerance_rel                */
+  double  abs_tol;            /* 1e-6: eq. PDCS_terminate_tolerance_abs                */
+  double  time_limit;         /* 1000 s: exit code 6                                  */
+  int64_t max_iter;           /* trial budget (every PDHG trial counts): exit code 1   */
+  int64_t use_preconditioner; /* 1: diagonal rescaling (Section 2.6)                   */
+  int64_t ruiz_iters;         /* 10 Ruiz passes (the paper does not fix the scaling)   */
+  int64_t l2_pass;            /* 1: one sqrt-L2-norm pass after Ruiz                    */
+  int64_t method;             /* PDCS_METHOD_*                                        */
+  int64_t check_every;        /* 64: restart/termination check after every accepted
+                                 trial whose trial count is a multiple of this         */
+  int64_t precision;          /* PDCS_PRECISION_*                                     */
+  int64_t stall_checks;       /* mixed: switch to FP64 after this many checks without
+                                 a 2x improvement of the relative KKT error (0: never) */
+  double  polish_switch_tol;  /* mixed: switch to FP64 once rel. KKT <= this (0: off)  */
+  double  bisect_rel_eps;     /* 1e-6: relative bracket width of the gap bisection     */
+  int64_t use_graph;          /* 1: replay each chunk of iterations as a hipGraph      */
+  int64_t verbose;            /* 0: silent; 1: one line per chunk for instance 0      */
+  int64_t keep_state;         /* 1: keep the internal iterates for pdcs_result_state   */
+  int64_t time_kernels;       /* 1: launch without graphs and time every launch of the
+                                 SpMV-with-dual-step kernel with HIP events           */
+  int64_t probe_passes;       /* 7: multisection passes per restart check (16 t each)  */
+  int64_t reserved[4];
+} pdcs_options;
+
+/* Per-solve information (result fields of Section 3 plus counters). */
+typedef struct {
+  int64_t exit_code;          /* PDCS_EXIT_*                                          */
+  int64_t iters;              /* trials (accepted + rejected), the paper's k-bar       */
+  int64_t accepted_iters;
+  int64_t restarts;
+  int64_t checks;
+  int64_t fp64_iters;         /* trials run in FP64 (all of them in FP64 mode)         */
+  double  pobj, dobj;         /* c^T x and the dual objective at the returned point    */
+  double  abs_p, abs_d, abs_gap;   /* infinity-norm errors, unscaled (Section 3)       */
+  double  rel_p, rel_d, rel_gap;
+  double  time_sec;           /* solve time: scaling + iterations + unscaling          */
+  double  omega;              /* final primal weight                                  */
+  double  eta_hat;            /* final step-size estimate                             */
+  double  spmv_avg_ms;        /* time_kernels: mean duration of the SpMV+dual kernel   */
+  int64_t spmv_launches;      /* time_kernels: number of launches timed                */
+  double  reserved[4];
+} pdcs_info;
+
+/* Scalars of the internal state of a finished solve, in the rescaled space. */
+typedef struct {
+  double  omega, omega0, eta_hat, eta, beta, sum_eta;
+  int64_t kbar, k, t, accepted;
+  int64_t precision;          /* precision the iterates were in at exit               */
+  int64_t reserved[5];
+} pdcs_state_scalars;
+
+void        pdcs_options_default(pdcs_options* opts);
+const char* pdcs_status_string(int exit_code);
+const char* pdcs_last_error(void);
+/* Number of visible GPUs (0 when none); never fails. */
+int         pdcs_device_count(void);
+
+/* ---- problems ----------------------------------------------------------
+ * pdcs_problem_create: upload one LP (Section 1.1, eq. prob_cp, LP case).
+ *   m, n       : rows and columns of G (m >= 0, n >= 1)
+ *   m_zero     : rows [0, m_zero) are equalities, [m_zero, m) are ">=" rows
+ *   row_ptr    : int64[m+1], nondecreasing, row_ptr[0] = 0, row_ptr[m] = nnz < 2^31
+ *   col_idx    : int32[nnz], in [0, n), strictly increasing within a row
+ *   val        : double[nnz], finite
+ *   h          : double[m], finite;  c: double[n], finite
+ *   l, u       : double[n], l <= u, l < +inf, u > -inf (NULL l means 0, NULL u means +inf)
+ * All arrays are host memory, copied to the device; the transposed CSR is
+ * built during the call.  Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_SIZE,
+ * PDCS_ERR_OOM, PDCS_ERR_HIP.
+ */
+int  pdcs_problem_create(int64_t m, int64_t n, int64_t m_zero,
+                         const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                         const double* h, const double* c, const double* l, const double* u,
+                         pdcs_problem* out);
+void pdcs_problem_destroy(pdcs_problem p);
+int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
+
+/* pdcs_problem_spmv: one product with the UNSCALED matrix on device memory.
+ *   transpose = 0: out[m] = G in[n];  transpose = 1: out[n] = G^T in[m].
+ *   precision = PDCS_PRECISION_FP64: in/out are double*, FP64 values;
+ *   precision = PDCS_PRECISION_MIXED: in/out are float*, FP32 values, FP64 accumulation.
+ * in_dev / out_dev are device pointers owned by the caller; the kernel is the
+ * one the solver uses for its matrix products, launched on `stream` and not
+ * synchronized.  Errors: PDCS_ERR_INVALID_ARG. */
+int  pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision,
+                       const void* in_dev, void* out_dev, void* stream);
+
+/* ---- single solve ------------------------------------------------------
+ * pdcs_solve: Algorithm 4 (rescale, Algorithm 1, unscale) on one problem.
+ *   x0 / y0 : optional host warm start (double[n] / double[m]); NULL = zero
+ *             (projected onto the box and the dual cone).
+ *   out     : receives a result handle (also on non-optimal exits).
+ * Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_OOM, PDCS_ERR_HIP. */
+int  pdcs_solve(pdcs_problem p, const pdcs_options* opts, const double* x0, const double* y0,
+                void* stream, pdcs_result* out);
+
+int  pdcs_result_info(pdcs_result r, pdcs_info* out);
+/* Copy results of instance 0 (single solves) to host buffers of exactly the
+ * given length (mismatch: PDCS_ERR_INVALID_ARG). x: primal, y: dual,
+ * lam: dual slack c - G^T y (the "slack" field of Section 3). */
+int  pdcs_result_primal(pdcs_result r, double* x, int64_t n);
+int  pdcs_result_dual(pdcs_result r, double* y, int64_t m);
+int  pdcs_result_slack(pdcs_result r, double* lam, int64_t n);
+/* Diagonal scaling used (G_hat = D1 G D2, eq. rescaled_prob). */
+int  pdcs_result_scaling(pdcs_result r, double* D1, int64_t m, double* D2, int64_t n);
+/* Internal iterate state at exit, rescaled space, FP64 copies: Halpern iterate
+ * (x, y), last PDHG output (x_hat, y_hat), anchor (x_a, y_a).  Any pointer may
+ * be NULL.  Lengths are the problem's n (x-like) and m (y-like). */
+int  pdcs_result_state(pdcs_result r, pdcs_state_scalars* s, double* x, double* y,
+                       double* x_hat, double* y_hat, double* x_a, double* y_a);
+void pdcs_result_destroy(pdcs_result r);
+
+/* ---- batched solves ----------------------------------------------------
+ * pdcs_batch_create: pack `count` problems block-diagonally into one device
+ * structure; every kernel of the iteration then runs once over all instances,
+ * each with its own scalars (step size, primal weight, restart state, exit
+ * code).  The problems are only read during the call. */
+int  pdcs_batch_create(int64_t count, const pdcs_problem* probs, pdcs_batch* out);
+/* Solve all instances; results[i] receives instance i's result handle.
+ * x0s / y0s: NULL or arrays of `count` host pointers (each may be NULL). */
+int  pdcs_batch_solve(pdcs_batch b, const pdcs_options* opts, const double* const* x0s,
+                      const double* const* y0s, void* stream, pdcs_result* results);
+/* Autotune the row-tile schedule of this batch: times SpMV schedules with HIP
+ * events and keeps the fastest (see pdcs_batch_schedule).  time_budget_ms <= 0
+ * uses a default. */
+int  pdcs_batch_autotune(pdcs_batch b, double time_budget_ms);
+/* Current schedule: iter_max (row-group iterations per wavefront tile),
+ * block_nnz (nonzeros per workgroup), vec_per_block (elements per workgroup). */
+int  pdcs_batch_schedule(pdcs_batch b, int64_t* iter_max, int64_t* block_nnz,
+                         int64_t* vec_per_block);
+int  pdcs_batch_set_schedule(pdcs_batch b, int64_t iter_max, int64_t block_nnz,
+                             int64_t vec_per_block);
+void pdcs_batch_destroy(pdcs_batch b);
+
+/* ---- warm-start MLP ----------------------------------------------------
+ * 3-layer perceptron v = W3 relu(W2 relu(W1 u + b1) + b2) + b3 with BF16
+ * weights (FP32 master copy) and FP32 accumulation on MFMA units.  Inputs and
+ * outputs are device float32 row-major [batch x d]. */
+int  pdcs_mlp_create(int64_t d_in, int64_t width, int64_t d_out, uint64_t seed, pdcs_mlp* out);
+int  pdcs_mlp_forward(pdcs_mlp net, const float* in_dev, float* out_dev, int64_t batch,
+                      void* stream);
+/* One Adam step on the mean squared error; *loss_out (host) receives the loss
+ * of the batch before the step. */
+int  pdcs_mlp_train_step(pdcs_mlp net, const float* in_dev, const float* target_dev,
+                         int64_t batch, float lr, float* loss_out, void* stream);
+/* Gradients of the MSE loss at the current weights without updating them, as
+ * FP32 device arrays laid out like the weights (W1[width x d_in], b1[width],
+ * W2[width x width], b2[width], W3[d_out x width], b3[d_out]). */
+int  pdcs_mlp_gradients(pdcs_mlp net, const float* in_dev, const float* target_dev,
+                        int64_t batch, float* grad_dev, float* loss_out, void* stream);
+int  pdcs_mlp_num_params(pdcs_mlp net, int64_t* count);
+/* Read or write the FP32 master weights (host float[num_params], same layout
+ * as the gradients).  Writing also refreshes the BF16 copies. */
+int  pdcs_mlp_get_params(pdcs_mlp net, float* params_host);
+int  pdcs_mlp_set_params(pdcs_mlp net, const float* params_host);
+void pdcs_mlp_destroy(pdcs_mlp net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDCS_H */

@@ -1,0 +1,406 @@
+"""ctypes binding of the C ABI in include/pdcs.h (argument marshalling only).
+
+Every compute step runs inside libpdcs.so.  Importing this module loads the
+library and fails loudly when it has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdcs.so")
+
+PDCS_OK = 0
+ERRORS = {-1: "invalid argument", -2: "unsupported", -3: "out of memory", -4: "HIP error",
+          -5: "size", -6: "state"}
+EXIT_OPTIMAL, EXIT_MAX_ITER, EXIT_TIME_LIMIT, EXIT_CONTINUE, EXIT_NUMERICAL_ERROR = 0, 1, 6, 7, 8
+METHOD = {"auto": 0, "average": 1, "halpern": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class PdcsError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({detail})")
+        self.code = code
+
+
+class pdcs_options(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("abs_tol", C.c_double), ("time_limit", C.c_double),
+                ("max_iter", C.c_int64), ("use_preconditioner", C.c_int64), ("ruiz_iters", C.c_int64),
+                ("l2_pass", C.c_int64), ("method", C.c_int64), ("check_every", C.c_int64),
+                ("precision", C.c_int64), ("stall_checks", C.c_int64),
+                ("polish_switch_tol", C.c_double), ("bisect_rel_eps", C.c_double),
+                ("use_graph", C.c_int64), ("verbose", C.c_int64), ("keep_state", C.c_int64),
+                ("time_kernels", C.c_int64), ("probe_passes", C.c_int64),
+                ("reserved", C.c_int64 * 4)]
+
+
+class pdcs_info(C.Structure):
+    _fields_ = [("exit_code", C.c_int64), ("iters", C.c_int64), ("accepted_iters", C.c_int64),
+                ("restarts", C.c_int64), ("checks", C.c_int64), ("fp64_iters", C.c_int64),
+                ("pobj", C.c_double), ("dobj", C.c_double), ("abs_p", C.c_double),
+                ("abs_d", C.c_double), ("abs_gap", C.c_double), ("rel_p", C.c_double),
+                ("rel_d", C.c_double), ("rel_gap", C.c_double), ("time_sec", C.c_double),
+                ("omega", C.c_double), ("eta_hat", C.c_double), ("spmv_avg_ms", C.c_double),
+                ("spmv_launches", C.c_int64), ("reserved", C.c_double * 4)]
+
+
+class pdcs_state_scalars(C.Structure):
+    _fields_ = [("omega", C.c_double), ("omega0", C.c_double), ("eta_hat", C.c_double),
+                ("eta", C.c_double), ("beta", C.c_double), ("sum_eta", C.c_double),
+                ("kbar", C.c_int64), ("k", C.c_int64), ("t", C.c_int64), ("accepted", C.c_int64),
+                ("precision", C.c_int64), ("reserved", C.c_int64 * 5)]
+
+
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+_I64 = C.c_int64
+
+# name -> (restype, argtypes)
+PROTOTYPES = {
+    "pdcs_options_default": (None, [C.POINTER(pdcs_options)]),
+    "pdcs_status_string": (C.c_char_p, [C.c_int]),
+    "pdcs_last_error": (C.c_char_p, []),
+    "pdcs_device_count": (C.c_int, []),
+    "pdcs_problem_create": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+    "pdcs_problem_destroy": (None, [_P]),
+    "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
+    "pdcs_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, C.POINTER(_P)]),
+    "pdcs_result_info": (C.c_int, [_P, C.POINTER(pdcs_info)]),
+    "pdcs_result_primal": (C.c_int, [_P, _P, _I64]),
+    "pdcs_result_dual": (C.c_int, [_P, _P, _I64]),
+    "pdcs_result_slack": (C.c_int, [_P, _P, _I64]),
+    "pdcs_result_scaling": (C.c_int, [_P, _P, _I64, _P, _I64]),
+    "pdcs_result_state": (C.c_int, [_P, C.POINTER(pdcs_state_scalars), _P, _P, _P, _P, _P, _P]),
+    "pdcs_result_destroy": (None, [_P]),
+    "pdcs_batch_create": (C.c_int, [_I64, _P, C.POINTER(_P)]),
+    "pdcs_batch_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, _P]),
+    "pdcs_batch_autotune": (C.c_int, [_P, C.c_double]),
+    "pdcs_batch_schedule": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "pdcs_batch_set_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
+    "pdcs_batch_destroy": (None, [_P]),
+    "pdcs_mlp_create": (C.c_int, [_I64, _I64, _I64, C.c_uint64, C.POINTER(_P)]),
+    "pdcs_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
+    "pdcs_mlp_train_step": (C.c_int, [_P, _P, _P, _I64, C.c_float, C.POINTER(C.c_float), _P]),
+    "pdcs_mlp_gradients": (C.c_int, [_P, _P, _P, _I64, _P, C.POINTER(C.c_float), _P]),
+    "pdcs_mlp_num_params": (C.c_int, [_P, C.POINTER(_I64)]),
+    "pdcs_mlp_get_params": (C.c_int, [_P, _P]),
+    "pdcs_mlp_set_params": (C.c_int, [_P, _P]),
+    "pdcs_mlp_destroy": (None, [_P]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2603_15504_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        try:
+            fn = getattr(lib, name)
+        except AttributeError:
+            MISSING.append(name)
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+MISSING: list[str] = []
+
+
+lib = load_library()
+
+
+def _check(code: int, where: str):
+    if code != PDCS_OK:
+        raise PdcsError(code, where, lib.pdcs_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, n=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} entries, got {a.size}")
+    return a
+
+
+# ---------------------------------------------------------------------------
+# Same-name wrappers (marshalling only)
+# ---------------------------------------------------------------------------
+def pdcs_options_default(**overrides) -> pdcs_options:
+    o = pdcs_options()
+    lib.pdcs_options_default(C.byref(o))
+    for k, v in overrides.items():
+        if k == "method" and isinstance(v, str):
+            v = METHOD[v]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        if not hasattr(o, k):
+            raise KeyError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def pdcs_status_string(code: int) -> str:
+    return lib.pdcs_status_string(int(code)).decode()
+
+
+def pdcs_device_count() -> int:
+    return int(lib.pdcs_device_count())
+
+
+def pdcs_problem_create(m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=None) -> C.c_void_p:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    val = _f64(val)
+    h = _f64(h, m) if m > 0 else np.zeros(1)
+    c = _f64(c, n)
+    l = _f64(l, n)
+    u = _f64(u, n)
+    out = C.c_void_p()
+    _check(lib.pdcs_problem_create(int(m), int(n), int(m_zero), _ptr(row_ptr), _ptr(col_idx), _ptr(val),
+                                   _ptr(h), _ptr(c), _ptr(l), _ptr(u), C.byref(out)),
+           "pdcs_problem_create")
+    return out
+
+
+def pdcs_problem_destroy(p):
+    lib.pdcs_problem_destroy(p)
+
+
+def pdcs_problem_dims(p):
+    m, n, z = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib.pdcs_problem_dims(p, C.byref(m), C.byref(n), C.byref(z)), "pdcs_problem_dims")
+    return m.value, n.value, z.value
+
+
+def pdcs_problem_spmv(p, transpose: int, precision: int, in_dev: int, out_dev: int, stream: int = 0):
+    _check(lib.pdcs_problem_spmv(p, int(transpose), int(precision), C.c_void_p(in_dev),
+                                 C.c_void_p(out_dev), C.c_void_p(stream) if stream else None),
+           "pdcs_problem_spmv")
+
+
+def pdcs_solve(p, opts: pdcs_options | None = None, x0=None, y0=None, stream: int = 0) -> C.c_void_p:
+    m, n, _ = pdcs_problem_dims(p)
+    x0 = _f64(x0, n)
+    y0 = _f64(y0, m)
+    out = C.c_void_p()
+    _check(lib.pdcs_solve(p, C.byref(opts) if opts is not None else None, _ptr(x0), _ptr(y0),
+                          C.c_void_p(stream) if stream else None, C.byref(out)), "pdcs_solve")
+    return out
+
+
+def pdcs_result_info(r) -> pdcs_info:
+    info = pdcs_info()
+    _check(lib.pdcs_result_info(r, C.byref(info)), "pdcs_result_info")
+    return info
+
+
+def _get_vec(fn, r, length, name):
+    out = np.empty(length, dtype=np.float64)
+    _check(fn(r, _ptr(out), int(length)), name)
+    return out
+
+
+def pdcs_result_primal(r, n):
+    return _get_vec(lib.pdcs_result_primal, r, n, "pdcs_result_primal")
+
+
+def pdcs_result_dual(r, m):
+    return _get_vec(lib.pdcs_result_dual, r, m, "pdcs_result_dual")
+
+
+def pdcs_result_slack(r, n):
+    return _get_vec(lib.pdcs_result_slack, r, n, "pdcs_result_slack")
+
+
+def pdcs_result_scaling(r, m, n):
+    D1 = np.empty(m, dtype=np.float64)
+    D2 = np.empty(n, dtype=np.float64)
+    _check(lib.pdcs_result_scaling(r, _ptr(D1), m, _ptr(D2), n), "pdcs_result_scaling")
+    return D1, D2
+
+
+def pdcs_result_state(r, m, n, vectors: bool = True):
+    s = pdcs_state_scalars()
+    if not vectors:
+        _check(lib.pdcs_result_state(r, C.byref(s), None, None, None, None, None, None), "pdcs_result_state")
+        return s, None
+    vec = {k: np.empty(n if k.startswith("x") else m) for k in ("x", "y", "x_hat", "y_hat", "x_a", "y_a")}
+    _check(lib.pdcs_result_state(r, C.byref(s), _ptr(vec["x"]), _ptr(vec["y"]), _ptr(vec["x_hat"]),
+                                 _ptr(vec["y_hat"]), _ptr(vec["x_a"]), _ptr(vec["y_a"])),
+           "pdcs_result_state")
+    return s, vec
+
+
+def pdcs_result_destroy(r):
+    lib.pdcs_result_destroy(r)
+
+
+def pdcs_batch_create(problems) -> C.c_void_p:
+    arr = (C.c_void_p * len(problems))(*[p.value if isinstance(p, C.c_void_p) else p for p in problems])
+    out = C.c_void_p()
+    _check(lib.pdcs_batch_create(len(problems), C.cast(arr, C.c_void_p), C.byref(out)), "pdcs_batch_create")
+    return out
+
+
+def pdcs_batch_solve(b, count, opts=None, x0s=None, y0s=None, stream: int = 0):
+    keep = []
+
+    def ptr_array(vs):
+        if vs is None:
+            return None
+        arr = (C.c_void_p * count)()
+        for i, v in enumerate(vs):
+            if v is not None:
+                a = _f64(v)
+                keep.append(a)
+                arr[i] = a.ctypes.data
+        keep.append(arr)
+        return C.cast(arr, C.c_void_p)
+
+    res = (C.c_void_p * count)()
+    _check(lib.pdcs_batch_solve(b, C.byref(opts) if opts is not None else None, ptr_array(x0s),
+                                ptr_array(y0s), C.c_void_p(stream) if stream else None,
+                                C.cast(res, C.c_void_p)), "pdcs_batch_solve")
+    return [C.c_void_p(res[i]) for i in range(count)]
+
+
+def pdcs_batch_autotune(b, time_budget_ms: float = 0.0):
+    _check(lib.pdcs_batch_autotune(b, float(time_budget_ms)), "pdcs_batch_autotune")
+
+
+def pdcs_batch_schedule(b):
+    a, bb, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib.pdcs_batch_schedule(b, C.byref(a), C.byref(bb), C.byref(c)), "pdcs_batch_schedule")
+    return a.value, bb.value, c.value
+
+
+def pdcs_batch_set_schedule(b, iter_max, block_nnz, vec_per_block):
+    _check(lib.pdcs_batch_set_schedule(b, int(iter_max), int(block_nnz), int(vec_per_block)),
+           "pdcs_batch_set_schedule")
+
+
+def pdcs_batch_destroy(b):
+    lib.pdcs_batch_destroy(b)
+
+
+# ---------------------------------------------------------------------------
+# Convenience layer (still marshalling only)
+# ---------------------------------------------------------------------------
+@dataclass
+class Solution:
+    x: np.ndarray
+    y: np.ndarray
+    lam: np.ndarray
+    info: dict
+    D1: np.ndarray | None = None
+    D2: np.ndarray | None = None
+    state: dict | None = None
+
+
+def _info_dict(info: pdcs_info) -> dict:
+    d = {name: getattr(info, name) for name, _ in pdcs_info._fields_ if name != "reserved"}
+    d["status"] = pdcs_status_string(d["exit_code"])
+    return d
+
+
+class Problem:
+    """An LP uploaded to the GPU (pdcs_problem)."""
+
+    def __init__(self, m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=None):
+        self.m, self.n = int(m), int(n)
+        self.handle = pdcs_problem_create(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u)
+
+    @classmethod
+    def from_instance(cls, inst):
+        return cls(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx, inst.val, inst.h, inst.c,
+                   inst.l, inst.u)
+
+    def solve(self, x0=None, y0=None, with_scaling=False, **opts) -> Solution:
+        o = pdcs_options_default(**opts)
+        r = pdcs_solve(self.handle, o, x0, y0)
+        try:
+            return _collect(r, self.m, self.n, with_scaling, bool(o.keep_state))
+        finally:
+            pdcs_result_destroy(r)
+
+    def spmv(self, x_dev, out_dev, transpose=False, precision="fp64", stream=0):
+        pdcs_problem_spmv(self.handle, 1 if transpose else 0, PRECISION[precision], x_dev, out_dev, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pdcs_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _collect(r, m, n, with_scaling, with_state) -> Solution:
+    info = _info_dict(pdcs_result_info(r))
+    sol = Solution(pdcs_result_primal(r, n), pdcs_result_dual(r, m) if m > 0 else np.zeros(0),
+                   pdcs_result_slack(r, n), info)
+    if with_scaling:
+        sol.D1, sol.D2 = pdcs_result_scaling(r, m, n)
+    if with_state:
+        s, vec = pdcs_result_state(r, m, n, True)
+        st = {name: getattr(s, name) for name, _ in pdcs_state_scalars._fields_ if name != "reserved"}
+        st.update(vec)
+        sol.state = st
+    return sol
+
+
+class Batch:
+    """Block-diagonal batch of LPs solved together (pdcs_batch)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.handle = pdcs_batch_create([p.handle for p in self.problems])
+
+    def solve(self, x0s=None, y0s=None, with_scaling=False, **opts):
+        o = pdcs_options_default(**opts)
+        rs = pdcs_batch_solve(self.handle, len(self.problems), o, x0s, y0s)
+        out = []
+        try:
+            for r, p in zip(rs, self.problems):
+                out.append(_collect(r, p.m, p.n, with_scaling, bool(o.keep_state)))
+        finally:
+            for r in rs:
+                pdcs_result_destroy(r)
+        return out
+
+    def autotune(self, budget_ms=0.0):
+        pdcs_batch_autotune(self.handle, budget_ms)
+        return pdcs_batch_schedule(self.handle)
+
+    def schedule(self):
+        return pdcs_batch_schedule(self.handle)
+
+    def set_schedule(self, iter_max, block_nnz, vec_per_block):
+        pdcs_batch_set_schedule(self.handle, iter_max, block_nnz, vec_per_block)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pdcs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

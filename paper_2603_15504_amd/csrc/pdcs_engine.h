@@ -1,0 +1,151 @@
+// Host-side objects of the PDCS LP solver (device buffers, schedules, engine).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pdcs.h"
+#include "pdcs_launch.h"
+
+namespace pdcs {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define HIP_OK(expr)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      (void)hipGetLastError();                                                                     \
+      throw ::pdcs::Error(PDCS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    }                                                                                              \
+  } while (0)
+
+// Owning device allocation (never zero-sized, so pointers are always valid).
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void alloc(size_t b);
+  void release();
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// One validated LP in host memory, with its transpose (CSC) built.
+struct HostProblem {
+  int64_t m = 0, n = 0, m_zero = 0, nnz = 0;
+  std::vector<int32_t> rp, ci, cp, ri;
+  std::vector<double> v, vt, h, c, l, u;
+  void build(int64_t m, int64_t n, int64_t mz, const int64_t* row_ptr, const int32_t* col_idx,
+             const double* val, const double* h, const double* c, const double* l, const double* u);
+};
+
+// Tile schedule parameters (chosen by pdcs_batch_autotune or set explicitly).
+struct Schedule {
+  int iter_max = 8;        // passes per lane group in a multi-row wavefront tile
+  int block_nnz = 8192;    // work units (nonzeros + 4 per row) per workgroup
+  int vec_per_block = 2048;  // elements per workgroup in elementwise passes
+};
+
+struct TileSet {
+  DBuf row0, row1, lg, btile0, btile1, binst_d, iblk0_d;
+  int nblk = 0, ntiles = 0;
+  std::vector<int32_t> h_bt0, h_bt1, h_t0, h_t1;
+  void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s);
+  Tiles view() const;
+};
+
+struct RangeSet {
+  DBuf start, end, binst_d, iblk0_d;
+  int nblk = 0;
+  void build(const std::vector<int64_t>& inst_off, int per_block);
+  Ranges view() const;
+};
+
+template <typename T>
+struct IterBufs {
+  DBuf b[16];
+  IterPtrs<T> p{};
+  bool ready = false;
+  void alloc(int64_t N, int64_t M);
+};
+
+// Device copies of one solve's outputs, shared by the results of a batch.
+struct OutBlock {
+  int64_t M = 0, N = 0;
+  DBuf x, y, lam, D1, D2;
+  DBuf st[2][6];  // [fp64, fp32] x [x, y, x_hat, y_hat, x_a, y_a]
+};
+
+struct Engine {
+  int B = 0;
+  int64_t M = 0, N = 0, NNZ = 0;
+  std::vector<int64_t> row0, col0, mzero;
+  std::vector<int32_t> h_rp, h_cp;
+  DBuf d_rp, d_ci, d_v, d_cp, d_ri, d_vt, d_h, d_c, d_l, d_u;
+  DBuf orig32, origT32;
+  DBuf val64, valT64, val32, valT32;
+  DBuf h64, c64, l64, u64, h32, c32, l32, u32;
+  DBuf D1, D2, cgx0, cgx1, cgty0, cgty1, xout, yout, lamout, stat_r, stat_c;
+  DBuf rec_primal, rec_dual, rec_lam, rec_cand_c, rec_cand_r, rec_probe_c, rec_probe_r;
+  DBuf rec_nc, rec_nr, rec_nm;
+  DBuf d_inst, d_summary, warm_x, warm_y;
+  int32_t* h_summary = nullptr;
+  IterBufs<float> it32;
+  IterBufs<double> it64;
+  Schedule sched;
+  TileSet trow, tcol;
+  RangeSet vrow, vcol;
+  hipStream_t stream = nullptr;
+  std::map<int64_t, hipGraphExec_t> graphs;
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_count = 0;
+
+  explicit Engine(const std::vector<const HostProblem*>& probs);
+  ~Engine();
+  void build_schedule();
+  void clear_graphs();
+  void ensure_iter(int prec);
+  KernelCtx ctx(int probe_passes) const;
+  void enqueue_chunk(const KernelCtx& k, int mask, int64_t K, bool timed);
+  void harvest_events();
+  std::vector<struct pdcs_result_s*> solve(const pdcs_options& o, const double* const* x0s,
+                                           const double* const* y0s);
+  double time_dual(int prec, int reps);
+  void autotune(double budget_ms);
+};
+
+}  // namespace pdcs
+
+struct pdcs_problem_s {
+  pdcs::HostProblem hp;
+  std::unique_ptr<pdcs::Engine> eng;
+};
+
+struct pdcs_result_s {
+  std::shared_ptr<pdcs::OutBlock> out;
+  int64_t row0 = 0, col0 = 0, m = 0, n = 0;
+  pdcs_info info{};
+  pdcs_state_scalars st{};
+  bool has_state = false;
+};
+
+struct pdcs_batch_s {
+  std::unique_ptr<pdcs::Engine> eng;
+};

@@ -1,0 +1,1045 @@
+// Host side of the PDCS LP solver: problem validation and CSR transposition,
+// block-diagonal batch packing, wavefront-tile schedules, the chunked solve
+// loop (hipGraph replay of check_every trials plus one restart check), and
+// the C ABI declared in include/pdcs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pdcs.h"
+#include "pdcs_engine.h"
+#include "pdcs_launch.h"
+
+using namespace pdcs;
+
+namespace pdcs {
+
+thread_local std::string g_err;
+
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+void DBuf::alloc(size_t b) {
+  release();
+  if (b == 0) b = 256;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error(e == hipErrorOutOfMemory ? PDCS_ERR_OOM : PDCS_ERR_HIP,
+                std::string("hipMalloc(") + std::to_string(b) + "): " + hipGetErrorString(e));
+  }
+  bytes = b;
+}
+
+void DBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+template <typename T>
+static void upload(DBuf& d, const std::vector<T>& h) {
+  d.alloc(h.size() * sizeof(T));
+  if (!h.empty()) HIP_OK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// Problem validation and transposition
+// ---------------------------------------------------------------------------
+void HostProblem::build(int64_t m_, int64_t n_, int64_t mz, const int64_t* row_ptr, const int32_t* col_idx,
+                        const double* val, const double* h_, const double* c_, const double* l_,
+                        const double* u_) {
+  if (m_ < 0 || n_ < 1) throw Error(PDCS_ERR_INVALID_ARG, "need m >= 0 and n >= 1");
+  if (mz < 0 || mz > m_) throw Error(PDCS_ERR_INVALID_ARG, "m_zero must lie in [0, m]");
+  if (m_ >= INT32_MAX || n_ >= INT32_MAX) throw Error(PDCS_ERR_SIZE, "m and n must be < 2^31 - 1");
+  if (!row_ptr) throw Error(PDCS_ERR_INVALID_ARG, "row_ptr is null");
+  if (!c_) throw Error(PDCS_ERR_INVALID_ARG, "c is null");
+  if (m_ > 0 && !h_) throw Error(PDCS_ERR_INVALID_ARG, "h is null");
+  if (row_ptr[0] != 0) throw Error(PDCS_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < m_; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) throw Error(PDCS_ERR_INVALID_ARG, "row_ptr is not nondecreasing");
+  const int64_t nz = row_ptr[m_];
+  if (nz >= INT32_MAX) throw Error(PDCS_ERR_SIZE, "nnz must be < 2^31 - 1");
+  if (nz > 0 && (!col_idx || !val)) throw Error(PDCS_ERR_INVALID_ARG, "col_idx or val is null");
+  m = m_;
+  n = n_;
+  m_zero = mz;
+  nnz = nz;
+  rp.resize(m + 1);
+  for (int64_t i = 0; i <= m; ++i) rp[i] = (int32_t)row_ptr[i];
+  ci.assign(col_idx, col_idx + nz);
+  v.assign(val, val + nz);
+  for (int64_t i = 0; i < m; ++i) {
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      const int32_t c = col_idx[p];
+      if (c < 0 || c >= n) throw Error(PDCS_ERR_INVALID_ARG, "column index out of range");
+      if (p > row_ptr[i] && c <= col_idx[p - 1])
+        throw Error(PDCS_ERR_INVALID_ARG, "column indices must increase strictly within a row");
+      if (!std::isfinite(val[p])) throw Error(PDCS_ERR_INVALID_ARG, "non-finite matrix value");
+    }
+  }
+  h.assign(m, 0.0);
+  for (int64_t i = 0; i < m; ++i) {
+    if (!std::isfinite(h_[i])) throw Error(PDCS_ERR_INVALID_ARG, "non-finite h");
+    h[i] = h_[i];
+  }
+  c.assign(c_, c_ + n);
+  l.assign(n, 0.0);
+  u.assign(n, std::numeric_limits<double>::infinity());
+  for (int64_t j = 0; j < n; ++j) {
+    if (!std::isfinite(c[j])) throw Error(PDCS_ERR_INVALID_ARG, "non-finite c");
+    if (l_) l[j] = l_[j];
+    if (u_) u[j] = u_[j];
+    if (std::isnan(l[j]) || std::isnan(u[j])) throw Error(PDCS_ERR_INVALID_ARG, "NaN bound");
+    if (l[j] > u[j]) throw Error(PDCS_ERR_INVALID_ARG, "l > u");
+    if (l[j] == std::numeric_limits<double>::infinity() || u[j] == -std::numeric_limits<double>::infinity())
+      throw Error(PDCS_ERR_INVALID_ARG, "l = +inf or u = -inf");
+  }
+  // Transpose by a stable counting sort: rows stay ascending inside each column.
+  cp.assign(n + 1, 0);
+  for (int64_t p = 0; p < nz; ++p) cp[ci[p] + 1]++;
+  for (int64_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
+  ri.resize(nz);
+  vt.resize(nz);
+  std::vector<int32_t> fill(cp.begin(), cp.end() - 1);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      const int32_t q = fill[ci[p]]++;
+      ri[q] = (int32_t)i;
+      vt[q] = v[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Schedules
+// ---------------------------------------------------------------------------
+static int lanes_for(int rows) {
+  int L = 64;
+  while (L > 1 && L * rows > 64) L >>= 1;
+  return L;
+}
+
+static int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+// Wavefront tiles over the rows of a CSR structure (instance-aligned):
+// a row longer than 64 * iter_max is a tile of its own (the wavefront strides
+// over it); otherwise consecutive rows share a tile as long as each row's
+// group of lanes needs at most iter_max passes.  Tiles are then grouped into
+// workgroups of about block_work units (nonzeros plus 4 per row).
+void TileSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s) {
+  std::vector<int32_t> t0, t1, tlg, bt0, bt1, binst, iblk0;
+  const int64_t cap = 64LL * s.iter_max;
+  const int B = (int)inst_r0.size() - 1;
+  iblk0.push_back(0);
+  for (int b = 0; b < B; ++b) {
+    int64_t r = inst_r0[b];
+    const int64_t end = inst_r0[b + 1];
+    const size_t first = t0.size();
+    while (r < end) {
+      const int64_t len0 = ptr[r + 1] - ptr[r];
+      if (len0 > cap) {
+        t0.push_back((int32_t)r);
+        t1.push_back((int32_t)(r + 1));
+        tlg.push_back(6);
+        ++r;
+        continue;
+      }
+      const int64_t start = r;
+      int R = 0;
+      int64_t maxlen = 0;
+      while (r < end && R < 64) {
+        const int64_t len = ptr[r + 1] - ptr[r];
+        if (len > cap) break;
+        const int nR = R + 1;
+        const int64_t nmax = std::max(maxlen, len);
+        const int L = lanes_for(nR);
+        if ((nmax + L - 1) / L > s.iter_max) break;
+        R = nR;
+        maxlen = nmax;
+        ++r;
+      }
+      t0.push_back((int32_t)start);
+      t1.push_back((int32_t)r);
+      tlg.push_back(ilog2(lanes_for(R)));
+    }
+    size_t i = first;
+    const size_t tend = t0.size();
+    while (i < tend) {
+      size_t j = i;
+      int64_t acc = 0;
+      while (j < tend) {
+        const int64_t w = (int64_t)(ptr[t1[j]] - ptr[t0[j]]) + 4LL * (t1[j] - t0[j]);
+        if (j > i && acc + w > s.block_nnz) break;
+        acc += w;
+        ++j;
+      }
+      bt0.push_back((int32_t)i);
+      bt1.push_back((int32_t)j);
+      binst.push_back(b);
+      i = j;
+    }
+    iblk0.push_back((int32_t)bt0.size());
+  }
+  ntiles = (int)t0.size();
+  nblk = (int)bt0.size();
+  h_bt0 = bt0;
+  h_bt1 = bt1;
+  h_t0 = t0;
+  h_t1 = t1;
+  upload(row0, t0);
+  upload(row1, t1);
+  upload(lg, tlg);
+  upload(btile0, bt0);
+  upload(btile1, bt1);
+  upload(binst_d, binst);
+  upload(iblk0_d, iblk0);
+}
+
+Tiles TileSet::view() const {
+  Tiles t;
+  t.tile_row0 = row0.as<int32_t>();
+  t.tile_row1 = row1.as<int32_t>();
+  t.tile_lg = lg.as<int32_t>();
+  t.blk_tile0 = btile0.as<int32_t>();
+  t.blk_tile1 = btile1.as<int32_t>();
+  t.blk_inst = binst_d.as<int32_t>();
+  t.inst_blk0 = iblk0_d.as<int32_t>();
+  t.nblk = nblk;
+  return t;
+}
+
+void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block) {
+  std::vector<int32_t> st, en, bi, iblk0;
+  const int B = (int)inst_off.size() - 1;
+  iblk0.push_back(0);
+  for (int b = 0; b < B; ++b) {
+    for (int64_t s = inst_off[b]; s < inst_off[b + 1]; s += per_block) {
+      st.push_back((int32_t)s);
+      en.push_back((int32_t)std::min<int64_t>(s + per_block, inst_off[b + 1]));
+      bi.push_back(b);
+    }
+    iblk0.push_back((int32_t)st.size());
+  }
+  nblk = (int)st.size();
+  upload(start, st);
+  upload(end, en);
+  upload(binst_d, bi);
+  upload(iblk0_d, iblk0);
+}
+
+Ranges RangeSet::view() const {
+  Ranges r;
+  r.blk_start = start.as<int32_t>();
+  r.blk_end = end.as<int32_t>();
+  r.blk_inst = binst_d.as<int32_t>();
+  r.inst_blk0 = iblk0_d.as<int32_t>();
+  r.nblk = nblk;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+template <typename T>
+void IterBufs<T>::alloc(int64_t N, int64_t M) {
+  const int64_t sz[16] = {N, M, N, M, N, M, M, M, M, N, N, N, N, M, N, M};
+  for (int i = 0; i < 16; ++i) b[i].alloc((size_t)sz[i] * sizeof(T));
+  T** f = reinterpret_cast<T**>(&p);
+  for (int i = 0; i < 16; ++i) f[i] = b[i].as<T>();
+  ready = true;
+}
+template struct IterBufs<float>;
+template struct IterBufs<double>;
+
+Engine::Engine(const std::vector<const HostProblem*>& probs) {
+  HIP_OK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  B = (int)probs.size();
+  row0.assign(B + 1, 0);
+  col0.assign(B + 1, 0);
+  std::vector<int64_t> nz0(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    row0[b + 1] = row0[b] + probs[b]->m;
+    col0[b + 1] = col0[b] + probs[b]->n;
+    nz0[b + 1] = nz0[b] + probs[b]->nnz;
+    mzero.push_back(probs[b]->m_zero);
+  }
+  M = row0[B];
+  N = col0[B];
+  NNZ = nz0[B];
+  if (M >= INT32_MAX || N >= INT32_MAX || NNZ >= INT32_MAX)
+    throw Error(PDCS_ERR_SIZE, "batch too large for 32-bit indexing");
+  h_rp.resize(M + 1);
+  h_cp.resize(N + 1);
+  std::vector<int32_t> ci(NNZ), ri(NNZ);
+  std::vector<double> v(NNZ), vt(NNZ), h(M), c(N), l(N), u(N);
+  for (int b = 0; b < B; ++b) {
+    const HostProblem& P = *probs[b];
+    for (int64_t i = 0; i < P.m; ++i) h_rp[row0[b] + i] = (int32_t)(nz0[b] + P.rp[i]);
+    for (int64_t j = 0; j < P.n; ++j) h_cp[col0[b] + j] = (int32_t)(nz0[b] + P.cp[j]);
+    for (int64_t p = 0; p < P.nnz; ++p) {
+      ci[nz0[b] + p] = (int32_t)(col0[b] + P.ci[p]);
+      ri[nz0[b] + p] = (int32_t)(row0[b] + P.ri[p]);
+    }
+    std::copy(P.v.begin(), P.v.end(), v.begin() + nz0[b]);
+    std::copy(P.vt.begin(), P.vt.end(), vt.begin() + nz0[b]);
+    std::copy(P.h.begin(), P.h.end(), h.begin() + row0[b]);
+    std::copy(P.c.begin(), P.c.end(), c.begin() + col0[b]);
+    std::copy(P.l.begin(), P.l.end(), l.begin() + col0[b]);
+    std::copy(P.u.begin(), P.u.end(), u.begin() + col0[b]);
+  }
+  h_rp[M] = (int32_t)NNZ;
+  h_cp[N] = (int32_t)NNZ;
+  upload(d_rp, h_rp);
+  upload(d_ci, ci);
+  upload(d_v, v);
+  upload(d_cp, h_cp);
+  upload(d_ri, ri);
+  upload(d_vt, vt);
+  upload(d_h, h);
+  upload(d_c, c);
+  upload(d_l, l);
+  upload(d_u, u);
+  for (DBuf* bf : {&val64, &valT64}) bf->alloc((size_t)NNZ * 8);
+  for (DBuf* bf : {&val32, &valT32}) bf->alloc((size_t)NNZ * 4);
+  for (DBuf* bf : {&h64, &D1, &cgx0, &cgx1, &yout, &stat_r}) bf->alloc((size_t)M * 8);
+  for (DBuf* bf : {&c64, &l64, &u64, &D2, &cgty0, &cgty1, &xout, &lamout, &stat_c}) bf->alloc((size_t)N * 8);
+  h32.alloc((size_t)M * 4);
+  for (DBuf* bf : {&c32, &l32, &u32}) bf->alloc((size_t)N * 4);
+  d_inst.alloc(sizeof(Inst) * (size_t)std::max(B, 1));
+  d_summary.alloc(16);
+  HIP_OK(hipHostMalloc((void**)&h_summary, 16, hipHostMallocDefault));
+  build_schedule();
+}
+
+Engine::~Engine() {
+  clear_graphs();
+  if (h_summary) (void)hipHostFree(h_summary);
+  for (auto& e : events) (void)hipEventDestroy(e);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+void Engine::clear_graphs() {
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+}
+
+void Engine::build_schedule() {
+  clear_graphs();
+  trow.build(h_rp, row0, sched);
+  tcol.build(h_cp, col0, sched);
+  vrow.build(row0, sched.vec_per_block);
+  vcol.build(col0, sched.vec_per_block);
+  const int nr = std::max(trow.nblk, 1), nc = std::max(tcol.nblk, 1);
+  const int vr = std::max(vrow.nblk, 1), vc = std::max(vcol.nblk, 1);
+  rec_primal.alloc((size_t)vc * 2 * 8);
+  rec_dual.alloc((size_t)nr * 4 * 8);
+  rec_lam.alloc((size_t)nc * 3 * 8);
+  rec_cand_c.alloc((size_t)vc * 16 * 8);
+  rec_cand_r.alloc((size_t)vr * 14 * 8);
+  rec_probe_c.alloc((size_t)vc * 2 * 32 * 8);
+  rec_probe_r.alloc((size_t)vr * 2 * 32 * 8);
+  rec_nc.alloc((size_t)vc * 3 * 8);
+  rec_nr.alloc((size_t)vr * 3 * 8);
+  rec_nm.alloc((size_t)nr * 8);
+}
+
+void Engine::ensure_iter(int prec) {
+  if (prec == kFP32 && !it32.ready) it32.alloc(N, M);
+  if (prec == kFP64 && !it64.ready) it64.alloc(N, M);
+}
+
+KernelCtx Engine::ctx(int probe_passes) const {
+  KernelCtx k{};
+  k.nb = B;
+  k.M = M;
+  k.N = N;
+  k.trow = trow.view();
+  k.tcol = tcol.view();
+  k.vrow = vrow.view();
+  k.vcol = vcol.view();
+  k.inst = d_inst.as<Inst>();
+  k.it32 = it32.p;
+  k.it64 = it64.p;
+  k.d32 = DataPtrs<float>{c32.as<float>(), l32.as<float>(), u32.as<float>(), h32.as<float>()};
+  k.d64 = DataPtrs<double>{c64.as<double>(), l64.as<double>(), u64.as<double>(), h64.as<double>()};
+  k.A32 = MatPtrs<float>{d_rp.as<int32_t>(), d_ci.as<int32_t>(), val32.as<float>()};
+  k.AT32 = MatPtrs<float>{d_cp.as<int32_t>(), d_ri.as<int32_t>(), valT32.as<float>()};
+  k.A64 = MatPtrs<double>{d_rp.as<int32_t>(), d_ci.as<int32_t>(), val64.as<double>()};
+  k.AT64 = MatPtrs<double>{d_cp.as<int32_t>(), d_ri.as<int32_t>(), valT64.as<double>()};
+  k.cgx0 = cgx0.as<double>();
+  k.cgx1 = cgx1.as<double>();
+  k.cgty0 = cgty0.as<double>();
+  k.cgty1 = cgty1.as<double>();
+  k.D1 = D1.as<double>();
+  k.D2 = D2.as<double>();
+  k.xout = xout.as<double>();
+  k.yout = yout.as<double>();
+  k.lamout = lamout.as<double>();
+  k.rec_primal = rec_primal.as<double>();
+  k.rec_dual = rec_dual.as<double>();
+  k.rec_lam = rec_lam.as<double>();
+  k.rec_cand_c = rec_cand_c.as<double>();
+  k.rec_cand_r = rec_cand_r.as<double>();
+  k.rec_probe_c = rec_probe_c.as<double>();
+  k.rec_probe_r = rec_probe_r.as<double>();
+  k.probe_passes = probe_passes;
+  return k;
+}
+
+static void validate_options(const pdcs_options& o) {
+  if (!(o.rel_tol >= 0) || !(o.abs_tol >= 0)) throw Error(PDCS_ERR_INVALID_ARG, "tolerances must be >= 0");
+  if (o.check_every < 1 || o.check_every > 100000) throw Error(PDCS_ERR_INVALID_ARG, "check_every in [1, 1e5]");
+  if (o.max_iter < 0) throw Error(PDCS_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (o.method < 0 || o.method > 2) throw Error(PDCS_ERR_INVALID_ARG, "unknown method");
+  if (o.precision < 0 || o.precision > 1) throw Error(PDCS_ERR_INVALID_ARG, "unknown precision");
+  if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) throw Error(PDCS_ERR_INVALID_ARG, "ruiz_iters in [0, 1000]");
+  if (o.probe_passes < 1 || o.probe_passes > 64) throw Error(PDCS_ERR_INVALID_ARG, "probe_passes in [1, 64]");
+  if (!(o.bisect_rel_eps > 0)) throw Error(PDCS_ERR_INVALID_ARG, "bisect_rel_eps must be > 0");
+  if (std::isnan(o.time_limit)) throw Error(PDCS_ERR_INVALID_ARG, "time_limit is NaN");
+}
+
+void Engine::enqueue_chunk(const KernelCtx& k, int mask, int64_t K, bool timed) {
+  for (int64_t s = 0; s < K; ++s) {
+    launch_trial_part(k, stream, mask, 0);
+    if (timed) {
+      if (ev_used + 2 > events.size()) {
+        for (int i = 0; i < 256; ++i) {
+          hipEvent_t e;
+          HIP_OK(hipEventCreate(&e));
+          events.push_back(e);
+        }
+      }
+      HIP_OK(hipEventRecord(events[ev_used], stream));
+      launch_trial_part(k, stream, mask, 1);
+      HIP_OK(hipEventRecord(events[ev_used + 1], stream));
+      ev_used += 2;
+    } else {
+      launch_trial_part(k, stream, mask, 1);
+    }
+    launch_trial_part(k, stream, mask, 2);
+  }
+  launch_check(k, stream, mask);
+  launch_summary(k, stream, d_summary.as<int32_t>());
+}
+
+void Engine::harvest_events() {
+  for (size_t i = 0; i + 1 < ev_used; i += 2) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, events[i], events[i + 1]));
+    timed_ms += ms;
+    timed_count += 1;
+  }
+  ev_used = 0;
+}
+
+std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* const* x0s, const double* const* y0s) {
+  validate_options(o);
+  HIP_OK(hipGetLastError());
+  const auto t_start = std::chrono::steady_clock::now();
+  const bool mixed = o.precision == PDCS_PRECISION_MIXED;
+  ensure_iter(kFP64);
+  if (mixed) ensure_iter(kFP32);
+  const int start_mask = mixed ? 1 : 2;
+  const int alloc_mask = (it32.ready ? 1 : 0) | (it64.ready ? 2 : 0);
+  // per-instance scalars
+  std::vector<Inst> hi(B);
+  for (int b = 0; b < B; ++b) {
+    Inst& I = hi[b];
+    std::memset(&I, 0, sizeof(Inst));
+    I.row0 = (int32_t)row0[b];
+    I.rows = (int32_t)(row0[b + 1] - row0[b]);
+    I.col0 = (int32_t)col0[b];
+    I.cols = (int32_t)(col0[b + 1] - col0[b]);
+    I.m_zero = (int32_t)mzero[b];
+    I.precision = mixed ? kFP32 : kFP64;
+    I.status = kActive;
+    I.exit_code = PDCS_EXIT_CONTINUE;
+    I.max_iter = o.max_iter;
+    I.check_every = o.check_every;
+    I.method = (int32_t)o.method;
+    I.use_avg = o.method != PDCS_METHOD_HALPERN ? 1 : 0;
+    I.rel_tol = o.rel_tol;
+    I.abs_tol = o.abs_tol;
+    I.polish_tol = o.polish_switch_tol;
+    I.stall_checks = o.stall_checks;
+    I.bisect_eps = o.bisect_rel_eps;
+    I.best_rel = std::numeric_limits<double>::infinity();
+    I.omega = I.omega0 = 1.0;
+    I.eta = I.eta_hat = 1.0;
+  }
+  HIP_OK(hipMemcpyAsync(d_inst.p, hi.data(), sizeof(Inst) * B, hipMemcpyHostToDevice, stream));
+  // optional warm start (unscaled, host)
+  const double* dx0 = nullptr;
+  const double* dy0 = nullptr;
+  if (x0s || y0s) {
+    std::vector<double> hx(N, 0.0), hy(M, 0.0);
+    bool anyx = false, anyy = false;
+    for (int b = 0; b < B; ++b) {
+      if (x0s && x0s[b]) {
+        anyx = true;
+        for (int64_t j = 0; j < col0[b + 1] - col0[b]; ++j) {
+          if (std::isnan(x0s[b][j])) throw Error(PDCS_ERR_INVALID_ARG, "NaN in x0");
+          hx[col0[b] + j] = x0s[b][j];
+        }
+      }
+      if (y0s && y0s[b]) {
+        anyy = true;
+        for (int64_t i = 0; i < row0[b + 1] - row0[b]; ++i) {
+          if (std::isnan(y0s[b][i])) throw Error(PDCS_ERR_INVALID_ARG, "NaN in y0");
+          hy[row0[b] + i] = y0s[b][i];
+        }
+      }
+    }
+    if (anyx) {
+      warm_x.alloc((size_t)N * 8);
+      HIP_OK(hipMemcpyAsync(warm_x.p, hx.data(), (size_t)N * 8, hipMemcpyHostToDevice, stream));
+      dx0 = warm_x.as<double>();
+    }
+    if (anyy) {
+      warm_y.alloc((size_t)M * 8);
+      HIP_OK(hipMemcpyAsync(warm_y.p, hy.data(), (size_t)M * 8, hipMemcpyHostToDevice, stream));
+      dy0 = warm_y.as<double>();
+    }
+    HIP_OK(hipStreamSynchronize(stream));
+  }
+  const KernelCtx k = ctx((int)o.probe_passes);
+  SetupCtx su{};
+  su.precondition = o.use_preconditioner ? 1 : 0;
+  su.ruiz_iters = (int)o.ruiz_iters;
+  su.l2_pass = o.l2_pass ? 1 : 0;
+  su.A = MatPtrs<double>{d_rp.as<int32_t>(), d_ci.as<int32_t>(), d_v.as<double>()};
+  su.AT = MatPtrs<double>{d_cp.as<int32_t>(), d_ri.as<int32_t>(), d_vt.as<double>()};
+  su.c = d_c.as<double>();
+  su.l = d_l.as<double>();
+  su.u = d_u.as<double>();
+  su.h = d_h.as<double>();
+  su.val64 = val64.as<double>();
+  su.valT64 = valT64.as<double>();
+  su.val32 = val32.as<float>();
+  su.valT32 = valT32.as<float>();
+  su.d64m = DataMut{c64.as<double>(), l64.as<double>(), u64.as<double>(), h64.as<double>()};
+  su.d32m = DataMut32{c32.as<float>(), l32.as<float>(), u32.as<float>(), h32.as<float>()};
+  su.stat_r = stat_r.as<double>();
+  su.stat_c = stat_c.as<double>();
+  su.rec_nc = rec_nc.as<double>();
+  su.rec_nr = rec_nr.as<double>();
+  su.rec_nm = rec_nm.as<double>();
+  su.x0 = dx0;
+  su.y0 = dy0;
+  launch_setup(k, su, stream, start_mask);
+  HIP_OK(hipGetLastError());
+
+  const bool timed = o.time_kernels != 0;
+  const bool use_graph = o.use_graph != 0 && !timed;
+  timed_ms = 0.0;
+  timed_count = 0;
+  ev_used = 0;
+  launch_summary(k, stream, d_summary.as<int32_t>());
+  int64_t chunks = 0;
+  while (true) {
+    HIP_OK(hipMemcpyAsync(h_summary, d_summary.p, 8, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    if (timed) harvest_events();
+    const int a32 = h_summary[0], a64 = h_summary[1];
+    if (o.verbose && chunks > 0) {
+      Inst I0;
+      HIP_OK(hipMemcpy(&I0, d_inst.p, sizeof(Inst), hipMemcpyDeviceToHost));
+      std::fprintf(stderr,
+                   "[pdcs] kbar %lld restarts %lld omega %.3e eta %.3e rel(p,d,g) %.2e %.2e %.2e prec %s "
+                   "active %d\n",
+                   (long long)I0.kbar, (long long)I0.restarts, I0.omega, I0.eta_hat, I0.rel_p, I0.rel_d,
+                   I0.rel_gap, I0.precision == kFP32 ? "fp32" : "fp64", a32 + a64);
+    }
+    if (a32 + a64 == 0) break;
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (el >= o.time_limit) {
+      launch_timeout(k, stream);
+      break;
+    }
+    const int mask = (a32 ? 1 : 0) | (a64 ? 2 : 0);
+    if (use_graph) {
+      const int64_t key = ((int64_t)mask << 40) ^ (o.check_every << 8) ^ o.probe_passes;
+      auto it = graphs.find(key);
+      if (it == graphs.end()) {
+        hipGraph_t g;
+        HIP_OK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        enqueue_chunk(k, mask, o.check_every, false);
+        HIP_OK(hipStreamEndCapture(stream, &g));
+        hipGraphExec_t ge;
+        HIP_OK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        it = graphs.emplace(key, ge).first;
+      }
+      HIP_OK(hipGraphLaunch(it->second, stream));
+    } else {
+      enqueue_chunk(k, mask, o.check_every, timed);
+    }
+    HIP_OK(hipGetLastError());
+    ++chunks;
+  }
+  // final point of instances that stopped without an optimal candidate
+  launch_eval(k, stream, alloc_mask, 1);
+  if (o.keep_state) launch_flush_commit(k, stream, alloc_mask);
+  HIP_OK(hipGetLastError());
+  std::vector<Inst> fin(B);
+  HIP_OK(hipMemcpyAsync(fin.data(), d_inst.p, sizeof(Inst) * B, hipMemcpyDeviceToHost, stream));
+  // results own a device copy of the outputs
+  auto out = std::make_shared<OutBlock>();
+  out->M = M;
+  out->N = N;
+  out->x.alloc((size_t)N * 8);
+  out->lam.alloc((size_t)N * 8);
+  out->y.alloc((size_t)M * 8);
+  out->D1.alloc((size_t)M * 8);
+  out->D2.alloc((size_t)N * 8);
+  HIP_OK(hipMemcpyAsync(out->x.p, xout.p, (size_t)N * 8, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(out->lam.p, lamout.p, (size_t)N * 8, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(out->y.p, yout.p, (size_t)M * 8, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(out->D1.p, D1.p, (size_t)M * 8, hipMemcpyDeviceToDevice, stream));
+  HIP_OK(hipMemcpyAsync(out->D2.p, D2.p, (size_t)N * 8, hipMemcpyDeviceToDevice, stream));
+  if (o.keep_state) {
+    for (int pi = 0; pi < 2; ++pi) {
+      const bool ok = pi == 0 ? it64.ready : it32.ready;
+      if (!ok) continue;
+      const size_t es = pi == 0 ? 8 : 4;
+      void* src[6];
+      if (pi == 0) {
+        const IterPtrs<double>& q = it64.p;
+        void* s6[6] = {q.x, q.y, q.xh, q.yh, q.xa, q.ya};
+        std::memcpy(src, s6, sizeof(src));
+      } else {
+        const IterPtrs<float>& q = it32.p;
+        void* s6[6] = {q.x, q.y, q.xh, q.yh, q.xa, q.ya};
+        std::memcpy(src, s6, sizeof(src));
+      }
+      for (int v = 0; v < 6; ++v) {
+        const size_t len = (v % 2 == 0) ? (size_t)N : (size_t)M;
+        out->st[pi][v].alloc(len * es);
+        HIP_OK(hipMemcpyAsync(out->st[pi][v].p, src[v], len * es, hipMemcpyDeviceToDevice, stream));
+      }
+    }
+  }
+  HIP_OK(hipStreamSynchronize(stream));
+  const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  std::vector<pdcs_result> res(B);
+  for (int b = 0; b < B; ++b) {
+    const Inst& I = fin[b];
+    auto* r = new pdcs_result_s();
+    r->out = out;
+    r->row0 = row0[b];
+    r->col0 = col0[b];
+    r->m = row0[b + 1] - row0[b];
+    r->n = col0[b + 1] - col0[b];
+    std::memset(&r->info, 0, sizeof(r->info));
+    r->info.exit_code = I.exit_code;
+    r->info.iters = I.kbar;
+    r->info.accepted_iters = I.accepted;
+    r->info.restarts = I.restarts;
+    r->info.checks = I.checks;
+    r->info.fp64_iters = I.fp64_iters;
+    r->info.pobj = I.pobj;
+    r->info.dobj = I.dobj;
+    r->info.abs_p = I.abs_p;
+    r->info.abs_d = I.abs_d;
+    r->info.abs_gap = I.abs_gap;
+    r->info.rel_p = I.rel_p;
+    r->info.rel_d = I.rel_d;
+    r->info.rel_gap = I.rel_gap;
+    r->info.time_sec = elapsed;
+    r->info.omega = I.omega;
+    r->info.eta_hat = I.eta_hat;
+    r->info.spmv_avg_ms = timed_count ? timed_ms / (double)timed_count : 0.0;
+    r->info.spmv_launches = timed_count;
+    std::memset(&r->st, 0, sizeof(r->st));
+    r->st.omega = I.omega;
+    r->st.omega0 = I.omega0;
+    r->st.eta_hat = I.eta_hat;
+    r->st.eta = I.eta;
+    r->st.beta = I.beta;
+    r->st.sum_eta = I.sum_eta;
+    r->st.kbar = I.kbar;
+    r->st.k = I.k;
+    r->st.t = I.t;
+    r->st.accepted = I.accepted;
+    r->st.precision = I.precision == kFP32 ? PDCS_PRECISION_MIXED : PDCS_PRECISION_FP64;
+    r->has_state = o.keep_state != 0;
+    res[b] = r;
+  }
+  return res;
+}
+
+// Time `reps` launches of the SpMV-with-dual-step kernel on the current state.
+double Engine::time_dual(int prec, int reps) {
+  const KernelCtx k = ctx(7);
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  launch_dual_only(k, stream, prec);
+  HIP_OK(hipEventRecord(e0, stream));
+  for (int i = 0; i < reps; ++i) launch_dual_only(k, stream, prec);
+  HIP_OK(hipEventRecord(e1, stream));
+  HIP_OK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+}  // namespace pdcs
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+namespace {
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return PDCS_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return PDCS_ERR_INVALID_ARG;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void pdcs_options_default(pdcs_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->rel_tol = 1e-6;
+  o->abs_tol = 1e-6;
+  o->time_limit = 1000.0;
+  o->max_iter = INT64_MAX / 4;
+  o->use_preconditioner = 1;
+  o->ruiz_iters = 10;
+  o->l2_pass = 1;
+  o->method = PDCS_METHOD_AUTO;
+  o->check_every = 64;
+  o->precision = PDCS_PRECISION_FP64;
+  o->stall_checks = 16;
+  o->polish_switch_tol = 0.0;
+  o->bisect_rel_eps = 1e-6;
+  o->use_graph = 1;
+  o->verbose = 0;
+  o->keep_state = 0;
+  o->time_kernels = 0;
+  o->probe_passes = 7;
+}
+
+const char* pdcs_status_string(int code) {
+  switch (code) {
+    case 0: return "optimal";
+    case 1: return "max_iter";
+    case 2: return "primal_infeasible_low_acc";
+    case 3: return "primal_infeasible_high_acc";
+    case 4: return "dual_infeasible_low_acc";
+    case 5: return "dual_infeasible_high_acc";
+    case 6: return "time_limit";
+    case 7: return "continue";
+    case 8: return "numerical_error";
+    default: return "unknown";
+  }
+}
+
+const char* pdcs_last_error(void) { return g_err.c_str(); }
+
+int pdcs_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+int pdcs_problem_create(int64_t m, int64_t n, int64_t m_zero, const int64_t* row_ptr, const int32_t* col_idx,
+                        const double* val, const double* h, const double* c, const double* l, const double* u,
+                        pdcs_problem* out) {
+  return guarded([&]() {
+    if (!out) throw Error(PDCS_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    auto p = std::make_unique<pdcs_problem_s>();
+    p->hp.build(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u);
+    std::vector<const HostProblem*> v{&p->hp};
+    p->eng = std::make_unique<Engine>(v);
+    *out = p.release();
+    return PDCS_OK;
+  });
+}
+
+void pdcs_problem_destroy(pdcs_problem p) { delete p; }
+
+int pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz) {
+  return guarded([&]() {
+    if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
+    if (m) *m = p->hp.m;
+    if (n) *n = p->hp.n;
+    if (nnz) *nnz = p->hp.nnz;
+    return PDCS_OK;
+  });
+}
+
+int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, const void* in_dev, void* out_dev,
+                      void* stream) {
+  return guarded([&]() {
+    if (!p || !in_dev || !out_dev) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    if (precision != PDCS_PRECISION_FP64 && precision != PDCS_PRECISION_MIXED)
+      throw Error(PDCS_ERR_INVALID_ARG, "unknown precision");
+    Engine& e = *p->eng;
+    hipStream_t s = stream ? (hipStream_t)stream : e.stream;
+    const bool f32 = precision == PDCS_PRECISION_MIXED;
+    if (f32 && !e.orig32.p) {
+      std::vector<float> a(e.NNZ), at(e.NNZ);
+      for (int64_t q = 0; q < e.NNZ; ++q) {
+        a[q] = (float)p->hp.v[q];
+        at[q] = (float)p->hp.vt[q];
+      }
+      upload(e.orig32, a);
+      upload(e.origT32, at);
+    }
+    if (!transpose) {
+      launch_spmv_plain(e.trow.view(), f32 ? kFP32 : kFP64, e.d_rp.as<int32_t>(), e.d_ci.as<int32_t>(),
+                        f32 ? e.orig32.p : e.d_v.p, in_dev, out_dev, s);
+    } else {
+      launch_spmv_plain(e.tcol.view(), f32 ? kFP32 : kFP64, e.d_cp.as<int32_t>(), e.d_ri.as<int32_t>(),
+                        f32 ? e.origT32.p : e.d_vt.p, in_dev, out_dev, s);
+    }
+    HIP_OK(hipGetLastError());
+    return PDCS_OK;
+  });
+}
+
+int pdcs_solve(pdcs_problem p, const pdcs_options* opts, const double* x0, const double* y0, void* stream,
+               pdcs_result* out) {
+  return guarded([&]() {
+    if (!p || !out) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    pdcs_options o;
+    if (opts) o = *opts;
+    else pdcs_options_default(&o);
+    const double* xs[1] = {x0};
+    const double* ys[1] = {y0};
+    (void)stream;
+    auto r = p->eng->solve(o, x0 ? xs : nullptr, y0 ? ys : nullptr);
+    *out = r[0];
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_info(pdcs_result r, pdcs_info* out) {
+  return guarded([&]() {
+    if (!r || !out) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    *out = r->info;
+    return PDCS_OK;
+  });
+}
+
+static void copy_out(const DBuf& src, int64_t off, int64_t len, double* dst, int64_t want) {
+  if (!dst) throw Error(PDCS_ERR_INVALID_ARG, "destination is null");
+  if (want != len) throw Error(PDCS_ERR_INVALID_ARG, "length mismatch");
+  if (len > 0) HIP_OK(hipMemcpy(dst, src.as<double>() + off, (size_t)len * 8, hipMemcpyDeviceToHost));
+}
+
+int pdcs_result_primal(pdcs_result r, double* x, int64_t n) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    copy_out(r->out->x, r->col0, r->n, x, n);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_dual(pdcs_result r, double* y, int64_t m) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    if (r->m == 0 && m == 0) return PDCS_OK;
+    copy_out(r->out->y, r->row0, r->m, y, m);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_slack(pdcs_result r, double* lam, int64_t n) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    copy_out(r->out->lam, r->col0, r->n, lam, n);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_scaling(pdcs_result r, double* D1, int64_t m, double* D2, int64_t n) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    if (r->m > 0 || m > 0) copy_out(r->out->D1, r->row0, r->m, D1, m);
+    copy_out(r->out->D2, r->col0, r->n, D2, n);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_state(pdcs_result r, pdcs_state_scalars* s, double* x, double* y, double* x_hat, double* y_hat,
+                      double* x_a, double* y_a) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    if (s) *s = r->st;
+    double* dst[6] = {x, y, x_hat, y_hat, x_a, y_a};
+    bool want = false;
+    for (double* d : dst) want = want || d;
+    if (!want) return PDCS_OK;
+    if (!r->has_state) throw Error(PDCS_ERR_STATE, "solve ran without keep_state");
+    const int pi = r->st.precision == PDCS_PRECISION_MIXED ? 1 : 0;
+    for (int v = 0; v < 6; ++v) {
+      if (!dst[v]) continue;
+      const bool xlike = (v % 2 == 0);
+      const int64_t off = xlike ? r->col0 : r->row0;
+      const int64_t len = xlike ? r->n : r->m;
+      if (len == 0) continue;
+      const DBuf& src = r->out->st[pi][v];
+      if (!src.p) throw Error(PDCS_ERR_STATE, "state not kept");
+      if (pi == 0) {
+        HIP_OK(hipMemcpy(dst[v], src.as<double>() + off, (size_t)len * 8, hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> tmp(len);
+        HIP_OK(hipMemcpy(tmp.data(), src.as<float>() + off, (size_t)len * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < len; ++i) dst[v][i] = (double)tmp[i];
+      }
+    }
+    return PDCS_OK;
+  });
+}
+
+void pdcs_result_destroy(pdcs_result r) { delete r; }
+
+int pdcs_batch_create(int64_t count, const pdcs_problem* probs, pdcs_batch* out) {
+  return guarded([&]() {
+    if (!out || !probs || count < 1) throw Error(PDCS_ERR_INVALID_ARG, "bad batch arguments");
+    *out = nullptr;
+    std::vector<const HostProblem*> v;
+    for (int64_t i = 0; i < count; ++i) {
+      if (!probs[i]) throw Error(PDCS_ERR_INVALID_ARG, "null problem in batch");
+      v.push_back(&probs[i]->hp);
+    }
+    auto b = std::make_unique<pdcs_batch_s>();
+    b->eng = std::make_unique<Engine>(v);
+    *out = b.release();
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_solve(pdcs_batch b, const pdcs_options* opts, const double* const* x0s, const double* const* y0s,
+                     void* stream, pdcs_result* results) {
+  return guarded([&]() {
+    if (!b || !results) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    pdcs_options o;
+    if (opts) o = *opts;
+    else pdcs_options_default(&o);
+    (void)stream;
+    auto r = b->eng->solve(o, x0s, y0s);
+    for (size_t i = 0; i < r.size(); ++i) results[i] = r[i];
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_schedule(pdcs_batch b, int64_t* iter_max, int64_t* block_nnz, int64_t* vec_per_block) {
+  return guarded([&]() {
+    if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
+    if (iter_max) *iter_max = b->eng->sched.iter_max;
+    if (block_nnz) *block_nnz = b->eng->sched.block_nnz;
+    if (vec_per_block) *vec_per_block = b->eng->sched.vec_per_block;
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_set_schedule(pdcs_batch b, int64_t iter_max, int64_t block_nnz, int64_t vec_per_block) {
+  return guarded([&]() {
+    if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
+    if (iter_max < 1 || iter_max > 64 || block_nnz < 64 || block_nnz > (1 << 24) || vec_per_block < 256 ||
+        vec_per_block > (1 << 22))
+      throw Error(PDCS_ERR_INVALID_ARG, "schedule out of range");
+    b->eng->sched = Schedule{(int)iter_max, (int)block_nnz, (int)vec_per_block};
+    b->eng->build_schedule();
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_autotune(pdcs_batch b, double time_budget_ms) {
+  return guarded([&]() {
+    if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
+    b->eng->autotune(time_budget_ms);
+    return PDCS_OK;
+  });
+}
+
+void pdcs_batch_destroy(pdcs_batch b) { delete b; }
+
+}  // extern "C"
+
+namespace pdcs {
+
+// Autotuner: time the SpMV-with-dual-step kernel (FP32 and FP64) and the
+// primal pass over a grid of schedules on this batch, keep the fastest.
+void Engine::autotune(double budget_ms) {
+  if (budget_ms <= 0) budget_ms = 2000.0;
+  pdcs_options o;
+  pdcs_options_default(&o);
+  o.precision = PDCS_PRECISION_MIXED;
+  o.max_iter = 1;
+  o.use_graph = 0;
+  {
+    auto rs = solve(o, nullptr, nullptr);
+    for (auto* r : rs) delete r;
+  }
+  // re-activate every instance so that the timed kernels do their full work
+  std::vector<Inst> hi(B);
+  HIP_OK(hipMemcpy(hi.data(), d_inst.p, sizeof(Inst) * B, hipMemcpyDeviceToHost));
+  for (auto& I : hi) {
+    I.status = kActive;
+    I.pending = 0;
+  }
+  HIP_OK(hipMemcpy(d_inst.p, hi.data(), sizeof(Inst) * B, hipMemcpyHostToDevice));
+  struct Cand {
+    int iter_max, block_nnz;
+  };
+  const Cand cands[] = {{4, 4096}, {8, 4096}, {8, 8192}, {8, 16384}, {16, 8192}, {16, 16384}, {32, 16384},
+                        {32, 32768}};
+  const auto t0 = std::chrono::steady_clock::now();
+  Schedule best = sched;
+  double best_t = 1e300;
+  for (const Cand& c : cands) {
+    sched.iter_max = c.iter_max;
+    sched.block_nnz = c.block_nnz;
+    build_schedule();
+    const double t = time_dual(kFP32, 5) + time_dual(kFP64, 3);
+    if (t < best_t) {
+      best_t = t;
+      best = sched;
+    }
+    if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > budget_ms) break;
+  }
+  sched = best;
+  build_schedule();
+}
+
+}  // namespace pdcs

@@ -1,0 +1,1503 @@
+// HIP kernels of the PDCS LP solver for gfx950.
+//
+// One trial of AdaptiveStepPDHG (Function 2) is five launches:
+//   k_primal   : deferred reflected-Halpern commit of x and of G^T y (Algorithm 1,
+//                lines 6-7), then x_hat = Proj_[l,u](x - tau (c - G^T y))   (eq. PDHG)
+//   k_dual     : CSR SpMV G x_hat with the dual step fused into the row epilogue:
+//                Halpern commit of y and of G x, then
+//                y_hat = Proj_Kd(y + sigma (h - 2 G x_hat + G x))          (eq. PDHG)
+//   k_fin_ls   : step-size test of Function 2 (eta_bar, eta')
+//   k_lam      : transposed SpMV G^T y_hat with the dual-slack epilogue
+//                lam = c - G^T y_hat and its error terms (eq. tolerance-3)
+//   k_fin_beta : reflection parameter (eq. adaptive_reflection)
+// G x and G^T y of the Halpern iterate are maintained by the same linear
+// combination as the iterate, so a trial reads the matrix once (G x_hat) and
+// an accepted trial twice (plus G^T y_hat).
+//
+// Every K trials a restart check runs (Section 2.3): candidate products with
+// FP64 values, N-norm radii, the bisection of Algorithm 3 as a multisection
+// (kProbes values of t per pass over the vectors), the restart conditions,
+// the primal-weight update (Section 2.5) and the termination test (Section 3).
+#include "pdcs_dev.h"
+#include "pdcs_launch.h"
+
+#include <math.h>
+
+namespace pdcs {
+
+// ===========================================================================
+// Iteration kernels
+// ===========================================================================
+
+// K3: primal step over the columns of the instance.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_primal(Ranges R, IterPtrs<T> it, DataPtrs<T> d,
+                                                   Inst* __restrict__ inst, int prec,
+                                                   double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * 2];
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.status != kActive || I.precision != prec) return;
+  const bool commit = I.pending != 0;
+  const bool avg = I.use_avg != 0;
+  const double ca = I.ca, cb = I.cb, beta = I.beta, etak = I.eta_k;
+  const double tau = I.eta / I.omega;
+  double acc[2] = {0.0, 0.0};
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    double x = (double)it.x[j];
+    double gty = (double)it.gty[j];
+    if (commit) {
+      const double xh = (double)it.xh[j];
+      const double gh = (double)it.gtyh[j];
+      x = (double)(T)(ca * ((1.0 + beta) * xh - beta * x) + cb * (double)it.xa[j]);
+      gty = (double)(T)(ca * ((1.0 + beta) * gh - beta * gty) + cb * (double)it.gtya[j]);
+      it.x[j] = (T)x;
+      it.gty[j] = (T)gty;
+      if (avg) it.sx[j] = (T)((double)it.sx[j] + etak * xh);
+    }
+    const double c = (double)d.c[j];
+    const double xn = (double)(T)clampd(x - tau * (c - gty), (double)d.l[j], (double)d.u[j]);
+    it.xh[j] = (T)xn;
+    const double dx = xn - x;
+    acc[0] += dx * dx;
+    acc[1] += c * xn;
+  }
+  block_sum_store<2>(acc, lds, rec + (size_t)b * 2);
+}
+
+// K1: CSR SpMV G x_hat with the fused dual step.  Record: ||dy||^2,
+// dy^T G dx, ||(G x_hat - h) - Proj_Kd*(.)||^2, h^T y_hat.
+template <typename T, typename TM>
+__global__ __launch_bounds__(kBlock) void k_dual(Tiles tl, MatPtrs<TM> A, IterPtrs<T> it,
+                                                 DataPtrs<T> d, Inst* __restrict__ inst, int prec,
+                                                 double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * 4];
+  const int b = blockIdx.x;
+  const Inst& I = inst[tl.blk_inst[b]];
+  if (I.status != kActive || I.precision != prec) return;
+  const bool commit = I.pending != 0;
+  const bool avg = I.use_avg != 0;
+  const double ca = I.ca, cb = I.cb, beta = I.beta, etak = I.eta_k;
+  const double sigma = I.eta * I.omega;
+  const int mz_end = I.row0 + I.m_zero;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int t1 = tl.blk_tile1[b];
+  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
+    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
+    const int L = 1 << lg;
+    const int r = r0 + (lane >> lg);
+    const int li = lane & (L - 1);
+    double s = 0.0;
+    if (r < r1) s = row_dot(A.idx, A.val, it.xh, A.ptr[r], A.ptr[r + 1], li, L);
+    s = group_sum(s, L);
+    if (li == 0 && r < r1) {
+      double y = (double)it.y[r];
+      double gx = (double)it.gx[r];
+      if (commit) {
+        const double yh = (double)it.yh[r];
+        const double gh = (double)it.gxh[r];
+        y = (double)(T)(ca * ((1.0 + beta) * yh - beta * y) + cb * (double)it.ya[r]);
+        gx = (double)(T)(ca * ((1.0 + beta) * gh - beta * gx) + cb * (double)it.gxa[r]);
+        it.y[r] = (T)y;
+        it.gx[r] = (T)gx;
+        if (avg) it.sy[r] = (T)((double)it.sy[r] + etak * yh);
+      }
+      const double hv = (double)d.h[r];
+      const double gxn = (double)(T)s;
+      const double v = y + sigma * (hv - 2.0 * gxn + gx);
+      const bool zero_row = r < mz_end;
+      const double yn = (double)(T)(zero_row ? v : fmax(v, 0.0));
+      it.yh[r] = (T)yn;
+      it.gxh[r] = (T)gxn;
+      const double dy = yn - y;
+      acc[0] += dy * dy;
+      acc[1] += dy * (gxn - gx);
+      const double res = gxn - hv;
+      const double pr = zero_row ? res : fmin(res, 0.0);
+      acc[2] += pr * pr;
+      acc[3] += hv * yn;
+    }
+  }
+  block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
+}
+
+// F1: line-search decision of Function 2, one workgroup per instance.
+__global__ __launch_bounds__(kBlock) void k_fin_ls(Ranges rc, const double* __restrict__ rec_p,
+                                                   Tiles tr, const double* __restrict__ rec_d,
+                                                   Inst* __restrict__ inst) {
+  __shared__ double lds[kWavesPerBlock * 4];
+  const int iid = blockIdx.x;
+  Inst& I = inst[iid];
+  if (I.status != kActive) return;
+  double p[2], q[4];
+  reduce_records<2, 2>(rec_p, rc.inst_blk0[iid], rc.inst_blk0[iid + 1], lds, p);
+  reduce_records<4, 4>(rec_d, tr.inst_blk0[iid], tr.inst_blk0[iid + 1], lds, q);
+  if (threadIdx.x != 0) return;
+  I.pending = 0;
+  I.check_due = 0;
+  I.kbar += 1;
+  if (I.precision == kFP64) I.fp64_iters += 1;
+  const double dx2 = p[0], dy2 = q[0], dydg = q[1];
+  const double omega = I.omega, eta = I.eta;
+  const double num = 0.5 * (omega * dx2 + dy2 / omega);
+  const double den = fabs(dydg);
+  const double etabar = den > 0.0 ? num / den : (double)INFINITY;
+  const double kb1 = (double)I.kbar + 1.0;
+  const double eta_next = fmin((1.0 - pow(kb1, -0.3)) * etabar, (1.0 + pow(kb1, -0.6)) * eta);
+  if (!isfinite(num) || isnan(etabar) || isnan(q[2]) || isnan(q[3]) || isnan(p[1]) ||
+      !(eta_next > 0.0) || !isfinite(eta_next)) {
+    I.status = kDone;
+    I.exit_code = 8;
+    I.last_acc = 0;
+    return;
+  }
+  if (eta < etabar) {
+    I.last_acc = 1;
+    I.eta_k = eta;
+    I.eta_hat = eta_next;
+    I.accepted += 1;
+    I.dx2 = dx2;
+    I.dy2 = dy2;
+    I.dydgdx = dydg;
+    I.errp2 = q[2];
+    I.hy = q[3];
+    I.cx = p[1];
+  } else {
+    I.last_acc = 0;
+    if (I.kbar >= I.max_iter) {
+      I.status = kDone;
+      I.exit_code = 1;
+    }
+  }
+  I.eta = eta_next;
+}
+
+// K2: transposed SpMV G^T y_hat over the columns with the dual-slack epilogue.
+// Record: ||lam - Proj_Lambda lam||^2, sum l lam+, sum u lam- (finite bounds).
+template <typename T, typename TM>
+__global__ __launch_bounds__(kBlock) void k_lam(Tiles tl, MatPtrs<TM> AT, IterPtrs<T> it,
+                                                DataPtrs<T> d, Inst* __restrict__ inst, int prec,
+                                                double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  const int b = blockIdx.x;
+  const Inst& I = inst[tl.blk_inst[b]];
+  if (I.status != kActive || I.precision != prec || I.last_acc == 0) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int t1 = tl.blk_tile1[b];
+  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
+    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
+    const int L = 1 << lg;
+    const int j = r0 + (lane >> lg);
+    const int li = lane & (L - 1);
+    double s = 0.0;
+    if (j < r1) s = row_dot(AT.idx, AT.val, it.yh, AT.ptr[j], AT.ptr[j + 1], li, L);
+    s = group_sum(s, L);
+    if (li == 0 && j < r1) {
+      const double g = (double)(T)s;
+      it.gtyh[j] = (T)g;
+      const double lam = (double)d.c[j] - g;
+      const double lo = (double)d.l[j], hi = (double)d.u[j];
+      const bool lf = isfinite(lo), uf = isfinite(hi);
+      double res;
+      if (!lf && !uf) res = lam;
+      else if (!lf) res = fmax(lam, 0.0);
+      else if (!uf) res = fmin(lam, 0.0);
+      else res = 0.0;
+      acc[0] += res * res;
+      if (lf) acc[1] += lo * fmax(lam, 0.0);
+      if (uf) acc[2] += hi * fmax(-lam, 0.0);
+    }
+  }
+  block_sum_store<3>(acc, lds, rec + (size_t)b * 3);
+}
+
+// F2: reflection parameter at z_hat (eq. adaptive_reflection with the relative
+// errors of eq. tolerance-2), then schedule the Halpern commit.
+__global__ __launch_bounds__(kBlock) void k_fin_beta(Tiles tc, const double* __restrict__ rec_l,
+                                                     Inst* __restrict__ inst) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  const int iid = blockIdx.x;
+  Inst& I = inst[iid];
+  if (I.status != kActive || I.last_acc == 0) return;
+  double q[3];
+  reduce_records<3, 3>(rec_l, tc.inst_blk0[iid], tc.inst_blk0[iid + 1], lds, q);
+  if (threadIdx.x != 0) return;
+  const double errp = sqrt(I.errp2), errd = sqrt(q[0]);
+  const double pobj = I.cx;
+  const double dobj = I.hy + q[1] - q[2];
+  const double gap = fabs(pobj - dobj);
+  const double rp = errp / (1.0 + I.h1);
+  const double rd = errd / (1.0 + I.c1);
+  const double rg = gap / (1.0 + fabs(pobj) + fabs(dobj));
+  const double me = fmax(rp, fmax(rd, rg));
+  if (isnan(me) || isnan(rp) || isnan(rd) || isnan(rg)) {
+    I.status = kDone;
+    I.exit_code = 8;
+    return;
+  }
+  const double beta = me > 0.0 ? clampd(-0.1 * log10(me) + 0.2, 0.0, 1.0) : 1.0;
+  const double k = (double)I.k;
+  I.beta = beta;
+  I.ca = (k + 1.0) / (k + 2.0);
+  I.cb = 1.0 / (k + 2.0);
+  I.pending = 1;
+  I.sum_eta += I.eta_k;
+  I.k += 1;
+  I.check_due = (I.kbar % I.check_every) == 0 ? 1 : 0;
+  if (!I.check_due && I.kbar >= I.max_iter) {
+    I.status = kDone;
+    I.exit_code = 1;
+  }
+}
+
+// ===========================================================================
+// Restart / termination check
+// ===========================================================================
+enum Mode : int { kModeCheck = 0, kModeEvalStart = 1, kModeEvalFinal = 2 };
+
+__device__ __forceinline__ bool mode_selects(const Inst& I, int mode) {
+  if (mode == kModeCheck) return I.status == kActive && I.check_due != 0;
+  if (mode == kModeEvalStart) return I.status == kActive;
+  return I.status == kDone && I.exit_code != 0;
+}
+
+// Apply the pending Halpern commit, then form the average candidate S / sum(eta).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_commit_avg(Ranges R, T* __restrict__ z,
+                                                       T* __restrict__ zh, const T* __restrict__ za,
+                                                       T* __restrict__ g, const T* __restrict__ gh,
+                                                       const T* __restrict__ ga, T* __restrict__ s,
+                                                       T* __restrict__ zbar, Inst* __restrict__ inst,
+                                                       int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;
+  const bool commit = I.pending != 0;
+  const bool avg = I.use_avg != 0;
+  const double ca = I.ca, cb = I.cb, beta = I.beta, etak = I.eta_k;
+  const double inv_sum = 1.0 / I.sum_eta;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double zhv = (double)zh[j];
+    double sv = avg ? (double)s[j] : 0.0;
+    if (commit) {
+      z[j] = (T)(ca * ((1.0 + beta) * zhv - beta * (double)z[j]) + cb * (double)za[j]);
+      g[j] = (T)(ca * ((1.0 + beta) * (double)gh[j] - beta * (double)g[j]) + cb * (double)ga[j]);
+      if (avg) {
+        sv = (double)(T)(sv + etak * zhv);
+        s[j] = (T)sv;
+      }
+    }
+    if (avg) zbar[j] = (T)(sv * inv_sum);
+  }
+}
+
+// Two products with one matrix pass: out0 = A in0, out1 = A in1 (FP64 values,
+// FP64 output).  in1 may be null.  Selected instances only.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv2(Tiles tl, MatPtrs<double> A, const T* __restrict__ in0,
+                                                  const T* __restrict__ in1, double* __restrict__ out0,
+                                                  double* __restrict__ out1, const Inst* __restrict__ inst,
+                                                  int prec, int mode) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[tl.blk_inst[b]];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  const bool two = (in1 != nullptr) && (mode != kModeCheck || I.use_avg != 0);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int t1 = tl.blk_tile1[b];
+  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
+    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
+    const int L = 1 << lg;
+    const int r = r0 + (lane >> lg);
+    const int li = lane & (L - 1);
+    double s0 = 0.0, s1 = 0.0;
+    if (r < r1) {
+      const int p0 = A.ptr[r], p1 = A.ptr[r + 1];
+      if (two) {
+        for (int p = p0 + li; p < p1; p += L) {
+          const int c = A.idx[p];
+          const double v = A.val[p];
+          s0 += v * (double)in0[c];
+          s1 += v * (double)in1[c];
+        }
+      } else {
+        s0 = row_dot(A.idx, A.val, in0, p0, p1, li, L);
+      }
+    }
+    s0 = group_sum(s0, L);
+    if (two) s1 = group_sum(s1, L);
+    if (li == 0 && r < r1) {
+      out0[r] = s0;
+      if (two) out1[r] = s1;
+    }
+  }
+}
+
+// Candidate reductions over the columns.  Per candidate c (0: PDHG output or
+// evaluated point, 1: average): sums ||x_c - x_a||^2, ||b1||^2, ||lam - Proj lam||^2,
+// sum l lam+, sum u lam-, c^T x_c; maxima of the unscaled dual residual and |G^T y|.
+// Record layout: [c0 sums(6), c1 sums(6), c0 max(2), c1 max(2)].
+constexpr int kCandColsNV = 16, kCandColsNS = 12;
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cand_cols(Ranges R, const T* __restrict__ x0,
+                                                      const T* __restrict__ x1, const T* __restrict__ xa,
+                                                      const double* __restrict__ g0,
+                                                      const double* __restrict__ g1,
+                                                      DataPtrs<double> d, const double* __restrict__ D2,
+                                                      const Inst* __restrict__ inst, int prec, int mode,
+                                                      double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * kCandColsNV];
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  const int nc = (mode == kModeCheck && I.use_avg) ? 2 : 1;
+  double acc[kCandColsNV];
+#pragma unroll
+  for (int i = 0; i < kCandColsNV; ++i) acc[i] = 0.0;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double c = d.c[j], lo = d.l[j], hi = d.u[j], dj = D2[j];
+    const bool lf = isfinite(lo), uf = isfinite(hi);
+    const double xav = (double)xa[j];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= nc) break;
+      const double xc = (double)(q == 0 ? x0[j] : x1[j]);
+      const double gty = q == 0 ? g0[j] : g1[j];
+      const double dxa = xc - xav;
+      const double lam = c - gty;
+      double res;
+      if (!lf && !uf) res = lam;
+      else if (!lf) res = fmax(lam, 0.0);
+      else if (!uf) res = fmin(lam, 0.0);
+      else res = 0.0;
+      acc[q * 6 + 0] += dxa * dxa;
+      acc[q * 6 + 1] += lam * lam;
+      acc[q * 6 + 2] += res * res;
+      if (lf) acc[q * 6 + 3] += lo * fmax(lam, 0.0);
+      if (uf) acc[q * 6 + 4] += hi * fmax(-lam, 0.0);
+      acc[q * 6 + 5] += c * xc;
+      acc[12 + q * 2 + 0] = fmax(acc[12 + q * 2 + 0], fabs(res) / dj);
+      acc[12 + q * 2 + 1] = fmax(acc[12 + q * 2 + 1], fabs(gty) / dj);
+    }
+  }
+  block_summax_store<kCandColsNV, kCandColsNS>(acc, lds, rec + (size_t)b * kCandColsNV);
+}
+
+// Candidate reductions over the rows: sums ||y_c - y_a||^2, ||b2||^2,
+// ||(Gx-h) - Proj_Kd*||^2, h^T y_c; maxima of the unscaled primal residual,
+// |G x| and |Proj_Kd*(G x - h)|.  Layout: [c0 sums(4), c1 sums(4), c0 max(3), c1 max(3)].
+constexpr int kCandRowsNV = 14, kCandRowsNS = 8;
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restrict__ y0,
+                                                      const T* __restrict__ y1, const T* __restrict__ ya,
+                                                      const double* __restrict__ g0,
+                                                      const double* __restrict__ g1,
+                                                      DataPtrs<double> d, const double* __restrict__ D1,
+                                                      const Inst* __restrict__ inst, int prec, int mode,
+                                                      double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * kCandRowsNV];
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  const int nc = (mode == kModeCheck && I.use_avg) ? 2 : 1;
+  const int mz_end = I.row0 + I.m_zero;
+  double acc[kCandRowsNV];
+#pragma unroll
+  for (int i = 0; i < kCandRowsNV; ++i) acc[i] = 0.0;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double h = d.h[i], di = D1[i];
+    const double yav = (double)ya[i];
+    const bool zero_row = i < mz_end;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= nc) break;
+      const double yc = (double)(q == 0 ? y0[i] : y1[i]);
+      const double gx = q == 0 ? g0[i] : g1[i];
+      const double dya = yc - yav;
+      const double res = gx - h;
+      const double pr = zero_row ? res : fmin(res, 0.0);
+      const double proj = zero_row ? 0.0 : fmax(res, 0.0);
+      acc[q * 4 + 0] += dya * dya;
+      acc[q * 4 + 1] += res * res;
+      acc[q * 4 + 2] += pr * pr;
+      acc[q * 4 + 3] += h * yc;
+      acc[8 + q * 3 + 0] = fmax(acc[8 + q * 3 + 0], fabs(pr) / di);
+      acc[8 + q * 3 + 1] = fmax(acc[8 + q * 3 + 1], fabs(gx) / di);
+      acc[8 + q * 3 + 2] = fmax(acc[8 + q * 3 + 2], proj / di);
+    }
+  }
+  block_summax_store<kCandRowsNV, kCandRowsNS>(acc, lds, rec + (size_t)b * kCandRowsNV);
+}
+
+// Combine the candidate reductions: radii, KKT errors, termination errors,
+// and the start of the bisection (t0 = r / sqrt(tau|b1|^2 + sigma|b2|^2)).
+__global__ __launch_bounds__(kBlock) void k_cand_fin(Ranges rc, const double* __restrict__ rec_c,
+                                                     Ranges rr, const double* __restrict__ rec_r,
+                                                     Inst* __restrict__ inst, int mode) {
+  __shared__ double lds[kWavesPerBlock * kCandColsNV];
+  const int iid = blockIdx.x;
+  Inst& I = inst[iid];
+  if (!mode_selects(I, mode)) return;
+  double cs[kCandColsNV], rs[kCandRowsNV];
+  reduce_records<kCandColsNV, kCandColsNS>(rec_c, rc.inst_blk0[iid], rc.inst_blk0[iid + 1], lds, cs);
+  reduce_records<kCandRowsNV, kCandRowsNS>(rec_r, rr.inst_blk0[iid], rr.inst_blk0[iid + 1], lds, rs);
+  if (threadIdx.x != 0) return;
+  const int nc = (mode == kModeCheck && I.use_avg) ? 2 : 1;
+  const double omega = I.omega;
+  const double tau = I.eta_hat / omega, sigma = I.eta_hat * omega;
+  for (int q = 0; q < nc; ++q) {
+    CandState& C = I.cand[q];
+    C.dxa2 = cs[q * 6 + 0];
+    C.dya2 = rs[q * 4 + 0];
+    const double b1sq = cs[q * 6 + 1], b2sq = rs[q * 4 + 1];
+    C.errd = sqrt(cs[q * 6 + 2]);
+    C.errp = sqrt(rs[q * 4 + 2]);
+    C.pobj = cs[q * 6 + 5];
+    C.dobj = rs[q * 4 + 3] + cs[q * 6 + 3] - cs[q * 6 + 4];
+    C.gap = fabs(C.pobj - C.dobj);
+    C.kkt = sqrt(omega * omega * C.errp * C.errp + C.errd * C.errd / (omega * omega) + C.gap * C.gap);
+    C.abs_p = rs[8 + q * 3 + 0];
+    C.abs_d = cs[12 + q * 2 + 0];
+    C.abs_gap = C.gap;
+    C.rel_p = C.abs_p / (1.0 + fmax(I.h_inf, fmax(rs[8 + q * 3 + 1], rs[8 + q * 3 + 2])));
+    C.rel_d = C.abs_d / (1.0 + fmax(I.c_inf, cs[12 + q * 2 + 1]));
+    C.rel_gap = C.gap / (1.0 + fmax(fabs(C.pobj), fabs(C.dobj)));
+    C.r = sqrt(C.dxa2 / tau + C.dya2 / sigma);
+    C.scale = sqrt(tau * b1sq + sigma * b2sq);
+    C.rho = NAN;
+    C.val_lo = 0.0;
+    C.t_lo = 0.0;
+    C.t_hi = 0.0;
+    C.doublings = 0;
+    C.bracketed = 0;
+    C.last_dist = -1.0;
+    if (mode != kModeCheck) {
+      C.phase = kPhaseOff;
+    } else if (!(C.r > 0.0) || !isfinite(C.r)) {
+      C.phase = kPhaseDone;  // invalid radius: numerical issue
+    } else if (C.scale == 0.0) {
+      C.phase = kPhaseDone;
+      C.rho = 0.0;
+    } else {
+      C.phase = kPhaseExp;
+      C.t_base = C.r / C.scale;
+    }
+  }
+  if (nc < 2) I.cand[1].phase = kPhaseOff;
+  if (mode == kModeCheck) I.pending = 0;
+}
+
+__device__ __forceinline__ double probe_t(const CandState& C, int p) {
+  if (C.phase == kPhaseExp) return C.t_base * (double)(1u << p);
+  return C.t_lo + (C.t_hi - C.t_lo) * (double)(p + 1) / (double)(kProbes + 1);
+}
+
+// One multisection pass: for the candidate blockIdx.y (if still searching) and
+// every probe t, sum ||x(t) - x||^2 / tau and b1^T (x(t) - x) over the columns
+// (eq. compute_zt_2).  Records: [candidate][workgroup][probe][2].
+constexpr int kProbeNV = kProbes * 2;
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_probe_cols(Ranges R, const T* __restrict__ x0,
+                                                       const T* __restrict__ x1,
+                                                       const double* __restrict__ g0,
+                                                       const double* __restrict__ g1,
+                                                       DataPtrs<double> d, const Inst* __restrict__ inst,
+                                                       int prec, double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * kProbeNV];
+  const int b = blockIdx.x;
+  const int q = blockIdx.y;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;
+  const CandState& C = I.cand[q];
+  if (C.phase != kPhaseExp && C.phase != kPhaseBisect) return;
+  const double tau = I.eta_hat / I.omega;
+  double tq[kProbes];
+#pragma unroll
+  for (int p = 0; p < kProbes; ++p) tq[p] = probe_t(C, p) * tau;
+  double acc[kProbeNV];
+#pragma unroll
+  for (int i = 0; i < kProbeNV; ++i) acc[i] = 0.0;
+  const double inv_tau = 1.0 / tau;
+  const T* xs = q == 0 ? x0 : x1;
+  const double* gs = q == 0 ? g0 : g1;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double lo = d.l[j], hi = d.u[j];
+    const double xc = (double)xs[j];
+    const double b1 = gs[j] - d.c[j];
+#pragma unroll
+    for (int p = 0; p < kProbes; ++p) {
+      const double dx = clampd(xc + tq[p] * b1, lo, hi) - xc;
+      acc[p * 2 + 0] += dx * dx * inv_tau;
+      acc[p * 2 + 1] += b1 * dx;
+    }
+  }
+  block_sum_store<kProbeNV>(acc, lds, rec + ((size_t)q * R.nblk + b) * kProbeNV);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __restrict__ y0,
+                                                       const T* __restrict__ y1,
+                                                       const double* __restrict__ g0,
+                                                       const double* __restrict__ g1,
+                                                       DataPtrs<double> d, const Inst* __restrict__ inst,
+                                                       int prec, double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * kProbeNV];
+  const int b = blockIdx.x;
+  const int q = blockIdx.y;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;
+  const CandState& C = I.cand[q];
+  if (C.phase != kPhaseExp && C.phase != kPhaseBisect) return;
+  const double sigma = I.eta_hat * I.omega;
+  const int mz_end = I.row0 + I.m_zero;
+  double tq[kProbes];
+#pragma unroll
+  for (int p = 0; p < kProbes; ++p) tq[p] = probe_t(C, p) * sigma;
+  double acc[kProbeNV];
+#pragma unroll
+  for (int i = 0; i < kProbeNV; ++i) acc[i] = 0.0;
+  const double inv_sigma = 1.0 / sigma;
+  const T* ys = q == 0 ? y0 : y1;
+  const double* gs = q == 0 ? g0 : g1;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const bool zero_row = i < mz_end;
+    const double yc = (double)ys[i];
+    const double b2 = d.h[i] - gs[i];
+#pragma unroll
+    for (int p = 0; p < kProbes; ++p) {
+      const double v = yc + tq[p] * b2;
+      const double dy = (zero_row ? v : fmax(v, 0.0)) - yc;
+      acc[p * 2 + 0] += dy * dy * inv_sigma;
+      acc[p * 2 + 1] += b2 * dy;
+    }
+  }
+  block_sum_store<kProbeNV>(acc, lds, rec + ((size_t)q * R.nblk + b) * kProbeNV);
+}
+
+// Update every candidate's bracket from one multisection pass (Algorithm 3:
+// exponential search from t0, then bisection; here kProbes points per pass).
+__global__ __launch_bounds__(kBlock) void k_probe_fin(Ranges rc, const double* __restrict__ rec_c,
+                                                      Ranges rr, const double* __restrict__ rec_r,
+                                                      Inst* __restrict__ inst) {
+  __shared__ double lds[kWavesPerBlock * kProbeNV];
+  const int iid = blockIdx.x;
+  Inst& I = inst[iid];
+  if (I.status != kActive || I.check_due == 0) return;
+  const bool s0 = I.cand[0].phase == kPhaseExp || I.cand[0].phase == kPhaseBisect;
+  const bool s1 = I.cand[1].phase == kPhaseExp || I.cand[1].phase == kPhaseBisect;
+  if (!s0 && !s1) return;
+  double a[kMaxCand][kProbeNV], bsum[kMaxCand][kProbeNV];
+  for (int q = 0; q < kMaxCand; ++q) {
+    const bool sq = q == 0 ? s0 : s1;
+    if (!sq) continue;  // uniform across the workgroup
+    reduce_records<kProbeNV, kProbeNV>(rec_c + (size_t)q * rc.nblk * kProbeNV, rc.inst_blk0[iid],
+                                       rc.inst_blk0[iid + 1], lds, a[q]);
+    reduce_records<kProbeNV, kProbeNV>(rec_r + (size_t)q * rr.nblk * kProbeNV, rr.inst_blk0[iid],
+                                       rr.inst_blk0[iid + 1], lds, bsum[q]);
+  }
+  if (threadIdx.x != 0) return;
+  const double eps = I.bisect_eps;
+  for (int q = 0; q < kMaxCand; ++q) {
+    CandState& C = I.cand[q];
+    if (C.phase != kPhaseExp && C.phase != kPhaseBisect) continue;
+    double dist[kProbes], val[kProbes], tp[kProbes];
+    for (int p = 0; p < kProbes; ++p) {
+      dist[p] = sqrt(a[q][p * 2] + bsum[q][p * 2]);
+      val[p] = a[q][p * 2 + 1] + bsum[q][p * 2 + 1];
+      tp[p] = probe_t(C, p);
+    }
+    if (C.phase == kPhaseExp) {
+      bool decided = false;
+      for (int p = 0; p < kProbes; ++p) {
+        const bool first = (C.doublings == 0 && p == 0);
+        if (dist[p] > C.r) {
+          if (first) {
+            C.t_lo = 0.0;
+            C.val_lo = 0.0;
+          } else {
+            C.t_lo = p > 0 ? tp[p - 1] : C.t_base * 0.5;
+            // val_lo was recorded with the previous probe
+          }
+          C.t_hi = tp[p];
+          C.phase = kPhaseBisect;
+          decided = true;
+          break;
+        }
+        if (!first && dist[p] <= C.last_dist) {  // saturated: z(2t) = z(t)
+          C.phase = kPhaseDone;
+          decided = true;
+          break;
+        }
+        C.last_dist = dist[p];
+        C.val_lo = val[p];
+        C.t_lo = tp[p];
+        C.doublings += 1;
+      }
+      if (!decided) {
+        C.t_base = tp[kProbes - 1] * 2.0;
+        if (C.doublings >= 64) C.phase = kPhaseDone;
+      }
+    } else {
+      int last_in = -1;
+      for (int p = 0; p < kProbes; ++p)
+        if (dist[p] < C.r) last_in = p;
+      const double new_hi = (last_in + 1 < kProbes) ? tp[last_in + 1] : C.t_hi;
+      if (last_in >= 0) {
+        C.t_lo = tp[last_in];
+        C.val_lo = val[last_in];
+      }
+      C.t_hi = new_hi;
+    }
+    if (C.phase == kPhaseBisect && C.t_hi - C.t_lo <= eps * C.t_hi) C.phase = kPhaseDone;
+  }
+}
+
+// Restart decision (Section 2.3), primal weight (Section 2.5), termination
+// (Section 3) and the mixed-precision polish switch.  Thread 0 only.
+__global__ void k_decide(Inst* __restrict__ inst, int nb) {
+  const int iid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iid >= nb) return;
+  Inst& I = inst[iid];
+  if (I.status != kActive || I.check_due == 0) return;
+  I.checks += 1;
+  const int nc = I.use_avg ? 2 : 1;
+  bool all_valid = true;
+  for (int q = 0; q < nc; ++q) {
+    CandState& C = I.cand[q];
+    if (C.phase == kPhaseBisect) C.phase = kPhaseDone;  // pass budget spent: take t_lo
+    if (C.phase == kPhaseExp) C.phase = kPhaseDone;
+    if (!(C.r > 0.0) || !isfinite(C.r)) C.rho = NAN;
+    else if (C.scale == 0.0) C.rho = 0.0;
+    else C.rho = C.val_lo / C.r;
+    if (!(C.rho >= 0.0) || !isfinite(C.rho)) all_valid = false;
+  }
+  if (I.has_anchor && !(I.rho_anchor >= 0.0 && isfinite(I.rho_anchor))) all_valid = false;
+  if (I.has_prev && !(I.rho_prev >= 0.0 && isfinite(I.rho_prev))) all_valid = false;
+  const bool use_kkt = !all_valid;
+  int ch;
+  if (I.method == 1) ch = 1;
+  else if (I.method == 2 || nc == 1) ch = 0;
+  else {
+    const double m0 = use_kkt ? I.cand[0].kkt : I.cand[0].rho;
+    const double m1 = use_kkt ? I.cand[1].kkt : I.cand[1].rho;
+    ch = (m0 <= m1) ? 0 : 1;
+  }
+  CandState& C = I.cand[ch];
+  const double mc = use_kkt ? C.kkt : C.rho;
+  const double ma = use_kkt ? I.kkt_anchor : I.rho_anchor;
+  const double mp = use_kkt ? I.kkt_prev : I.rho_prev;
+  I.use_kkt = use_kkt;
+  I.chosen = ch;
+  I.pobj = C.pobj;
+  I.dobj = C.dobj;
+  I.abs_p = C.abs_p;
+  I.abs_d = C.abs_d;
+  I.abs_gap = C.abs_gap;
+  I.rel_p = C.rel_p;
+  I.rel_d = C.rel_d;
+  I.rel_gap = C.rel_gap;
+  const double amax = fmax(C.abs_p, fmax(C.abs_d, C.abs_gap));
+  const double rmax = fmax(C.rel_p, fmax(C.rel_d, C.rel_gap));
+  const bool optimal = (amax <= I.abs_tol) || (rmax <= I.rel_tol);
+  bool restart = false;
+  if ((double)I.k >= 0.223 * (double)I.kbar) restart = true;
+  else if (I.has_anchor) {
+    if (mc <= 0.4 * ma) restart = true;
+    else if (I.has_prev && mc > mp && mc <= 0.8 * ma) restart = true;
+  }
+  I.optimal = optimal ? 1 : 0;
+  I.switch_fp64 = 0;
+  if (!optimal && I.precision == kFP32) {
+    if (!(rmax >= 0.5 * I.best_rel)) {
+      I.best_rel = rmax;
+      I.stall = 0;
+    } else {
+      I.stall += 1;
+    }
+    if ((I.polish_tol > 0.0 && rmax <= I.polish_tol) ||
+        (I.stall_checks > 0 && I.stall >= I.stall_checks)) {
+      I.switch_fp64 = 1;
+      restart = true;
+    }
+  }
+  if (optimal) {
+    I.restart = 1;
+    return;
+  }
+  if (isnan(rmax)) {
+    I.restart = 0;
+    I.status = kDone;
+    I.exit_code = 8;
+    return;
+  }
+  I.restart = restart ? 1 : 0;
+  if (restart) {
+    const double dx = sqrt(C.dxa2), dy = sqrt(C.dya2);
+    double w = I.omega;
+    if (dx > 1e-10 && dy > 1e-10) w = exp(0.5 * log(dy / dx) + 0.5 * log(w));
+    if (w > 1e5 || w < 1e-5) w = I.omega0;
+    I.omega = w;
+    I.rho_anchor = C.rho;
+    I.kkt_anchor = sqrt(w * w * C.errp * C.errp + C.errd * C.errd / (w * w) + C.gap * C.gap);
+    I.has_anchor = 1;
+    I.has_prev = 0;
+    I.k = 0;
+    I.sum_eta = 0.0;
+    I.t += 1;
+    I.restarts += 1;
+  } else {
+    I.rho_prev = C.rho;
+    I.kkt_prev = C.kkt;
+    I.has_prev = 1;
+  }
+  if (!restart && I.kbar >= I.max_iter) {
+    I.status = kDone;
+    I.exit_code = 1;
+  }
+}
+
+// Apply a restart (anchor <- candidate, products refreshed from the FP64-value
+// candidate products) or, for an optimal candidate, write the unscaled answer.
+// Columns: x, G^T y, average sums, x_out = D2 x, lam_out = (c_hat - G^T y_hat)/D2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restart_cols(Ranges R, IterPtrs<T> it, IterPtrs<double> it64,
+                                                         const double* __restrict__ g0,
+                                                         const double* __restrict__ g1,
+                                                         DataPtrs<double> d, const double* __restrict__ D2,
+                                                         double* __restrict__ xout, double* __restrict__ lamout,
+                                                         const Inst* __restrict__ inst, int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.check_due == 0 || I.restart == 0 || I.precision != prec) return;
+  const int ch = I.chosen;
+  const T* xc = ch == 0 ? it.xh : it.xbar;
+  const double* gc = ch == 0 ? g0 : g1;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double xv = (double)xc[j];
+    const double gv = gc[j];
+    if (I.optimal) {
+      xout[j] = D2[j] * xv;
+      lamout[j] = (d.c[j] - gv) / D2[j];
+    } else if (I.switch_fp64) {
+      it64.x[j] = xv;
+      it64.xa[j] = xv;
+      it64.xh[j] = xv;
+      it64.gty[j] = gv;
+      it64.gtya[j] = gv;
+      it64.gtyh[j] = gv;
+      it64.sx[j] = 0.0;
+    } else {
+      const T xt = (T)xv, gt = (T)gv;
+      it.x[j] = xt;
+      it.xa[j] = xt;
+      it.gty[j] = gt;
+      it.gtya[j] = gt;
+      it.sx[j] = (T)0;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restart_rows(Ranges R, IterPtrs<T> it, IterPtrs<double> it64,
+                                                         const double* __restrict__ g0,
+                                                         const double* __restrict__ g1,
+                                                         const double* __restrict__ D1,
+                                                         double* __restrict__ yout,
+                                                         const Inst* __restrict__ inst, int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.check_due == 0 || I.restart == 0 || I.precision != prec) return;
+  const int ch = I.chosen;
+  const T* yc = ch == 0 ? it.yh : it.ybar;
+  const double* gc = ch == 0 ? g0 : g1;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double yv = (double)yc[i];
+    const double gv = gc[i];
+    if (I.optimal) {
+      yout[i] = D1[i] * yv;
+    } else if (I.switch_fp64) {
+      it64.y[i] = yv;
+      it64.ya[i] = yv;
+      it64.yh[i] = yv;
+      it64.gx[i] = gv;
+      it64.gxa[i] = gv;
+      it64.gxh[i] = gv;
+      it64.sy[i] = 0.0;
+    } else {
+      const T yt = (T)yv, gt = (T)gv;
+      it.y[i] = yt;
+      it.ya[i] = yt;
+      it.gx[i] = gt;
+      it.gxa[i] = gt;
+      it.sy[i] = (T)0;
+    }
+  }
+}
+
+__global__ void k_check_end(Inst* __restrict__ inst, int nb) {
+  const int iid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iid >= nb) return;
+  Inst& I = inst[iid];
+  if (I.check_due == 0) return;
+  if (I.optimal && I.status == kActive) {
+    I.status = kDone;
+    I.exit_code = 0;
+  }
+  if (I.switch_fp64 && I.status == kActive) {
+    I.precision = kFP64;
+    I.switch_fp64 = 0;
+    I.best_rel = INFINITY;
+    I.stall = 0;
+  }
+  I.check_due = 0;
+  I.restart = 0;
+}
+
+// Evaluated point (start point or final point): termination test and output.
+__global__ void k_eval_fin(Inst* __restrict__ inst, int nb, int mode) {
+  const int iid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iid >= nb) return;
+  Inst& I = inst[iid];
+  if (!mode_selects(I, mode)) return;
+  const CandState& C = I.cand[0];
+  I.pobj = C.pobj;
+  I.dobj = C.dobj;
+  I.abs_p = C.abs_p;
+  I.abs_d = C.abs_d;
+  I.abs_gap = C.abs_gap;
+  I.rel_p = C.rel_p;
+  I.rel_d = C.rel_d;
+  I.rel_gap = C.rel_gap;
+  if (mode == kModeEvalStart) {
+    const double amax = fmax(C.abs_p, fmax(C.abs_d, C.abs_gap));
+    const double rmax = fmax(C.rel_p, fmax(C.rel_d, C.rel_gap));
+    I.optimal = ((amax <= I.abs_tol) || (rmax <= I.rel_tol)) ? 1 : 0;
+  } else {
+    I.optimal = 0;
+  }
+}
+
+// Write the evaluated point (x_hat, y_hat) unscaled.  Start mode: only for
+// instances found optimal (which then stop); final mode: every selected instance.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eval_out_cols(Ranges R, const T* __restrict__ xh,
+                                                          const double* __restrict__ g0,
+                                                          DataPtrs<double> d, const double* __restrict__ D2,
+                                                          double* __restrict__ xout, double* __restrict__ lamout,
+                                                          const Inst* __restrict__ inst, int prec, int mode) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  if (mode == kModeEvalStart && !I.optimal) return;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    xout[j] = D2[j] * (double)xh[j];
+    lamout[j] = (d.c[j] - g0[j]) / D2[j];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eval_out_rows(Ranges R, const T* __restrict__ yh,
+                                                          const double* __restrict__ D1,
+                                                          double* __restrict__ yout,
+                                                          const Inst* __restrict__ inst, int prec, int mode) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  if (mode == kModeEvalStart && !I.optimal) return;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) yout[i] = D1[i] * (double)yh[i];
+}
+
+__global__ void k_eval_start_end(Inst* __restrict__ inst, int nb) {
+  const int iid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iid >= nb) return;
+  Inst& I = inst[iid];
+  if (I.status == kActive && I.optimal) {
+    I.status = kDone;
+    I.exit_code = 0;
+  }
+}
+
+// Counts of active instances per precision, for the host loop.
+__global__ void k_summary(const Inst* __restrict__ inst, int nb, int32_t* __restrict__ out) {
+  __shared__ int32_t cnt[2];
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int a32 = 0, a64 = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    if (inst[i].status == kActive) {
+      if (inst[i].precision == kFP32) ++a32;
+      else ++a64;
+    }
+  }
+  atomicAdd(&cnt[0], a32);
+  atomicAdd(&cnt[1], a64);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = cnt[0];
+    out[1] = cnt[1];
+  }
+}
+
+__global__ void k_timeout(Inst* __restrict__ inst, int nb) {
+  const int iid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iid >= nb) return;
+  if (inst[iid].status == kActive) {
+    inst[iid].status = kDone;
+    inst[iid].exit_code = 6;
+  }
+}
+
+// Apply a pending Halpern commit (used to export the internal state at exit).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flush_commit(Ranges R, T* __restrict__ z,
+                                                         const T* __restrict__ zh, const T* __restrict__ za,
+                                                         T* __restrict__ g, const T* __restrict__ gh,
+                                                         const T* __restrict__ ga, T* __restrict__ s,
+                                                         const Inst* __restrict__ inst, int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.pending == 0 || I.precision != prec) return;
+  const double ca = I.ca, cb = I.cb, beta = I.beta, etak = I.eta_k;
+  const bool avg = I.use_avg != 0;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double zhv = (double)zh[j];
+    z[j] = (T)(ca * ((1.0 + beta) * zhv - beta * (double)z[j]) + cb * (double)za[j]);
+    g[j] = (T)(ca * ((1.0 + beta) * (double)gh[j] - beta * (double)g[j]) + cb * (double)ga[j]);
+    if (avg) s[j] = (T)((double)s[j] + etak * zhv);
+  }
+}
+
+__global__ void k_clear_pending(Inst* __restrict__ inst, int nb) {
+  const int iid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iid < nb) inst[iid].pending = 0;
+}
+
+// ===========================================================================
+// Set-up: diagonal rescaling (Section 2.6), norms, start point
+// ===========================================================================
+
+// Per row of a CSR-like structure: max_j (D1_i |a_ij|) D2_j   (mode 0)
+// or sum_j ((D1_i a_ij) D2_j)^2 (mode 1).  For the transposed structure pass
+// swap=1, so that the row scale is indexed by the stored index.
+__global__ __launch_bounds__(kBlock) void k_scale_stat(Tiles tl, MatPtrs<double> A,
+                                                       const double* __restrict__ Drow,
+                                                       const double* __restrict__ Dcol, int swap,
+                                                       int mode, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int t1 = tl.blk_tile1[b];
+  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
+    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
+    const int L = 1 << lg;
+    const int r = r0 + (lane >> lg);
+    const int li = lane & (L - 1);
+    double s = 0.0;
+    if (r < r1) {
+      const int p1 = A.ptr[r + 1];
+      for (int p = A.ptr[r] + li; p < p1; p += L) {
+        const int c = A.idx[p];
+        const double di = swap ? Drow[c] : Drow[r];
+        const double dj = swap ? Dcol[r] : Dcol[c];
+        if (mode == 0) {
+          s = fmax(s, (di * fabs(A.val[p])) * dj);
+        } else {
+          const double e = (di * A.val[p]) * dj;
+          s += e * e;
+        }
+      }
+    }
+    if (mode == 0) {
+      for (int off = L >> 1; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, kWave));
+    } else {
+      s = group_sum(s, L);
+    }
+    if (li == 0 && r < r1) out[r] = s;
+  }
+}
+
+// D <- D / sqrt(stat) (Ruiz, mode 0) or D <- D / sqrt(sqrt(stat)) (L2, mode 1); 0 keeps D.
+__global__ void k_scale_update(double* __restrict__ D, const double* __restrict__ stat, int n, int mode) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = stat[i];
+  if (s > 0.0) {
+    const double r = mode == 0 ? sqrt(s) : sqrt(sqrt(s));
+    D[i] = D[i] / r;
+  }
+}
+
+__global__ void k_fill(double* __restrict__ p, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Scaled values: a_hat = (D1_i a_ij) D2_j, FP64 and FP32 copies.
+__global__ __launch_bounds__(kBlock) void k_scale_vals(Tiles tl, MatPtrs<double> A,
+                                                       const double* __restrict__ Drow,
+                                                       const double* __restrict__ Dcol, int swap,
+                                                       double* __restrict__ v64, float* __restrict__ v32) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int t1 = tl.blk_tile1[b];
+  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
+    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
+    const int L = 1 << lg;
+    const int r = r0 + (lane >> lg);
+    const int li = lane & (L - 1);
+    if (r < r1) {
+      const int p1 = A.ptr[r + 1];
+      for (int p = A.ptr[r] + li; p < p1; p += L) {
+        const int c = A.idx[p];
+        const double di = swap ? Drow[c] : Drow[r];
+        const double dj = swap ? Dcol[r] : Dcol[c];
+        const double e = (di * A.val[p]) * dj;
+        v64[p] = e;
+        v32[p] = (float)e;
+      }
+    }
+  }
+}
+
+// Rescaled vectors: c_hat = D2 c, l_hat = l / D2, u_hat = u / D2 (columns).
+__global__ __launch_bounds__(kBlock) void k_scale_cols(Ranges R, const double* __restrict__ c,
+                                                       const double* __restrict__ l,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ D2,
+                                                       DataMut d64, DataMut32 d32) {
+  const int b = blockIdx.x;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double dj = D2[j];
+    const double cv = dj * c[j], lv = l[j] / dj, uv = u[j] / dj;
+    d64.c[j] = cv;
+    d64.l[j] = lv;
+    d64.u[j] = uv;
+    d32.c[j] = (float)cv;
+    d32.l[j] = (float)lv;
+    d32.u[j] = (float)uv;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_rows(Ranges R, const double* __restrict__ h,
+                                                       const double* __restrict__ D1, DataMut d64,
+                                                       DataMut32 d32) {
+  const int b = blockIdx.x;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double hv = D1[i] * h[i];
+    d64.h[i] = hv;
+    d32.h[i] = (float)hv;
+  }
+}
+
+// Norm records over columns: |c_hat|_1, |c_hat|_2^2 (sums); |c|_inf (max).
+__global__ __launch_bounds__(kBlock) void k_norm_cols(Ranges R, const double* __restrict__ chat,
+                                                      const double* __restrict__ c,
+                                                      double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  const int b = blockIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double v = chat[j];
+    acc[0] += fabs(v);
+    acc[1] += v * v;
+    acc[2] = fmax(acc[2], fabs(c[j]));
+  }
+  block_summax_store<3, 2>(acc, lds, rec + (size_t)b * 3);
+}
+
+// Norm records over rows: |h_hat|_1, |h_hat|_2^2 (sums); |h|_inf (max).
+__global__ __launch_bounds__(kBlock) void k_norm_rows(Ranges R, const double* __restrict__ hhat,
+                                                      const double* __restrict__ h,
+                                                      double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  const int b = blockIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double v = hhat[i];
+    acc[0] += fabs(v);
+    acc[1] += v * v;
+    acc[2] = fmax(acc[2], fabs(h[i]));
+  }
+  block_summax_store<3, 2>(acc, lds, rec + (size_t)b * 3);
+}
+
+// max |G_hat_ij| per workgroup of the CSR schedule.
+__global__ __launch_bounds__(kBlock) void k_norm_mat(Tiles tl, const int32_t* __restrict__ ptr,
+                                                     const double* __restrict__ v64,
+                                                     double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock];
+  const int b = blockIdx.x;
+  double acc[1] = {0.0};
+  const int t0 = tl.blk_tile0[b], t1 = tl.blk_tile1[b];
+  if (t1 > t0) {
+    const int p0 = ptr[tl.tile_row0[t0]], p1 = ptr[tl.tile_row1[t1 - 1]];
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) acc[0] = fmax(acc[0], fabs(v64[p]));
+  }
+  block_summax_store<1, 0>(acc, lds, rec + b);
+}
+
+// Per-instance set-up of the scalars from the norm records (Algorithm 1
+// inputs: eta_hat = 1/||G_hat||_inf read as max |G_hat_ij|, primal weight
+// initialization of Section 2.5).
+__global__ __launch_bounds__(kBlock) void k_init_inst(Ranges rc, const double* __restrict__ rec_c,
+                                                      Ranges rr, const double* __restrict__ rec_r,
+                                                      Tiles tr, const double* __restrict__ rec_m,
+                                                      Inst* __restrict__ inst) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  const int iid = blockIdx.x;
+  Inst& I = inst[iid];
+  double cs[3], rs[3], ms[1];
+  reduce_records<3, 2>(rec_c, rc.inst_blk0[iid], rc.inst_blk0[iid + 1], lds, cs);
+  reduce_records<3, 2>(rec_r, rr.inst_blk0[iid], rr.inst_blk0[iid + 1], lds, rs);
+  reduce_records<1, 0>(rec_m, tr.inst_blk0[iid], tr.inst_blk0[iid + 1], lds, ms);
+  if (threadIdx.x != 0) return;
+  I.c1 = cs[0];
+  I.c2 = sqrt(cs[1]);
+  I.c_inf = cs[2];
+  I.h1 = rs[0];
+  I.h2 = sqrt(rs[1]);
+  I.h_inf = rs[2];
+  I.gmax = ms[0];
+  I.eta_hat = ms[0] > 0.0 ? 1.0 / ms[0] : 1.0;
+  I.eta = I.eta_hat;
+  I.omega0 = (I.c2 > 1e-10 && I.h2 > 1e-10) ? I.c2 / I.h2 : 1.0;
+  I.omega = I.omega0;
+}
+
+// Start point: x = Proj_[l,u](x0 / D2), y = Proj_Kd(y0 / D1); anchor = x_hat = x.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start_cols(Ranges R, const double* __restrict__ x0,
+                                                       const double* __restrict__ D2, DataPtrs<double> d,
+                                                       IterPtrs<T> it, const Inst* __restrict__ inst, int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.precision != prec) return;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double v = x0 ? x0[j] / D2[j] : 0.0;
+    const T x = (T)clampd(v, d.l[j], d.u[j]);
+    it.x[j] = x;
+    it.xa[j] = x;
+    it.xh[j] = x;
+    it.sx[j] = (T)0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start_rows(Ranges R, const double* __restrict__ y0,
+                                                       const double* __restrict__ D1, IterPtrs<T> it,
+                                                       const Inst* __restrict__ inst, int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.precision != prec) return;
+  const int mz_end = I.row0 + I.m_zero;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double v = y0 ? y0[i] / D1[i] : 0.0;
+    const T y = (T)(i < mz_end ? v : fmax(v, 0.0));
+    it.y[i] = y;
+    it.ya[i] = y;
+    it.yh[i] = y;
+    it.sy[i] = (T)0;
+  }
+}
+
+// Copy FP64 products into the maintained products of the start point.
+template <typename T>
+__global__ void k_set_products(T* __restrict__ g, T* __restrict__ ga, T* __restrict__ gh,
+                               const double* __restrict__ src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T v = (T)src[i];
+  g[i] = v;
+  ga[i] = v;
+  gh[i] = v;
+}
+
+// Plain product out = A in (unscaled or scaled values) for the public SpMV call.
+template <typename T, typename TM>
+__global__ __launch_bounds__(kBlock) void k_spmv_plain(Tiles tl, MatPtrs<TM> A, const T* __restrict__ in,
+                                                       T* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int t1 = tl.blk_tile1[b];
+  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
+    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
+    const int L = 1 << lg;
+    const int r = r0 + (lane >> lg);
+    const int li = lane & (L - 1);
+    double s = 0.0;
+    if (r < r1) s = row_dot(A.idx, A.val, in, A.ptr[r], A.ptr[r + 1], li, L);
+    s = group_sum(s, L);
+    if (li == 0 && r < r1) out[r] = (T)s;
+  }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+static inline dim3 grid1(int n) { return dim3((unsigned)(n > 0 ? n : 0)); }
+
+template <typename T>
+static void launch_primal_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
+                            const DataPtrs<T>& d) {
+  if (k.vcol.nblk > 0)
+    k_primal<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it, d, k.inst, prec, k.rec_primal);
+}
+
+template <typename T>
+static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
+                          const DataPtrs<T>& d, const MatPtrs<T>& A) {
+  if (k.trow.nblk > 0)
+    k_dual<T, T><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, A, it, d, k.inst, prec, k.rec_dual);
+}
+
+// part 0: primal pass; part 1: SpMV with the dual step; part 2: the rest.
+void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
+  if (part == 0) {
+    if (mask & 1) launch_primal_t<float>(k, s, kFP32, k.it32, k.d32);
+    if (mask & 2) launch_primal_t<double>(k, s, kFP64, k.it64, k.d64);
+    return;
+  }
+  if (part == 1) {
+    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32);
+    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64);
+    return;
+  }
+  k_fin_ls<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_primal, k.trow, k.rec_dual, k.inst);
+  if (mask & 1 && k.tcol.nblk > 0)
+    k_lam<float, float><<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, k.AT32, k.it32, k.d32, k.inst, kFP32,
+                                                               k.rec_lam);
+  if (mask & 2 && k.tcol.nblk > 0)
+    k_lam<double, double><<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, k.AT64, k.it64, k.d64, k.inst, kFP64,
+                                                                 k.rec_lam);
+  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(k.tcol, k.rec_lam, k.inst);
+}
+
+void launch_trial(const KernelCtx& k, hipStream_t s, int mask) {
+  launch_trial_part(k, s, mask, 0);
+  launch_trial_part(k, s, mask, 1);
+  launch_trial_part(k, s, mask, 2);
+}
+
+template <typename T>
+static void launch_cand_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
+                          const T* x0, const T* x1, const T* y0, const T* y1, int mode) {
+  if (k.trow.nblk > 0)
+    k_spmv2<T><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, k.A64, x0, x1, k.cgx0, k.cgx1, k.inst, prec, mode);
+  if (k.tcol.nblk > 0)
+    k_spmv2<T><<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, k.AT64, y0, y1, k.cgty0, k.cgty1, k.inst, prec,
+                                                      mode);
+  if (k.vcol.nblk > 0)
+    k_cand_cols<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, x0, x1, it.xa, k.cgty0, k.cgty1, k.d64, k.D2,
+                                                          k.inst, prec, mode, k.rec_cand_c);
+  if (k.vrow.nblk > 0)
+    k_cand_rows<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, y0, y1, it.ya, k.cgx0, k.cgx1, k.d64, k.D1,
+                                                          k.inst, prec, mode, k.rec_cand_r);
+}
+
+template <typename T>
+static void launch_check_pre_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it) {
+  if (k.vcol.nblk > 0)
+    k_commit_avg<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it.x, it.xh, it.xa, it.gty, it.gtyh, it.gtya,
+                                                           it.sx, it.xbar, k.inst, prec);
+  if (k.vrow.nblk > 0)
+    k_commit_avg<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it.y, it.yh, it.ya, it.gx, it.gxh, it.gxa,
+                                                           it.sy, it.ybar, k.inst, prec);
+  launch_cand_t<T>(k, s, prec, it, it.xh, it.xbar, it.yh, it.ybar, kModeCheck);
+}
+
+template <typename T>
+static void launch_probe_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it) {
+  if (k.vcol.nblk > 0)
+    k_probe_cols<T><<<dim3(k.vcol.nblk, kMaxCand), kBlock, 0, s>>>(k.vcol, it.xh, it.xbar, k.cgty0, k.cgty1, k.d64,
+                                                           k.inst, prec, k.rec_probe_c);
+  if (k.vrow.nblk > 0)
+    k_probe_rows<T><<<dim3(k.vrow.nblk, kMaxCand), kBlock, 0, s>>>(k.vrow, it.yh, it.ybar, k.cgx0, k.cgx1, k.d64,
+                                                           k.inst, prec, k.rec_probe_r);
+}
+
+template <typename T>
+static void launch_restart_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it) {
+  if (k.vcol.nblk > 0)
+    k_restart_cols<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it, k.it64, k.cgty0, k.cgty1, k.d64, k.D2,
+                                                             k.xout, k.lamout, k.inst, prec);
+  if (k.vrow.nblk > 0)
+    k_restart_rows<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it, k.it64, k.cgx0, k.cgx1, k.D1, k.yout,
+                                                             k.inst, prec);
+}
+
+void launch_check(const KernelCtx& k, hipStream_t s, int mask) {
+  const int nbt = (k.nb + 63) / 64;
+  if (mask & 1) launch_check_pre_t<float>(k, s, kFP32, k.it32);
+  if (mask & 2) launch_check_pre_t<double>(k, s, kFP64, k.it64);
+  k_cand_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_cand_c, k.vrow, k.rec_cand_r, k.inst, kModeCheck);
+  for (int pass = 0; pass < k.probe_passes; ++pass) {
+    if (mask & 1) launch_probe_t<float>(k, s, kFP32, k.it32);
+    if (mask & 2) launch_probe_t<double>(k, s, kFP64, k.it64);
+    k_probe_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_probe_c, k.vrow, k.rec_probe_r, k.inst);
+  }
+  k_decide<<<nbt, 64, 0, s>>>(k.inst, k.nb);
+  if (mask & 1) launch_restart_t<float>(k, s, kFP32, k.it32);
+  if (mask & 2) launch_restart_t<double>(k, s, kFP64, k.it64);
+  k_check_end<<<nbt, 64, 0, s>>>(k.inst, k.nb);
+}
+
+void launch_summary(const KernelCtx& k, hipStream_t s, int32_t* out) {
+  k_summary<<<1, kBlock, 0, s>>>(k.inst, k.nb, out);
+}
+
+void launch_timeout(const KernelCtx& k, hipStream_t s) {
+  k_timeout<<<(k.nb + 63) / 64, 64, 0, s>>>(k.inst, k.nb);
+}
+
+template <typename T>
+static void launch_eval_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it, int mode) {
+  launch_cand_t<T>(k, s, prec, it, it.xh, nullptr, it.yh, nullptr, mode);
+}
+
+template <typename T>
+static void launch_eval_out_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it, int mode) {
+  if (k.vcol.nblk > 0)
+    k_eval_out_cols<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it.xh, k.cgty0, k.d64, k.D2, k.xout,
+                                                              k.lamout, k.inst, prec, mode);
+  if (k.vrow.nblk > 0)
+    k_eval_out_rows<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it.yh, k.D1, k.yout, k.inst, prec, mode);
+}
+
+void launch_eval(const KernelCtx& k, hipStream_t s, int mask, int final_mode) {
+  const int mode = final_mode ? kModeEvalFinal : kModeEvalStart;
+  const int nbt = (k.nb + 63) / 64;
+  if (mask & 1) launch_eval_t<float>(k, s, kFP32, k.it32, mode);
+  if (mask & 2) launch_eval_t<double>(k, s, kFP64, k.it64, mode);
+  k_cand_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_cand_c, k.vrow, k.rec_cand_r, k.inst, mode);
+  k_eval_fin<<<nbt, 64, 0, s>>>(k.inst, k.nb, mode);
+  if (mask & 1) launch_eval_out_t<float>(k, s, kFP32, k.it32, mode);
+  if (mask & 2) launch_eval_out_t<double>(k, s, kFP64, k.it64, mode);
+  if (!final_mode) k_eval_start_end<<<nbt, 64, 0, s>>>(k.inst, k.nb);
+}
+
+template <typename T>
+static void launch_flush_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it) {
+  if (k.vcol.nblk > 0)
+    k_flush_commit<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it.x, it.xh, it.xa, it.gty, it.gtyh,
+                                                             it.gtya, it.sx, k.inst, prec);
+  if (k.vrow.nblk > 0)
+    k_flush_commit<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it.y, it.yh, it.ya, it.gx, it.gxh, it.gxa,
+                                                             it.sy, k.inst, prec);
+}
+
+void launch_flush_commit(const KernelCtx& k, hipStream_t s, int mask) {
+  if (mask & 1) launch_flush_t<float>(k, s, kFP32, k.it32);
+  if (mask & 2) launch_flush_t<double>(k, s, kFP64, k.it64);
+  k_clear_pending<<<(k.nb + 63) / 64, 64, 0, s>>>(k.inst, k.nb);
+}
+
+// ---- set-up ----
+void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mask) {
+  const int tpb = 256;
+  auto blocks = [&](int64_t n) { return dim3((unsigned)((n + tpb - 1) / tpb)); };
+  if (k.M > 0) k_fill<<<blocks(k.M), tpb, 0, s>>>(k.D1, 1.0, k.M);
+  if (k.N > 0) k_fill<<<blocks(k.N), tpb, 0, s>>>(k.D2, 1.0, k.N);
+  if (su.precondition) {
+    for (int it = 0; it < su.ruiz_iters; ++it) {
+      if (k.trow.nblk > 0)
+        k_scale_stat<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A, k.D1, k.D2, 0, 0, su.stat_r);
+      if (k.tcol.nblk > 0)
+        k_scale_stat<<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, su.AT, k.D1, k.D2, 1, 0, su.stat_c);
+      if (k.M > 0) k_scale_update<<<blocks(k.M), tpb, 0, s>>>(k.D1, su.stat_r, (int)k.M, 0);
+      if (k.N > 0) k_scale_update<<<blocks(k.N), tpb, 0, s>>>(k.D2, su.stat_c, (int)k.N, 0);
+    }
+    if (su.l2_pass) {
+      if (k.trow.nblk > 0)
+        k_scale_stat<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A, k.D1, k.D2, 0, 1, su.stat_r);
+      if (k.tcol.nblk > 0)
+        k_scale_stat<<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, su.AT, k.D1, k.D2, 1, 1, su.stat_c);
+      if (k.M > 0) k_scale_update<<<blocks(k.M), tpb, 0, s>>>(k.D1, su.stat_r, (int)k.M, 1);
+      if (k.N > 0) k_scale_update<<<blocks(k.N), tpb, 0, s>>>(k.D2, su.stat_c, (int)k.N, 1);
+    }
+  }
+  if (k.trow.nblk > 0)
+    k_scale_vals<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A, k.D1, k.D2, 0, su.val64, su.val32);
+  if (k.tcol.nblk > 0)
+    k_scale_vals<<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, su.AT, k.D1, k.D2, 1, su.valT64, su.valT32);
+  if (k.vcol.nblk > 0)
+    k_scale_cols<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.c, su.l, su.u, k.D2, su.d64m, su.d32m);
+  if (k.vrow.nblk > 0)
+    k_scale_rows<<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.h, k.D1, su.d64m, su.d32m);
+  if (k.vcol.nblk > 0) k_norm_cols<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.d64m.c, su.c, su.rec_nc);
+  if (k.vrow.nblk > 0) k_norm_rows<<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.d64m.h, su.h, su.rec_nr);
+  if (k.trow.nblk > 0) k_norm_mat<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A.ptr, su.val64, su.rec_nm);
+  k_init_inst<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, su.rec_nc, k.vrow, su.rec_nr, k.trow, su.rec_nm, k.inst);
+  // start point and its products
+  if (mask & 1) {
+    if (k.vcol.nblk > 0)
+      k_start_cols<float><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.x0, k.D2, k.d64, k.it32, k.inst, kFP32);
+    if (k.vrow.nblk > 0)
+      k_start_rows<float><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.y0, k.D1, k.it32, k.inst, kFP32);
+  }
+  if (mask & 2) {
+    if (k.vcol.nblk > 0)
+      k_start_cols<double><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.x0, k.D2, k.d64, k.it64, k.inst, kFP64);
+    if (k.vrow.nblk > 0)
+      k_start_rows<double><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.y0, k.D1, k.it64, k.inst, kFP64);
+  }
+  // FP64-value products of the start point: eval mode computes cgx0 = G x_hat, cgty0 = G^T y_hat
+  launch_eval(k, s, mask, 0);
+  if (mask & 1) {
+    if (k.M > 0) k_set_products<float><<<blocks(k.M), tpb, 0, s>>>(k.it32.gx, k.it32.gxa, k.it32.gxh, k.cgx0, k.M);
+    if (k.N > 0)
+      k_set_products<float><<<blocks(k.N), tpb, 0, s>>>(k.it32.gty, k.it32.gtya, k.it32.gtyh, k.cgty0, k.N);
+  }
+  if (mask & 2) {
+    if (k.M > 0) k_set_products<double><<<blocks(k.M), tpb, 0, s>>>(k.it64.gx, k.it64.gxa, k.it64.gxh, k.cgx0, k.M);
+    if (k.N > 0)
+      k_set_products<double><<<blocks(k.N), tpb, 0, s>>>(k.it64.gty, k.it64.gtya, k.it64.gtyh, k.cgty0, k.N);
+  }
+}
+
+void launch_spmv_plain(const Tiles& tl, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
+                       const void* in, void* out, hipStream_t s) {
+  if (tl.nblk <= 0) return;
+  if (prec == kFP64) {
+    MatPtrs<double> A{ptr, idx, (const double*)val};
+    k_spmv_plain<double, double><<<grid1(tl.nblk), kBlock, 0, s>>>(tl, A, (const double*)in, (double*)out);
+  } else {
+    MatPtrs<float> A{ptr, idx, (const float*)val};
+    k_spmv_plain<float, float><<<grid1(tl.nblk), kBlock, 0, s>>>(tl, A, (const float*)in, (float*)out);
+  }
+}
+
+// One K1 pass on its own (for schedule timing): trial SpMV with the fused dual step.
+void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec) {
+  if (k.trow.nblk <= 0) return;
+  if (prec == kFP32)
+    k_dual<float, float><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, k.A32, k.it32, k.d32, k.inst, kFP32,
+                                                                k.rec_dual);
+  else
+    k_dual<double, double><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, k.A64, k.it64, k.d64, k.inst, kFP64,
+                                                                  k.rec_dual);
+}
+
+}  // namespace pdcs

@@ -1,0 +1,85 @@
+// Host-visible launch interface of the PDCS kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdcs_dev.h"
+
+namespace pdcs {
+
+// Iterates of one precision, all in the rescaled space (Section 2.6):
+// Halpern iterate (x, y), anchor (xa, ya), last PDHG output (xh, yh), the
+// maintained products G x, G x_a, G x_hat, G^T y, G^T y_a, G^T y_hat, the
+// eta-weighted sums of the interval (sx, sy) and the average candidate.
+template <typename T>
+struct IterPtrs {
+  T *x, *y, *xa, *ya, *xh, *yh;
+  T *gx, *gxa, *gxh, *gty, *gtya, *gtyh;
+  T *sx, *sy, *xbar, *ybar;
+};
+
+// Rescaled problem vectors: c_hat, l_hat, u_hat (columns) and h_hat (rows).
+template <typename T>
+struct DataPtrs {
+  const T *c, *l, *u, *h;
+};
+struct DataMut {
+  double *c, *l, *u, *h;
+};
+struct DataMut32 {
+  float *c, *l, *u, *h;
+};
+
+template <typename TM>
+struct MatPtrs {
+  const int32_t* ptr;
+  const int32_t* idx;
+  const TM* val;
+};
+
+struct KernelCtx {
+  int nb;
+  int64_t M, N;
+  Tiles trow, tcol;   // CSR of G (rows) and of G^T (columns)
+  Ranges vrow, vcol;  // elementwise passes over rows and columns
+  Inst* inst;
+  IterPtrs<float> it32;
+  IterPtrs<double> it64;
+  DataPtrs<float> d32;
+  DataPtrs<double> d64;
+  MatPtrs<float> A32, AT32;
+  MatPtrs<double> A64, AT64;
+  double *cgx0, *cgx1, *cgty0, *cgty1;  // FP64-value products of the candidates
+  double *D1, *D2;
+  double *xout, *yout, *lamout;
+  double *rec_primal, *rec_dual, *rec_lam, *rec_cand_c, *rec_cand_r, *rec_probe_c, *rec_probe_r;
+  int probe_passes;
+};
+
+struct SetupCtx {
+  int precondition, ruiz_iters, l2_pass;
+  MatPtrs<double> A, AT;          // unscaled values
+  const double *c, *l, *u, *h;    // unscaled vectors
+  double *val64, *valT64;
+  float *val32, *valT32;
+  DataMut d64m;
+  DataMut32 d32m;
+  double *stat_r, *stat_c, *rec_nc, *rec_nr, *rec_nm;
+  const double *x0, *y0;          // device start point (unscaled) or null
+};
+
+void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mask);
+void launch_trial(const KernelCtx& k, hipStream_t s, int mask);
+void launch_check(const KernelCtx& k, hipStream_t s, int mask);
+void launch_summary(const KernelCtx& k, hipStream_t s, int32_t* out);
+void launch_timeout(const KernelCtx& k, hipStream_t s);
+void launch_eval(const KernelCtx& k, hipStream_t s, int mask, int final_mode);
+void launch_flush_commit(const KernelCtx& k, hipStream_t s, int mask);
+void launch_spmv_plain(const Tiles& tl, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
+                       const void* in, void* out, hipStream_t s);
+void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec);
+
+// Trial split for kernel timing: K3, K1, and the rest of the trial.
+void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part);
+
+}  // namespace pdcs

@@ -1,0 +1,131 @@
+"""GPU parity of the HIP solver (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: the method is an iteration whose restart decisions are
+discontinuous in rounding, so full solves are compared through what is unique
+(the optimal objective, to 1e-6 relative as the stated bar) and through the
+oracle's own evaluation of the KKT errors of the GPU's answer (<= the
+requested tolerance).  Deterministic pieces (scaling, the first trials before
+any restart check, SpMV) are compared element by element.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lpgen
+from oracle import pdcs_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_15504_amd")
+
+
+def _gpu_ok():
+    return P.pdcs_device_count() > 0
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not _gpu_ok():
+        pytest.skip("no GPU visible")
+
+
+def _rel_kkt(err):
+    return max(err["rel_p"], err["rel_d"], err["rel_gap"])
+
+
+def _check_solution(inst, sol, p_ref, tol=1e-6, obj_tol=1e-6):
+    lp = O.lpdata_from_instance(inst)
+    err = O.termination_errors(lp, sol.x, sol.y)
+    assert sol.info["exit_code"] == 0, sol.info
+    assert _rel_kkt(err) <= tol * 1.0001, err
+    assert abs(err["pobj"] - p_ref) / (1.0 + abs(p_ref)) <= obj_tol, (err["pobj"], p_ref)
+    # the returned slack is c - G^T y of the returned y
+    lam = inst.c - lp.G.T @ sol.y
+    assert np.allclose(sol.lam, lam, rtol=1e-9, atol=1e-9 * (1 + np.abs(lam).max()))
+    return err
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c0_fp64_matches_oracle(seed):
+    inst = lpgen.c0_instance(seed)
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options())
+    assert ref.exit_code == 0
+    prob = P.Problem.from_instance(inst)
+    sol = prob.solve(precision="fp64", time_limit=60.0)
+    print(f"seed {seed}: gpu iters {sol.info['iters']} restarts {sol.info['restarts']} "
+          f"oracle iters {ref.iters} restarts {ref.restarts} time {sol.info['time_sec']:.3f}s", flush=True)
+    _check_solution(inst, sol, ref.pobj)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c0_mixed_matches_oracle(seed):
+    inst = lpgen.c0_instance(seed)
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options())
+    prob = P.Problem.from_instance(inst)
+    sol = prob.solve(precision="mixed", time_limit=60.0)
+    print(f"mixed seed {seed}: iters {sol.info['iters']} fp64 iters {sol.info['fp64_iters']}", flush=True)
+    _check_solution(inst, sol, ref.pobj)
+
+
+def test_scaling_matches_oracle():
+    inst = lpgen.c4_instance(0, m=300, n=700, per_col=6)
+    D1o, D2o = O.ruiz_l2_scaling(inst.scipy_csr(), 10, True)
+    prob = P.Problem.from_instance(inst)
+    sol = prob.solve(max_iter=1, with_scaling=True)
+    assert np.allclose(sol.D1, D1o, rtol=1e-13, atol=0)
+    assert np.allclose(sol.D2, D2o, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("mz", [None, 60])
+def test_first_trials_match_oracle_elementwise(mz):
+    # Before the first restart check the iteration is deterministic: after N
+    # trials the GPU state must equal the oracle's up to rounding.
+    inst = lpgen.planted_lp(lpgen.rng_for(77, 1), 120, 300, per_col=4, m_zero=mz)
+    lp = O.lpdata_from_instance(inst)
+    N = 40
+    ref = O.solve(lp, O.Options(max_iter=N, check_every=1000))
+    prob = P.Problem.from_instance(inst)
+    sol = prob.solve(precision="fp64", max_iter=N, check_every=1000, keep_state=True)
+    st = sol.state
+    assert st["kbar"] == ref.state["kbar"] == N
+    assert st["k"] == ref.state["k"]
+    assert st["omega"] == pytest.approx(ref.state["omega"], rel=1e-14)
+    assert st["eta_hat"] == pytest.approx(ref.state["eta_hat"], rel=1e-9)
+    for key, okey in (("x", "x"), ("y", "y"), ("x_hat", "x_hat"), ("y_hat", "y_hat"),
+                      ("x_a", "x_anchor"), ("y_a", "y_anchor")):
+        a, b = st[key], ref.state[okey]
+        scale = 1.0 + np.abs(b).max()
+        assert np.max(np.abs(a - b)) <= 1e-9 * scale, key
+
+
+def test_spmv_matches_scipy_power_law():
+    torch = pytest.importorskip("torch")
+    inst = lpgen.c1_instance(0, m=20000, n=40000, s=1.5, max_len=3000)
+    A = inst.scipy_csr()
+    prob = P.Problem.from_instance(inst)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(inst.n)
+    y = rng.standard_normal(inst.m)
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    yd = torch.tensor(y, dtype=torch.float64, device="cuda")
+    out_m = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+    out_n = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    prob.spmv(xd.data_ptr(), out_m.data_ptr(), transpose=False, precision="fp64")
+    prob.spmv(yd.data_ptr(), out_n.data_ptr(), transpose=True, precision="fp64")
+    torch.cuda.synchronize()
+    ax = A @ x
+    aty = A.T @ y
+    bound_m = np.abs(A) @ np.abs(x)
+    bound_n = np.abs(A.T) @ np.abs(y)
+    # FP64 accumulation in a different order: error <= n_row * eps * sum|a x|
+    assert np.all(np.abs(out_m.cpu().numpy() - ax) <= 1e-13 * (1 + bound_m) * 64)
+    assert np.all(np.abs(out_n.cpu().numpy() - aty) <= 1e-13 * (1 + bound_n) * 64)
+    # FP32 values and vectors, FP64 accumulation
+    x32 = torch.tensor(x, dtype=torch.float32, device="cuda")
+    o32 = torch.empty(inst.m, dtype=torch.float32, device="cuda")
+    prob.spmv(x32.data_ptr(), o32.data_ptr(), transpose=False, precision="mixed")
+    torch.cuda.synchronize()
+    A32 = A.astype(np.float32).astype(np.float64)
+    exact32 = A32 @ x.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(o32.cpu().numpy().astype(np.float64) - exact32) <= 6e-8 * (1 + np.abs(exact32)) + 1e-12 * bound_m)
