@@ -87,11 +87,13 @@ typedef struct {
                                  trial whose trial count is a multiple of this         */
   int64_t precision;          /* PDCS_PRECISION_*                                     */
   int64_t stall_checks;       /* mixed: switch to FP64 after this many checks without
-                                 a 2x improvement of the relative KKT error (0: never) */
+                                 a 2x improvement of the relative KKT error, counted
+                                 once that error is below 100 * rel_tol (0: never)    */
   double  polish_switch_tol;  /* mixed: switch to FP64 once rel. KKT <= this (0: off)  */
   double  bisect_rel_eps;     /* 1e-6: relative bracket width of the gap bisection     */
   int64_t use_graph;          /* 1: replay each chunk of iterations as a hipGraph      */
-  int64_t verbose;            /* 0: silent; 1: one line per chunk for instance 0      */
+  int64_t verbose;            /* 0: silent; 1: a line about every 2 s for instance 0;
+                                 2: a line per chunk of check_every trials             */
   int64_t keep_state;         /* 1: keep the internal iterates for pdcs_result_state   */
   int64_t time_kernels;       /* 1: launch without graphs and time every launch of the
                                  SpMV-with-dual-step kernel with HIP events           */
@@ -161,6 +163,14 @@ int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
  * synchronized.  Errors: PDCS_ERR_INVALID_ARG. */
 int  pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision,
                        const void* in_dev, void* out_dev, void* stream);
+
+/* pdcs_problem_set_panels: column-panel split of the two SpMVs of a single
+ * problem.  px panels split the columns gathered by G x, py the rows gathered
+ * by G^T y; each panel's workgroups are routed to a fixed subset of the 8 XCDs
+ * so that its slice of the gathered vector stays in that XCD's L2.
+ * 0 = automatic (about 256 Ki entries per panel), 1 = off, 2/4/8 = forced.
+ * Errors: PDCS_ERR_INVALID_ARG for other values. */
+int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
 
 /* ---- single solve ------------------------------------------------------
  * pdcs_solve: Algorithm 4 (rescale, Algorithm 1, unscale) on one problem.

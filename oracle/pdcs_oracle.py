@@ -486,6 +486,7 @@ class Result:
     time_sec: float
     D1: np.ndarray
     D2: np.ndarray
+    setup_sec: float = 0.0         # scaling and start point, before the first trial
     state: dict = field(default_factory=dict)
     trace: list = field(default_factory=list)
     checks_log: list = field(default_factory=list)
@@ -547,13 +548,14 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
         err = termination_errors(lp, xu, yu)
         lam = lp.c - lp.G.T @ yu
         return Result(xu, yu, lam, code, err["pobj"], err["dobj"], err, kbar, accepted,
-                      restarts, checks, time.perf_counter() - t_start, D1, D2,
+                      restarts, checks, time.perf_counter() - t_start, D1, D2, setup_sec,
                       state=dict(x=x.copy(), y=y.copy(), x_hat=xh.copy(), y_hat=yh.copy(),
                                  x_anchor=xa.copy(), y_anchor=ya.copy(), Sx=Sx.copy(),
                                  Sy=Sy.copy(), SH=SH, omega=omega, omega0=omega0,
                                  eta_hat=eta_hat, kbar=kbar, k=k, t=t),
                       trace=trial_log or [], checks_log=checks_log)
 
+    setup_sec = time.perf_counter() - t_start
     # Termination test of the start point.
     xu, yu = unscale(x, y)
     if is_optimal(termination_errors(lp, xu, yu), opts.rel_tol, opts.abs_tol):

@@ -5,4 +5,4 @@ package only marshals arguments.  Importing it fails loudly when the library
 has not been built.
 """
 from ._binding import *  # noqa: F401,F403
-from ._binding import Batch, Problem, Solution, lib  # noqa: F401
+from ._binding import MLP, Batch, Problem, Solution, lib  # noqa: F401

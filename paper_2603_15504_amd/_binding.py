@@ -70,6 +70,7 @@ PROTOTYPES = {
     "pdcs_problem_destroy": (None, [_P]),
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
+    "pdcs_problem_set_panels": (C.c_int, [_P, _I64, _I64]),
     "pdcs_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, C.POINTER(_P)]),
     "pdcs_result_info": (C.c_int, [_P, C.POINTER(pdcs_info)]),
     "pdcs_result_primal": (C.c_int, [_P, _P, _I64]),
@@ -95,7 +96,18 @@ PROTOTYPES = {
 }
 
 
+def _bind_hip_runtime_of_torch():
+    """torch ships its own libamdhip64.so.7 (same soname as /opt/rocm's).  Two
+    HIP runtimes cannot share a process, so when torch is importable it is
+    loaded first and libpdcs.so binds to the runtime torch already holds."""
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
+    _bind_hip_runtime_of_torch()
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2603_15504_amd.build` "
                           "(there is no CPU fallback)")
@@ -189,6 +201,10 @@ def pdcs_problem_spmv(p, transpose: int, precision: int, in_dev: int, out_dev: i
     _check(lib.pdcs_problem_spmv(p, int(transpose), int(precision), C.c_void_p(in_dev),
                                  C.c_void_p(out_dev), C.c_void_p(stream) if stream else None),
            "pdcs_problem_spmv")
+
+
+def pdcs_problem_set_panels(p, px: int, py: int):
+    _check(lib.pdcs_problem_set_panels(p, int(px), int(py)), "pdcs_problem_set_panels")
 
 
 def pdcs_solve(p, opts: pdcs_options | None = None, x0=None, y0=None, stream: int = 0) -> C.c_void_p:
@@ -336,6 +352,9 @@ class Problem:
         finally:
             pdcs_result_destroy(r)
 
+    def set_panels(self, px=0, py=0):
+        pdcs_problem_set_panels(self.handle, px, py)
+
     def spmv(self, x_dev, out_dev, transpose=False, precision="fp64", stream=0):
         pdcs_problem_spmv(self.handle, 1 if transpose else 0, PRECISION[precision], x_dev, out_dev, stream)
 
@@ -397,6 +416,109 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             pdcs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Warm-start MLP (pdcs_mlp_*)
+# ---------------------------------------------------------------------------
+def pdcs_mlp_create(d_in, width, d_out, seed=0):
+    out = C.c_void_p()
+    _check(lib.pdcs_mlp_create(int(d_in), int(width), int(d_out), int(seed), C.byref(out)), "pdcs_mlp_create")
+    return out
+
+
+def pdcs_mlp_forward(net, in_dev: int, out_dev: int, batch: int, stream: int = 0):
+    _check(lib.pdcs_mlp_forward(net, C.c_void_p(in_dev), C.c_void_p(out_dev), int(batch),
+                                C.c_void_p(stream) if stream else None), "pdcs_mlp_forward")
+
+
+def pdcs_mlp_train_step(net, in_dev: int, target_dev: int, batch: int, lr: float, stream: int = 0) -> float:
+    loss = C.c_float()
+    _check(lib.pdcs_mlp_train_step(net, C.c_void_p(in_dev), C.c_void_p(target_dev), int(batch), float(lr),
+                                   C.byref(loss), C.c_void_p(stream) if stream else None), "pdcs_mlp_train_step")
+    return loss.value
+
+
+def pdcs_mlp_gradients(net, in_dev: int, target_dev: int, batch: int, grad_dev: int, stream: int = 0) -> float:
+    loss = C.c_float()
+    _check(lib.pdcs_mlp_gradients(net, C.c_void_p(in_dev), C.c_void_p(target_dev), int(batch),
+                                  C.c_void_p(grad_dev) if grad_dev else None, C.byref(loss),
+                                  C.c_void_p(stream) if stream else None), "pdcs_mlp_gradients")
+    return loss.value
+
+
+def pdcs_mlp_num_params(net) -> int:
+    n = C.c_int64()
+    _check(lib.pdcs_mlp_num_params(net, C.byref(n)), "pdcs_mlp_num_params")
+    return n.value
+
+
+def pdcs_mlp_get_params(net) -> np.ndarray:
+    out = np.empty(pdcs_mlp_num_params(net), dtype=np.float32)
+    _check(lib.pdcs_mlp_get_params(net, _ptr(out)), "pdcs_mlp_get_params")
+    return out
+
+
+def pdcs_mlp_set_params(net, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != pdcs_mlp_num_params(net):
+        raise ValueError("parameter count mismatch")
+    _check(lib.pdcs_mlp_set_params(net, _ptr(p)), "pdcs_mlp_set_params")
+
+
+def pdcs_mlp_destroy(net):
+    lib.pdcs_mlp_destroy(net)
+
+
+class MLP:
+    """3-layer perceptron with BF16 MFMA kernels (pdcs_mlp).  Device tensors are
+    torch tensors (float32, contiguous, row-major [batch x features])."""
+
+    def __init__(self, d_in, width, d_out, seed=0):
+        self.d_in, self.width, self.d_out = int(d_in), int(width), int(d_out)
+        self.handle = pdcs_mlp_create(d_in, width, d_out, seed)
+
+    def forward(self, u):
+        import torch
+
+        assert u.dtype == torch.float32 and u.is_contiguous() and u.shape[1] == self.d_in
+        out = torch.empty((u.shape[0], self.d_out), dtype=torch.float32, device=u.device)
+        pdcs_mlp_forward(self.handle, u.data_ptr(), out.data_ptr(), u.shape[0],
+                         torch.cuda.current_stream().cuda_stream)
+        return out
+
+    def train_step(self, u, t, lr):
+        import torch
+
+        return pdcs_mlp_train_step(self.handle, u.data_ptr(), t.data_ptr(), u.shape[0], lr,
+                                   torch.cuda.current_stream().cuda_stream)
+
+    def gradients(self, u, t):
+        import torch
+
+        g = torch.empty(pdcs_mlp_num_params(self.handle), dtype=torch.float32, device=u.device)
+        loss = pdcs_mlp_gradients(self.handle, u.data_ptr(), t.data_ptr(), u.shape[0], g.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+        return loss, g
+
+    @property
+    def params(self):
+        return pdcs_mlp_get_params(self.handle)
+
+    @params.setter
+    def params(self, p):
+        pdcs_mlp_set_params(self.handle, p)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pdcs_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -78,6 +78,18 @@ struct Tiles {
   int32_t nblk;
 };
 
+// Row-block schedule of a CSR-like pass (one workgroup per block): either a
+// single row of any length, or several consecutive rows holding at most
+// kRowBlockCap nonzeros, which are staged as products in LDS.
+constexpr int kRowBlockCap = 2048;
+struct RowBlocks {
+  const int32_t* blk_row0;     // first row of the block
+  const int32_t* blk_row1;     // one past the last row
+  const int32_t* blk_inst;     // instance (or panel) of the block
+  const int32_t* inst_blk0;    // per instance: first block (B+1 entries)
+  int32_t nblk;
+};
+
 // Schedule of an elementwise pass: contiguous element ranges per workgroup.
 struct Ranges {
   const int32_t* blk_start;
@@ -149,8 +161,22 @@ __device__ __forceinline__ void reduce_records(const double* rec, int b0, int b1
                                                double (&res)[NV]) {
   double acc[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = (i < NS) ? 0.0 : 0.0;
-  for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) {
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  // four records per step: independent loads in flight before they are combined
+  constexpr int U = NV <= 8 ? 4 : 1;
+  int b = b0 + (int)threadIdx.x;
+  for (; b + (U - 1) * kBlock < b1; b += U * kBlock) {
+    double v[U][NV];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[u][i] = rec[(size_t)(b + u * kBlock) * NV + i];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] = (i < NS) ? acc[i] + v[u][i] : fmax(acc[i], v[u][i]);
+  }
+  for (; b < b1; b += kBlock) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double v = rec[(size_t)b * NV + i];
@@ -193,6 +219,142 @@ __device__ __forceinline__ double row_dot(const int32_t* __restrict__ col, const
   }
   for (; p < p1; p += L) s += (double)val[p] * (double)x[col[p]];
   return s;
+}
+
+// As row_dot, but the matrix stream (indices and values, read once per pass)
+// uses non-temporal loads so that it does not evict the gathered vector from L2.
+template <typename TM, typename TV>
+__device__ __forceinline__ double row_dot_stream(const int32_t* __restrict__ col, const TM* __restrict__ val,
+                                                 const TV* __restrict__ x, int p0, int p1, int li, int L) {
+  double s = 0.0;
+  int p = p0 + li;
+  for (; p + 3 * L < p1; p += 4 * L) {
+    const int c0 = __builtin_nontemporal_load(col + p);
+    const int c1 = __builtin_nontemporal_load(col + p + L);
+    const int c2 = __builtin_nontemporal_load(col + p + 2 * L);
+    const int c3 = __builtin_nontemporal_load(col + p + 3 * L);
+    const double v0 = (double)__builtin_nontemporal_load(val + p);
+    const double v1 = (double)__builtin_nontemporal_load(val + p + L);
+    const double v2 = (double)__builtin_nontemporal_load(val + p + 2 * L);
+    const double v3 = (double)__builtin_nontemporal_load(val + p + 3 * L);
+    const double x0 = (double)x[c0], x1 = (double)x[c1], x2 = (double)x[c2], x3 = (double)x[c3];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; p < p1; p += L)
+    s += (double)__builtin_nontemporal_load(val + p) * (double)x[__builtin_nontemporal_load(col + p)];
+  return s;
+}
+
+// Products of one row block with NV gathered vectors, reduced per row; fn(r, s)
+// is called exactly once per row r of the block, by one thread, with s[k] the
+// row's dot product with xs[k] (FP64 accumulation).  lds: NV * kRowBlockCap
+// doubles plus kWavesPerBlock * NV doubles.  Every thread of the workgroup must
+// call this (it synchronizes).
+template <int NV, typename TM, typename TV, class Fn>
+__device__ __forceinline__ void block_rows(int r0, int r1, const int32_t* __restrict__ ptr,
+                                           const int32_t* __restrict__ idx, const TM* __restrict__ val,
+                                           const TV* const (&xs)[NV], double* lds, Fn&& fn) {
+  const int tid = threadIdx.x;
+  const int R = r1 - r0;
+  const int q0 = ptr[r0], q1 = ptr[r1];
+  if (R == 1) {
+    // one row of any length: register accumulation, unrolled streaming loads
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    int q = q0 + tid;
+    for (; q + 3 * kBlock < q1; q += 4 * kBlock) {
+      int c[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = __builtin_nontemporal_load(idx + q + u * kBlock);
+        v[u] = (double)__builtin_nontemporal_load(val + q + u * kBlock);
+      }
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[k] += v[u] * (double)xs[k][c[u]];
+    }
+    for (; q < q1; q += kBlock) {
+      const int c = __builtin_nontemporal_load(idx + q);
+      const double v = (double)__builtin_nontemporal_load(val + q);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] += v * (double)xs[k][c];
+    }
+    double* red = lds + NV * kRowBlockCap;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double w = wave_sum(s[k]);
+      if (lane == 0) red[wave * NV + k] = w;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        t[k] = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) t[k] += red[w * NV + k];
+      }
+      fn(r0, t);
+    }
+    return;
+  }
+  // several rows, at most kRowBlockCap nonzeros: stage the products in LDS
+  const int n = q1 - q0;
+  for (int i0 = 0; i0 < n; i0 += 4 * kBlock) {
+    int c[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * kBlock + tid;
+      c[u] = i < n ? __builtin_nontemporal_load(idx + q0 + i) : 0;
+      v[u] = i < n ? (double)__builtin_nontemporal_load(val + q0 + i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * kBlock + tid;
+      if (i < n) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * kRowBlockCap + i] = v[u] * (double)xs[k][c[u]];
+      }
+    }
+  }
+  __syncthreads();
+  if (R <= kBlock) {
+    int T = 64;
+    while (T > 1 && T * R > kBlock) T >>= 1;
+    const int g = tid / T, li = tid & (T - 1);
+    const int r = r0 + g;
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    if (g < R) {
+      const int a = ptr[r] - q0, e = ptr[r + 1] - q0;
+      for (int i = a + li; i < e; i += T)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] += lds[k * kRowBlockCap + i];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      for (int off = T >> 1; off > 0; off >>= 1) s[k] += __shfl_xor(s[k], off, kWave);
+    if (li == 0 && g < R) fn(r, s);
+  } else {
+    for (int r = r0 + tid; r < r1; r += kBlock) {
+      const int a = ptr[r] - q0, e = ptr[r + 1] - q0;
+      double s[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] = 0.0;
+      for (int i = a; i < e; ++i)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] += lds[k * kRowBlockCap + i];
+      fn(r, s);
+    }
+  }
 }
 
 // Sum over the L-lane groups of a wavefront (L a power of two <= 64).

@@ -64,9 +64,19 @@ struct Schedule {
 struct TileSet {
   DBuf row0, row1, lg, btile0, btile1, binst_d, iblk0_d;
   int nblk = 0, ntiles = 0;
-  std::vector<int32_t> h_bt0, h_bt1, h_t0, h_t1;
+  std::vector<int32_t> h_bt0, h_bt1, h_t0, h_t1, h_binst;
   void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s);
   Tiles view() const;
+};
+
+// Row blocks: a single row of any length, or consecutive rows with at most
+// kRowBlockCap nonzeros whose per-row reduction needs at most red_max passes.
+struct RowBlockSet {
+  DBuf r0, r1, binst_d, iblk0_d;
+  int nblk = 0;
+  std::vector<int32_t> h_binst;
+  void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max);
+  RowBlocks view() const;
 };
 
 struct RangeSet {
@@ -74,6 +84,23 @@ struct RangeSet {
   int nblk = 0;
   void build(const std::vector<int64_t>& inst_off, int per_block);
   Ranges view() const;
+};
+
+// Panel-major copy of a CSR-like structure whose gathered index range is split
+// into P panels: virtual row v = p * R + r holds the entries of row r whose
+// gathered index falls in panel p.  Used for single large instances so that
+// the gathered slice of each panel fits in one XCD's L2.
+struct PanelSet {
+  int P = 1;
+  int64_t R = 0;
+  std::vector<int32_t> h_ptr;
+  DBuf d_ptr, d_idx, d_val, val64, val32, part32, part64, part64b, slot;
+  int nslot = 0;
+  TileSet tiles;        // set-up passes
+  RowBlockSet blocks;   // iteration passes
+  void build(int P, int64_t R, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx,
+             const std::vector<double>& val, const Schedule& s);
+  void build_slots();
 };
 
 template <typename T>
@@ -109,7 +136,13 @@ struct Engine {
   IterBufs<double> it64;
   Schedule sched;
   TileSet trow, tcol;
+  RowBlockSet brow, bcol;
   RangeSet vrow, vcol;
+  PanelSet prow, pcol;         // panel-major G (gathers x) and G^T (gathers y) when split
+  std::vector<int32_t> h_ci, h_ri;
+  std::vector<double> h_v, h_vt;
+  DBuf rec_dual_epi, rec_lam_epi;
+  int panels_x = 0, panels_y = 0;   // 0: automatic
   hipStream_t stream = nullptr;
   std::map<int64_t, hipGraphExec_t> graphs;
   std::vector<hipEvent_t> events;

@@ -203,6 +203,7 @@ void TileSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>&
   h_bt1 = bt1;
   h_t0 = t0;
   h_t1 = t1;
+  h_binst = binst;
   upload(row0, t0);
   upload(row1, t1);
   upload(lg, tlg);
@@ -223,6 +224,74 @@ Tiles TileSet::view() const {
   t.inst_blk0 = iblk0_d.as<int32_t>();
   t.nblk = nblk;
   return t;
+}
+
+static int threads_per_row(int R) {
+  int T = 64;
+  while (T > 1 && T * R > 256) T >>= 1;
+  return T;
+}
+
+void RowBlockSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max) {
+  std::vector<int32_t> a, e, bi, iblk0;
+  const int B = (int)inst_r0.size() - 1;
+  const int64_t cap = kRowBlockCap;
+  iblk0.push_back(0);
+  for (int b = 0; b < B; ++b) {
+    int64_t r = inst_r0[b];
+    const int64_t end = inst_r0[b + 1];
+    while (r < end) {
+      const int64_t len0 = ptr[r + 1] - ptr[r];
+      if (len0 > cap) {
+        a.push_back((int32_t)r);
+        e.push_back((int32_t)(r + 1));
+        bi.push_back(b);
+        ++r;
+        continue;
+      }
+      const int64_t start = r;
+      int64_t nnz = 0, maxlen = 0;
+      int R = 0;
+      while (r < end && R < 4096) {
+        const int64_t len = ptr[r + 1] - ptr[r];
+        if (len > cap || nnz + len > cap) break;
+        const int nR = R + 1;
+        const int64_t nmax = std::max(maxlen, len);
+        int64_t cost;
+        if (nR <= 256) {
+          const int T = threads_per_row(nR);
+          cost = (nmax + T - 1) / T;
+        } else {
+          cost = ((nR + 255) / 256) * nmax;
+        }
+        if (nR > 1 && cost > red_max) break;
+        R = nR;
+        nnz += len;
+        maxlen = nmax;
+        ++r;
+      }
+      a.push_back((int32_t)start);
+      e.push_back((int32_t)r);
+      bi.push_back(b);
+    }
+    iblk0.push_back((int32_t)a.size());
+  }
+  nblk = (int)a.size();
+  h_binst = bi;
+  upload(r0, a);
+  upload(r1, e);
+  upload(binst_d, bi);
+  upload(iblk0_d, iblk0);
+}
+
+RowBlocks RowBlockSet::view() const {
+  RowBlocks r;
+  r.blk_row0 = r0.as<int32_t>();
+  r.blk_row1 = r1.as<int32_t>();
+  r.blk_inst = binst_d.as<int32_t>();
+  r.inst_blk0 = iblk0_d.as<int32_t>();
+  r.nblk = nblk;
+  return r;
 }
 
 void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block) {
@@ -252,6 +321,76 @@ Ranges RangeSet::view() const {
   r.inst_blk0 = iblk0_d.as<int32_t>();
   r.nblk = nblk;
   return r;
+}
+
+// ---------------------------------------------------------------------------
+// Panel split
+// ---------------------------------------------------------------------------
+void PanelSet::build(int P_, int64_t R_, int64_t G, const std::vector<int32_t>& ptr,
+                     const std::vector<int32_t>& idx, const std::vector<double>& val, const Schedule& s) {
+  P = P_;
+  R = R_;
+  const int64_t nnz = ptr[R];
+  if ((int64_t)P * R >= INT32_MAX) throw Error(PDCS_ERR_SIZE, "panel split too large");
+  const int64_t width = (G + P - 1) / P;
+  h_ptr.assign((size_t)P * R + 1, 0);
+  // counts per (panel, row)
+  for (int64_t r = 0; r < R; ++r)
+    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) h_ptr[(size_t)(idx[q] / width) * R + r + 1]++;
+  for (size_t v = 0; v < (size_t)P * R; ++v) h_ptr[v + 1] += h_ptr[v];
+  std::vector<int32_t> pidx(nnz);
+  std::vector<double> pval(nnz);
+  std::vector<int32_t> fill(h_ptr.begin(), h_ptr.end() - 1);
+  for (int64_t r = 0; r < R; ++r)
+    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
+      const int32_t dst = fill[(size_t)(idx[q] / width) * R + r]++;
+      pidx[dst] = idx[q];
+      pval[dst] = val[q];
+    }
+  upload(d_ptr, h_ptr);
+  upload(d_idx, pidx);
+  upload(d_val, pval);
+  val64.alloc((size_t)nnz * 8);
+  val32.alloc((size_t)nnz * 4);
+  part32.alloc((size_t)P * R * 4);
+  part64.alloc((size_t)P * R * 8);
+  part64b.alloc((size_t)P * R * 8);
+  std::vector<int64_t> vr0(P + 1);
+  for (int p = 0; p <= P; ++p) vr0[p] = (int64_t)p * R;
+  tiles.build(h_ptr, vr0, s);
+  blocks.build(h_ptr, vr0, s.iter_max * 4);
+  build_slots();
+}
+
+// Launch slot s runs on XCD s % 8 (workgroups are dispatched to the XCDs in
+// round-robin order).  Panel p is served by the XCDs x with x % P == p, which
+// take its workgroups in interleaved order; slots without work hold -1.
+void PanelSet::build_slots() {
+  const int nx = 8;
+  const int share = nx / P;
+  std::vector<std::vector<int32_t>> per_xcd(nx);
+  std::vector<int> seen(P, 0);
+  for (int b = 0; b < blocks.nblk; ++b) {
+    const int p = blocks.h_binst[b];
+    const int k = seen[p]++;
+    per_xcd[p + P * (k % share)].push_back(b);
+  }
+  size_t S = 0;
+  for (auto& l : per_xcd) S = std::max(S, l.size());
+  std::vector<int32_t> sl(S * nx, -1);
+  for (size_t k = 0; k < S; ++k)
+    for (int x = 0; x < nx; ++x)
+      if (k < per_xcd[x].size()) sl[k * nx + x] = per_xcd[x][k];
+  nslot = (int)sl.size();
+  upload(slot, sl);
+}
+
+static int auto_panels(int64_t gathered) {
+  // about 1 MiB of FP32 gathered values per panel, at most 8 (one per XCD)
+  const int64_t per = 256 * 1024;
+  int P = 1;
+  while (P < 8 && gathered > per * P) P *= 2;
+  return P;
 }
 
 // ---------------------------------------------------------------------------
@@ -306,6 +445,12 @@ Engine::Engine(const std::vector<const HostProblem*>& probs) {
   }
   h_rp[M] = (int32_t)NNZ;
   h_cp[N] = (int32_t)NNZ;
+  if (B == 1) {  // kept for the panel split of single large instances
+    h_ci = ci;
+    h_ri = ri;
+    h_v = v;
+    h_vt = vt;
+  }
   upload(d_rp, h_rp);
   upload(d_ci, ci);
   upload(d_v, v);
@@ -344,9 +489,21 @@ void Engine::build_schedule() {
   clear_graphs();
   trow.build(h_rp, row0, sched);
   tcol.build(h_cp, col0, sched);
+  brow.build(h_rp, row0, sched.iter_max * 4);
+  bcol.build(h_cp, col0, sched.iter_max * 4);
   vrow.build(row0, sched.vec_per_block);
   vcol.build(col0, sched.vec_per_block);
-  const int nr = std::max(trow.nblk, 1), nc = std::max(tcol.nblk, 1);
+  int P1 = 1, P2 = 1;
+  if (B == 1) {
+    P1 = panels_x > 0 ? panels_x : auto_panels(N);
+    P2 = panels_y > 0 ? panels_y : auto_panels(M);
+  }
+  prow.P = pcol.P = 1;
+  if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
+  if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
+  rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
+  rec_lam_epi.alloc((size_t)std::max(vcol.nblk, 1) * 3 * 8);
+  const int nr = std::max(brow.nblk, 1), nc = std::max(bcol.nblk, 1);
   const int vr = std::max(vrow.nblk, 1), vc = std::max(vcol.nblk, 1);
   rec_primal.alloc((size_t)vc * 2 * 8);
   rec_dual.alloc((size_t)nr * 4 * 8);
@@ -357,7 +514,7 @@ void Engine::build_schedule() {
   rec_probe_r.alloc((size_t)vr * 2 * 32 * 8);
   rec_nc.alloc((size_t)vc * 3 * 8);
   rec_nr.alloc((size_t)vr * 3 * 8);
-  rec_nm.alloc((size_t)nr * 8);
+  rec_nm.alloc((size_t)std::max(trow.nblk, 1) * 8);
 }
 
 void Engine::ensure_iter(int prec) {
@@ -372,6 +529,8 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.N = N;
   k.trow = trow.view();
   k.tcol = tcol.view();
+  k.brow = brow.view();
+  k.bcol = bcol.view();
   k.vrow = vrow.view();
   k.vcol = vcol.view();
   k.inst = d_inst.as<Inst>();
@@ -400,6 +559,32 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.rec_probe_c = rec_probe_c.as<double>();
   k.rec_probe_r = rec_probe_r.as<double>();
   k.probe_passes = probe_passes;
+  k.P1 = prow.P;
+  k.P2 = pcol.P;
+  k.rec_dual_epi = rec_dual_epi.as<double>();
+  k.rec_lam_epi = rec_lam_epi.as<double>();
+  if (prow.P > 1) {
+    k.prow = prow.tiles.view();
+    k.bprow = prow.blocks.view();
+    k.slot1 = prow.slot.as<int32_t>();
+    k.nslot1 = prow.nslot;
+    k.PA32 = MatPtrs<float>{prow.d_ptr.as<int32_t>(), prow.d_idx.as<int32_t>(), prow.val32.as<float>()};
+    k.PA64 = MatPtrs<double>{prow.d_ptr.as<int32_t>(), prow.d_idx.as<int32_t>(), prow.val64.as<double>()};
+    k.part32 = prow.part32.as<float>();
+    k.part64 = prow.part64.as<double>();
+    k.part64b = prow.part64b.as<double>();
+  }
+  if (pcol.P > 1) {
+    k.pcol = pcol.tiles.view();
+    k.bpcol = pcol.blocks.view();
+    k.slot2 = pcol.slot.as<int32_t>();
+    k.nslot2 = pcol.nslot;
+    k.PAT32 = MatPtrs<float>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.val32.as<float>()};
+    k.PAT64 = MatPtrs<double>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.val64.as<double>()};
+    k.partT32 = pcol.part32.as<float>();
+    k.partT64 = pcol.part64.as<double>();
+    k.partT64b = pcol.part64b.as<double>();
+  }
   return k;
 }
 
@@ -543,6 +728,16 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
   su.rec_nm = rec_nm.as<double>();
   su.x0 = dx0;
   su.y0 = dy0;
+  if (prow.P > 1) {
+    su.PA = MatPtrs<double>{prow.d_ptr.as<int32_t>(), prow.d_idx.as<int32_t>(), prow.d_val.as<double>()};
+    su.pval64 = prow.val64.as<double>();
+    su.pval32 = prow.val32.as<float>();
+  }
+  if (pcol.P > 1) {
+    su.PAT = MatPtrs<double>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.d_val.as<double>()};
+    su.pvalT64 = pcol.val64.as<double>();
+    su.pvalT32 = pcol.val32.as<float>();
+  }
   launch_setup(k, su, stream, start_mask);
   HIP_OK(hipGetLastError());
 
@@ -553,17 +748,21 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
   ev_used = 0;
   launch_summary(k, stream, d_summary.as<int32_t>());
   int64_t chunks = 0;
+  auto last_print = std::chrono::steady_clock::now();
   while (true) {
     HIP_OK(hipMemcpyAsync(h_summary, d_summary.p, 8, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     if (timed) harvest_events();
     const int a32 = h_summary[0], a64 = h_summary[1];
-    if (o.verbose && chunks > 0) {
+    const double since = std::chrono::duration<double>(std::chrono::steady_clock::now() - last_print).count();
+    if (o.verbose && chunks > 0 && (since >= 2.0 || o.verbose > 1)) {
+      last_print = std::chrono::steady_clock::now();
       Inst I0;
       HIP_OK(hipMemcpy(&I0, d_inst.p, sizeof(Inst), hipMemcpyDeviceToHost));
       std::fprintf(stderr,
-                   "[pdcs] kbar %lld restarts %lld omega %.3e eta %.3e rel(p,d,g) %.2e %.2e %.2e prec %s "
+                   "[pdcs] %.1fs kbar %lld restarts %lld omega %.3e eta %.3e rel(p,d,g) %.2e %.2e %.2e prec %s "
                    "active %d\n",
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(),
                    (long long)I0.kbar, (long long)I0.restarts, I0.omega, I0.eta_hat, I0.rel_p, I0.rel_d,
                    I0.rel_gap, I0.precision == kFP32 ? "fp32" : "fp64", a32 + a64);
     }
@@ -823,13 +1022,25 @@ int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, cons
       upload(e.origT32, at);
     }
     if (!transpose) {
-      launch_spmv_plain(e.trow.view(), f32 ? kFP32 : kFP64, e.d_rp.as<int32_t>(), e.d_ci.as<int32_t>(),
+      launch_spmv_plain(e.brow.view(), f32 ? kFP32 : kFP64, e.d_rp.as<int32_t>(), e.d_ci.as<int32_t>(),
                         f32 ? e.orig32.p : e.d_v.p, in_dev, out_dev, s);
     } else {
-      launch_spmv_plain(e.tcol.view(), f32 ? kFP32 : kFP64, e.d_cp.as<int32_t>(), e.d_ri.as<int32_t>(),
+      launch_spmv_plain(e.bcol.view(), f32 ? kFP32 : kFP64, e.d_cp.as<int32_t>(), e.d_ri.as<int32_t>(),
                         f32 ? e.origT32.p : e.d_vt.p, in_dev, out_dev, s);
     }
     HIP_OK(hipGetLastError());
+    return PDCS_OK;
+  });
+}
+
+int pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py) {
+  return guarded([&]() {
+    if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
+    auto ok = [](int64_t v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
+    if (!ok(px) || !ok(py)) throw Error(PDCS_ERR_INVALID_ARG, "panels must be 0, 1, 2, 4 or 8");
+    p->eng->panels_x = (int)px;
+    p->eng->panels_y = (int)py;
+    p->eng->build_schedule();
     return PDCS_OK;
   });
 }

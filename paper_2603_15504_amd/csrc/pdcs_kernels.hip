@@ -68,73 +68,173 @@ __global__ __launch_bounds__(kBlock) void k_primal(Ranges R, IterPtrs<T> it, Dat
 
 // K1: CSR SpMV G x_hat with the fused dual step.  Record: ||dy||^2,
 // dy^T G dx, ||(G x_hat - h) - Proj_Kd*(.)||^2, h^T y_hat.
+template <typename T>
+struct DualEpilogue {
+  IterPtrs<T> it;
+  DataPtrs<T> d;
+  bool commit, avg;
+  double ca, cb, beta, etak, sigma;
+  int mz_end;
+  __device__ __forceinline__ void operator()(int r, double s, double (&acc)[4]) const {
+    double y = (double)it.y[r];
+    double gx = (double)it.gx[r];
+    if (commit) {
+      const double yh = (double)it.yh[r];
+      const double gh = (double)it.gxh[r];
+      y = (double)(T)(ca * ((1.0 + beta) * yh - beta * y) + cb * (double)it.ya[r]);
+      gx = (double)(T)(ca * ((1.0 + beta) * gh - beta * gx) + cb * (double)it.gxa[r]);
+      it.y[r] = (T)y;
+      it.gx[r] = (T)gx;
+      if (avg) it.sy[r] = (T)((double)it.sy[r] + etak * yh);
+    }
+    const double hv = (double)d.h[r];
+    const double gxn = (double)(T)s;
+    const double v = y + sigma * (hv - 2.0 * gxn + gx);
+    const bool zero_row = r < mz_end;
+    const double yn = (double)(T)(zero_row ? v : fmax(v, 0.0));
+    it.yh[r] = (T)yn;
+    it.gxh[r] = (T)gxn;
+    const double dy = yn - y;
+    acc[0] += dy * dy;
+    acc[1] += dy * (gxn - gx);
+    const double res = gxn - hv;
+    const double pr = zero_row ? res : fmin(res, 0.0);
+    acc[2] += pr * pr;
+    acc[3] += hv * yn;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ DualEpilogue<T> make_dual_epilogue(const Inst& I, const IterPtrs<T>& it,
+                                                              const DataPtrs<T>& d) {
+  DualEpilogue<T> e;
+  e.it = it;
+  e.d = d;
+  e.commit = I.pending != 0;
+  e.avg = I.use_avg != 0;
+  e.ca = I.ca;
+  e.cb = I.cb;
+  e.beta = I.beta;
+  e.etak = I.eta_k;
+  e.sigma = I.eta * I.omega;
+  e.mz_end = I.row0 + I.m_zero;
+  return e;
+}
+
+template <typename T>
+__device__ __forceinline__ void lam_epilogue(int j, double s, const IterPtrs<T>& it, const DataPtrs<T>& d,
+                                             double (&acc)[3]) {
+  const double g = (double)(T)s;
+  it.gtyh[j] = (T)g;
+  const double lam = (double)d.c[j] - g;
+  const double lo = (double)d.l[j], hi = (double)d.u[j];
+  const bool lf = isfinite(lo), uf = isfinite(hi);
+  double res;
+  if (!lf && !uf) res = lam;
+  else if (!lf) res = fmax(lam, 0.0);
+  else if (!uf) res = fmin(lam, 0.0);
+  else res = 0.0;
+  acc[0] += res * res;
+  if (lf) acc[1] += lo * fmax(lam, 0.0);
+  if (uf) acc[2] += hi * fmax(-lam, 0.0);
+}
+
 template <typename T, typename TM>
-__global__ __launch_bounds__(kBlock) void k_dual(Tiles tl, MatPtrs<TM> A, IterPtrs<T> it,
+__global__ __launch_bounds__(kBlock) void k_dual(RowBlocks rb, MatPtrs<TM> A, IterPtrs<T> it,
                                                  DataPtrs<T> d, Inst* __restrict__ inst, int prec,
                                                  double* __restrict__ rec) {
+  __shared__ double lds[kRowBlockCap + kWavesPerBlock * 4];
+  const int b = blockIdx.x;
+  const Inst& I = inst[rb.blk_inst[b]];
+  if (I.status != kActive || I.precision != prec) return;
+  const DualEpilogue<T> epi = make_dual_epilogue(I, it, d);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const T* const xs[1] = {it.xh};
+  block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
+                [&](int r, const double* s) { epi(r, s[0], acc); });
+  __syncthreads();
+  block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
+}
+
+// ---------------------------------------------------------------------------
+// Column-panel SpMV for large instances.  The gathered index range is split
+// into P panels stored panel-major ("virtual rows" v = p * R + r), and the
+// slot table routes panel p's workgroups to the XCDs with blockIdx % 8 = p
+// (mod P), so that each XCD's L2 holds only its slice of the gathered vector.
+// Partial sums part[v] are combined, in panel order, by the epilogue passes.
+// ---------------------------------------------------------------------------
+// Split mode serves a single instance: inst[0] says whether this pass is needed
+// (need_acc: only after an accepted trial).
+template <typename T, typename TM>
+__global__ __launch_bounds__(kBlock) void k_spmv_part(RowBlocks rb, const int32_t* __restrict__ slot,
+                                                      MatPtrs<TM> A, const T* __restrict__ x,
+                                                      T* __restrict__ part, const Inst* __restrict__ inst,
+                                                      int need_acc) {
+  __shared__ double lds[kRowBlockCap + kWavesPerBlock];
+  const int b = slot[blockIdx.x];
+  if (b < 0) return;
+  if (inst[0].status != kActive || (need_acc && inst[0].last_acc == 0)) return;
+  const T* const xs[1] = {x};
+  block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
+                [&](int r, const double* s) { part[r] = (T)s[0]; });
+}
+
+// K1b: combine the P partial sums of G x_hat per row, then the dual step
+// (same epilogue and record as k_dual).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restrict__ part, int P,
+                                                     int64_t M, IterPtrs<T> it, DataPtrs<T> d,
+                                                     Inst* __restrict__ inst, int prec,
+                                                     double* __restrict__ rec) {
   __shared__ double lds[kWavesPerBlock * 4];
   const int b = blockIdx.x;
-  const Inst& I = inst[tl.blk_inst[b]];
+  const Inst& I = inst[R.blk_inst[b]];
   if (I.status != kActive || I.precision != prec) return;
-  const bool commit = I.pending != 0;
-  const bool avg = I.use_avg != 0;
-  const double ca = I.ca, cb = I.cb, beta = I.beta, etak = I.eta_k;
-  const double sigma = I.eta * I.omega;
-  const int mz_end = I.row0 + I.m_zero;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const DualEpilogue<T> epi = make_dual_epilogue(I, it, d);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int t1 = tl.blk_tile1[b];
-  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
-    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
-    const int L = 1 << lg;
-    const int r = r0 + (lane >> lg);
-    const int li = lane & (L - 1);
+  const int r1 = R.blk_end[b];
+  for (int r = R.blk_start[b] + (int)threadIdx.x; r < r1; r += kBlock) {
     double s = 0.0;
-    if (r < r1) s = row_dot(A.idx, A.val, it.xh, A.ptr[r], A.ptr[r + 1], li, L);
-    s = group_sum(s, L);
-    if (li == 0 && r < r1) {
-      double y = (double)it.y[r];
-      double gx = (double)it.gx[r];
-      if (commit) {
-        const double yh = (double)it.yh[r];
-        const double gh = (double)it.gxh[r];
-        y = (double)(T)(ca * ((1.0 + beta) * yh - beta * y) + cb * (double)it.ya[r]);
-        gx = (double)(T)(ca * ((1.0 + beta) * gh - beta * gx) + cb * (double)it.gxa[r]);
-        it.y[r] = (T)y;
-        it.gx[r] = (T)gx;
-        if (avg) it.sy[r] = (T)((double)it.sy[r] + etak * yh);
-      }
-      const double hv = (double)d.h[r];
-      const double gxn = (double)(T)s;
-      const double v = y + sigma * (hv - 2.0 * gxn + gx);
-      const bool zero_row = r < mz_end;
-      const double yn = (double)(T)(zero_row ? v : fmax(v, 0.0));
-      it.yh[r] = (T)yn;
-      it.gxh[r] = (T)gxn;
-      const double dy = yn - y;
-      acc[0] += dy * dy;
-      acc[1] += dy * (gxn - gx);
-      const double res = gxn - hv;
-      const double pr = zero_row ? res : fmin(res, 0.0);
-      acc[2] += pr * pr;
-      acc[3] += hv * yn;
-    }
+    for (int p = 0; p < P; ++p) s += (double)part[(size_t)p * M + r];
+    epi(r, s, acc);
   }
   block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
 }
 
+// K2b: combine the P partial sums of G^T y_hat per column, then the dual-slack
+// epilogue (same record as k_lam).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lam_epi(Ranges R, const T* __restrict__ part, int P,
+                                                    int64_t N, IterPtrs<T> it, DataPtrs<T> d,
+                                                    Inst* __restrict__ inst, int prec,
+                                                    double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (I.status != kActive || I.precision != prec || I.last_acc == 0) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += (double)part[(size_t)p * N + j];
+    lam_epilogue<T>(j, s, it, d, acc);
+  }
+  block_sum_store<3>(acc, lds, rec + (size_t)b * 3);
+}
+
 // F1: line-search decision of Function 2, one workgroup per instance.
-__global__ __launch_bounds__(kBlock) void k_fin_ls(Ranges rc, const double* __restrict__ rec_p,
-                                                   Tiles tr, const double* __restrict__ rec_d,
+__global__ __launch_bounds__(kBlock) void k_fin_ls(const int32_t* __restrict__ iblk_p,
+                                                   const double* __restrict__ rec_p,
+                                                   const int32_t* __restrict__ iblk_d,
+                                                   const double* __restrict__ rec_d,
                                                    Inst* __restrict__ inst) {
   __shared__ double lds[kWavesPerBlock * 4];
   const int iid = blockIdx.x;
   Inst& I = inst[iid];
   if (I.status != kActive) return;
   double p[2], q[4];
-  reduce_records<2, 2>(rec_p, rc.inst_blk0[iid], rc.inst_blk0[iid + 1], lds, p);
-  reduce_records<4, 4>(rec_d, tr.inst_blk0[iid], tr.inst_blk0[iid + 1], lds, q);
+  reduce_records<2, 2>(rec_p, iblk_p[iid], iblk_p[iid + 1], lds, p);
+  reduce_records<4, 4>(rec_d, iblk_d[iid], iblk_d[iid + 1], lds, q);
   if (threadIdx.x != 0) return;
   I.pending = 0;
   I.check_due = 0;
@@ -178,54 +278,32 @@ __global__ __launch_bounds__(kBlock) void k_fin_ls(Ranges rc, const double* __re
 // K2: transposed SpMV G^T y_hat over the columns with the dual-slack epilogue.
 // Record: ||lam - Proj_Lambda lam||^2, sum l lam+, sum u lam- (finite bounds).
 template <typename T, typename TM>
-__global__ __launch_bounds__(kBlock) void k_lam(Tiles tl, MatPtrs<TM> AT, IterPtrs<T> it,
+__global__ __launch_bounds__(kBlock) void k_lam(RowBlocks rb, MatPtrs<TM> AT, IterPtrs<T> it,
                                                 DataPtrs<T> d, Inst* __restrict__ inst, int prec,
                                                 double* __restrict__ rec) {
-  __shared__ double lds[kWavesPerBlock * 3];
+  __shared__ double lds[kRowBlockCap + kWavesPerBlock * 3];
   const int b = blockIdx.x;
-  const Inst& I = inst[tl.blk_inst[b]];
+  const Inst& I = inst[rb.blk_inst[b]];
   if (I.status != kActive || I.precision != prec || I.last_acc == 0) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
   double acc[3] = {0.0, 0.0, 0.0};
-  const int t1 = tl.blk_tile1[b];
-  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
-    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
-    const int L = 1 << lg;
-    const int j = r0 + (lane >> lg);
-    const int li = lane & (L - 1);
-    double s = 0.0;
-    if (j < r1) s = row_dot(AT.idx, AT.val, it.yh, AT.ptr[j], AT.ptr[j + 1], li, L);
-    s = group_sum(s, L);
-    if (li == 0 && j < r1) {
-      const double g = (double)(T)s;
-      it.gtyh[j] = (T)g;
-      const double lam = (double)d.c[j] - g;
-      const double lo = (double)d.l[j], hi = (double)d.u[j];
-      const bool lf = isfinite(lo), uf = isfinite(hi);
-      double res;
-      if (!lf && !uf) res = lam;
-      else if (!lf) res = fmax(lam, 0.0);
-      else if (!uf) res = fmin(lam, 0.0);
-      else res = 0.0;
-      acc[0] += res * res;
-      if (lf) acc[1] += lo * fmax(lam, 0.0);
-      if (uf) acc[2] += hi * fmax(-lam, 0.0);
-    }
-  }
+  const T* const ys[1] = {it.yh};
+  block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], AT.ptr, AT.idx, AT.val, ys, lds,
+                [&](int j, const double* s) { lam_epilogue<T>(j, s[0], it, d, acc); });
+  __syncthreads();
   block_sum_store<3>(acc, lds, rec + (size_t)b * 3);
 }
 
 // F2: reflection parameter at z_hat (eq. adaptive_reflection with the relative
 // errors of eq. tolerance-2), then schedule the Halpern commit.
-__global__ __launch_bounds__(kBlock) void k_fin_beta(Tiles tc, const double* __restrict__ rec_l,
+__global__ __launch_bounds__(kBlock) void k_fin_beta(const int32_t* __restrict__ iblk_l,
+                                                     const double* __restrict__ rec_l,
                                                      Inst* __restrict__ inst) {
   __shared__ double lds[kWavesPerBlock * 3];
   const int iid = blockIdx.x;
   Inst& I = inst[iid];
   if (I.status != kActive || I.last_acc == 0) return;
   double q[3];
-  reduce_records<3, 3>(rec_l, tc.inst_blk0[iid], tc.inst_blk0[iid + 1], lds, q);
+  reduce_records<3, 3>(rec_l, iblk_l[iid], iblk_l[iid + 1], lds, q);
   if (threadIdx.x != 0) return;
   const double errp = sqrt(I.errp2), errd = sqrt(q[0]);
   const double pobj = I.cx;
@@ -300,43 +378,71 @@ __global__ __launch_bounds__(kBlock) void k_commit_avg(Ranges R, T* __restrict__
 // Two products with one matrix pass: out0 = A in0, out1 = A in1 (FP64 values,
 // FP64 output).  in1 may be null.  Selected instances only.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spmv2(Tiles tl, MatPtrs<double> A, const T* __restrict__ in0,
+__global__ __launch_bounds__(kBlock) void k_spmv2(RowBlocks rb, MatPtrs<double> A, const T* __restrict__ in0,
                                                   const T* __restrict__ in1, double* __restrict__ out0,
                                                   double* __restrict__ out1, const Inst* __restrict__ inst,
                                                   int prec, int mode) {
+  __shared__ double lds[2 * kRowBlockCap + kWavesPerBlock * 2];
   const int b = blockIdx.x;
-  const Inst& I = inst[tl.blk_inst[b]];
+  const Inst& I = inst[rb.blk_inst[b]];
   if (!mode_selects(I, mode) || I.precision != prec) return;
   const bool two = (in1 != nullptr) && (mode != kModeCheck || I.use_avg != 0);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int t1 = tl.blk_tile1[b];
-  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
-    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
-    const int L = 1 << lg;
-    const int r = r0 + (lane >> lg);
-    const int li = lane & (L - 1);
-    double s0 = 0.0, s1 = 0.0;
-    if (r < r1) {
-      const int p0 = A.ptr[r], p1 = A.ptr[r + 1];
-      if (two) {
-        for (int p = p0 + li; p < p1; p += L) {
-          const int c = A.idx[p];
-          const double v = A.val[p];
-          s0 += v * (double)in0[c];
-          s1 += v * (double)in1[c];
-        }
-      } else {
-        s0 = row_dot(A.idx, A.val, in0, p0, p1, li, L);
-      }
-    }
-    s0 = group_sum(s0, L);
-    if (two) s1 = group_sum(s1, L);
-    if (li == 0 && r < r1) {
-      out0[r] = s0;
-      if (two) out1[r] = s1;
-    }
+  if (two) {
+    const T* const xs[2] = {in0, in1};
+    block_rows<2>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds, [&](int r, const double* s) {
+      out0[r] = s[0];
+      out1[r] = s[1];
+    });
+  } else {
+    const T* const xs[1] = {in0};
+    block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
+                  [&](int r, const double* s) { out0[r] = s[0]; });
   }
+}
+
+// Split mode: two products with one pass over the panel-major FP64 values,
+// partial sums per panel, then combined in panel order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv2_part(RowBlocks rb, const int32_t* __restrict__ slot,
+                                                       MatPtrs<double> A, const T* __restrict__ in0,
+                                                       const T* __restrict__ in1, double* __restrict__ part0,
+                                                       double* __restrict__ part1, const Inst* __restrict__ inst,
+                                                       int prec, int mode) {
+  __shared__ double lds[2 * kRowBlockCap + kWavesPerBlock * 2];
+  const int b = slot[blockIdx.x];
+  if (b < 0) return;
+  const Inst& I = inst[0];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  const bool two = (in1 != nullptr) && (mode != kModeCheck || I.use_avg != 0);
+  if (two) {
+    const T* const xs[2] = {in0, in1};
+    block_rows<2>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds, [&](int r, const double* s) {
+      part0[r] = s[0];
+      part1[r] = s[1];
+    });
+  } else {
+    const T* const xs[1] = {in0};
+    block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
+                  [&](int r, const double* s) { part0[r] = s[0]; });
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_combine2(int64_t R, int P, const double* __restrict__ part0,
+                                                     const double* __restrict__ part1, double* __restrict__ out0,
+                                                     double* __restrict__ out1, const Inst* __restrict__ inst,
+                                                     int mode) {
+  const Inst& I = inst[0];
+  if (!mode_selects(I, mode)) return;
+  const bool two = part1 != nullptr && (mode != kModeCheck || I.use_avg != 0);
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= R) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int p = 0; p < P; ++p) {
+    s0 += part0[(size_t)p * R + r];
+    if (two) s1 += part1[(size_t)p * R + r];
+  }
+  out0[r] = s0;
+  if (two) out1[r] = s1;
 }
 
 // Candidate reductions over the columns.  Per candidate c (0: PDHG output or
@@ -718,7 +824,9 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
   I.optimal = optimal ? 1 : 0;
   I.switch_fp64 = 0;
   if (!optimal && I.precision == kFP32) {
-    if (!(rmax >= 0.5 * I.best_rel)) {
+    // FP32 storage limits the attainable error only near the tolerance: stalls
+    // are counted once the relative KKT error is within 100x of rel_tol.
+    if (!(rmax >= 0.5 * I.best_rel) || rmax > 100.0 * I.rel_tol) {
       I.best_rel = rmax;
       I.stall = 0;
     } else {
@@ -1051,7 +1159,8 @@ __global__ void k_fill(double* __restrict__ p, double v, int64_t n) {
 __global__ __launch_bounds__(kBlock) void k_scale_vals(Tiles tl, MatPtrs<double> A,
                                                        const double* __restrict__ Drow,
                                                        const double* __restrict__ Dcol, int swap,
-                                                       double* __restrict__ v64, float* __restrict__ v32) {
+                                                       int vmod, double* __restrict__ v64,
+                                                       float* __restrict__ v32) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -1062,11 +1171,12 @@ __global__ __launch_bounds__(kBlock) void k_scale_vals(Tiles tl, MatPtrs<double>
     const int r = r0 + (lane >> lg);
     const int li = lane & (L - 1);
     if (r < r1) {
+      const int rr = vmod > 0 ? r % vmod : r;  // panel-major structures: real row of virtual row r
       const int p1 = A.ptr[r + 1];
       for (int p = A.ptr[r] + li; p < p1; p += L) {
         const int c = A.idx[p];
-        const double di = swap ? Drow[c] : Drow[r];
-        const double dj = swap ? Dcol[r] : Dcol[c];
+        const double di = swap ? Drow[c] : Drow[rr];
+        const double dj = swap ? Dcol[rr] : Dcol[c];
         const double e = (di * A.val[p]) * dj;
         v64[p] = e;
         v32[p] = (float)e;
@@ -1236,22 +1346,13 @@ __global__ void k_set_products(T* __restrict__ g, T* __restrict__ ga, T* __restr
 
 // Plain product out = A in (unscaled or scaled values) for the public SpMV call.
 template <typename T, typename TM>
-__global__ __launch_bounds__(kBlock) void k_spmv_plain(Tiles tl, MatPtrs<TM> A, const T* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_spmv_plain(RowBlocks rb, MatPtrs<TM> A, const T* __restrict__ in,
                                                        T* __restrict__ out) {
+  __shared__ double lds[kRowBlockCap + kWavesPerBlock];
   const int b = blockIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int t1 = tl.blk_tile1[b];
-  for (int t = tl.blk_tile0[b] + wave; t < t1; t += kWavesPerBlock) {
-    const int r0 = tl.tile_row0[t], r1 = tl.tile_row1[t], lg = tl.tile_lg[t];
-    const int L = 1 << lg;
-    const int r = r0 + (lane >> lg);
-    const int li = lane & (L - 1);
-    double s = 0.0;
-    if (r < r1) s = row_dot(A.idx, A.val, in, A.ptr[r], A.ptr[r + 1], li, L);
-    s = group_sum(s, L);
-    if (li == 0 && r < r1) out[r] = (T)s;
-  }
+  const T* const xs[1] = {in};
+  block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
+                [&](int r, const double* s) { out[r] = (T)s[0]; });
 }
 
 // ===========================================================================
@@ -1268,12 +1369,39 @@ static void launch_primal_t(const KernelCtx& k, hipStream_t s, int prec, const I
 
 template <typename T>
 static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
-                          const DataPtrs<T>& d, const MatPtrs<T>& A) {
-  if (k.trow.nblk > 0)
-    k_dual<T, T><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, A, it, d, k.inst, prec, k.rec_dual);
+                          const DataPtrs<T>& d, const MatPtrs<T>& A, const MatPtrs<T>& PA, T* part) {
+  if (k.P1 > 1) {
+    if (k.nslot1 > 0)
+      k_spmv_part<T, T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, PA, it.xh, part, k.inst, 0);
+  } else if (k.brow.nblk > 0) {
+    k_dual<T, T><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, A, it, d, k.inst, prec, k.rec_dual);
+  }
 }
 
-// part 0: primal pass; part 1: SpMV with the dual step; part 2: the rest.
+template <typename T>
+static void launch_dual_epi_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
+                              const DataPtrs<T>& d, const T* part) {
+  if (k.P1 > 1 && k.vrow.nblk > 0)
+    k_dual_epi<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, part, k.P1, k.M, it, d, k.inst, prec,
+                                                         k.rec_dual_epi);
+}
+
+template <typename T>
+static void launch_lam_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
+                         const DataPtrs<T>& d, const MatPtrs<T>& AT, const MatPtrs<T>& PAT, T* part) {
+  if (k.P2 > 1) {
+    if (k.nslot2 > 0)
+      k_spmv_part<T, T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, PAT, it.yh, part, k.inst, 1);
+    if (k.vcol.nblk > 0)
+      k_lam_epi<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, part, k.P2, k.N, it, d, k.inst, prec,
+                                                          k.rec_lam_epi);
+  } else if (k.bcol.nblk > 0) {
+    k_lam<T, T><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, AT, it, d, k.inst, prec, k.rec_lam);
+  }
+}
+
+// part 0: primal pass; part 1: the SpMV G x_hat (fused with the dual step
+// unless the instance is split into panels); part 2: the rest of the trial.
 void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
   if (part == 0) {
     if (mask & 1) launch_primal_t<float>(k, s, kFP32, k.it32, k.d32);
@@ -1281,18 +1409,20 @@ void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
     return;
   }
   if (part == 1) {
-    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32);
-    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64);
+    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, k.part32);
+    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, k.part64);
     return;
   }
-  k_fin_ls<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_primal, k.trow, k.rec_dual, k.inst);
-  if (mask & 1 && k.tcol.nblk > 0)
-    k_lam<float, float><<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, k.AT32, k.it32, k.d32, k.inst, kFP32,
-                                                               k.rec_lam);
-  if (mask & 2 && k.tcol.nblk > 0)
-    k_lam<double, double><<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, k.AT64, k.it64, k.d64, k.inst, kFP64,
-                                                                 k.rec_lam);
-  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(k.tcol, k.rec_lam, k.inst);
+  if (mask & 1) launch_dual_epi_t<float>(k, s, kFP32, k.it32, k.d32, k.part32);
+  if (mask & 2) launch_dual_epi_t<double>(k, s, kFP64, k.it64, k.d64, k.part64);
+  const bool s1 = k.P1 > 1, s2 = k.P2 > 1;
+  k_fin_ls<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol.inst_blk0, k.rec_primal,
+                                           s1 ? k.vrow.inst_blk0 : k.brow.inst_blk0,
+                                           s1 ? k.rec_dual_epi : k.rec_dual, k.inst);
+  if (mask & 1) launch_lam_t<float>(k, s, kFP32, k.it32, k.d32, k.AT32, k.PAT32, k.partT32);
+  if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.PAT64, k.partT64);
+  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(s2 ? k.vcol.inst_blk0 : k.tcol.inst_blk0,
+                                             s2 ? k.rec_lam_epi : k.rec_lam, k.inst);
 }
 
 void launch_trial(const KernelCtx& k, hipStream_t s, int mask) {
@@ -1304,11 +1434,28 @@ void launch_trial(const KernelCtx& k, hipStream_t s, int mask) {
 template <typename T>
 static void launch_cand_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                           const T* x0, const T* x1, const T* y0, const T* y1, int mode) {
-  if (k.trow.nblk > 0)
-    k_spmv2<T><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, k.A64, x0, x1, k.cgx0, k.cgx1, k.inst, prec, mode);
-  if (k.tcol.nblk > 0)
-    k_spmv2<T><<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, k.AT64, y0, y1, k.cgty0, k.cgty1, k.inst, prec,
+  auto blocks = [](int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
+  if (k.P1 > 1) {
+    if (k.nslot1 > 0)
+      k_spmv2_part<T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, k.PA64, x0, x1, k.part64, k.part64b,
+                                                          k.inst, prec, mode);
+    if (k.M > 0)
+      k_combine2<<<blocks(k.M), kBlock, 0, s>>>(k.M, k.P1, k.part64, x1 ? k.part64b : nullptr, k.cgx0, k.cgx1,
+                                                 k.inst, mode);
+  } else if (k.brow.nblk > 0) {
+    k_spmv2<T><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, k.A64, x0, x1, k.cgx0, k.cgx1, k.inst, prec, mode);
+  }
+  if (k.P2 > 1) {
+    if (k.nslot2 > 0)
+      k_spmv2_part<T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, k.PAT64, y0, y1, k.partT64,
+                                                          k.partT64b, k.inst, prec, mode);
+    if (k.N > 0)
+      k_combine2<<<blocks(k.N), kBlock, 0, s>>>(k.N, k.P2, k.partT64, y1 ? k.partT64b : nullptr, k.cgty0,
+                                                 k.cgty1, k.inst, mode);
+  } else if (k.bcol.nblk > 0) {
+    k_spmv2<T><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, k.AT64, y0, y1, k.cgty0, k.cgty1, k.inst, prec,
                                                       mode);
+  }
   if (k.vcol.nblk > 0)
     k_cand_cols<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, x0, x1, it.xa, k.cgty0, k.cgty1, k.d64, k.D2,
                                                           k.inst, prec, mode, k.rec_cand_c);
@@ -1439,9 +1586,15 @@ void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mas
     }
   }
   if (k.trow.nblk > 0)
-    k_scale_vals<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A, k.D1, k.D2, 0, su.val64, su.val32);
+    k_scale_vals<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A, k.D1, k.D2, 0, 0, su.val64, su.val32);
+  if (k.P1 > 1 && k.prow.nblk > 0)
+    k_scale_vals<<<grid1(k.prow.nblk), kBlock, 0, s>>>(k.prow, su.PA, k.D1, k.D2, 0, (int)k.M, su.pval64,
+                                                        su.pval32);
   if (k.tcol.nblk > 0)
-    k_scale_vals<<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, su.AT, k.D1, k.D2, 1, su.valT64, su.valT32);
+    k_scale_vals<<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, su.AT, k.D1, k.D2, 1, 0, su.valT64, su.valT32);
+  if (k.P2 > 1 && k.pcol.nblk > 0)
+    k_scale_vals<<<grid1(k.pcol.nblk), kBlock, 0, s>>>(k.pcol, su.PAT, k.D1, k.D2, 1, (int)k.N, su.pvalT64,
+                                                        su.pvalT32);
   if (k.vcol.nblk > 0)
     k_scale_cols<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.c, su.l, su.u, k.D2, su.d64m, su.d32m);
   if (k.vrow.nblk > 0)
@@ -1477,27 +1630,22 @@ void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mas
   }
 }
 
-void launch_spmv_plain(const Tiles& tl, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
+void launch_spmv_plain(const RowBlocks& rb, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
                        const void* in, void* out, hipStream_t s) {
-  if (tl.nblk <= 0) return;
+  if (rb.nblk <= 0) return;
   if (prec == kFP64) {
     MatPtrs<double> A{ptr, idx, (const double*)val};
-    k_spmv_plain<double, double><<<grid1(tl.nblk), kBlock, 0, s>>>(tl, A, (const double*)in, (double*)out);
+    k_spmv_plain<double, double><<<grid1(rb.nblk), kBlock, 0, s>>>(rb, A, (const double*)in, (double*)out);
   } else {
     MatPtrs<float> A{ptr, idx, (const float*)val};
-    k_spmv_plain<float, float><<<grid1(tl.nblk), kBlock, 0, s>>>(tl, A, (const float*)in, (float*)out);
+    k_spmv_plain<float, float><<<grid1(rb.nblk), kBlock, 0, s>>>(rb, A, (const float*)in, (float*)out);
   }
 }
 
-// One K1 pass on its own (for schedule timing): trial SpMV with the fused dual step.
+// One K1 pass on its own (for schedule timing).
 void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec) {
-  if (k.trow.nblk <= 0) return;
-  if (prec == kFP32)
-    k_dual<float, float><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, k.A32, k.it32, k.d32, k.inst, kFP32,
-                                                                k.rec_dual);
-  else
-    k_dual<double, double><<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, k.A64, k.it64, k.d64, k.inst, kFP64,
-                                                                  k.rec_dual);
+  if (prec == kFP32) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, k.part32);
+  else launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, k.part64);
 }
 
 }  // namespace pdcs

@@ -40,7 +40,8 @@ struct MatPtrs {
 struct KernelCtx {
   int nb;
   int64_t M, N;
-  Tiles trow, tcol;   // CSR of G (rows) and of G^T (columns)
+  Tiles trow, tcol;   // CSR of G (rows) and of G^T (columns): wavefront tiles (set-up passes)
+  RowBlocks brow, bcol;  // the same structures in row blocks (iteration passes)
   Ranges vrow, vcol;  // elementwise passes over rows and columns
   Inst* inst;
   IterPtrs<float> it32;
@@ -54,6 +55,17 @@ struct KernelCtx {
   double *xout, *yout, *lamout;
   double *rec_primal, *rec_dual, *rec_lam, *rec_cand_c, *rec_cand_r, *rec_probe_c, *rec_probe_r;
   int probe_passes;
+  // Column-panel split of large single instances (P1 panels for G x, P2 for G^T y).
+  int P1, P2;
+  Tiles prow, pcol;              // tiles over the panel-major structures ("virtual rows")
+  RowBlocks bprow, bpcol;        // row blocks over the panel-major structures
+  const int32_t *slot1, *slot2;  // launch slot -> workgroup of the panel schedule (-1: idle)
+  int nslot1, nslot2;
+  MatPtrs<float> PA32, PAT32;
+  MatPtrs<double> PA64, PAT64;
+  float *part32, *partT32;
+  double *part64, *partT64, *part64b, *partT64b;
+  double *rec_dual_epi, *rec_lam_epi;
 };
 
 struct SetupCtx {
@@ -66,6 +78,9 @@ struct SetupCtx {
   DataMut32 d32m;
   double *stat_r, *stat_c, *rec_nc, *rec_nr, *rec_nm;
   const double *x0, *y0;          // device start point (unscaled) or null
+  MatPtrs<double> PA, PAT;        // panel-major unscaled values (when split)
+  double *pval64, *pvalT64;
+  float *pval32, *pvalT32;
 };
 
 void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mask);
@@ -75,7 +90,7 @@ void launch_summary(const KernelCtx& k, hipStream_t s, int32_t* out);
 void launch_timeout(const KernelCtx& k, hipStream_t s);
 void launch_eval(const KernelCtx& k, hipStream_t s, int mask, int final_mode);
 void launch_flush_commit(const KernelCtx& k, hipStream_t s, int mask);
-void launch_spmv_plain(const Tiles& tl, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
+void launch_spmv_plain(const RowBlocks& rb, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
                        const void* in, void* out, hipStream_t s);
 void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec);
 

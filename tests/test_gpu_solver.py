@@ -129,3 +129,28 @@ def test_spmv_matches_scipy_power_law():
     A32 = A.astype(np.float32).astype(np.float64)
     exact32 = A32 @ x.astype(np.float32).astype(np.float64)
     assert np.all(np.abs(o32.cpu().numpy().astype(np.float64) - exact32) <= 6e-8 * (1 + np.abs(exact32)) + 1e-12 * bound_m)
+
+
+@pytest.mark.parametrize("panels", [(4, 2), (8, 8)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_panel_split_matches_oracle(panels, precision):
+    # The XCD panel split changes only the summation order of the SpMVs.
+    inst = lpgen.c0_instance(3)
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options())
+    prob = P.Problem.from_instance(inst)
+    prob.set_panels(*panels)
+    sol = prob.solve(precision=precision, time_limit=60.0)
+    _check_solution(inst, sol, ref.pobj)
+
+
+def test_panel_split_first_trials_elementwise():
+    inst = lpgen.planted_lp(lpgen.rng_for(77, 2), 150, 400, per_col=4, m_zero=70)
+    lp = O.lpdata_from_instance(inst)
+    N = 30
+    ref = O.solve(lp, O.Options(max_iter=N, check_every=1000))
+    prob = P.Problem.from_instance(inst)
+    prob.set_panels(8, 4)
+    sol = prob.solve(precision="fp64", max_iter=N, check_every=1000, keep_state=True)
+    for key, okey in (("x", "x"), ("y", "y"), ("x_hat", "x_hat"), ("y_hat", "y_hat")):
+        a, b = sol.state[key], ref.state[okey]
+        assert np.max(np.abs(a - b)) <= 1e-9 * (1.0 + np.abs(b).max()), key
