@@ -98,7 +98,8 @@ typedef struct {
   int64_t time_kernels;       /* 1: launch without graphs and time every launch of the
                                  SpMV-with-dual-step kernel with HIP events           */
   int64_t probe_passes;       /* 7: multisection passes per restart check (16 t each)  */
-  int64_t reserved[4];
+  int64_t trace_trials;       /* record the scalars of the first this-many trials      */
+  int64_t reserved[3];
 } pdcs_options;
 
 /* Per-solve information (result fields of Section 3 plus counters). */
@@ -125,7 +126,10 @@ typedef struct {
   double  omega, omega0, eta_hat, eta, beta, sum_eta;
   int64_t kbar, k, t, accepted;
   int64_t precision;          /* precision the iterates were in at exit               */
-  int64_t reserved[5];
+  double  rho_cur, rho_avg;   /* normalized duality gaps of the two restart candidates
+                                 at the last check (Section 2.3)                      */
+  double  r_cur, r_avg;       /* their radii ||z_c - z_anchor||_N                      */
+  int64_t chosen;             /* candidate taken at the last check: 0 current, 1 average */
 } pdcs_state_scalars;
 
 void        pdcs_options_default(pdcs_options* opts);
@@ -195,6 +199,16 @@ int  pdcs_result_scaling(pdcs_result r, double* D1, int64_t m, double* D2, int64
  * be NULL.  Lengths are the problem's n (x-like) and m (y-like). */
 int  pdcs_result_state(pdcs_result r, pdcs_state_scalars* s, double* x, double* y,
                        double* x_hat, double* y_hat, double* x_a, double* y_a);
+/* Rescaled products G^T y_hat and G x_hat of the last trial (keep_state solves):
+ * double[n] and double[m]; either pointer may be NULL. */
+int  pdcs_result_products(pdcs_result r, double* gty_hat, double* gx_hat);
+/* Scalars of the first trace_trials trials of instance 0 (16 doubles per trial:
+ * kbar, eta, eta_bar, ||dx||^2, ||dy||^2, dy^T G dx, accepted, eta', beta, k
+ * before the trial, then c^T x_hat, h^T y_hat, sum l lam+, sum u lam-,
+ * err_p^2, err_d^2 of the rescaled problem; NaN where a rejected trial has no
+ * value); *count receives the number of rows written.  Requires
+ * trace_trials > 0 in the solve's options. */
+int  pdcs_result_trace(pdcs_result r, double* out, int64_t max_trials, int64_t* count);
 void pdcs_result_destroy(pdcs_result r);
 
 /* ---- batched solves ----------------------------------------------------

@@ -602,7 +602,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
                 rho = normalized_gap(sl, cx, cy, tau_c, sig_c, r, opts.bisect_rel_eps,
                                      opts.max_doublings)
                 ep, ed, eg, _, _ = abs_errors_l2(sl, cx, cy)
-                info[name] = dict(rho=rho, kkt=kkt_omega(ep, ed, eg, omega), err=(ep, ed, eg))
+                info[name] = dict(rho=rho, kkt=kkt_omega(ep, ed, eg, omega), err=(ep, ed, eg), r=r)
             # Numerical issue (Section 2.3): any gap value of this check, of the
             # anchor or of the previous candidate that is negative, NaN or has
             # r = 0 switches every comparison of this check to KKT_omega.
@@ -623,6 +623,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
             done = is_optimal(err, opts.rel_tol, opts.abs_tol)
             checks_log.append(dict(kbar=kbar, k=k, t=t, chosen=chosen, use_kkt=use_kkt,
                                    rho={nm: v["rho"] for nm, v in info.items()},
+                                   r={nm: v["r"] for nm, v in info.items()},
                                    restart=bool(restart or done), rule=rule, omega=omega,
                                    rel=max(err["rel_p"], err["rel_d"], err["rel_gap"])))
             if done:

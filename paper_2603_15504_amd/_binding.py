@@ -36,7 +36,7 @@ class pdcs_options(C.Structure):
                 ("polish_switch_tol", C.c_double), ("bisect_rel_eps", C.c_double),
                 ("use_graph", C.c_int64), ("verbose", C.c_int64), ("keep_state", C.c_int64),
                 ("time_kernels", C.c_int64), ("probe_passes", C.c_int64),
-                ("reserved", C.c_int64 * 4)]
+                ("trace_trials", C.c_int64), ("reserved", C.c_int64 * 3)]
 
 
 class pdcs_info(C.Structure):
@@ -53,7 +53,8 @@ class pdcs_state_scalars(C.Structure):
     _fields_ = [("omega", C.c_double), ("omega0", C.c_double), ("eta_hat", C.c_double),
                 ("eta", C.c_double), ("beta", C.c_double), ("sum_eta", C.c_double),
                 ("kbar", C.c_int64), ("k", C.c_int64), ("t", C.c_int64), ("accepted", C.c_int64),
-                ("precision", C.c_int64), ("reserved", C.c_int64 * 5)]
+                ("precision", C.c_int64), ("rho_cur", C.c_double), ("rho_avg", C.c_double),
+                ("r_cur", C.c_double), ("r_avg", C.c_double), ("chosen", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -78,6 +79,8 @@ PROTOTYPES = {
     "pdcs_result_slack": (C.c_int, [_P, _P, _I64]),
     "pdcs_result_scaling": (C.c_int, [_P, _P, _I64, _P, _I64]),
     "pdcs_result_state": (C.c_int, [_P, C.POINTER(pdcs_state_scalars), _P, _P, _P, _P, _P, _P]),
+    "pdcs_result_products": (C.c_int, [_P, _P, _P]),
+    "pdcs_result_trace": (C.c_int, [_P, _P, _I64, C.POINTER(_I64)]),
     "pdcs_result_destroy": (None, [_P]),
     "pdcs_batch_create": (C.c_int, [_I64, _P, C.POINTER(_P)]),
     "pdcs_batch_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, _P]),
@@ -260,6 +263,17 @@ def pdcs_result_state(r, m, n, vectors: bool = True):
     return s, vec
 
 
+TRACE_FIELDS = ("kbar", "eta", "eta_bar", "dx2", "dy2", "dydgdx", "accepted", "eta_next", "beta", "k",
+                "pobj", "hy", "l_lam_plus", "u_lam_minus", "errp2", "errd2")
+
+
+def pdcs_result_trace(r, max_trials: int) -> np.ndarray:
+    out = np.empty((max(int(max_trials), 1), len(TRACE_FIELDS)), dtype=np.float64)
+    cnt = C.c_int64()
+    _check(lib.pdcs_result_trace(r, _ptr(out), int(max_trials), C.byref(cnt)), "pdcs_result_trace")
+    return out[:cnt.value]
+
+
 def pdcs_result_destroy(r):
     lib.pdcs_result_destroy(r)
 
@@ -324,6 +338,7 @@ class Solution:
     D1: np.ndarray | None = None
     D2: np.ndarray | None = None
     state: dict | None = None
+    trace: np.ndarray | None = None
 
 
 def _info_dict(info: pdcs_info) -> dict:
@@ -348,7 +363,7 @@ class Problem:
         o = pdcs_options_default(**opts)
         r = pdcs_solve(self.handle, o, x0, y0)
         try:
-            return _collect(r, self.m, self.n, with_scaling, bool(o.keep_state))
+            return _collect(r, self.m, self.n, with_scaling, bool(o.keep_state), int(o.trace_trials))
         finally:
             pdcs_result_destroy(r)
 
@@ -370,7 +385,7 @@ class Problem:
             pass
 
 
-def _collect(r, m, n, with_scaling, with_state) -> Solution:
+def _collect(r, m, n, with_scaling, with_state, trace=0) -> Solution:
     info = _info_dict(pdcs_result_info(r))
     sol = Solution(pdcs_result_primal(r, n), pdcs_result_dual(r, m) if m > 0 else np.zeros(0),
                    pdcs_result_slack(r, n), info)
@@ -380,7 +395,14 @@ def _collect(r, m, n, with_scaling, with_state) -> Solution:
         s, vec = pdcs_result_state(r, m, n, True)
         st = {name: getattr(s, name) for name, _ in pdcs_state_scalars._fields_ if name != "reserved"}
         st.update(vec)
+        gty = np.empty(n)
+        gx = np.empty(m)
+        _check(lib.pdcs_result_products(r, _ptr(gty), _ptr(gx)), "pdcs_result_products")
+        st["gty_hat"] = gty
+        st["gx_hat"] = gx
         sol.state = st
+    if trace > 0:
+        sol.trace = pdcs_result_trace(r, trace)
     return sol
 
 
@@ -396,8 +418,9 @@ class Batch:
         rs = pdcs_batch_solve(self.handle, len(self.problems), o, x0s, y0s)
         out = []
         try:
-            for r, p in zip(rs, self.problems):
-                out.append(_collect(r, p.m, p.n, with_scaling, bool(o.keep_state)))
+            for i, (r, p) in enumerate(zip(rs, self.problems)):
+                out.append(_collect(r, p.m, p.n, with_scaling, bool(o.keep_state),
+                                    int(o.trace_trials) if i == 0 else 0))
         finally:
             for r in rs:
                 pdcs_result_destroy(r)

@@ -64,7 +64,12 @@ struct Inst {
   // termination errors of the last evaluated point
   double pobj, dobj, abs_p, abs_d, abs_gap, rel_p, rel_d, rel_gap;
   CandState cand[kMaxCand];
+  double chk_rho[kMaxCand], chk_r[kMaxCand];  // values of the last restart check
+  double* trace;            // per-trial scalars of the first trace_cap trials (or null)
+  int64_t trace_cap;
 };
+constexpr int kTraceStride = 16;  // kbar, eta, eta_bar, dx2, dy2, dy^T G dx, accepted, eta', beta, k,
+                                  // then for accepted trials: c^T x_hat, h^T y_hat, sum l lam+, sum u lam-, err_p^2, err_d^2
 
 // Schedule of a CSR-like pass: wavefront tiles grouped into workgroup ranges.
 struct Tiles {

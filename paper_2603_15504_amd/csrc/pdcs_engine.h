@@ -115,7 +115,7 @@ struct IterBufs {
 struct OutBlock {
   int64_t M = 0, N = 0;
   DBuf x, y, lam, D1, D2;
-  DBuf st[2][6];  // [fp64, fp32] x [x, y, x_hat, y_hat, x_a, y_a]
+  DBuf st[2][8];  // [fp64, fp32] x [x, y, x_hat, y_hat, x_a, y_a, G^T y_hat, G x_hat]
 };
 
 struct Engine {
@@ -130,7 +130,7 @@ struct Engine {
   DBuf D1, D2, cgx0, cgx1, cgty0, cgty1, xout, yout, lamout, stat_r, stat_c;
   DBuf rec_primal, rec_dual, rec_lam, rec_cand_c, rec_cand_r, rec_probe_c, rec_probe_r;
   DBuf rec_nc, rec_nr, rec_nm;
-  DBuf d_inst, d_summary, warm_x, warm_y;
+  DBuf d_inst, d_summary, warm_x, warm_y, d_trace;
   int32_t* h_summary = nullptr;
   IterBufs<float> it32;
   IterBufs<double> it64;
@@ -177,6 +177,7 @@ struct pdcs_result_s {
   pdcs_info info{};
   pdcs_state_scalars st{};
   bool has_state = false;
+  std::vector<double> trace;
 };
 
 struct pdcs_batch_s {

@@ -669,6 +669,11 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     I.omega = I.omega0 = 1.0;
     I.eta = I.eta_hat = 1.0;
   }
+  if (o.trace_trials > 0) {
+    d_trace.alloc((size_t)o.trace_trials * kTraceStride * 8);
+    hi[0].trace = d_trace.as<double>();
+    hi[0].trace_cap = o.trace_trials;
+  }
   HIP_OK(hipMemcpyAsync(d_inst.p, hi.data(), sizeof(Inst) * B, hipMemcpyHostToDevice, stream));
   // optional warm start (unscaled, host)
   const double* dx0 = nullptr;
@@ -760,11 +765,12 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
       Inst I0;
       HIP_OK(hipMemcpy(&I0, d_inst.p, sizeof(Inst), hipMemcpyDeviceToHost));
       std::fprintf(stderr,
-                   "[pdcs] %.1fs kbar %lld restarts %lld omega %.3e eta %.3e rel(p,d,g) %.2e %.2e %.2e prec %s "
-                   "active %d\n",
+                   "[pdcs] %.1fs kbar %lld k %lld t %lld restarts %lld omega %.3e eta %.3e rel(p,d,g) %.2e %.2e %.2e "
+                   "rho(cur,avg,anchor) %.3e %.3e %.3e chosen %d kkt %d prec %s active %d\n",
                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(),
-                   (long long)I0.kbar, (long long)I0.restarts, I0.omega, I0.eta_hat, I0.rel_p, I0.rel_d,
-                   I0.rel_gap, I0.precision == kFP32 ? "fp32" : "fp64", a32 + a64);
+                   (long long)I0.kbar, (long long)I0.k, (long long)I0.t, (long long)I0.restarts, I0.omega,
+                   I0.eta_hat, I0.rel_p, I0.rel_d, I0.rel_gap, I0.cand[0].rho, I0.cand[1].rho, I0.rho_anchor,
+                   I0.chosen, I0.use_kkt, I0.precision == kFP32 ? "fp32" : "fp64", a32 + a64);
     }
     if (a32 + a64 == 0) break;
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -818,17 +824,17 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
       const bool ok = pi == 0 ? it64.ready : it32.ready;
       if (!ok) continue;
       const size_t es = pi == 0 ? 8 : 4;
-      void* src[6];
+      void* src[8];
       if (pi == 0) {
         const IterPtrs<double>& q = it64.p;
-        void* s6[6] = {q.x, q.y, q.xh, q.yh, q.xa, q.ya};
-        std::memcpy(src, s6, sizeof(src));
+        void* s8[8] = {q.x, q.y, q.xh, q.yh, q.xa, q.ya, q.gtyh, q.gxh};
+        std::memcpy(src, s8, sizeof(src));
       } else {
         const IterPtrs<float>& q = it32.p;
-        void* s6[6] = {q.x, q.y, q.xh, q.yh, q.xa, q.ya};
-        std::memcpy(src, s6, sizeof(src));
+        void* s8[8] = {q.x, q.y, q.xh, q.yh, q.xa, q.ya, q.gtyh, q.gxh};
+        std::memcpy(src, s8, sizeof(src));
       }
-      for (int v = 0; v < 6; ++v) {
+      for (int v = 0; v < 8; ++v) {
         const size_t len = (v % 2 == 0) ? (size_t)N : (size_t)M;
         out->st[pi][v].alloc(len * es);
         HIP_OK(hipMemcpyAsync(out->st[pi][v].p, src[v], len * es, hipMemcpyDeviceToDevice, stream));
@@ -878,7 +884,18 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     r->st.t = I.t;
     r->st.accepted = I.accepted;
     r->st.precision = I.precision == kFP32 ? PDCS_PRECISION_MIXED : PDCS_PRECISION_FP64;
+    r->st.rho_cur = I.chk_rho[0];
+    r->st.rho_avg = I.chk_rho[1];
+    r->st.r_cur = I.chk_r[0];
+    r->st.r_avg = I.chk_r[1];
+    r->st.chosen = I.chosen;
     r->has_state = o.keep_state != 0;
+    if (b == 0 && o.trace_trials > 0) {
+      const int64_t rows = std::min<int64_t>(o.trace_trials, I.kbar);
+      r->trace.resize((size_t)rows * kTraceStride);
+      if (rows > 0)
+        HIP_OK(hipMemcpy(r->trace.data(), d_trace.p, (size_t)rows * kTraceStride * 8, hipMemcpyDeviceToHost));
+    }
     res[b] = r;
   }
   return res;
@@ -1137,6 +1154,40 @@ int pdcs_result_state(pdcs_result r, pdcs_state_scalars* s, double* x, double* y
         for (int64_t i = 0; i < len; ++i) dst[v][i] = (double)tmp[i];
       }
     }
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_products(pdcs_result r, double* gty_hat, double* gx_hat) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    if (!r->has_state) throw Error(PDCS_ERR_STATE, "solve ran without keep_state");
+    const int pi = r->st.precision == PDCS_PRECISION_MIXED ? 1 : 0;
+    double* dst[2] = {gty_hat, gx_hat};
+    for (int v = 0; v < 2; ++v) {
+      if (!dst[v]) continue;
+      const int64_t off = v == 0 ? r->col0 : r->row0;
+      const int64_t len = v == 0 ? r->n : r->m;
+      const DBuf& src = r->out->st[pi][6 + v];
+      if (len == 0) continue;
+      if (pi == 0) {
+        HIP_OK(hipMemcpy(dst[v], src.as<double>() + off, (size_t)len * 8, hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> tmp(len);
+        HIP_OK(hipMemcpy(tmp.data(), src.as<float>() + off, (size_t)len * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < len; ++i) dst[v][i] = (double)tmp[i];
+      }
+    }
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_trace(pdcs_result r, double* out, int64_t max_trials, int64_t* count) {
+  return guarded([&]() {
+    if (!r || !out || !count || max_trials < 0) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    const int64_t rows = std::min<int64_t>(max_trials, (int64_t)(r->trace.size() / kTraceStride));
+    std::memcpy(out, r->trace.data(), (size_t)rows * kTraceStride * 8);
+    *count = rows;
     return PDCS_OK;
   });
 }

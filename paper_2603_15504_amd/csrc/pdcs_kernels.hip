@@ -254,6 +254,19 @@ __global__ __launch_bounds__(kBlock) void k_fin_ls(const int32_t* __restrict__ i
     I.last_acc = 0;
     return;
   }
+  if (I.trace && I.kbar <= I.trace_cap) {
+    double* tr = I.trace + (I.kbar - 1) * kTraceStride;
+    tr[0] = (double)I.kbar;
+    tr[1] = eta;
+    tr[2] = etabar;
+    tr[3] = dx2;
+    tr[4] = dy2;
+    tr[5] = dydg;
+    tr[6] = eta < etabar ? 1.0 : 0.0;
+    tr[7] = eta_next;
+    for (int f = 8; f < kTraceStride; ++f) tr[f] = NAN;
+    tr[9] = (double)I.k;
+  }
   if (eta < etabar) {
     I.last_acc = 1;
     I.eta_k = eta;
@@ -319,6 +332,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(const int32_t* __restrict__
     return;
   }
   const double beta = me > 0.0 ? clampd(-0.1 * log10(me) + 0.2, 0.0, 1.0) : 1.0;
+  if (I.trace && I.kbar <= I.trace_cap) {
+    double* tr = I.trace + (I.kbar - 1) * kTraceStride;
+    tr[8] = beta;
+    tr[10] = I.cx;
+    tr[11] = I.hy;
+    tr[12] = q[1];
+    tr[13] = q[2];
+    tr[14] = I.errp2;
+    tr[15] = q[0];
+  }
   const double k = (double)I.k;
   I.beta = beta;
   I.ca = (k + 1.0) / (k + 2.0);
@@ -787,6 +810,10 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
     else C.rho = C.val_lo / C.r;
     if (!(C.rho >= 0.0) || !isfinite(C.rho)) all_valid = false;
   }
+  for (int q = 0; q < kMaxCand; ++q) {
+    I.chk_rho[q] = q < nc ? I.cand[q].rho : NAN;
+    I.chk_r[q] = q < nc ? I.cand[q].r : NAN;
+  }
   if (I.has_anchor && !(I.rho_anchor >= 0.0 && isfinite(I.rho_anchor))) all_valid = false;
   if (I.has_prev && !(I.rho_prev >= 0.0 && isfinite(I.rho_prev))) all_valid = false;
   const bool use_kkt = !all_valid;
@@ -868,7 +895,7 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
     I.kkt_prev = C.kkt;
     I.has_prev = 1;
   }
-  if (!restart && I.kbar >= I.max_iter) {
+  if (I.kbar >= I.max_iter) {  // trial budget spent: stop after this check
     I.status = kDone;
     I.exit_code = 1;
   }
@@ -1421,7 +1448,7 @@ void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
                                            s1 ? k.rec_dual_epi : k.rec_dual, k.inst);
   if (mask & 1) launch_lam_t<float>(k, s, kFP32, k.it32, k.d32, k.AT32, k.PAT32, k.partT32);
   if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.PAT64, k.partT64);
-  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(s2 ? k.vcol.inst_blk0 : k.tcol.inst_blk0,
+  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(s2 ? k.vcol.inst_blk0 : k.bcol.inst_blk0,
                                              s2 ? k.rec_lam_epi : k.rec_lam, k.inst);
 }
 

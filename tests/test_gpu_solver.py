@@ -154,3 +154,62 @@ def test_panel_split_first_trials_elementwise():
     for key, okey in (("x", "x"), ("y", "y"), ("x_hat", "x_hat"), ("y_hat", "y_hat")):
         a, b = sol.state[key], ref.state[okey]
         assert np.max(np.abs(a - b)) <= 1e-9 * (1.0 + np.abs(b).max()), key
+
+
+@pytest.mark.parametrize("seed,m", [(0, 300), (1, 1000)])
+def test_first_restart_check_matches_oracle(seed, m):
+    # The trajectory is deterministic up to the first restart check, so the
+    # radii and normalized duality gaps of both candidates there must agree
+    # (bisection tolerance 1e-6 relative), and so must the state.
+    inst = lpgen.c1_instance(seed, m=m, n=2 * m)
+    lp = O.lpdata_from_instance(inst)
+    ref = O.solve(lp, O.Options(max_iter=64, check_every=64))
+    assert ref.checks == 1, "the reference must reach its first check"
+    c = ref.checks_log[0]
+    prob = P.Problem.from_instance(inst)
+    sol = prob.solve(precision="fp64", max_iter=64, check_every=64, keep_state=True)
+    st = sol.state
+    print("gpu", st["r_cur"], st["r_avg"], st["rho_cur"], st["rho_avg"], "oracle", c["r"], c["rho"])
+    assert st["r_cur"] == pytest.approx(c["r"]["cur"], rel=1e-9)
+    assert st["r_avg"] == pytest.approx(c["r"]["avg"], rel=1e-9)
+    assert st["rho_cur"] == pytest.approx(c["rho"]["cur"], rel=2e-5)
+    assert st["rho_avg"] == pytest.approx(c["rho"]["avg"], rel=2e-5)
+
+
+@pytest.mark.parametrize("seed,m", [(0, 300)])
+def test_state_before_first_check_matches_oracle(seed, m):
+    inst = lpgen.c1_instance(seed, m=m, n=2 * m)
+    lp = O.lpdata_from_instance(inst)
+    ref = O.solve(lp, O.Options(max_iter=63, check_every=1000))
+    prob = P.Problem.from_instance(inst)
+    sol = prob.solve(precision="fp64", max_iter=63, check_every=1000, keep_state=True)
+    st = sol.state
+    assert st["k"] == ref.state["k"] and st["kbar"] == ref.state["kbar"]
+    # each eta depends on norms reduced in a different order on the two sides,
+    # so the sum of 63 of them agrees to about 1e-12 relative
+    assert st["sum_eta"] == pytest.approx(ref.state["SH"], rel=1e-10)
+    for key, okey in (("x", "x"), ("y", "y"), ("x_hat", "x_hat"), ("y_hat", "y_hat")):
+        a, b = st[key], ref.state[okey]
+        assert np.max(np.abs(a - b)) <= 1e-9 * (1.0 + np.abs(b).max()), key
+
+
+@pytest.mark.parametrize("seed,m,panels", [(0, 300, (1, 1)), (1, 1000, (1, 1)), (0, 300, (4, 2))])
+def test_first_trials_scalars_match_oracle(seed, m, panels):
+    # Per-trial step sizes, acceptance and reflection parameters of the first
+    # 64 trials (deterministic up to the first restart check) on a power-law
+    # LP, whose SpMV schedules have many workgroups per instance.
+    inst = lpgen.c1_instance(seed, m=m, n=2 * m)
+    lp = O.lpdata_from_instance(inst)
+    ref = O.solve(lp, O.Options(max_iter=64, check_every=64), trace=True)
+    prob = P.Problem.from_instance(inst)
+    prob.set_panels(*panels)
+    sol = prob.solve(precision="fp64", max_iter=64, check_every=64, trace_trials=64)
+    tr = sol.trace
+    assert len(tr) == 64 == len(ref.trace)
+    for row, t in zip(tr, ref.trace):
+        assert int(row[0]) == t["kbar"]
+        assert bool(row[6]) == t["accepted"]
+        assert row[1] == pytest.approx(t["eta"], rel=1e-9)
+        assert row[7] == pytest.approx(t["eta_next"], rel=1e-9)
+        if t["accepted"]:
+            assert row[8] == pytest.approx(t["beta"], rel=1e-9, abs=1e-12)
