@@ -161,10 +161,14 @@ int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
 /* pdcs_problem_spmv: one product with the UNSCALED matrix on device memory.
  *   transpose = 0: out[m] = G in[n];  transpose = 1: out[n] = G^T in[m].
  *   precision = PDCS_PRECISION_FP64: in/out are double*, FP64 values;
- *   precision = PDCS_PRECISION_MIXED: in/out are float*, FP32 values, FP64 accumulation.
+ *   precision = PDCS_PRECISION_MIXED: in/out are float*, FP32 values (row
+ *               layout: FP64 accumulation; band layout: FP32 accumulation per
+ *               window, FP64 sum of the window partials).
  * in_dev / out_dev are device pointers owned by the caller; the kernel is the
- * one the solver uses for its matrix products, launched on `stream` and not
- * synchronized.  Errors: PDCS_ERR_INVALID_ARG. */
+ * one the solver uses for its trial products under the problem's current
+ * layout (pdcs_problem_set_layout), launched on `stream` and not synchronized;
+ * the band layout also writes its own partial-sum buffer, so calls on one
+ * problem must not overlap.  Errors: PDCS_ERR_INVALID_ARG. */
 int  pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision,
                        const void* in_dev, void* out_dev, void* stream);
 
@@ -175,6 +179,23 @@ int  pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision,
  * 0 = automatic (about 256 Ki entries per panel), 1 = off, 2/4/8 = forced.
  * Errors: PDCS_ERR_INVALID_ARG for other values. */
 int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
+
+/* pdcs_problem_set_layout: storage of the matrix for the two SpMVs of every
+ * trial of a single problem.
+ *   PDCS_LAYOUT_ROWS : CSR row blocks, fused with the dual / dual-slack steps
+ *                      (with the column-panel split of pdcs_problem_set_panels);
+ *   PDCS_LAYOUT_BANDS: band tiles: row bands x gathered-index windows, entries
+ *                      sorted by gathered index and summed per row in LDS, then
+ *                      one partial sum per window combined by the epilogues;
+ *   PDCS_LAYOUT_AUTO : bands for problems with at least 2^23 nonzeros.
+ * Both layouts compute the same products up to rounding order.  Building the
+ * band tiles takes host time proportional to nnz log nnz and 20 bytes of device
+ * memory per nonzero of each of G and G^T.
+ * Errors: PDCS_ERR_INVALID_ARG for an unknown layout. */
+#define PDCS_LAYOUT_AUTO  0
+#define PDCS_LAYOUT_ROWS  1
+#define PDCS_LAYOUT_BANDS 2
+int  pdcs_problem_set_layout(pdcs_problem p, int64_t layout);
 
 /* ---- single solve ------------------------------------------------------
  * pdcs_solve: Algorithm 4 (rescale, Algorithm 1, unscale) on one problem.

@@ -30,6 +30,7 @@ __all__ = [
     "c4_instance",
     "zipf_row_lengths",
     "rng_for",
+    "dense_runs_instance",
 ]
 
 
@@ -233,3 +234,25 @@ def c4_instance(seed: int = 0, m: int = 200_000, n: int = 500_000, per_col: int 
     cs = 10.0 ** rng.uniform(-2.0, 2.0, size=n)
     return planted_lp(rng, m, n, per_col=per_col, row_scale=rs, col_scale=cs,
                       name=f"c4_m{m}_n{n}_s{seed}")
+
+
+def dense_runs_instance(seed: int = 0, m: int = 256, run: int = 64, coupling: int = 1) -> LPInstance:
+    """Edge-case LP for sorted-column layouts: row i holds the ``run`` consecutive
+    columns [run*i, run*(i+1)) (a long run of one row between neighbouring
+    gathered indices), plus ``coupling`` uniform random rows per column so the
+    rows interact.  Values N(0,1), planted as in ``planted_lp``."""
+    rng = rng_for(90, seed)
+    n = m * run
+    row_a = np.repeat(np.arange(m, dtype=np.int64), run)
+    col_a = np.arange(n, dtype=np.int64)
+    row_b, col_b = _distinct_rows_per_column(rng, m, n, coupling)
+    keep = row_b != col_b // run
+    row = np.concatenate([row_a, row_b[keep]])
+    col = np.concatenate([col_a, col_b[keep]])
+    val = rng.standard_normal(row.size)
+    row_ptr, col_idx, val = csr_from_columns(m, n, row, col, val)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    h = _csr_matvec(row_ptr, col_idx, val, x0)
+    c = rng.uniform(0.0, 1.0, size=n)
+    return LPInstance(m, n, m, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, 10.0),
+                      name=f"dense_runs_{seed}", x_planted=x0)

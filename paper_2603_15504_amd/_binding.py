@@ -72,6 +72,7 @@ PROTOTYPES = {
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
     "pdcs_problem_set_panels": (C.c_int, [_P, _I64, _I64]),
+    "pdcs_problem_set_layout": (C.c_int, [_P, _I64]),
     "pdcs_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, C.POINTER(_P)]),
     "pdcs_result_info": (C.c_int, [_P, C.POINTER(pdcs_info)]),
     "pdcs_result_primal": (C.c_int, [_P, _P, _I64]),
@@ -208,6 +209,13 @@ def pdcs_problem_spmv(p, transpose: int, precision: int, in_dev: int, out_dev: i
 
 def pdcs_problem_set_panels(p, px: int, py: int):
     _check(lib.pdcs_problem_set_panels(p, int(px), int(py)), "pdcs_problem_set_panels")
+
+
+LAYOUTS = {"auto": 0, "rows": 1, "bands": 2}
+
+
+def pdcs_problem_set_layout(p, layout: int):
+    _check(lib.pdcs_problem_set_layout(p, int(layout)), "pdcs_problem_set_layout")
 
 
 def pdcs_solve(p, opts: pdcs_options | None = None, x0=None, y0=None, stream: int = 0) -> C.c_void_p:
@@ -369,6 +377,10 @@ class Problem:
 
     def set_panels(self, px=0, py=0):
         pdcs_problem_set_panels(self.handle, px, py)
+
+    def set_layout(self, layout="auto"):
+        """Matrix storage for the trial SpMVs: "auto", "rows" or "bands"."""
+        pdcs_problem_set_layout(self.handle, LAYOUTS[layout] if isinstance(layout, str) else layout)
 
     def spmv(self, x_dev, out_dev, transpose=False, precision="fp64", stream=0):
         pdcs_problem_spmv(self.handle, 1 if transpose else 0, PRECISION[precision], x_dev, out_dev, stream)

@@ -95,6 +95,40 @@ struct RowBlocks {
   int32_t nblk;
 };
 
+// Band-tile layout of a sparse matrix for single large instances.  A band-tile
+// holds the entries of one band of at most kBandRows consecutive rows whose
+// gathered index falls in one window of at most 2^kBandColBits indices.  Its
+// entries are sorted by gathered index and padded to whole iterations of
+// kBandUnroll * kWave entries; entry e packs (index - window start) <<
+// kBandSlotBits | slot, where slot < kBandSlots names the LDS accumulator it
+// adds into: slots below the band's row count are the rows themselves, higher
+// slots are extra accumulators of rows that repeat within one group of kWave
+// consecutive entries (no two entries of such a group share a slot), and the
+// last slot is the sink of the padding.  A workgroup runs kBandWaves waves, each
+// on one band-tile of the same window.
+constexpr int kBandRows = 8192;
+constexpr int kBandSlots = 9216;
+constexpr int kBandSlotBits = 14;
+constexpr int kBandColBits = 32 - kBandSlotBits;
+constexpr int kBandWaves = 2;
+constexpr int kBandUnroll = 16;
+struct BandTiles {
+  const int32_t* group;      // per workgroup slot group, per wave: band-tile or -1
+  const int32_t* slot;       // launch slot -> group (-1: idle); slot s runs on XCD s % 8
+  const int32_t* start;      // per band-tile: first entry (ntile + 1 entries)
+  const int32_t* row0;       // per band-tile: first row
+  const int32_t* nrows;      // per band-tile: rows
+  const int32_t* col0;       // per band-tile: window start
+  const int32_t* panel;      // per band-tile: window index (partial-sum array)
+  const int32_t* run_start;  // per band-tile: first run (ntile + 1 entries)
+  const int32_t* run_row;    // per run: row (band-local) owning extra slots
+  const int32_t* run_ext;    // per run: first extra slot in ext (nrun + 1 entries)
+  const int32_t* ext;        // extra slots, grouped by run
+  const uint32_t* pk;        // packed entries
+  int32_t nslot;             // launch slots (workgroups)
+  int32_t P;                 // windows
+};
+
 // Schedule of an elementwise pass: contiguous element ranges per workgroup.
 struct Ranges {
   const int32_t* blk_start;

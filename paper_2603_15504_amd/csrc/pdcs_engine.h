@@ -103,6 +103,20 @@ struct PanelSet {
   void build_slots();
 };
 
+// Band-tile layout of a CSR-like structure (see BandTiles): R rows gathering
+// from a vector of G entries.  src maps every packed entry to its position in
+// the CSR order (-1 for padding), so the scaled values can be filled in.
+struct BandSet {
+  int P = 1;
+  int ntile = 0, nslot = 0;
+  int64_t R = 0, nent = 0;
+  DBuf group, slot, start, row0, nrows, col0, panel, run_start, run_row, run_ext, ext, pk, src;
+  DBuf val32, val64, part32, part64;
+  DBuf orig32, orig64;  // unscaled values (plain products), filled on first use
+  void build(int64_t R, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx);
+  BandTiles view() const;
+};
+
 template <typename T>
 struct IterBufs {
   DBuf b[16];
@@ -143,6 +157,9 @@ struct Engine {
   std::vector<double> h_v, h_vt;
   DBuf rec_dual_epi, rec_lam_epi;
   int panels_x = 0, panels_y = 0;   // 0: automatic
+  int layout = PDCS_LAYOUT_AUTO;
+  bool use_band = false;
+  BandSet band1, band2;             // band tiles of G (gathers x) and G^T (gathers y)
   hipStream_t stream = nullptr;
   std::map<int64_t, hipGraphExec_t> graphs;
   std::vector<hipEvent_t> events;

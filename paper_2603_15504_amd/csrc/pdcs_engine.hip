@@ -385,6 +385,221 @@ void PanelSet::build_slots() {
   upload(slot, sl);
 }
 
+// ---------------------------------------------------------------------------
+// Band tiles
+// ---------------------------------------------------------------------------
+namespace {
+struct BandBuild {
+  std::vector<int32_t> start, row0, nrows, col0, panel, run_start, run_row, run_ext, ext, src;
+  std::vector<uint32_t> pk;
+  std::vector<int64_t> work;  // entries per band-tile
+  std::vector<size_t> sizes() const {
+    return {start.size(), row0.size(), nrows.size(), col0.size(), panel.size(), run_start.size(), run_row.size(),
+            run_ext.size(), ext.size(), src.size(), pk.size(), work.size()};
+  }
+  void truncate(const std::vector<size_t>& z) {
+    start.resize(z[0]);
+    row0.resize(z[1]);
+    nrows.resize(z[2]);
+    col0.resize(z[3]);
+    panel.resize(z[4]);
+    run_start.resize(z[5]);
+    run_row.resize(z[6]);
+    run_ext.resize(z[7]);
+    ext.resize(z[8]);
+    src.resize(z[9]);
+    pk.resize(z[10]);
+    work.resize(z[11]);
+  }
+};
+
+// Entries of rows [r0, r1) with gathered index in window p, sorted by gathered
+// index, with accumulator slots assigned per 64-entry group; false if the
+// band needs more than kBandSlots - 1 slots.
+bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t W, const std::vector<int32_t>& ptr,
+                     const std::vector<int32_t>& idx, std::vector<int32_t>& stamp, std::vector<int32_t>& next,
+                     int32_t& gid, BandBuild& out) {
+  const int64_t c0 = (int64_t)p * W, c1 = c0 + W;
+  std::vector<std::pair<uint64_t, int32_t>> E;
+  for (int64_t r = r0; r < r1; ++r)
+    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
+      const int64_t c = idx[q];
+      if (c >= c0 && c < c1) E.push_back({((uint64_t)(c - c0) << 20) | (uint64_t)(r - r0), (int32_t)q});
+    }
+  std::sort(E.begin(), E.end());
+  const int nr = (int)(r1 - r0);
+  std::fill(next.begin(), next.end(), -1);
+  int nxt = nr;
+  const size_t base = out.pk.size();
+  out.start.push_back((int32_t)base);
+  out.row0.push_back((int32_t)r0);
+  out.nrows.push_back(nr);
+  out.col0.push_back((int32_t)c0);
+  out.panel.push_back(p);
+  for (size_t k = 0; k < E.size(); ++k) {
+    if (k % kWave == 0) ++gid;
+    const uint32_t col = (uint32_t)(E[k].first >> 20);
+    int s = (int)(E[k].first & 0xFFFFFu);
+    while (stamp[s] == gid) {
+      if (next[s] < 0) {
+        if (nxt >= kBandSlots - 1) return false;
+        next[s] = nxt++;
+      }
+      s = next[s];
+    }
+    stamp[s] = gid;
+    out.pk.push_back((col << kBandSlotBits) | (uint32_t)s);
+    out.src.push_back(E[k].second);
+  }
+  const size_t q = (size_t)kBandUnroll * kWave;
+  while ((out.pk.size() - base) % q) {
+    out.pk.push_back((uint32_t)(kBandSlots - 1));
+    out.src.push_back(-1);
+  }
+  for (int r = 0; r < nr; ++r) {
+    if (next[r] < 0) continue;
+    out.run_row.push_back(r);
+    for (int e = next[r]; e >= 0; e = next[e]) out.ext.push_back(e);
+    out.run_ext.push_back((int32_t)out.ext.size());
+  }
+  out.run_start.push_back((int32_t)out.run_row.size());
+  out.work.push_back((int64_t)E.size());
+  return true;
+}
+}  // namespace
+
+void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx) {
+  R = R_;
+  const int64_t wmax = (int64_t)1 << kBandColBits;
+  P = (int)std::max<int64_t>(1, (G + wmax - 1) / wmax);
+  const int64_t W = std::max<int64_t>(1, (G + P - 1) / P);
+  // band height: as tall as possible (better gather locality) while keeping
+  // at least about 768 band-tiles to spread over the 256 CUs
+  int64_t rb = kBandRows;
+  while (rb > 256 && ((R + rb - 1) / rb) * P < 768) rb /= 2;
+  BandBuild bb;
+  bb.run_start.push_back(0);
+  bb.run_ext.push_back(0);
+  std::vector<int32_t> stamp(kBandSlots, -1), next(kBandSlots, -1);
+  int32_t gid = 0;
+  std::vector<std::pair<int64_t, int64_t>> bands;  // row ranges, split on slot overflow
+  std::vector<std::pair<int64_t, int64_t>> todo;
+  for (int64_t r = R; r > 0; r -= rb) todo.push_back({std::max<int64_t>(0, r - rb), r});
+  while (!todo.empty()) {
+    const auto br = todo.back();
+    todo.pop_back();
+    const std::vector<size_t> save = bb.sizes();
+    bool ok = true;
+    for (int p = 0; p < P && ok; ++p) ok = build_band_tile(br.first, br.second, p, W, ptr, idx, stamp, next, gid, bb);
+    if (ok) {
+      bands.push_back(br);
+      continue;
+    }
+    if (br.second - br.first <= 1) throw Error(PDCS_ERR_SIZE, "band tile slot overflow");
+    bb.truncate(save);
+    const int64_t mid = br.first + (br.second - br.first) / 2;
+    todo.push_back({mid, br.second});
+    todo.push_back({br.first, mid});
+  }
+  bb.start.push_back((int32_t)bb.pk.size());
+  if (bb.pk.size() >= (size_t)INT32_MAX) throw Error(PDCS_ERR_SIZE, "band tiles exceed 2^31 entries");
+  ntile = (int)bands.size() * P;
+  nent = (int64_t)bb.pk.size();
+  // workgroups: kBandWaves consecutive bands of one window; windows routed to
+  // XCDs (slot s runs on XCD s % 8), window p to the XCDs x with x % P == p
+  const int nb = (int)bands.size();
+  const int ng = (nb + kBandWaves - 1) / kBandWaves;
+  std::vector<int32_t> grp;
+  std::vector<std::vector<int32_t>> per_xcd(8);
+  std::vector<int64_t> load(8, 0);
+  for (int p = 0; p < P; ++p)
+    for (int g = 0; g < ng; ++g) {
+      const int gi = (int)(grp.size() / kBandWaves);
+      int64_t work = 0;
+      for (int w = 0; w < kBandWaves; ++w) {
+        const int b = g * kBandWaves + w;
+        const int t = b < nb ? b * P + p : -1;
+        grp.push_back(t);
+        if (t >= 0) work += bb.work[t];
+      }
+      int best = -1;
+      for (int x = 0; x < 8; ++x) {
+        const bool serves = P >= 8 ? (p % 8 == x) : (x % P == p);
+        if (serves && (best < 0 || load[x] < load[best])) best = x;
+      }
+      load[best] += work + 1;
+      per_xcd[best].push_back(gi);
+    }
+  size_t depth = 0;
+  for (auto& l : per_xcd) depth = std::max(depth, l.size());
+  std::vector<int32_t> sl(depth * 8, -1);
+  for (int x = 0; x < 8; ++x)
+    for (size_t k = 0; k < per_xcd[x].size(); ++k) sl[k * 8 + x] = per_xcd[x][k];
+  nslot = (int)sl.size();
+  // every index the kernel reads, checked before anything reaches the device
+  auto fail = [](const char* what) { throw Error(PDCS_ERR_STATE, std::string("band layout check: ") + what); };
+  if ((int)bb.start.size() != ntile + 1 || (int)bb.run_start.size() != ntile + 1) fail("tile tables");
+  if (bb.run_ext.size() != bb.run_row.size() + 1 || bb.src.size() != bb.pk.size()) fail("run tables");
+  for (int32_t g : sl)
+    if (g >= (int32_t)(grp.size() / kBandWaves)) fail("slot table");
+  for (int32_t t : grp)
+    if (t >= ntile) fail("group table");
+  for (int t = 0; t < ntile; ++t) {
+    const int64_t e0 = bb.start[t], e1 = bb.start[t + 1];
+    if (e1 < e0 || (e1 - e0) % ((int64_t)kBandUnroll * kWave)) fail("tile padding");
+    if (bb.nrows[t] < 0 || bb.nrows[t] > kBandRows || (int64_t)bb.row0[t] + bb.nrows[t] > R) fail("tile rows");
+    if (bb.panel[t] < 0 || bb.panel[t] >= P || bb.col0[t] < 0) fail("tile window");
+    if (e1 > e0 && bb.col0[t] >= G) fail("tile window start");
+    for (int64_t e = e0; e < e1; ++e) {
+      const uint32_t slot_e = bb.pk[e] & ((1u << kBandSlotBits) - 1u);
+      const int64_t col = (int64_t)bb.col0[t] + (bb.pk[e] >> kBandSlotBits);
+      if (slot_e >= (uint32_t)kBandSlots || col >= G) fail("entry");
+      if (bb.src[e] >= 0 && (bb.src[e] >= ptr[R] || idx[bb.src[e]] != col)) fail("entry source");
+    }
+    for (int32_t r = bb.run_start[t]; r < bb.run_start[t + 1]; ++r) {
+      if (bb.run_row[r] < 0 || bb.run_row[r] >= bb.nrows[t]) fail("run row");
+      for (int32_t q = bb.run_ext[r]; q < bb.run_ext[r + 1]; ++q)
+        if (bb.ext[q] < bb.nrows[t] || bb.ext[q] >= kBandSlots - 1) fail("extra slot");
+    }
+  }
+  upload(group, grp);
+  upload(slot, sl);
+  upload(start, bb.start);
+  upload(row0, bb.row0);
+  upload(nrows, bb.nrows);
+  upload(col0, bb.col0);
+  upload(panel, bb.panel);
+  upload(run_start, bb.run_start);
+  upload(run_row, bb.run_row);
+  upload(run_ext, bb.run_ext);
+  upload(ext, bb.ext);
+  upload(pk, bb.pk);
+  upload(src, bb.src);
+  val32.alloc((size_t)nent * 4);
+  val64.alloc((size_t)nent * 8);
+  part32.alloc((size_t)P * R * 4);
+  part64.alloc((size_t)P * R * 8);
+}
+
+BandTiles BandSet::view() const {
+  BandTiles b{};
+  b.group = group.as<int32_t>();
+  b.slot = slot.as<int32_t>();
+  b.start = start.as<int32_t>();
+  b.row0 = row0.as<int32_t>();
+  b.nrows = nrows.as<int32_t>();
+  b.col0 = col0.as<int32_t>();
+  b.panel = panel.as<int32_t>();
+  b.run_start = run_start.as<int32_t>();
+  b.run_row = run_row.as<int32_t>();
+  b.run_ext = run_ext.as<int32_t>();
+  b.ext = ext.as<int32_t>();
+  b.pk = pk.as<uint32_t>();
+  b.nslot = nslot;
+  b.P = P;
+  return b;
+}
+
 static int auto_panels(int64_t gathered) {
   // about 1 MiB of FP32 gathered values per panel, at most 8 (one per XCD)
   const int64_t per = 256 * 1024;
@@ -501,6 +716,13 @@ void Engine::build_schedule() {
   prow.P = pcol.P = 1;
   if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
   if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
+  const bool want_band = B == 1 && (layout == PDCS_LAYOUT_BANDS ||
+                                    (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 23)));
+  if (want_band && !use_band) {
+    band1.build(M, N, h_rp, h_ci);
+    band2.build(N, M, h_cp, h_ri);
+  }
+  use_band = want_band;
   rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
   rec_lam_epi.alloc((size_t)std::max(vcol.nblk, 1) * 3 * 8);
   const int nr = std::max(brow.nblk, 1), nc = std::max(bcol.nblk, 1);
@@ -573,6 +795,19 @@ KernelCtx Engine::ctx(int probe_passes) const {
     k.part32 = prow.part32.as<float>();
     k.part64 = prow.part64.as<double>();
     k.part64b = prow.part64b.as<double>();
+  }
+  k.use_band = use_band ? 1 : 0;
+  if (use_band) {
+    k.band1 = band1.view();
+    k.band2 = band2.view();
+    k.bval32 = band1.val32.as<float>();
+    k.bval64 = band1.val64.as<double>();
+    k.bvalT32 = band2.val32.as<float>();
+    k.bvalT64 = band2.val64.as<double>();
+    k.bpart32 = band1.part32.as<float>();
+    k.bpart64 = band1.part64.as<double>();
+    k.bpartT32 = band2.part32.as<float>();
+    k.bpartT64 = band2.part64.as<double>();
   }
   if (pcol.P > 1) {
     k.pcol = pcol.tiles.view();
@@ -742,6 +977,16 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     su.PAT = MatPtrs<double>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.d_val.as<double>()};
     su.pvalT64 = pcol.val64.as<double>();
     su.pvalT32 = pcol.val32.as<float>();
+  }
+  if (use_band) {
+    su.bsrc = band1.src.as<int32_t>();
+    su.bsrcT = band2.src.as<int32_t>();
+    su.bn = band1.nent;
+    su.bnT = band2.nent;
+    su.bval64 = band1.val64.as<double>();
+    su.bval32 = band1.val32.as<float>();
+    su.bvalT64 = band2.val64.as<double>();
+    su.bvalT32 = band2.val32.as<float>();
   }
   launch_setup(k, su, stream, start_mask);
   HIP_OK(hipGetLastError());
@@ -1038,7 +1283,17 @@ int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, cons
       upload(e.orig32, a);
       upload(e.origT32, at);
     }
-    if (!transpose) {
+    if (e.use_band) {
+      BandSet& bs = transpose ? e.band2 : e.band1;
+      if (!bs.orig64.p) {
+        bs.orig64.alloc((size_t)bs.nent * 8);
+        bs.orig32.alloc((size_t)bs.nent * 4);
+        launch_band_vals(bs.src.as<int32_t>(), bs.nent, transpose ? e.d_vt.as<double>() : e.d_v.as<double>(),
+                         bs.orig64.as<double>(), bs.orig32.as<float>(), s);
+      }
+      launch_band_plain(bs.view(), f32 ? kFP32 : kFP64, f32 ? bs.orig32.p : bs.orig64.p, in_dev,
+                        f32 ? bs.part32.p : bs.part64.p, bs.R, out_dev, s);
+    } else if (!transpose) {
       launch_spmv_plain(e.brow.view(), f32 ? kFP32 : kFP64, e.d_rp.as<int32_t>(), e.d_ci.as<int32_t>(),
                         f32 ? e.orig32.p : e.d_v.p, in_dev, out_dev, s);
     } else {
@@ -1046,6 +1301,17 @@ int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, cons
                         f32 ? e.origT32.p : e.d_vt.p, in_dev, out_dev, s);
     }
     HIP_OK(hipGetLastError());
+    return PDCS_OK;
+  });
+}
+
+int pdcs_problem_set_layout(pdcs_problem p, int64_t layout) {
+  return guarded([&]() {
+    if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
+    if (layout != PDCS_LAYOUT_AUTO && layout != PDCS_LAYOUT_ROWS && layout != PDCS_LAYOUT_BANDS)
+      throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
+    p->eng->layout = (int)layout;
+    p->eng->build_schedule();
     return PDCS_OK;
   });
 }

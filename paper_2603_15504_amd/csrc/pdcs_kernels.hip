@@ -179,6 +179,124 @@ __global__ __launch_bounds__(kBlock) void k_spmv_part(RowBlocks rb, const int32_
                 [&](int r, const double* s) { part[r] = (T)s[0]; });
 }
 
+// ---------------------------------------------------------------------------
+// Band-tile SpMV for single large instances (layout: BandTiles).  The gathers
+// of a band-tile stay inside one window of the gathered vector, held in the L2
+// of the XCDs that serve the window, and since the entries are sorted by
+// gathered index the 64 lanes of a wave instruction read few cache lines.  Each
+// wave sums its band in a private LDS array with plain read-modify-writes: the
+// host never lets two entries of one 64-entry group share a slot, and LDS
+// operations of one wave complete in issue order, so no atomics are needed and
+// the result does not depend on scheduling.  The entry stream is software
+// pipelined: packed entries and values are loaded two iterations ahead and the
+// gathers one iteration ahead of the accumulation.  Output: part[panel * R + r].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, const T* __restrict__ val,
+                                                                  const T* __restrict__ x, T* __restrict__ part,
+                                                                  int64_t R, const Inst* __restrict__ inst,
+                                                                  int need_acc) {
+  constexpr int U = kBandUnroll;
+  __shared__ T acc[kBandWaves * kBandSlots];
+  const int g = bt.slot[blockIdx.x];
+  if (g < 0) return;
+  if (inst && (inst[0].status != kActive || (need_acc && inst[0].last_acc == 0))) return;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int t = bt.group[g * kBandWaves + w];
+  if (t < 0) return;
+  T* a = acc + w * kBandSlots;
+  for (int i = lane; i < kBandSlots; i += kWave) a[i] = T(0);
+  const T* xs = x + bt.col0[t];
+  const int e0 = bt.start[t];
+  const int nit = (bt.start[t + 1] - e0) / (U * kWave);
+  const uint32_t* pp = bt.pk + e0 + lane;
+  const T* vp = val + e0 + lane;
+  constexpr uint32_t kSlotMask = (1u << kBandSlotBits) - 1u;
+  uint32_t pA[U], pB[U], pC[U];
+  T vA[U], vB[U], vC[U], xA[U], xB[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    pA[u] = pB[u] = pC[u] = 0u;
+    vA[u] = vB[u] = vC[u] = xA[u] = xB[u] = T(0);
+  }
+  if (nit > 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      pA[u] = __builtin_nontemporal_load(pp + u * kWave);
+      vA[u] = __builtin_nontemporal_load(vp + u * kWave);
+    }
+  }
+  if (nit > 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      pB[u] = __builtin_nontemporal_load(pp + (U + u) * kWave);
+      vB[u] = __builtin_nontemporal_load(vp + (U + u) * kWave);
+    }
+  }
+  if (nit > 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) xA[u] = xs[pA[u] >> kBandSlotBits];
+  }
+  for (int it = 0; it < nit; ++it) {
+    if (it + 2 < nit) {
+      const int off = (it + 2) * U * kWave;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        pC[u] = __builtin_nontemporal_load(pp + off + u * kWave);
+        vC[u] = __builtin_nontemporal_load(vp + off + u * kWave);
+      }
+    }
+    if (it + 1 < nit) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) xB[u] = xs[pB[u] >> kBandSlotBits];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t sl = pA[u] & kSlotMask;
+      a[sl] = a[sl] + vA[u] * xA[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      pA[u] = pB[u];
+      vA[u] = vB[u];
+      xA[u] = xB[u];
+      pB[u] = pC[u];
+      vB[u] = vC[u];
+    }
+  }
+  // fold the extra slots into their rows (one lane per run, runs own distinct rows)
+  for (int r = bt.run_start[t] + lane; r < bt.run_start[t + 1]; r += kWave) {
+    const int row = bt.run_row[r];
+    T s = a[row];
+    for (int q = bt.run_ext[r]; q < bt.run_ext[r + 1]; ++q) s += a[bt.ext[q]];
+    a[row] = s;
+  }
+  const int nr = bt.nrows[t];
+  T* out = part + (size_t)bt.panel[t] * R + bt.row0[t];
+  for (int i = lane; i < nr; i += kWave) out[i] = a[i];
+}
+
+// Sum of the P window partial sums per row (plain product of the band layout).
+template <typename T>
+__global__ void k_band_sum(const T* __restrict__ part, int P, int64_t R, T* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += (double)part[(size_t)p * R + r];
+  out[r] = (T)s;
+}
+
+// Set-up: band-tile values from the scaled CSR (CSC) values.
+__global__ void k_band_vals(const int32_t* __restrict__ src, int64_t n, const double* __restrict__ v64,
+                            double* __restrict__ o64, float* __restrict__ o32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int32_t q = src[e];
+  const double v = q >= 0 ? v64[q] : 0.0;
+  o64[e] = v;
+  o32[e] = (float)v;
+}
+
 // K1b: combine the P partial sums of G x_hat per row, then the dual step
 // (same epilogue and record as k_dual).
 template <typename T>
@@ -1395,9 +1513,24 @@ static void launch_primal_t(const KernelCtx& k, hipStream_t s, int prec, const I
 }
 
 template <typename T>
+static const T* band_val(const KernelCtx& k, int which);
+template <>
+const float* band_val<float>(const KernelCtx& k, int which) {
+  return which ? k.bvalT32 : k.bval32;
+}
+template <>
+const double* band_val<double>(const KernelCtx& k, int which) {
+  return which ? k.bvalT64 : k.bval64;
+}
+
+template <typename T>
 static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                           const DataPtrs<T>& d, const MatPtrs<T>& A, const MatPtrs<T>& PA, T* part) {
-  if (k.P1 > 1) {
+  if (k.use_band) {
+    if (k.band1.nslot > 0)
+      k_band_spmv<T><<<grid1(k.band1.nslot), kBandWaves * kWave, 0, s>>>(k.band1, band_val<T>(k, 0), it.xh, part,
+                                                                         k.M, k.inst, 0);
+  } else if (k.P1 > 1) {
     if (k.nslot1 > 0)
       k_spmv_part<T, T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, PA, it.xh, part, k.inst, 0);
   } else if (k.brow.nblk > 0) {
@@ -1408,20 +1541,25 @@ static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const Ite
 template <typename T>
 static void launch_dual_epi_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                               const DataPtrs<T>& d, const T* part) {
-  if (k.P1 > 1 && k.vrow.nblk > 0)
-    k_dual_epi<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, part, k.P1, k.M, it, d, k.inst, prec,
-                                                         k.rec_dual_epi);
+  if (k.split1() && k.vrow.nblk > 0)
+    k_dual_epi<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, part, k.use_band ? k.band1.P : k.P1, k.M, it, d,
+                                                         k.inst, prec, k.rec_dual_epi);
 }
 
 template <typename T>
 static void launch_lam_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                          const DataPtrs<T>& d, const MatPtrs<T>& AT, const MatPtrs<T>& PAT, T* part) {
-  if (k.P2 > 1) {
-    if (k.nslot2 > 0)
+  if (k.split2()) {
+    if (k.use_band) {
+      if (k.band2.nslot > 0)
+        k_band_spmv<T><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, band_val<T>(k, 1), it.yh,
+                                                                           part, k.N, k.inst, 1);
+    } else if (k.nslot2 > 0) {
       k_spmv_part<T, T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, PAT, it.yh, part, k.inst, 1);
+    }
     if (k.vcol.nblk > 0)
-      k_lam_epi<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, part, k.P2, k.N, it, d, k.inst, prec,
-                                                          k.rec_lam_epi);
+      k_lam_epi<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, part, k.use_band ? k.band2.P : k.P2, k.N, it, d,
+                                                          k.inst, prec, k.rec_lam_epi);
   } else if (k.bcol.nblk > 0) {
     k_lam<T, T><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, AT, it, d, k.inst, prec, k.rec_lam);
   }
@@ -1435,19 +1573,21 @@ void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
     if (mask & 2) launch_primal_t<double>(k, s, kFP64, k.it64, k.d64);
     return;
   }
+  float* p32 = k.use_band ? k.bpart32 : k.part32;
+  double* p64 = k.use_band ? k.bpart64 : k.part64;
   if (part == 1) {
-    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, k.part32);
-    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, k.part64);
+    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, p32);
+    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, p64);
     return;
   }
-  if (mask & 1) launch_dual_epi_t<float>(k, s, kFP32, k.it32, k.d32, k.part32);
-  if (mask & 2) launch_dual_epi_t<double>(k, s, kFP64, k.it64, k.d64, k.part64);
-  const bool s1 = k.P1 > 1, s2 = k.P2 > 1;
+  if (mask & 1) launch_dual_epi_t<float>(k, s, kFP32, k.it32, k.d32, p32);
+  if (mask & 2) launch_dual_epi_t<double>(k, s, kFP64, k.it64, k.d64, p64);
+  const bool s1 = k.split1(), s2 = k.split2();
   k_fin_ls<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol.inst_blk0, k.rec_primal,
                                            s1 ? k.vrow.inst_blk0 : k.brow.inst_blk0,
                                            s1 ? k.rec_dual_epi : k.rec_dual, k.inst);
-  if (mask & 1) launch_lam_t<float>(k, s, kFP32, k.it32, k.d32, k.AT32, k.PAT32, k.partT32);
-  if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.PAT64, k.partT64);
+  if (mask & 1) launch_lam_t<float>(k, s, kFP32, k.it32, k.d32, k.AT32, k.PAT32, k.use_band ? k.bpartT32 : k.partT32);
+  if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.PAT64, k.use_band ? k.bpartT64 : k.partT64);
   k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(s2 ? k.vcol.inst_blk0 : k.bcol.inst_blk0,
                                              s2 ? k.rec_lam_epi : k.rec_lam, k.inst);
 }
@@ -1622,6 +1762,12 @@ void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mas
   if (k.P2 > 1 && k.pcol.nblk > 0)
     k_scale_vals<<<grid1(k.pcol.nblk), kBlock, 0, s>>>(k.pcol, su.PAT, k.D1, k.D2, 1, (int)k.N, su.pvalT64,
                                                         su.pvalT32);
+  if (k.use_band) {
+    if (su.bn > 0)
+      k_band_vals<<<blocks(su.bn), tpb, 0, s>>>(su.bsrc, su.bn, su.val64, su.bval64, su.bval32);
+    if (su.bnT > 0)
+      k_band_vals<<<blocks(su.bnT), tpb, 0, s>>>(su.bsrcT, su.bnT, su.valT64, su.bvalT64, su.bvalT32);
+  }
   if (k.vcol.nblk > 0)
     k_scale_cols<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.c, su.l, su.u, k.D2, su.d64m, su.d32m);
   if (k.vrow.nblk > 0)
@@ -1670,9 +1816,28 @@ void launch_spmv_plain(const RowBlocks& rb, int prec, const int32_t* ptr, const 
 }
 
 // One K1 pass on its own (for schedule timing).
+void launch_band_plain(const BandTiles& bt, int prec, const void* val, const void* in, void* part, int64_t R,
+                       void* out, hipStream_t s) {
+  if (bt.nslot <= 0 || R <= 0) return;
+  const dim3 g((unsigned)((R + 255) / 256));
+  if (prec == kFP64) {
+    k_band_spmv<double><<<grid1(bt.nslot), kBandWaves * kWave, 0, s>>>(bt, (const double*)val, (const double*)in,
+                                                                       (double*)part, R, nullptr, 0);
+    k_band_sum<double><<<g, 256, 0, s>>>((const double*)part, bt.P, R, (double*)out);
+  } else {
+    k_band_spmv<float><<<grid1(bt.nslot), kBandWaves * kWave, 0, s>>>(bt, (const float*)val, (const float*)in,
+                                                                      (float*)part, R, nullptr, 0);
+    k_band_sum<float><<<g, 256, 0, s>>>((const float*)part, bt.P, R, (float*)out);
+  }
+}
+
+void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* o64, float* o32, hipStream_t s) {
+  if (n > 0) k_band_vals<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, v64, o64, o32);
+}
+
 void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec) {
-  if (prec == kFP32) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, k.part32);
-  else launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, k.part64);
+  if (prec == kFP32) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, k.use_band ? k.bpart32 : k.part32);
+  else launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, k.use_band ? k.bpart64 : k.part64);
 }
 
 }  // namespace pdcs

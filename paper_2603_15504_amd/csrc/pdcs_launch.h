@@ -66,6 +66,19 @@ struct KernelCtx {
   float *part32, *partT32;
   double *part64, *partT64, *part64b, *partT64b;
   double *rec_dual_epi, *rec_lam_epi;
+  // Band-tile layout (single instances): when use_band is set, the two SpMVs of
+  // a trial run on band1 (G, windows over x) and band2 (G^T, windows over y),
+  // writing band1.P (band2.P) partial sums per row that the epilogues combine.
+  int use_band;
+  BandTiles band1, band2;
+  const float *bval32, *bvalT32;
+  const double *bval64, *bvalT64;
+  float *bpart32, *bpartT32;
+  double *bpart64, *bpartT64;
+
+  // the K1 (K2) product is split into partial sums plus an epilogue pass
+  bool split1() const { return use_band || P1 > 1; }
+  bool split2() const { return use_band || P2 > 1; }
 };
 
 struct SetupCtx {
@@ -81,6 +94,11 @@ struct SetupCtx {
   MatPtrs<double> PA, PAT;        // panel-major unscaled values (when split)
   double *pval64, *pvalT64;
   float *pval32, *pvalT32;
+  // band-tile values: entry e takes the scaled CSR (CSC) value at src[e] (-1: padding)
+  const int32_t *bsrc, *bsrcT;
+  int64_t bn, bnT;
+  double *bval64, *bvalT64;
+  float *bval32, *bvalT32;
 };
 
 void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mask);
@@ -93,6 +111,10 @@ void launch_flush_commit(const KernelCtx& k, hipStream_t s, int mask);
 void launch_spmv_plain(const RowBlocks& rb, int prec, const int32_t* ptr, const int32_t* idx, const void* val,
                        const void* in, void* out, hipStream_t s);
 void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec);
+// Plain product with band tiles: partial sums into part (P x R), then out = their sum.
+void launch_band_plain(const BandTiles& bt, int prec, const void* val, const void* in, void* part, int64_t R,
+                       void* out, hipStream_t s);
+void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* o64, float* o32, hipStream_t s);
 
 // Trial split for kernel timing: K3, K1, and the rest of the trial.
 void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part);

@@ -213,3 +213,106 @@ def test_first_trials_scalars_match_oracle(seed, m, panels):
         assert row[7] == pytest.approx(t["eta_next"], rel=1e-9)
         if t["accepted"]:
             assert row[8] == pytest.approx(t["beta"], rel=1e-9, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Band-tile layout (forced on instances small enough for the oracle)
+# ---------------------------------------------------------------------------
+def _band_problem(inst):
+    prob = P.Problem.from_instance(inst)
+    prob.set_layout("bands")
+    return prob
+
+
+@pytest.mark.parametrize("seed,m", [(0, 300), (1, 3000)])
+def test_band_layout_first_trials_match_oracle(seed, m):
+    inst = lpgen.c1_instance(seed, m=m, n=2 * m)
+    lp = O.lpdata_from_instance(inst)
+    ref = O.solve(lp, O.Options(max_iter=64, check_every=64), trace=True)
+    sol = _band_problem(inst).solve(precision="fp64", max_iter=64, check_every=64, trace_trials=64)
+    for row, t in zip(sol.trace, ref.trace):
+        assert int(row[0]) == t["kbar"] and bool(row[6]) == t["accepted"]
+        assert row[1] == pytest.approx(t["eta"], rel=1e-9)
+        assert row[7] == pytest.approx(t["eta_next"], rel=1e-9)
+        if t["accepted"]:
+            assert row[8] == pytest.approx(t["beta"], rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("maker", ["c1", "dense_runs"])
+def test_band_layout_state_matches_oracle(maker):
+    # dense_runs puts 64 consecutive gathered indices in one row, so every
+    # 64-entry group of its tiles repeats a row: extra accumulator slots, and
+    # (256 rows x 63 extras > slot capacity) a band split, are exercised
+    inst = lpgen.c1_instance(2, m=2000, n=4000) if maker == "c1" else lpgen.dense_runs_instance(0)
+    lp = O.lpdata_from_instance(inst)
+    ref = O.solve(lp, O.Options(max_iter=63, check_every=1000))
+    sol = _band_problem(inst).solve(precision="fp64", max_iter=63, check_every=1000, keep_state=True)
+    st = sol.state
+    assert st["k"] == ref.state["k"] and st["kbar"] == ref.state["kbar"]
+    # dense_runs amplifies rounding: in the oracle itself, a 1e-16 relative
+    # perturbation of its values moves y by 2.6e-11 after 63 trials (c1: 2.6e-13),
+    # and its rows of 64 nearly cancelling terms are summed in another order here
+    tol = 1e-9 if maker == "c1" else 1e-7
+    for key in ("x", "y", "x_hat", "y_hat"):
+        a, b = st[key], ref.state[key]
+        assert np.max(np.abs(a - b)) <= tol * (1.0 + np.abs(b).max()), key
+    # maintained products against a direct product of the oracle's iterates
+    G = lp.G.toarray() if lp.G.shape[0] * lp.G.shape[1] < 4e7 else None
+    if G is not None:
+        D1, D2 = O.ruiz_l2_scaling(lp.G, 10, True)
+        Gs = (D1[:, None] * G) * D2[None, :]
+        gty = Gs.T @ ref.state["y_hat"]
+        assert np.max(np.abs(st["gty_hat"] - gty)) <= 1e-9 * (1 + np.abs(gty).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_band_layout_solves_c0(precision):
+    inst = lpgen.c0_instance(3)
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options())
+    sol = _band_problem(inst).solve(precision=precision, time_limit=60.0)
+    _check_solution(inst, sol, ref.pobj)
+
+
+def test_band_layout_solves_dense_runs():
+    inst = lpgen.dense_runs_instance(1)
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options(time_limit=120))
+    assert ref.exit_code == 0
+    sol = _band_problem(inst).solve(precision="mixed", time_limit=60.0)
+    _check_solution(inst, sol, ref.pobj)
+
+
+@pytest.mark.parametrize("maker", ["c1", "dense_runs", "c1_wide"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_band_layout_spmv_elementwise(maker, precision):
+    # The band SpMV itself, both directions, against scipy.  Each row is summed
+    # sequentially per accumulator slot and window, the window sums are stored
+    # in the value type and added in FP64, so with u the unit roundoff of the
+    # value type the error is at most (len + 4) u sum_j |a_ij x_j|.
+    torch = pytest.importorskip("torch")
+    if maker == "c1":
+        inst = lpgen.c1_instance(3, m=5000, n=10000)
+    elif maker == "c1_wide":      # more than 2^18 gathered columns: several windows
+        inst = lpgen.c1_instance(4, m=20000, n=600000, max_len=400)
+    else:
+        inst = lpgen.dense_runs_instance(2)
+    A = inst.scipy_csr()
+    prob = _band_problem(inst)
+    rng = np.random.default_rng(7)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    for transpose in (False, True):
+        M = (A.T if transpose else A).tocsr()
+        x = rng.standard_normal(M.shape[1])
+        if precision == "mixed":
+            x = x.astype(np.float32).astype(np.float64)
+            M.data = M.data.astype(np.float32).astype(np.float64)
+        want = M @ x
+        bound = abs(M) @ np.abs(x)
+        xin = torch.tensor(x, dtype=dt, device="cuda")
+        out = torch.empty(M.shape[0], dtype=dt, device="cuda")
+        prob.spmv(xin.data_ptr(), out.data_ptr(), transpose=transpose, precision=precision)
+        torch.cuda.synchronize()
+        got = out.double().cpu().numpy()
+        lens = np.diff(M.indptr)
+        err = np.abs(got - want)
+        assert np.all(err <= (lens + 4) * u * bound), (transpose, np.max(err / (bound + 1e-300)))
