@@ -22,8 +22,11 @@
  *  - Handles (problem, result, batch, mlp) are owned by the library until the
  *    matching *_destroy call.  A handle must not be used from two threads at once.
  *  - +-infinity bounds are IEEE infinities.  NaN anywhere in the data is an error.
- *  - "stream" arguments are a hipStream_t passed as void* (NULL = the library's
- *    own stream).  Solve calls are synchronous: they return with results on host.
+ *  - "stream" arguments are a hipStream_t passed as void*.  The device-pointer
+ *    calls (pdcs_problem_spmv, pdcs_mlp_*) are enqueued on that stream, NULL
+ *    meaning the HIP null stream, which is ordered with the caller's work on
+ *    blocking streams (e.g. PyTorch's default stream).  Solve calls run on the
+ *    library's own stream and are synchronous: they return with results on host.
  *  - pdcs_last_error() returns a static string describing the last failure of
  *    the calling thread.
  */

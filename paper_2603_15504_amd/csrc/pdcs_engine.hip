@@ -1272,7 +1272,7 @@ int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, cons
     if (precision != PDCS_PRECISION_FP64 && precision != PDCS_PRECISION_MIXED)
       throw Error(PDCS_ERR_INVALID_ARG, "unknown precision");
     Engine& e = *p->eng;
-    hipStream_t s = stream ? (hipStream_t)stream : e.stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL: the HIP null stream
     const bool f32 = precision == PDCS_PRECISION_MIXED;
     if (f32 && !e.orig32.p) {
       std::vector<float> a(e.NNZ), at(e.NNZ);

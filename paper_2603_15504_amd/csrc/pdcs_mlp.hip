@@ -342,7 +342,9 @@ int pdcs_mlp_create(int64_t d_in, int64_t width, int64_t d_out, uint64_t seed, p
   }
 }
 
-static hipStream_t pick(pdcs_mlp net, void* stream) { return stream ? (hipStream_t)stream : net->stream; }
+// the caller's stream; NULL is the HIP null stream (ordered with the caller's
+// default-stream work), never the library's own non-blocking stream
+static hipStream_t pick(pdcs_mlp, void* stream) { return (hipStream_t)stream; }
 
 int pdcs_mlp_forward(pdcs_mlp net, const float* in_dev, float* out_dev, int64_t batch, void* stream) {
   try {
@@ -411,7 +413,7 @@ int pdcs_mlp_num_params(pdcs_mlp net, int64_t* count) {
 int pdcs_mlp_get_params(pdcs_mlp net, float* params_host) {
   try {
     if (!net || !params_host) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
-    HIP_OK(hipStreamSynchronize(net->stream));
+    HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(params_host, net->params.p, net->np * 4, hipMemcpyDeviceToHost));
     return PDCS_OK;
   } catch (const Error& e) {
