@@ -273,6 +273,15 @@ int  pdcs_mlp_train_step(pdcs_mlp net, const float* in_dev, const float* target_
  * W2[width x width], b2[width], W3[d_out x width], b3[d_out]). */
 int  pdcs_mlp_gradients(pdcs_mlp net, const float* in_dev, const float* target_dev,
                         int64_t batch, float* grad_dev, float* loss_out, void* stream);
+/* Feature standardization, host float arrays: the network sees
+ * (u - in_mean) / in_scale (d_in features) and its raw output z is returned by
+ * pdcs_mlp_forward as z * out_scale + out_mean (d_out features); training
+ * targets are standardized the same way, so the loss is the MSE in
+ * standardized units.  A NULL mean/scale pair means identity for that side
+ * (the default).  Scales must be finite and > 0.  Copied; the call waits for
+ * the device to be idle.  Errors: PDCS_ERR_INVALID_ARG. */
+int  pdcs_mlp_set_normalization(pdcs_mlp net, const float* in_mean, const float* in_scale,
+                                const float* out_mean, const float* out_scale);
 int  pdcs_mlp_num_params(pdcs_mlp net, int64_t* count);
 /* Read or write the FP32 master weights (host float[num_params], same layout
  * as the gradients).  Writing also refreshes the BF16 copies. */

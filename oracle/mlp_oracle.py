@@ -95,3 +95,19 @@ def adam_step(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def forward_normalized(params, u, d_in, w, d_out, norm, bf16=False):
+    """Forward pass with feature standardization norm = (in_mean, in_scale,
+    out_mean, out_scale): the network sees (u - in_mean) / in_scale and its
+    output z is returned as z * out_scale + out_mean."""
+    in_mean, in_scale, out_mean, out_scale = (np.asarray(a, np.float64) for a in norm)
+    z, _ = forward(params, (np.asarray(u, np.float64) - in_mean) / in_scale, d_in, w, d_out, bf16)
+    return z * out_scale + out_mean
+
+
+def loss_and_grad_normalized(params, u, t, d_in, w, d_out, norm, bf16=False):
+    """MSE in standardized units: inputs and targets standardized per feature."""
+    in_mean, in_scale, out_mean, out_scale = (np.asarray(a, np.float64) for a in norm)
+    return loss_and_grad(params, (np.asarray(u, np.float64) - in_mean) / in_scale,
+                         (np.asarray(t, np.float64) - out_mean) / out_scale, d_in, w, d_out, bf16)

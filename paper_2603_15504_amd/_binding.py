@@ -93,6 +93,7 @@ PROTOTYPES = {
     "pdcs_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
     "pdcs_mlp_train_step": (C.c_int, [_P, _P, _P, _I64, C.c_float, C.POINTER(C.c_float), _P]),
     "pdcs_mlp_gradients": (C.c_int, [_P, _P, _P, _I64, _P, C.POINTER(C.c_float), _P]),
+    "pdcs_mlp_set_normalization": (C.c_int, [_P, _P, _P, _P, _P]),
     "pdcs_mlp_num_params": (C.c_int, [_P, C.POINTER(_I64)]),
     "pdcs_mlp_get_params": (C.c_int, [_P, _P]),
     "pdcs_mlp_set_params": (C.c_int, [_P, _P]),
@@ -489,6 +490,12 @@ def pdcs_mlp_gradients(net, in_dev: int, target_dev: int, batch: int, grad_dev: 
     return loss.value
 
 
+def pdcs_mlp_set_normalization(net, in_mean=None, in_scale=None, out_mean=None, out_scale=None):
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+            for a in (in_mean, in_scale, out_mean, out_scale)]
+    _check(lib.pdcs_mlp_set_normalization(net, *[_ptr(a) for a in arrs]), "pdcs_mlp_set_normalization")
+
+
 def pdcs_mlp_num_params(net) -> int:
     n = C.c_int64()
     _check(lib.pdcs_mlp_num_params(net, C.byref(n)), "pdcs_mlp_num_params")
@@ -542,6 +549,10 @@ class MLP:
         loss = pdcs_mlp_gradients(self.handle, u.data_ptr(), t.data_ptr(), u.shape[0], g.data_ptr(),
                                   torch.cuda.current_stream().cuda_stream)
         return loss, g
+
+    def set_normalization(self, in_mean=None, in_scale=None, out_mean=None, out_scale=None):
+        """Per-feature standardization of inputs and outputs (host arrays)."""
+        pdcs_mlp_set_normalization(self.handle, in_mean, in_scale, out_mean, out_scale)
 
     @property
     def params(self):

@@ -131,14 +131,48 @@ __global__ void k_to_bf16(const float* __restrict__ in, bf16* __restrict__ out, 
   if (i < n) out[i] = to_bf16(in[i]);
 }
 
-// Per-block partial sums of (v - t)^2; dv = 2 (v - t) / count; BF16 copy of dv.
+// Standardized BF16 input: (u - mean) / scale per feature (identity when mean is null).
+__global__ void k_in_norm(const float* __restrict__ in, const float* __restrict__ mu,
+                          const float* __restrict__ inv_scale, int64_t n, int d, bf16* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v = in[i];
+  if (mu) {
+    const int j = (int)(i % d);
+    v = (v - mu[j]) * inv_scale[j];
+  }
+  out[i] = to_bf16(v);
+}
+
+// Network output in the caller's units: z * scale + mean per feature.
+__global__ void k_out_denorm(const float* __restrict__ z, const float* __restrict__ mu,
+                             const float* __restrict__ scale, int64_t n, int d, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v = z[i];
+  if (mu) {
+    const int j = (int)(i % d);
+    v = v * scale[j] + mu[j];
+  }
+  out[i] = v;
+}
+
+// Per-block partial sums of (v - t)^2 with t standardized like the outputs
+// ((t - mean) / scale per feature when mean is non-null); dv = 2 (v - t) / count;
+// BF16 copy of dv.
 __global__ void k_mse(const float* __restrict__ v, const float* __restrict__ t, int64_t n, float scale,
+                      const float* __restrict__ tmu, const float* __restrict__ tinv, int d,
                       float* __restrict__ dv, bf16* __restrict__ dv16, double* __restrict__ part) {
   __shared__ double red[256];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double e2 = 0.0;
   if (i < n) {
-    const float d = v[i] - t[i];
+    float ti = t[i];
+    if (tmu) {
+      const int j = (int)(i % d);
+      ti = (ti - tmu[j]) * tinv[j];
+    }
+    const float d = v[i] - ti;
     e2 = (double)d * (double)d;
     const float g = 2.0f * d * scale;
     dv[i] = g;
@@ -197,6 +231,11 @@ struct pdcs_mlp_s {
   int64_t din = 0, w = 0, dout = 0, np = 0;
   int64_t off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
   DBuf params, grads, adam_m, adam_v, wbf;  // wbf: BF16 W1 | W2 | W3
+  // feature standardization (in: mean, 1/scale; out: mean, scale, 1/scale)
+  DBuf in_mu, in_inv, out_mu, out_sc, out_inv;
+  bool norm_in = false, norm_out = false;
+  const float* imu() const { return norm_in ? in_mu.as<float>() : nullptr; }
+  const float* omu() const { return norm_out ? out_mu.as<float>() : nullptr; }
   int64_t step = 0;
   int64_t cap = 0;  // batch capacity of the activation buffers
   DBuf u16, z1, h1_16, z2, h2_16, vout, dv, dv16, dh, dz16a, dz16b, part, lossp, lossv;
@@ -255,7 +294,7 @@ struct pdcs_mlp_s {
 
   void forward(const float* in, int64_t B, hipStream_t s) {
     ensure(B);
-    k_to_bf16<<<lin(B * din), 256, 0, s>>>(in, u16.as<bf16>(), B * din);
+    k_in_norm<<<lin(B * din), 256, 0, s>>>(in, imu(), in_inv.as<float>(), B * din, (int)din, u16.as<bf16>());
     gemm(u16.as<bf16>(), din, 0, W1(), din, 1, B, w, din, P(off_b1), 1, nullptr, z1.as<float>(), h1_16.as<bf16>(), s);
     gemm(h1_16.as<bf16>(), w, 0, W2(), w, 1, B, w, w, P(off_b2), 1, nullptr, z2.as<float>(), h2_16.as<bf16>(), s);
     gemm(h2_16.as<bf16>(), w, 0, W3(), w, 1, B, dout, w, P(off_b3), 0, nullptr, vout.as<float>(), nullptr, s);
@@ -265,8 +304,8 @@ struct pdcs_mlp_s {
   float backward(const float* target, int64_t B, hipStream_t s) {
     const int64_t n = B * dout;
     const int nb = (int)((n + 255) / 256);
-    k_mse<<<nb, 256, 0, s>>>(vout.as<float>(), target, n, 1.0f / (float)n, dv.as<float>(), dv16.as<bf16>(),
-                             lossp.as<double>());
+    k_mse<<<nb, 256, 0, s>>>(vout.as<float>(), target, n, 1.0f / (float)n, omu(), out_inv.as<float>(), (int)dout,
+                             dv.as<float>(), dv16.as<bf16>(), lossp.as<double>());
     k_sum_parts<<<1, 256, 0, s>>>(lossp.as<double>(), nb, 1.0 / (double)n, lossv.as<float>());
     // layer 3: dW3 = dV^T H2, db3 = colsum dV, dH2 = dV W3, dZ2 = dH2 * (z2 > 0)
     gemm(dv16.as<bf16>(), dout, 1, h2_16.as<bf16>(), w, 0, dout, w, B, nullptr, 0, nullptr, G(off_w3), nullptr, s);
@@ -351,7 +390,8 @@ int pdcs_mlp_forward(pdcs_mlp net, const float* in_dev, float* out_dev, int64_t 
     if (!net || !in_dev || !out_dev || batch < 1) throw Error(PDCS_ERR_INVALID_ARG, "bad forward arguments");
     hipStream_t s = pick(net, stream);
     net->forward(in_dev, batch, s);
-    HIP_OK(hipMemcpyAsync(out_dev, net->vout.p, batch * net->dout * 4, hipMemcpyDeviceToDevice, s));
+    k_out_denorm<<<lin(batch * net->dout), 256, 0, s>>>(net->vout.as<float>(), net->omu(), net->out_sc.as<float>(),
+                                                       batch * net->dout, (int)net->dout, out_dev);
     HIP_OK(hipGetLastError());
     return PDCS_OK;
   } catch (const Error& e) {
@@ -415,6 +455,47 @@ int pdcs_mlp_get_params(pdcs_mlp net, float* params_host) {
     if (!net || !params_host) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
     HIP_OK(hipDeviceSynchronize());
     HIP_OK(hipMemcpy(params_host, net->params.p, net->np * 4, hipMemcpyDeviceToHost));
+    return PDCS_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  }
+}
+
+int pdcs_mlp_set_normalization(pdcs_mlp net, const float* in_mean, const float* in_scale, const float* out_mean,
+                               const float* out_scale) {
+  try {
+    if (!net) throw Error(PDCS_ERR_INVALID_ARG, "null network");
+    if ((in_mean == nullptr) != (in_scale == nullptr) || (out_mean == nullptr) != (out_scale == nullptr))
+      throw Error(PDCS_ERR_INVALID_ARG, "mean and scale must be given together");
+    auto check = [](const float* mu, const float* sc, int64_t d) {
+      for (int64_t j = 0; j < d; ++j)
+        if (!std::isfinite(mu[j]) || !std::isfinite(sc[j]) || !(sc[j] > 0.0f))
+          throw Error(PDCS_ERR_INVALID_ARG, "means must be finite and scales finite and positive");
+    };
+    HIP_OK(hipDeviceSynchronize());
+    if (in_mean) {
+      check(in_mean, in_scale, net->din);
+      std::vector<float> inv(net->din);
+      for (int64_t j = 0; j < net->din; ++j) inv[j] = 1.0f / in_scale[j];
+      net->in_mu.alloc(net->din * 4);
+      net->in_inv.alloc(net->din * 4);
+      HIP_OK(hipMemcpy(net->in_mu.p, in_mean, net->din * 4, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(net->in_inv.p, inv.data(), net->din * 4, hipMemcpyHostToDevice));
+    }
+    net->norm_in = in_mean != nullptr;
+    if (out_mean) {
+      check(out_mean, out_scale, net->dout);
+      std::vector<float> inv(net->dout);
+      for (int64_t j = 0; j < net->dout; ++j) inv[j] = 1.0f / out_scale[j];
+      net->out_mu.alloc(net->dout * 4);
+      net->out_sc.alloc(net->dout * 4);
+      net->out_inv.alloc(net->dout * 4);
+      HIP_OK(hipMemcpy(net->out_mu.p, out_mean, net->dout * 4, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(net->out_sc.p, out_scale, net->dout * 4, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(net->out_inv.p, inv.data(), net->dout * 4, hipMemcpyHostToDevice));
+    }
+    net->norm_out = out_mean != nullptr;
     return PDCS_OK;
   } catch (const Error& e) {
     set_last_error(e.what());
