@@ -89,9 +89,11 @@ typedef struct {
   int64_t check_every;        /* 64: restart/termination check after every accepted
                                  trial whose trial count is a multiple of this         */
   int64_t precision;          /* PDCS_PRECISION_*                                     */
-  int64_t stall_checks;       /* mixed: switch to FP64 after this many checks without
-                                 a 2x improvement of the relative KKT error, counted
-                                 once that error is below 100 * rel_tol (0: never)    */
+  int64_t stall_checks;       /* 16; mixed: switch to FP64 after this many checks
+                                 without a 2x improvement of the relative KKT error
+                                 once that error is below 100 * rel_tol, or after 8x
+                                 this many checks without a new lowest error at any
+                                 level (0: never)                                     */
   double  polish_switch_tol;  /* mixed: switch to FP64 once rel. KKT <= this (0: off)  */
   double  bisect_rel_eps;     /* 1e-6: relative bracket width of the gap bisection     */
   int64_t use_graph;          /* 1: replay each chunk of iterations as a hipGraph      */

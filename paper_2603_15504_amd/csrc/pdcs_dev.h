@@ -61,6 +61,8 @@ struct Inst {
   int32_t restart, chosen, optimal, use_kkt;
   double best_rel, rel_tol, abs_tol, polish_tol, bisect_eps;
   int64_t stall, stall_checks;
+  double best_any;    // lowest relative KKT error of the FP32 phase
+  int64_t stall_any;  // checks since that record
   // termination errors of the last evaluated point
   double pobj, dobj, abs_p, abs_d, abs_gap, rel_p, rel_d, rel_gap;
   CandState cand[kMaxCand];

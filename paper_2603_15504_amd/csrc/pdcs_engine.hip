@@ -901,6 +901,8 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     I.stall_checks = o.stall_checks;
     I.bisect_eps = o.bisect_rel_eps;
     I.best_rel = std::numeric_limits<double>::infinity();
+    I.best_any = std::numeric_limits<double>::infinity();
+    I.stall_any = 0;
     I.omega = I.omega0 = 1.0;
     I.eta = I.eta_hat = 1.0;
   }

@@ -969,16 +969,25 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
   I.optimal = optimal ? 1 : 0;
   I.switch_fp64 = 0;
   if (!optimal && I.precision == kFP32) {
-    // FP32 storage limits the attainable error only near the tolerance: stalls
-    // are counted once the relative KKT error is within 100x of rel_tol.
+    // Two signs that FP32 storage limits the attainable error.  Near the
+    // tolerance (within 100x of rel_tol): stall_checks checks without halving
+    // the best error.  At any level: 8 x stall_checks checks without any new
+    // record low -- a steady (even slow) descent keeps setting records, while
+    // an error that fluctuates at a rounding floor sets them ever more rarely.
     if (!(rmax >= 0.5 * I.best_rel) || rmax > 100.0 * I.rel_tol) {
       I.best_rel = rmax;
       I.stall = 0;
     } else {
       I.stall += 1;
     }
+    if (rmax < I.best_any) {
+      I.best_any = rmax;
+      I.stall_any = 0;
+    } else {
+      I.stall_any += 1;
+    }
     if ((I.polish_tol > 0.0 && rmax <= I.polish_tol) ||
-        (I.stall_checks > 0 && I.stall >= I.stall_checks)) {
+        (I.stall_checks > 0 && (I.stall >= I.stall_checks || I.stall_any >= 8 * I.stall_checks))) {
       I.switch_fp64 = 1;
       restart = true;
     }
@@ -1113,6 +1122,8 @@ __global__ void k_check_end(Inst* __restrict__ inst, int nb) {
     I.switch_fp64 = 0;
     I.best_rel = INFINITY;
     I.stall = 0;
+    I.best_any = INFINITY;
+    I.stall_any = 0;
   }
   I.check_due = 0;
   I.restart = 0;
