@@ -49,6 +49,192 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def oracle_trial_seconds(inst, trials):
+    """Seconds per trial of the FP64 oracle on one instance (no rescaling)."""
+    from oracle import pdcs_oracle as O
+
+    lp = O.lpdata_from_instance(inst)
+    t0 = time.perf_counter()
+    r = O.solve(lp, O.Options(use_preconditioner=False, max_iter=trials, check_every=1 << 30))
+    return (time.perf_counter() - t0 - r.setup_sec) / max(r.iters, 1)
+
+
+def common_fields(args, value, unit, ms, dtype, config, extra=None):
+    out = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra or {})
+    return out
+
+
+def run_c2(args, P, np):
+    """C2: 512 LPs of uneven size (m log-uniform in [1e3, 5e4], n = 2m, 8 rows
+    per column) in one batched solve to relative KKT 1e-6; a step is one solve."""
+    import lpgen
+
+    t = time.perf_counter()
+    insts = lpgen.c2_batch(count=args.c2_count)
+    probs = [P.Problem.from_instance(i) for i in insts]
+    batch = P.Batch(probs)
+    log(f"c2: {len(insts)} LPs, sum m {sum(i.m for i in insts)}, sum nnz {sum(i.nnz for i in insts)}, "
+        f"set up in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    sched = batch.autotune(2000.0)
+    log(f"autotuned schedule {sched} in {time.perf_counter() - t:.1f}s")
+    opts = dict(precision="mixed", time_limit=600.0)
+    for _ in range(args.warmup):
+        batch.solve(**opts)
+    walls, sols = [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        sols = batch.solve(**opts)
+        walls.append(time.perf_counter() - t0)
+    wall = float(np.median(walls))
+    ok = sum(s.info["exit_code"] == 0 for s in sols)
+    its = np.array([s.info["iters"] for s in sols])
+    value = len(insts) / wall
+    f64 = None
+    if not args.no_extras:
+        t0 = time.perf_counter()
+        s64 = batch.solve(precision="fp64", time_limit=600.0)
+        f64 = {"solves_per_s": round(len(insts) / (time.perf_counter() - t0), 3),
+               "optimal": int(sum(x.info["exit_code"] == 0 for x in s64))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(0)
+        pick = rng.choice(len(insts), size=4, replace=False)
+        secs = [oracle_trial_seconds(insts[i], 30) * its[i] for i in pick]
+        cores = os.cpu_count() or 1
+        cpu = {"value": round(cores / float(np.mean(secs)), 5), "unit": "solves/s", "cores": cores, "kind": "oracle",
+               "sample": (f"30 trials of the FP64 oracle on each of 4 random members (no rescaling), times "
+                          f"extrapolated to the GPU's trial counts of those members and spread over {cores} "
+                          f"processes with perfect scaling")}
+    return common_fields(args, round(value, 4), "solves/s", wall * 1e3, "f32+f64", {
+        "workload": f"{len(insts)} LPs m~logU[1e3,5e4], n=2m, 8 nnz/col, one batched solve to rel. KKT 1e-6",
+        "sum_nnz": int(sum(i.nnz for i in insts)), "optimal": int(ok), "trials_median": int(np.median(its)),
+        "trials_max": int(its.max()), "schedule": list(sched), "fp64_batched": f64},
+        {"roofline": None, "cpu_baseline": cpu})
+
+
+def run_c4(args, P, np):
+    """C4: the ill-conditioned LP to relative KKT 1e-6, mixed (FP32 with FP64
+    polish) against plain FP64; a step is one solve."""
+    import lpgen
+
+    inst = lpgen.c4_instance(0)
+    prob = P.Problem.from_instance(inst)
+    res = {}
+    for prec in ("mixed", "fp64"):
+        for _ in range(args.warmup):
+            prob.solve(precision=prec, time_limit=300.0)
+        walls, s = [], None
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            s = prob.solve(precision=prec, time_limit=300.0)
+            walls.append(time.perf_counter() - t0)
+        res[prec] = (float(np.median(walls)), s.info)
+        log(f"c4 {prec}: {res[prec][0]:.2f}s, {s.info['iters']} trials ({s.info['fp64_iters']} FP64), "
+            f"{s.info['status']}")
+    wall, info = res["mixed"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        sec = oracle_trial_seconds(inst, 20) * info["iters"]
+        cpu = {"value": round(1.0 / sec, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "20 trials of the FP64 oracle (no rescaling), extrapolated to the GPU's trial count"}
+    return common_fields(args, round(1.0 / wall, 5), "solves/s", wall * 1e3, "f32+f64", {
+        "workload": "ill-conditioned LP m=2e5 n=5e5 nnz=5e6, row scales 10^U[-3,3], col scales 10^U[-2,2], "
+                    "rel. KKT 1e-6",
+        "mixed": {"seconds": round(wall, 3), "trials": info["iters"], "fp64_trials": info["fp64_iters"],
+                  "status": info["status"]},
+        "fp64": {"seconds": round(res["fp64"][0], 3), "trials": res["fp64"][1]["iters"],
+                 "status": res["fp64"][1]["status"]},
+        "obj_rel_diff_mixed_vs_fp64": abs(info["pobj"] - res["fp64"][1]["pobj"]) / (1 + abs(res["fp64"][1]["pobj"]))},
+        {"roofline": None, "cpu_baseline": cpu})
+
+
+def run_c3(args, P, np):
+    """C3: warm start on a family sharing G (m=2e4, n=4e4, nnz=3e5): solve the
+    training members, train the network, then a step solves the held-out
+    members warm; cold solves of the same members are timed beside them."""
+    import lpgen
+    from paper_2603_15504_amd import warmstart as W
+
+    base = lpgen.c3_family_base()
+    ntr, nte = args.c3_train, args.c3_test
+    fam = [lpgen.c3_perturb(base, k) for k in range(ntr + nte)]
+
+    def solve_all(insts, xs=None, ys=None, chunk=256):
+        out = []
+        for lo in range(0, len(insts), chunk):
+            probs = [P.Problem.from_instance(i) for i in insts[lo:lo + chunk]]
+            out += P.Batch(probs).solve(None if xs is None else list(xs[lo:lo + chunk]),
+                                        None if ys is None else list(ys[lo:lo + chunk]),
+                                        precision="mixed", time_limit=600.0)
+        return out
+
+    t0 = time.perf_counter()
+    sols = solve_all(fam[:ntr])
+    t_solve = time.perf_counter() - t0
+    ok = [i for i, s in enumerate(sols) if s.info["exit_code"] == 0]
+    U = W.pack_inputs([fam[i].h for i in ok], [fam[i].c for i in ok])
+    Z = W.pack_targets([sols[i].x for i in ok], [sols[i].y for i in ok])
+    log(f"c3: {ntr} training members solved in {t_solve:.1f}s ({len(ok)} optimal)")
+    net = W.WarmStartNet(base.m, base.n, width=512, seed=0)
+    t0 = time.perf_counter()
+    losses = net.fit(U, Z, epochs=args.c3_epochs, batch=256, lr=1e-3)
+    t_fit = time.perf_counter() - t0
+    log(f"network trained in {t_fit:.1f}s, validation loss {losses[0]:.3e} -> {min(losses):.3e}")
+    held = fam[ntr:]
+    Uh = W.pack_inputs([h.h for h in held], [h.c for h in held])
+    t0 = time.perf_counter()
+    xw, yw = net.predict(Uh)
+    t_pred = time.perf_counter() - t0
+    walls_w, walls_c = [], []
+    for _ in range(args.warmup + args.steps):
+        t0 = time.perf_counter()
+        warm = solve_all(held, xw, yw)
+        walls_w.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        cold = solve_all(held)
+        walls_c.append(time.perf_counter() - t0)
+    ww = float(np.median(walls_w[args.warmup:])) + t_pred
+    wc = float(np.median(walls_c[args.warmup:]))
+    it_w = np.array([s.info["iters"] for s in warm])
+    it_c = np.array([s.info["iters"] for s in cold])
+    zt = np.hstack([np.array([s.x for s in cold]), np.array([s.y for s in cold])])
+    err = float(np.linalg.norm(np.hstack([xw, yw]) - zt) / np.linalg.norm(zt))
+    err_mean = float(np.linalg.norm(Z.mean(0) - zt) / np.linalg.norm(zt))
+    # one training step of the network at this shape: 6 GEMMs of 2 x batch x
+    # (6e4 x 512 + 512 x 512 + 512 x 6e4) flops each pass (forward + 2 backward)
+    import torch
+
+    ub = torch.tensor(U[:256], device="cuda")
+    zb = torch.tensor(Z[:256], device="cuda")
+    net.net.train_step(ub, zb, 1e-9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        net.net.train_step(ub, zb, 1e-9)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / 10 * 1e3
+    d = base.m + base.n
+    flops = 3 * 2 * 256 * (d * 512 + 512 * 512 + 512 * d)
+    tflops = flops / (ms_step * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": round(tflops / 2500.0, 5), "traffic": None,
+            "kernel": "MLP training step (k_gemm BF16 MFMA + epilogues + Adam), batch 256",
+            "ms_per_train_step": round(ms_step, 3)}
+    return common_fields(args, round(len(held) / ww, 4), "solves/s", ww * 1e3, "f32+f64 (MLP bf16)", {
+        "workload": f"LP family m=2e4 n=4e4 nnz=3e5, h and c perturbed by 10% N(0,1); {ntr} training and "
+                    f"{nte} held-out members (the full family has 16000 and 4000)",
+        "warm_solves_per_s": round(len(held) / ww, 4), "cold_solves_per_s": round(len(held) / wc, 4),
+        "trials_warm_mean": float(it_w.mean()), "trials_cold_mean": float(it_c.mean()),
+        "start_rel_error_network": round(err, 4), "start_rel_error_training_mean": round(err_mean, 4),
+        "train_solve_seconds": round(t_solve, 2), "fit_seconds": round(t_fit, 2),
+        "optimal_warm": int(sum(s.info["exit_code"] == 0 for s in warm))},
+        {"roofline": roof, "cpu_baseline": None})
+
+
 def workload(name: str):
     import lpgen
 
@@ -159,7 +345,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed chunks of 64 trials + restart check")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c1_nnz_matched"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c1_nnz_matched", "c2", "c3", "c4"])
+    ap.add_argument("--c2-count", type=int, default=512)
+    ap.add_argument("--c3-train", type=int, default=1024)
+    ap.add_argument("--c3-test", type=int, default=256)
+    ap.add_argument("--c3-epochs", type=int, default=30)
     ap.add_argument("--cpu-trials", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and plain-SpMV side measurements")
@@ -179,6 +369,13 @@ def main():
     if P.pdcs_device_count() < 1 or not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
+
+    if args.workload in ("c2", "c3", "c4"):
+        if args.steps == 200 and args.warmup == 20:   # the C1 defaults: one step each here
+            args.steps, args.warmup = 1, 0
+        fn = {"c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload]
+        print(json.dumps(fn(args, P, np)), flush=True)
+        return
 
     t = time.perf_counter()
     inst, desc = workload(args.workload)

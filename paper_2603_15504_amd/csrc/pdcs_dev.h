@@ -120,6 +120,7 @@ struct BandTiles {
   const int32_t* start;      // per band-tile: first entry (ntile + 1 entries)
   const int32_t* row0;       // per band-tile: first row
   const int32_t* nrows;      // per band-tile: rows
+  const int32_t* used;       // per band-tile: slots in use (rows + extra slots; the sink excluded)
   const int32_t* col0;       // per band-tile: window start
   const int32_t* panel;      // per band-tile: window index (partial-sum array)
   const int32_t* run_start;  // per band-tile: first run (ntile + 1 entries)

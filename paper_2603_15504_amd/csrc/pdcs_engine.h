@@ -110,7 +110,7 @@ struct BandSet {
   int P = 1;
   int ntile = 0, nslot = 0;
   int64_t R = 0, nent = 0;
-  DBuf group, slot, start, row0, nrows, col0, panel, run_start, run_row, run_ext, ext, pk, src;
+  DBuf group, slot, start, row0, nrows, used, col0, panel, run_start, run_row, run_ext, ext, pk, src;
   DBuf val32, val64, part32, part64;
   DBuf orig32, orig64;  // unscaled values (plain products), filled on first use
   void build(int64_t R, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx);

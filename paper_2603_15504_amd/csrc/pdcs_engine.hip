@@ -390,12 +390,12 @@ void PanelSet::build_slots() {
 // ---------------------------------------------------------------------------
 namespace {
 struct BandBuild {
-  std::vector<int32_t> start, row0, nrows, col0, panel, run_start, run_row, run_ext, ext, src;
+  std::vector<int32_t> start, row0, nrows, used, col0, panel, run_start, run_row, run_ext, ext, src;
   std::vector<uint32_t> pk;
   std::vector<int64_t> work;  // entries per band-tile
   std::vector<size_t> sizes() const {
     return {start.size(), row0.size(), nrows.size(), col0.size(), panel.size(), run_start.size(), run_row.size(),
-            run_ext.size(), ext.size(), src.size(), pk.size(), work.size()};
+            run_ext.size(), ext.size(), src.size(), pk.size(), work.size(), used.size()};
   }
   void truncate(const std::vector<size_t>& z) {
     start.resize(z[0]);
@@ -410,6 +410,7 @@ struct BandBuild {
     src.resize(z[9]);
     pk.resize(z[10]);
     work.resize(z[11]);
+    used.resize(z[12]);
   }
 };
 
@@ -464,6 +465,7 @@ bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t W, const std::vector
   }
   out.run_start.push_back((int32_t)out.run_row.size());
   out.work.push_back((int64_t)E.size());
+  out.used.push_back(nxt);
   return true;
 }
 }  // namespace
@@ -538,7 +540,8 @@ void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, cons
   nslot = (int)sl.size();
   // every index the kernel reads, checked before anything reaches the device
   auto fail = [](const char* what) { throw Error(PDCS_ERR_STATE, std::string("band layout check: ") + what); };
-  if ((int)bb.start.size() != ntile + 1 || (int)bb.run_start.size() != ntile + 1) fail("tile tables");
+  if ((int)bb.start.size() != ntile + 1 || (int)bb.run_start.size() != ntile + 1 || (int)bb.used.size() != ntile)
+    fail("tile tables");
   if (bb.run_ext.size() != bb.run_row.size() + 1 || bb.src.size() != bb.pk.size()) fail("run tables");
   for (int32_t g : sl)
     if (g >= (int32_t)(grp.size() / kBandWaves)) fail("slot table");
@@ -549,17 +552,18 @@ void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, cons
     if (e1 < e0 || (e1 - e0) % ((int64_t)kBandUnroll * kWave)) fail("tile padding");
     if (bb.nrows[t] < 0 || bb.nrows[t] > kBandRows || (int64_t)bb.row0[t] + bb.nrows[t] > R) fail("tile rows");
     if (bb.panel[t] < 0 || bb.panel[t] >= P || bb.col0[t] < 0) fail("tile window");
+    if (bb.used[t] < bb.nrows[t] || bb.used[t] > kBandSlots - 1) fail("tile slots");
     if (e1 > e0 && bb.col0[t] >= G) fail("tile window start");
     for (int64_t e = e0; e < e1; ++e) {
       const uint32_t slot_e = bb.pk[e] & ((1u << kBandSlotBits) - 1u);
       const int64_t col = (int64_t)bb.col0[t] + (bb.pk[e] >> kBandSlotBits);
-      if (slot_e >= (uint32_t)kBandSlots || col >= G) fail("entry");
+      if ((slot_e >= (uint32_t)bb.used[t] && slot_e != (uint32_t)(kBandSlots - 1)) || col >= G) fail("entry");
       if (bb.src[e] >= 0 && (bb.src[e] >= ptr[R] || idx[bb.src[e]] != col)) fail("entry source");
     }
     for (int32_t r = bb.run_start[t]; r < bb.run_start[t + 1]; ++r) {
       if (bb.run_row[r] < 0 || bb.run_row[r] >= bb.nrows[t]) fail("run row");
       for (int32_t q = bb.run_ext[r]; q < bb.run_ext[r + 1]; ++q)
-        if (bb.ext[q] < bb.nrows[t] || bb.ext[q] >= kBandSlots - 1) fail("extra slot");
+        if (bb.ext[q] < bb.nrows[t] || bb.ext[q] >= bb.used[t]) fail("extra slot");
     }
   }
   upload(group, grp);
@@ -567,6 +571,7 @@ void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, cons
   upload(start, bb.start);
   upload(row0, bb.row0);
   upload(nrows, bb.nrows);
+  upload(used, bb.used);
   upload(col0, bb.col0);
   upload(panel, bb.panel);
   upload(run_start, bb.run_start);
@@ -588,6 +593,7 @@ BandTiles BandSet::view() const {
   b.start = start.as<int32_t>();
   b.row0 = row0.as<int32_t>();
   b.nrows = nrows.as<int32_t>();
+  b.used = used.as<int32_t>();
   b.col0 = col0.as<int32_t>();
   b.panel = panel.as<int32_t>();
   b.run_start = run_start.as<int32_t>();

@@ -205,7 +205,9 @@ __global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, 
   const int t = bt.group[g * kBandWaves + w];
   if (t < 0) return;
   T* a = acc + w * kBandSlots;
-  for (int i = lane; i < kBandSlots; i += kWave) a[i] = T(0);
+  // the sink slot of the padding is never read and stays uninitialized
+  const int used = bt.used[t];
+  for (int i = lane; i < used; i += kWave) a[i] = T(0);
   const T* xs = x + bt.col0[t];
   const int e0 = bt.start[t];
   const int nit = (bt.start[t + 1] - e0) / (U * kWave);
