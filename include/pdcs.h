@@ -104,7 +104,10 @@ typedef struct {
                                  SpMV-with-dual-step kernel with HIP events           */
   int64_t probe_passes;       /* 7: multisection passes per restart check (16 t each)  */
   int64_t trace_trials;       /* record the scalars of the first this-many trials      */
-  int64_t reserved[3];
+  int64_t compact;            /* 1: a batch of >= 8 LPs rebuilds its schedules over the
+                                 still-active instances each time half of them have
+                                 finished (results are identical either way)          */
+  int64_t reserved[2];
 } pdcs_options;
 
 /* Per-solve information (result fields of Section 3 plus counters). */
@@ -192,7 +195,8 @@ int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
  *   PDCS_LAYOUT_BANDS: band tiles: row bands x gathered-index windows, entries
  *                      sorted by gathered index and summed per row in LDS, then
  *                      one partial sum per window combined by the epilogues;
- *   PDCS_LAYOUT_AUTO : bands for problems with at least 2^23 nonzeros.
+ *   PDCS_LAYOUT_AUTO : bands for problems (and batches, see
+ *                      pdcs_batch_set_layout) with at least 2^22 nonzeros.
  * Both layouts compute the same products up to rounding order.  Building the
  * band tiles takes host time proportional to nnz log nnz and 20 bytes of device
  * memory per nonzero of each of G and G^T.
@@ -257,6 +261,10 @@ int  pdcs_batch_schedule(pdcs_batch b, int64_t* iter_max, int64_t* block_nnz,
                          int64_t* vec_per_block);
 int  pdcs_batch_set_schedule(pdcs_batch b, int64_t iter_max, int64_t block_nnz,
                              int64_t vec_per_block);
+/* pdcs_batch_set_layout: as pdcs_problem_set_layout, for every instance of the
+ * batch (each instance gets its own bands and gathered-index windows).
+ * Errors: PDCS_ERR_INVALID_ARG. */
+int  pdcs_batch_set_layout(pdcs_batch b, int64_t layout);
 void pdcs_batch_destroy(pdcs_batch b);
 
 /* ---- warm-start MLP ----------------------------------------------------

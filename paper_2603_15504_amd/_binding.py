@@ -36,7 +36,7 @@ class pdcs_options(C.Structure):
                 ("polish_switch_tol", C.c_double), ("bisect_rel_eps", C.c_double),
                 ("use_graph", C.c_int64), ("verbose", C.c_int64), ("keep_state", C.c_int64),
                 ("time_kernels", C.c_int64), ("probe_passes", C.c_int64),
-                ("trace_trials", C.c_int64), ("reserved", C.c_int64 * 3)]
+                ("trace_trials", C.c_int64), ("compact", C.c_int64), ("reserved", C.c_int64 * 2)]
 
 
 class pdcs_info(C.Structure):
@@ -88,6 +88,7 @@ PROTOTYPES = {
     "pdcs_batch_autotune": (C.c_int, [_P, C.c_double]),
     "pdcs_batch_schedule": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_batch_set_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
+    "pdcs_batch_set_layout": (C.c_int, [_P, _I64]),
     "pdcs_batch_destroy": (None, [_P]),
     "pdcs_mlp_create": (C.c_int, [_I64, _I64, _I64, C.c_uint64, C.POINTER(_P)]),
     "pdcs_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
@@ -316,6 +317,10 @@ def pdcs_batch_solve(b, count, opts=None, x0s=None, y0s=None, stream: int = 0):
     return [C.c_void_p(res[i]) for i in range(count)]
 
 
+def pdcs_batch_set_layout(b, layout: int):
+    _check(lib.pdcs_batch_set_layout(b, int(layout)), "pdcs_batch_set_layout")
+
+
 def pdcs_batch_autotune(b, time_budget_ms: float = 0.0):
     _check(lib.pdcs_batch_autotune(b, float(time_budget_ms)), "pdcs_batch_autotune")
 
@@ -448,6 +453,10 @@ class Batch:
 
     def set_schedule(self, iter_max, block_nnz, vec_per_block):
         pdcs_batch_set_schedule(self.handle, iter_max, block_nnz, vec_per_block)
+
+    def set_layout(self, layout="auto"):
+        """Matrix storage for the trial SpMVs of every instance: "auto", "rows" or "bands"."""
+        pdcs_batch_set_layout(self.handle, LAYOUTS[layout] if isinstance(layout, str) else layout)
 
     def close(self):
         if getattr(self, "handle", None):

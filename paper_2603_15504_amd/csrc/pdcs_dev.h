@@ -107,7 +107,9 @@ struct RowBlocks {
 // slots are extra accumulators of rows that repeat within one group of kWave
 // consecutive entries (no two entries of such a group share a slot), and the
 // last slot is the sink of the padding.  A workgroup runs kBandWaves waves, each
-// on one band-tile of the same window.
+// on one band-tile of the same window index.  In a batch every instance has its
+// own bands and windows; an instance with fewer windows than the batch's
+// largest count has empty tiles (zero partial sums) for the missing ones.
 constexpr int kBandRows = 8192;
 constexpr int kBandSlots = 9216;
 constexpr int kBandSlotBits = 14;
@@ -121,6 +123,7 @@ struct BandTiles {
   const int32_t* row0;       // per band-tile: first row
   const int32_t* nrows;      // per band-tile: rows
   const int32_t* used;       // per band-tile: slots in use (rows + extra slots; the sink excluded)
+  const int32_t* tinst;      // per band-tile: instance (bands never cross instances)
   const int32_t* col0;       // per band-tile: window start
   const int32_t* panel;      // per band-tile: window index (partial-sum array)
   const int32_t* run_start;  // per band-tile: first run (ntile + 1 entries)

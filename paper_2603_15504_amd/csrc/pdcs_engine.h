@@ -65,7 +65,9 @@ struct TileSet {
   DBuf row0, row1, lg, btile0, btile1, binst_d, iblk0_d;
   int nblk = 0, ntiles = 0;
   std::vector<int32_t> h_bt0, h_bt1, h_t0, h_t1, h_binst;
-  void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s);
+  // active: optional per-instance mask; instances outside it get no workgroups
+  void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s,
+             const std::vector<char>* active = nullptr);
   Tiles view() const;
 };
 
@@ -75,14 +77,15 @@ struct RowBlockSet {
   DBuf r0, r1, binst_d, iblk0_d;
   int nblk = 0;
   std::vector<int32_t> h_binst;
-  void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max);
+  void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max,
+             const std::vector<char>* active = nullptr);
   RowBlocks view() const;
 };
 
 struct RangeSet {
   DBuf start, end, binst_d, iblk0_d;
   int nblk = 0;
-  void build(const std::vector<int64_t>& inst_off, int per_block);
+  void build(const std::vector<int64_t>& inst_off, int per_block, const std::vector<char>* active = nullptr);
   Ranges view() const;
 };
 
@@ -103,17 +106,19 @@ struct PanelSet {
   void build_slots();
 };
 
-// Band-tile layout of a CSR-like structure (see BandTiles): R rows gathering
-// from a vector of G entries.  src maps every packed entry to its position in
+// Band-tile layout of a CSR-like structure (see BandTiles), per instance of a
+// batch.  src maps every packed entry to its position in
 // the CSR order (-1 for padding), so the scaled values can be filled in.
 struct BandSet {
   int P = 1;
   int ntile = 0, nslot = 0;
   int64_t R = 0, nent = 0;
-  DBuf group, slot, start, row0, nrows, used, col0, panel, run_start, run_row, run_ext, ext, pk, src;
+  DBuf group, slot, start, row0, nrows, used, tinst, col0, panel, run_start, run_row, run_ext, ext, pk, src;
   DBuf val32, val64, part32, part64;
   DBuf orig32, orig64;  // unscaled values (plain products), filled on first use
-  void build(int64_t R, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx);
+  // instance b: rows [r0s[b], r0s[b+1]) gathering from [g0s[b], g0s[b+1])
+  void build(const std::vector<int64_t>& r0s, const std::vector<int64_t>& g0s, const std::vector<int32_t>& ptr,
+             const std::vector<int32_t>& idx);
   BandTiles view() const;
 };
 
@@ -159,6 +164,7 @@ struct Engine {
   int panels_x = 0, panels_y = 0;   // 0: automatic
   int layout = PDCS_LAYOUT_AUTO;
   bool use_band = false;
+  bool band_suspended = false;      // auto layout: the active instances of a batch fell below the band threshold
   BandSet band1, band2;             // band tiles of G (gathers x) and G^T (gathers y)
   hipStream_t stream = nullptr;
   std::map<int64_t, hipGraphExec_t> graphs;
@@ -170,6 +176,8 @@ struct Engine {
   explicit Engine(const std::vector<const HostProblem*>& probs);
   ~Engine();
   void build_schedule();
+  // iteration schedules over the instances in `active` (all when null)
+  void build_iteration_schedules(const std::vector<char>* active);
   void clear_graphs();
   void ensure_iter(int prec);
   KernelCtx ctx(int probe_passes) const;

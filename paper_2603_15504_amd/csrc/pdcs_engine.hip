@@ -143,14 +143,15 @@ static int ilog2(int v) {
 // over it); otherwise consecutive rows share a tile as long as each row's
 // group of lanes needs at most iter_max passes.  Tiles are then grouped into
 // workgroups of about block_work units (nonzeros plus 4 per row).
-void TileSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s) {
+void TileSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, const Schedule& s,
+                    const std::vector<char>* active) {
   std::vector<int32_t> t0, t1, tlg, bt0, bt1, binst, iblk0;
   const int64_t cap = 64LL * s.iter_max;
   const int B = (int)inst_r0.size() - 1;
   iblk0.push_back(0);
   for (int b = 0; b < B; ++b) {
     int64_t r = inst_r0[b];
-    const int64_t end = inst_r0[b + 1];
+    const int64_t end = (active && !(*active)[b]) ? r : inst_r0[b + 1];
     const size_t first = t0.size();
     while (r < end) {
       const int64_t len0 = ptr[r + 1] - ptr[r];
@@ -232,14 +233,15 @@ static int threads_per_row(int R) {
   return T;
 }
 
-void RowBlockSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max) {
+void RowBlockSet::build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max,
+                        const std::vector<char>* active) {
   std::vector<int32_t> a, e, bi, iblk0;
   const int B = (int)inst_r0.size() - 1;
   const int64_t cap = kRowBlockCap;
   iblk0.push_back(0);
   for (int b = 0; b < B; ++b) {
     int64_t r = inst_r0[b];
-    const int64_t end = inst_r0[b + 1];
+    const int64_t end = (active && !(*active)[b]) ? r : inst_r0[b + 1];
     while (r < end) {
       const int64_t len0 = ptr[r + 1] - ptr[r];
       if (len0 > cap) {
@@ -294,14 +296,15 @@ RowBlocks RowBlockSet::view() const {
   return r;
 }
 
-void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block) {
+void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block, const std::vector<char>* active) {
   std::vector<int32_t> st, en, bi, iblk0;
   const int B = (int)inst_off.size() - 1;
   iblk0.push_back(0);
   for (int b = 0; b < B; ++b) {
-    for (int64_t s = inst_off[b]; s < inst_off[b + 1]; s += per_block) {
+    const int64_t stop = (active && !(*active)[b]) ? inst_off[b] : inst_off[b + 1];
+    for (int64_t s = inst_off[b]; s < stop; s += per_block) {
       st.push_back((int32_t)s);
-      en.push_back((int32_t)std::min<int64_t>(s + per_block, inst_off[b + 1]));
+      en.push_back((int32_t)std::min<int64_t>(s + per_block, stop));
       bi.push_back(b);
     }
     iblk0.push_back((int32_t)st.size());
@@ -390,12 +393,12 @@ void PanelSet::build_slots() {
 // ---------------------------------------------------------------------------
 namespace {
 struct BandBuild {
-  std::vector<int32_t> start, row0, nrows, used, col0, panel, run_start, run_row, run_ext, ext, src;
+  std::vector<int32_t> start, row0, nrows, used, col0, panel, tinst, run_start, run_row, run_ext, ext, src;
   std::vector<uint32_t> pk;
   std::vector<int64_t> work;  // entries per band-tile
   std::vector<size_t> sizes() const {
     return {start.size(), row0.size(), nrows.size(), col0.size(), panel.size(), run_start.size(), run_row.size(),
-            run_ext.size(), ext.size(), src.size(), pk.size(), work.size(), used.size()};
+            run_ext.size(), ext.size(), src.size(), pk.size(), work.size(), used.size(), tinst.size()};
   }
   void truncate(const std::vector<size_t>& z) {
     start.resize(z[0]);
@@ -411,16 +414,16 @@ struct BandBuild {
     pk.resize(z[10]);
     work.resize(z[11]);
     used.resize(z[12]);
+    tinst.resize(z[13]);
   }
 };
 
 // Entries of rows [r0, r1) with gathered index in window p, sorted by gathered
 // index, with accumulator slots assigned per 64-entry group; false if the
 // band needs more than kBandSlots - 1 slots.
-bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t W, const std::vector<int32_t>& ptr,
+bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t c0, int64_t c1, int inst, const std::vector<int32_t>& ptr,
                      const std::vector<int32_t>& idx, std::vector<int32_t>& stamp, std::vector<int32_t>& next,
                      int32_t& gid, BandBuild& out) {
-  const int64_t c0 = (int64_t)p * W, c1 = c0 + W;
   std::vector<std::pair<uint64_t, int32_t>> E;
   for (int64_t r = r0; r < r1; ++r)
     for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
@@ -437,6 +440,7 @@ bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t W, const std::vector
   out.nrows.push_back(nr);
   out.col0.push_back((int32_t)c0);
   out.panel.push_back(p);
+  out.tinst.push_back(inst);
   for (size_t k = 0; k < E.size(); ++k) {
     if (k % kWave == 0) ++gid;
     const uint32_t col = (uint32_t)(E[k].first >> 20);
@@ -470,38 +474,60 @@ bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t W, const std::vector
 }
 }  // namespace
 
-void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx) {
-  R = R_;
+void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>& g0s, const std::vector<int32_t>& ptr,
+                    const std::vector<int32_t>& idx) {
+  const int NB = (int)r0s.size() - 1;
+  R = r0s[NB];
+  const int64_t G = g0s[NB];
   const int64_t wmax = (int64_t)1 << kBandColBits;
-  P = (int)std::max<int64_t>(1, (G + wmax - 1) / wmax);
-  const int64_t W = std::max<int64_t>(1, (G + P - 1) / P);
+  // windows per instance; P is the batch's largest count
+  std::vector<int> Pb(NB);
+  P = 1;
+  for (int b = 0; b < NB; ++b) {
+    Pb[b] = (int)std::max<int64_t>(1, (g0s[b + 1] - g0s[b] + wmax - 1) / wmax);
+    P = std::max(P, Pb[b]);
+  }
   // band height: as tall as possible (better gather locality) while keeping
   // at least about 768 band-tiles to spread over the 256 CUs
+  auto tiles_for = [&](int64_t rb) {
+    int64_t t = 0;
+    for (int b = 0; b < NB; ++b) t += ((r0s[b + 1] - r0s[b] + rb - 1) / rb) * P;
+    return t;
+  };
   int64_t rb = kBandRows;
-  while (rb > 256 && ((R + rb - 1) / rb) * P < 768) rb /= 2;
+  while (rb > 256 && tiles_for(rb) < 768) rb /= 2;
   BandBuild bb;
   bb.run_start.push_back(0);
   bb.run_ext.push_back(0);
   std::vector<int32_t> stamp(kBandSlots, -1), next(kBandSlots, -1);
   int32_t gid = 0;
   std::vector<std::pair<int64_t, int64_t>> bands;  // row ranges, split on slot overflow
-  std::vector<std::pair<int64_t, int64_t>> todo;
-  for (int64_t r = R; r > 0; r -= rb) todo.push_back({std::max<int64_t>(0, r - rb), r});
-  while (!todo.empty()) {
-    const auto br = todo.back();
-    todo.pop_back();
-    const std::vector<size_t> save = bb.sizes();
-    bool ok = true;
-    for (int p = 0; p < P && ok; ++p) ok = build_band_tile(br.first, br.second, p, W, ptr, idx, stamp, next, gid, bb);
-    if (ok) {
-      bands.push_back(br);
-      continue;
+  for (int b = 0; b < NB; ++b) {
+    const int64_t gb = g0s[b], wb = g0s[b + 1] - g0s[b];
+    const int64_t W = std::max<int64_t>(1, (wb + Pb[b] - 1) / Pb[b]);
+    std::vector<std::pair<int64_t, int64_t>> todo;
+    for (int64_t r = r0s[b + 1]; r > r0s[b]; r -= rb) todo.push_back({std::max<int64_t>(r0s[b], r - rb), r});
+    while (!todo.empty()) {
+      const auto br = todo.back();
+      todo.pop_back();
+      const std::vector<size_t> save = bb.sizes();
+      bool ok = true;
+      for (int p = 0; p < P && ok; ++p) {
+        // window p of instance b (empty beyond its own window count)
+        const int64_t c0 = p < Pb[b] ? gb + std::min<int64_t>(wb, p * W) : gb;
+        const int64_t c1 = p < Pb[b] ? gb + std::min<int64_t>(wb, (p + 1) * W) : gb;
+        ok = build_band_tile(br.first, br.second, p, c0, c1, b, ptr, idx, stamp, next, gid, bb);
+      }
+      if (ok) {
+        bands.push_back(br);
+        continue;
+      }
+      if (br.second - br.first <= 1) throw Error(PDCS_ERR_SIZE, "band tile slot overflow");
+      bb.truncate(save);
+      const int64_t mid = br.first + (br.second - br.first) / 2;
+      todo.push_back({mid, br.second});
+      todo.push_back({br.first, mid});
     }
-    if (br.second - br.first <= 1) throw Error(PDCS_ERR_SIZE, "band tile slot overflow");
-    bb.truncate(save);
-    const int64_t mid = br.first + (br.second - br.first) / 2;
-    todo.push_back({mid, br.second});
-    todo.push_back({br.first, mid});
   }
   bb.start.push_back((int32_t)bb.pk.size());
   if (bb.pk.size() >= (size_t)INT32_MAX) throw Error(PDCS_ERR_SIZE, "band tiles exceed 2^31 entries");
@@ -553,11 +579,14 @@ void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, cons
     if (bb.nrows[t] < 0 || bb.nrows[t] > kBandRows || (int64_t)bb.row0[t] + bb.nrows[t] > R) fail("tile rows");
     if (bb.panel[t] < 0 || bb.panel[t] >= P || bb.col0[t] < 0) fail("tile window");
     if (bb.used[t] < bb.nrows[t] || bb.used[t] > kBandSlots - 1) fail("tile slots");
+    const int ti = bb.tinst[t];
+    if (ti < 0 || ti >= NB || bb.row0[t] < r0s[ti] || (int64_t)bb.row0[t] + bb.nrows[t] > r0s[ti + 1]) fail("tile instance");
+    if (bb.start[t + 1] > bb.start[t] && (bb.col0[t] < g0s[ti] || bb.col0[t] >= g0s[ti + 1])) fail("tile window instance");
     if (e1 > e0 && bb.col0[t] >= G) fail("tile window start");
     for (int64_t e = e0; e < e1; ++e) {
       const uint32_t slot_e = bb.pk[e] & ((1u << kBandSlotBits) - 1u);
       const int64_t col = (int64_t)bb.col0[t] + (bb.pk[e] >> kBandSlotBits);
-      if ((slot_e >= (uint32_t)bb.used[t] && slot_e != (uint32_t)(kBandSlots - 1)) || col >= G) fail("entry");
+      if ((slot_e >= (uint32_t)bb.used[t] && slot_e != (uint32_t)(kBandSlots - 1)) || col >= g0s[ti + 1]) fail("entry");
       if (bb.src[e] >= 0 && (bb.src[e] >= ptr[R] || idx[bb.src[e]] != col)) fail("entry source");
     }
     for (int32_t r = bb.run_start[t]; r < bb.run_start[t + 1]; ++r) {
@@ -572,6 +601,7 @@ void BandSet::build(int64_t R_, int64_t G, const std::vector<int32_t>& ptr, cons
   upload(row0, bb.row0);
   upload(nrows, bb.nrows);
   upload(used, bb.used);
+  upload(tinst, bb.tinst);
   upload(col0, bb.col0);
   upload(panel, bb.panel);
   upload(run_start, bb.run_start);
@@ -594,6 +624,7 @@ BandTiles BandSet::view() const {
   b.row0 = row0.as<int32_t>();
   b.nrows = nrows.as<int32_t>();
   b.used = used.as<int32_t>();
+  b.tinst = tinst.as<int32_t>();
   b.col0 = col0.as<int32_t>();
   b.panel = panel.as<int32_t>();
   b.run_start = run_start.as<int32_t>();
@@ -666,9 +697,9 @@ Engine::Engine(const std::vector<const HostProblem*>& probs) {
   }
   h_rp[M] = (int32_t)NNZ;
   h_cp[N] = (int32_t)NNZ;
+  h_ci = ci;  // kept for the band tiles
+  h_ri = ri;
   if (B == 1) {  // kept for the panel split of single large instances
-    h_ci = ci;
-    h_ri = ri;
     h_v = v;
     h_vt = vt;
   }
@@ -706,14 +737,18 @@ void Engine::clear_graphs() {
   graphs.clear();
 }
 
-void Engine::build_schedule() {
+void Engine::build_iteration_schedules(const std::vector<char>* active) {
   clear_graphs();
-  trow.build(h_rp, row0, sched);
-  tcol.build(h_cp, col0, sched);
-  brow.build(h_rp, row0, sched.iter_max * 4);
-  bcol.build(h_cp, col0, sched.iter_max * 4);
-  vrow.build(row0, sched.vec_per_block);
-  vcol.build(col0, sched.vec_per_block);
+  trow.build(h_rp, row0, sched, active);
+  tcol.build(h_cp, col0, sched, active);
+  brow.build(h_rp, row0, sched.iter_max * 4, active);
+  bcol.build(h_cp, col0, sched.iter_max * 4, active);
+  vrow.build(row0, sched.vec_per_block, active);
+  vcol.build(col0, sched.vec_per_block, active);
+}
+
+void Engine::build_schedule() {
+  build_iteration_schedules(nullptr);
   int P1 = 1, P2 = 1;
   if (B == 1) {
     P1 = panels_x > 0 ? panels_x : auto_panels(N);
@@ -722,11 +757,10 @@ void Engine::build_schedule() {
   prow.P = pcol.P = 1;
   if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
   if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
-  const bool want_band = B == 1 && (layout == PDCS_LAYOUT_BANDS ||
-                                    (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 23)));
-  if (want_band && !use_band) {
-    band1.build(M, N, h_rp, h_ci);
-    band2.build(N, M, h_cp, h_ri);
+  const bool want_band = layout == PDCS_LAYOUT_BANDS || (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 22));
+  if (want_band && !band1.nslot && !band2.nslot) {
+    band1.build(row0, col0, h_rp, h_ci);
+    band2.build(col0, row0, h_cp, h_ri);
   }
   use_band = want_band;
   rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
@@ -802,8 +836,8 @@ KernelCtx Engine::ctx(int probe_passes) const {
     k.part64 = prow.part64.as<double>();
     k.part64b = prow.part64b.as<double>();
   }
-  k.use_band = use_band ? 1 : 0;
-  if (use_band) {
+  k.use_band = use_band && !band_suspended ? 1 : 0;
+  if (k.use_band) {
     k.band1 = band1.view();
     k.band2 = band2.view();
     k.bval32 = band1.val32.as<float>();
@@ -879,6 +913,10 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
   validate_options(o);
   HIP_OK(hipGetLastError());
   const auto t_start = std::chrono::steady_clock::now();
+  if (band_suspended) {  // left over from a solve that ended early
+    band_suspended = false;
+    build_iteration_schedules(nullptr);
+  }
   const bool mixed = o.precision == PDCS_PRECISION_MIXED;
   ensure_iter(kFP64);
   if (mixed) ensure_iter(kFP32);
@@ -952,7 +990,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     }
     HIP_OK(hipStreamSynchronize(stream));
   }
-  const KernelCtx k = ctx((int)o.probe_passes);
+  KernelCtx k = ctx((int)o.probe_passes);
   SetupCtx su{};
   su.precondition = o.use_preconditioner ? 1 : 0;
   su.ruiz_iters = (int)o.ruiz_iters;
@@ -1007,6 +1045,11 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
   launch_summary(k, stream, d_summary.as<int32_t>());
   int64_t chunks = 0;
   auto last_print = std::chrono::steady_clock::now();
+  // Retire-and-compact: when the active instances of a batch have halved
+  // since the schedules were built, rebuild the iteration schedules over the
+  // active ones only, so finished instances stop costing workgroups.
+  int active_built = B;
+  bool compacted = false;
   while (true) {
     HIP_OK(hipMemcpyAsync(h_summary, d_summary.p, 8, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
@@ -1026,6 +1069,23 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
                    I0.chosen, I0.use_kkt, I0.precision == kFP32 ? "fp32" : "fp64", a32 + a64);
     }
     if (a32 + a64 == 0) break;
+    if (o.compact && B >= 8 && a32 + a64 <= active_built / 2) {
+      std::vector<Inst> cur(B);
+      HIP_OK(hipMemcpy(cur.data(), d_inst.p, sizeof(Inst) * B, hipMemcpyDeviceToHost));
+      std::vector<char> act(B, 0);
+      int64_t act_nnz = 0;
+      for (int b = 0; b < B; ++b) {
+        act[b] = cur[b].status == kActive ? 1 : 0;
+        if (act[b]) act_nnz += h_rp[row0[b + 1]] - h_rp[row0[b]];
+      }
+      build_iteration_schedules(&act);
+      // the automatic layout choice, made again for the instances still running:
+      // few large tiles would leave most of the chip idle, compacted row blocks do not
+      if (layout == PDCS_LAYOUT_AUTO && act_nnz < ((int64_t)1 << 22)) band_suspended = true;
+      k = ctx((int)o.probe_passes);
+      active_built = a32 + a64;
+      compacted = true;
+    }
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     if (el >= o.time_limit) {
       launch_timeout(k, stream);
@@ -1051,6 +1111,11 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     }
     HIP_OK(hipGetLastError());
     ++chunks;
+  }
+  if (compacted) {  // the final evaluation covers every instance
+    build_iteration_schedules(nullptr);
+    band_suspended = false;
+    k = ctx((int)o.probe_passes);
   }
   // final point of instances that stopped without an optimal candidate
   launch_eval(k, stream, alloc_mask, 1);
@@ -1218,6 +1283,7 @@ void pdcs_options_default(pdcs_options* o) {
   o->keep_state = 0;
   o->time_kernels = 0;
   o->probe_passes = 7;
+  o->compact = 1;
 }
 
 const char* pdcs_status_string(int code) {
@@ -1515,6 +1581,17 @@ int pdcs_batch_set_schedule(pdcs_batch b, int64_t iter_max, int64_t block_nnz, i
         vec_per_block > (1 << 22))
       throw Error(PDCS_ERR_INVALID_ARG, "schedule out of range");
     b->eng->sched = Schedule{(int)iter_max, (int)block_nnz, (int)vec_per_block};
+    b->eng->build_schedule();
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_set_layout(pdcs_batch b, int64_t layout) {
+  return guarded([&]() {
+    if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
+    if (layout != PDCS_LAYOUT_AUTO && layout != PDCS_LAYOUT_ROWS && layout != PDCS_LAYOUT_BANDS)
+      throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
+    b->eng->layout = (int)layout;
     b->eng->build_schedule();
     return PDCS_OK;
   });

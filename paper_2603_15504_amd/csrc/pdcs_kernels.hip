@@ -195,15 +195,18 @@ template <typename T>
 __global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, const T* __restrict__ val,
                                                                   const T* __restrict__ x, T* __restrict__ part,
                                                                   int64_t R, const Inst* __restrict__ inst,
-                                                                  int need_acc) {
+                                                                  int prec, int need_acc) {
   constexpr int U = kBandUnroll;
   __shared__ T acc[kBandWaves * kBandSlots];
   const int g = bt.slot[blockIdx.x];
   if (g < 0) return;
-  if (inst && (inst[0].status != kActive || (need_acc && inst[0].last_acc == 0))) return;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int t = bt.group[g * kBandWaves + w];
   if (t < 0) return;
+  if (inst) {  // solver passes: only instances iterating in this precision (and accepted, for G^T y)
+    const Inst& I = inst[bt.tinst[t]];
+    if (I.status != kActive || I.precision != prec || (need_acc && I.last_acc == 0)) return;
+  }
   T* a = acc + w * kBandSlots;
   // the sink slot of the padding is never read and stays uninitialized
   const int used = bt.used[t];
@@ -1542,7 +1545,7 @@ static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const Ite
   if (k.use_band) {
     if (k.band1.nslot > 0)
       k_band_spmv<T><<<grid1(k.band1.nslot), kBandWaves * kWave, 0, s>>>(k.band1, band_val<T>(k, 0), it.xh, part,
-                                                                         k.M, k.inst, 0);
+                                                                         k.M, k.inst, prec, 0);
   } else if (k.P1 > 1) {
     if (k.nslot1 > 0)
       k_spmv_part<T, T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, PA, it.xh, part, k.inst, 0);
@@ -1566,7 +1569,7 @@ static void launch_lam_t(const KernelCtx& k, hipStream_t s, int prec, const Iter
     if (k.use_band) {
       if (k.band2.nslot > 0)
         k_band_spmv<T><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, band_val<T>(k, 1), it.yh,
-                                                                           part, k.N, k.inst, 1);
+                                                                           part, k.N, k.inst, prec, 1);
     } else if (k.nslot2 > 0) {
       k_spmv_part<T, T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, PAT, it.yh, part, k.inst, 1);
     }
@@ -1835,11 +1838,11 @@ void launch_band_plain(const BandTiles& bt, int prec, const void* val, const voi
   const dim3 g((unsigned)((R + 255) / 256));
   if (prec == kFP64) {
     k_band_spmv<double><<<grid1(bt.nslot), kBandWaves * kWave, 0, s>>>(bt, (const double*)val, (const double*)in,
-                                                                       (double*)part, R, nullptr, 0);
+                                                                       (double*)part, R, nullptr, kFP64, 0);
     k_band_sum<double><<<g, 256, 0, s>>>((const double*)part, bt.P, R, (double*)out);
   } else {
     k_band_spmv<float><<<grid1(bt.nslot), kBandWaves * kWave, 0, s>>>(bt, (const float*)val, (const float*)in,
-                                                                      (float*)part, R, nullptr, 0);
+                                                                      (float*)part, R, nullptr, kFP32, 0);
     k_band_sum<float><<<g, 256, 0, s>>>((const float*)part, bt.P, R, (float*)out);
   }
 }

@@ -35,6 +35,27 @@ def test_options_defaults_follow_the_paper():
     assert o.use_preconditioner == 1 and o.method == 0
     assert P.pdcs_status_string(0) == "optimal" and P.pdcs_status_string(8) == "numerical_error"
     assert P.pdcs_status_string(6) == "time_limit"
+    # engineering defaults of the added options
+    assert o.check_every == 64 and o.stall_checks == 16 and o.probe_passes == 7
+    assert o.use_graph == 1 and o.compact == 1 and o.precision == 0
+
+
+def test_options_struct_matches_header():
+    # the ctypes mirror has the C struct's size: every field is 8 bytes wide
+    import ctypes
+    import re
+
+    import paper_2603_15504_amd as P
+
+    hdr = open(__file__.replace("tests/test_abi.py", "include/pdcs.h")).read()
+    body = hdr[hdr.index("typedef struct {", hdr.index("pdcs_options")):]
+    body = body[: body.index("} pdcs_options;")]
+    n = 0
+    for decl in re.findall(r"^\s*(?:int64_t|double)\s+([^;]+);", body, re.M):
+        for name in decl.split(","):
+            m = re.search(r"\[(\d+)\]", name)
+            n += int(m.group(1)) if m else 1
+    assert ctypes.sizeof(P.pdcs_options) == 8 * n
 
 
 def _tiny():

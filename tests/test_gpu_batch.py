@@ -123,3 +123,63 @@ def test_batch_of_one_equals_single_solve(refs):
     s2 = P.Batch([P.Problem.from_instance(insts[1])]).solve(precision="fp64", max_iter=2000)[0]
     assert s1.info["iters"] == s2.info["iters"]
     assert np.array_equal(s1.x, s2.x) and np.array_equal(s1.y, s2.y)
+
+
+def test_batch_compaction_is_exact():
+    # 12 LPs of uneven difficulty: the schedules are rebuilt over the active
+    # instances as they finish; every instance keeps exactly its own blocks,
+    # so results are bitwise those of the uncompacted run
+    insts = _small_c2(12, 9, m_lo=30, m_hi=300)
+    b = P.Batch([P.Problem.from_instance(i) for i in insts])
+    a = b.solve(precision="mixed", compact=1, time_limit=120.0)
+    c = b.solve(precision="mixed", compact=0, time_limit=120.0)
+    its = [s.info["iters"] for s in a]
+    assert max(its) > 2 * min(its)
+    for sa, sc in zip(a, c):
+        assert sa.info["iters"] == sc.info["iters"] and sa.info["exit_code"] == sc.info["exit_code"]
+        assert np.array_equal(sa.x, sc.x) and np.array_equal(sa.y, sc.y)
+    for inst, sa in list(zip(insts, a))[:3]:
+        ref = O.solve(O.lpdata_from_instance(inst), O.Options(time_limit=120))
+        _check(inst, sa, ref.pobj)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_band_layout_matches_oracle(refs, precision):
+    # band tiles per instance (own bands and windows), per-instance gating of
+    # the band kernel, window sums combined by the instance-aware epilogues
+    insts, rs = refs
+    b = P.Batch([P.Problem.from_instance(i) for i in insts])
+    b.set_layout("bands")
+    sols = b.solve(precision=precision, time_limit=120.0)
+    for inst, sol, r in zip(insts, sols, rs):
+        _check(inst, sol, r.pobj)
+
+
+def test_batch_band_layout_first_trials_match_oracle(refs):
+    insts, _ = refs
+    lp = O.lpdata_from_instance(insts[0])
+    ref = O.solve(lp, O.Options(max_iter=64, check_every=64), trace=True)
+    b = P.Batch([P.Problem.from_instance(i) for i in insts])
+    b.set_layout("bands")
+    tr = b.solve(precision="fp64", max_iter=64, check_every=64, trace_trials=64)[0].trace
+    for row, t in zip(tr, ref.trace):
+        assert int(row[0]) == t["kbar"] and bool(row[6]) == t["accepted"]
+        assert row[1] == pytest.approx(t["eta"], rel=1e-9)
+        if t["accepted"]:
+            assert row[8] == pytest.approx(t["beta"], rel=1e-9, abs=1e-12)
+
+
+def test_batch_band_layout_mixed_precisions_and_compaction():
+    # 12 instances, mixed precision with an early polish switch: instances run
+    # in FP32 and FP64 side by side, finish at different times, and the band
+    # kernels skip instances in the other precision
+    insts = _small_c2(12, 10, m_lo=30, m_hi=300)
+    b = P.Batch([P.Problem.from_instance(i) for i in insts])
+    b.set_layout("bands")
+    sols = b.solve(precision="mixed", polish_switch_tol=1e-4, time_limit=120.0)
+    assert any(0 < s.info["fp64_iters"] < s.info["iters"] for s in sols)
+    for inst, s in zip(insts, sols):
+        lp = O.lpdata_from_instance(inst)
+        err = O.termination_errors(lp, s.x, s.y)
+        assert s.info["exit_code"] == 0
+        assert max(err["rel_p"], err["rel_d"], err["rel_gap"]) <= 1e-6 * 1.0001
