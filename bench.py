@@ -76,12 +76,16 @@ def run_c2(args, P, np):
     insts = lpgen.c2_batch(count=args.c2_count)
     probs = [P.Problem.from_instance(i) for i in insts]
     batch = P.Batch(probs)
+    if args.layout != "auto":
+        batch.set_layout(args.layout)
     log(f"c2: {len(insts)} LPs, sum m {sum(i.m for i in insts)}, sum nnz {sum(i.nnz for i in insts)}, "
         f"set up in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     sched = batch.autotune(2000.0)
     log(f"autotuned schedule {sched} in {time.perf_counter() - t:.1f}s")
     opts = dict(precision="mixed", time_limit=600.0)
+    if args.max_trials:
+        opts["max_iter"] = args.max_trials
     for _ in range(args.warmup):
         batch.solve(**opts)
     walls, sols = [], None
@@ -170,6 +174,7 @@ def run_c3(args, P, np):
             out += P.Batch(probs).solve(None if xs is None else list(xs[lo:lo + chunk]),
                                         None if ys is None else list(ys[lo:lo + chunk]),
                                         precision="mixed", time_limit=600.0)
+            log(f"  solved members {lo}..{lo + len(probs) - 1}")
         return out
 
     t0 = time.perf_counter()
@@ -347,9 +352,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1", choices=["c1", "c1_nnz_matched", "c2", "c3", "c4"])
     ap.add_argument("--c2-count", type=int, default=512)
+    ap.add_argument("--layout", default="auto", choices=["auto", "rows", "bands"],
+                    help="c2: matrix layout of the batch (profiling)")
+    ap.add_argument("--max-trials", type=int, default=0, help="c2: cap on trials per instance (profiling)")
     ap.add_argument("--c3-train", type=int, default=1024)
     ap.add_argument("--c3-test", type=int, default=256)
-    ap.add_argument("--c3-epochs", type=int, default=30)
+    ap.add_argument("--c3-epochs", type=int, default=200)
     ap.add_argument("--cpu-trials", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and plain-SpMV side measurements")

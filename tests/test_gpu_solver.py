@@ -77,15 +77,48 @@ def test_scaling_matches_oracle():
     assert np.allclose(sol.D2, D2o, rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("mz", [None, 60])
-def test_first_trials_match_oracle_elementwise(mz):
+def _edge_lp():
+    # >= rows, an empty row, an empty column, and every kind of bound:
+    # [l, u], [l, inf), (-inf, u], free
+    inst = lpgen.planted_lp(lpgen.rng_for(78, 0), 90, 200, per_col=4, m_zero=50)
+    rp, ci, v = inst.row_ptr.copy(), inst.col_idx.copy(), inst.val.copy()
+    # empty row 7 and empty column 11
+    keep = np.ones(v.size, bool)
+    rows = np.repeat(np.arange(inst.m), np.diff(rp))
+    keep &= rows != 7
+    keep &= ci != 11
+    rows, ci, v = rows[keep], ci[keep], v[keep]
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=inst.m))]).astype(np.int64)
+    l, u = inst.l.copy(), inst.u.copy()
+    j = np.arange(inst.n)
+    l[j % 4 == 1] = -np.inf
+    u[j % 4 == 2] = np.inf
+    l[j % 4 == 3], u[j % 4 == 3] = -np.inf, np.inf
+    x0 = inst.x_planted
+    h = np.zeros(inst.m)
+    np.add.at(h, rows, v * x0[ci])
+    h[inst.m_zero:] -= 0.5       # >= rows hold with slack at x0
+    # costs that keep the LP bounded: no recession direction lowers c^T x
+    c = inst.c.copy()
+    c[j % 4 == 1] *= -1.0         # (-inf, u]: decreasing x raises the cost
+    c[j % 4 == 3] = 0.0           # free columns
+    return lpgen.LPInstance(inst.m, inst.n, inst.m_zero, rp, ci.astype(np.int32), v, h, c, l, u, name="edge")
+
+
+@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("mz", [None, 60, "edge"])
+def test_first_trials_match_oracle_elementwise(mz, layout):
     # Before the first restart check the iteration is deterministic: after N
     # trials the GPU state must equal the oracle's up to rounding.
-    inst = lpgen.planted_lp(lpgen.rng_for(77, 1), 120, 300, per_col=4, m_zero=mz)
+    if mz == "edge":
+        inst = _edge_lp()
+    else:
+        inst = lpgen.planted_lp(lpgen.rng_for(77, 1), 120, 300, per_col=4, m_zero=mz)
     lp = O.lpdata_from_instance(inst)
     N = 40
     ref = O.solve(lp, O.Options(max_iter=N, check_every=1000))
     prob = P.Problem.from_instance(inst)
+    prob.set_layout(layout)
     sol = prob.solve(precision="fp64", max_iter=N, check_every=1000, keep_state=True)
     st = sol.state
     assert st["kbar"] == ref.state["kbar"] == N
@@ -316,3 +349,22 @@ def test_band_layout_spmv_elementwise(maker, precision):
         lens = np.diff(M.indptr)
         err = np.abs(got - want)
         assert np.all(err <= (lens + 4) * u * bound), (transpose, np.max(err / (bound + 1e-300)))
+
+
+
+@pytest.fixture(scope="module")
+def edge_ref():
+    inst = _edge_lp()
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options(time_limit=120))
+    assert ref.exit_code == 0
+    return inst, ref
+
+
+@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_edge_lp_solves(edge_ref, layout, precision):
+    inst, ref = edge_ref
+    prob = P.Problem.from_instance(inst)
+    prob.set_layout(layout)
+    sol = prob.solve(precision=precision, time_limit=60.0)
+    _check_solution(inst, sol, ref.pobj)
