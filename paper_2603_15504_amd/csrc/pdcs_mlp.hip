@@ -29,18 +29,80 @@ constexpr int TM = 128, TN = 128, TK = 32, LDK = TK + 8;  // LDS row stride: 80 
 
 __device__ __forceinline__ bf16 to_bf16(float v) { return (bf16)v; }
 
+// One operand tile (128 rows of op(X) x TK) staged through registers.  op(X)
+// row r, column k lives at X[k * ld + r] when trans, else X[r * ld + k].  Each
+// thread owns two 8-element vectors of the tile: along k when the source is
+// k-contiguous (not trans), along r otherwise.  vec: the launch guarantees
+// 16-byte alignment of the source and ld % 8 == 0, so whole vectors inside the
+// bounds load with one 16-byte access; anything else loads element by element.
+struct TileRegs {
+  bf16x8 v[2];
+};
+
+__device__ __forceinline__ void tile_load(const bf16* __restrict__ X, int ld, int trans, int vec, int r0, int R,
+                                          int k0, int kend, TileRegs& t) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = tid + q * 256;  // vector index in the tile: 512 vectors of 8
+    int rr, kk;
+    if (!trans) {
+      rr = e / (TK / 8);
+      kk = (e % (TK / 8)) * 8;
+    } else {
+      kk = e / (TM / 8);
+      rr = (e % (TM / 8)) * 8;
+    }
+    const int gr = r0 + rr, gk = k0 + kk;
+    bf16x8 v;
+    if (!trans) {
+      if (vec && gr < R && gk + 8 <= kend) {
+        v = *reinterpret_cast<const bf16x8*>(X + (size_t)gr * ld + gk);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (gr < R && gk + i < kend) ? X[(size_t)gr * ld + gk + i] : to_bf16(0.0f);
+      }
+    } else {
+      if (vec && gk < kend && gr + 8 <= R) {
+        v = *reinterpret_cast<const bf16x8*>(X + (size_t)gk * ld + gr);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (gk < kend && gr + i < R) ? X[(size_t)gk * ld + gr + i] : to_bf16(0.0f);
+      }
+    }
+    t.v[q] = v;
+  }
+}
+
+__device__ __forceinline__ void tile_store(bf16 (*S)[LDK], int trans, const TileRegs& t) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = tid + q * 256;
+    if (!trans) {
+      const int rr = e / (TK / 8), kk = (e % (TK / 8)) * 8;
+      *reinterpret_cast<bf16x8*>(&S[rr][kk]) = t.v[q];
+    } else {
+      const int kk = e / (TM / 8), rr = (e % (TM / 8)) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[rr + i][kk] = t.v[q][i];
+    }
+  }
+}
+
 // C_part[z] = op(A)[m0:m0+128, kz] * op(B)[kz, n0:n0+128]
 //   op(A)[m][k] = ta ? A[k * lda + m] : A[m * lda + k]
 //   op(B)[k][n] = tb ? B[n * ldb + k] : B[k * ldb + n]
-__global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int lda, int ta,
-                                              const bf16* __restrict__ B, int ldb, int tb,
+// (op(B) is staged as its transpose, rows n, so both tiles are row x k.)
+__global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int lda, int ta, int veca,
+                                              const bf16* __restrict__ B, int ldb, int tb, int vecb,
                                               float* __restrict__ C, int M, int N, int K, int kchunk) {
   __shared__ __attribute__((aligned(16))) bf16 As[TM][LDK];
   __shared__ __attribute__((aligned(16))) bf16 Bs[TN][LDK];
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   f32x16 acc[2][2];
 #pragma unroll
@@ -49,39 +111,19 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  TileRegs ra, rb;
+  if (kbeg < kend) {
+    tile_load(A, lda, ta, veca, m0, M, kbeg, kend, ra);
+    tile_load(B, ldb, !tb, vecb, n0, N, kbeg, kend, rb);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
-    // A tile -> As[m][k]; walk the contiguous dimension of the source
-#pragma unroll 4
-    for (int e = tid; e < TM * TK; e += 256) {
-      int mm, kk;
-      if (!ta) {
-        mm = e / TK;
-        kk = e % TK;
-      } else {
-        kk = e / TM;
-        mm = e % TM;
-      }
-      const int gm = m0 + mm, gk = k0 + kk;
-      bf16 v = to_bf16(0.0f);
-      if (gm < M && gk < kend) v = ta ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-      As[mm][kk] = v;
-    }
-#pragma unroll 4
-    for (int e = tid; e < TN * TK; e += 256) {
-      int nn, kk;
-      if (tb) {
-        nn = e / TK;
-        kk = e % TK;
-      } else {
-        kk = e / TN;
-        nn = e % TN;
-      }
-      const int gn = n0 + nn, gk = k0 + kk;
-      bf16 v = to_bf16(0.0f);
-      if (gn < N && gk < kend) v = tb ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-      Bs[nn][kk] = v;
-    }
+    tile_store(As, ta, ra);
+    tile_store(Bs, !tb, rb);
     __syncthreads();
+    if (k0 + TK < kend) {  // prefetch the next tile while the matrix cores work
+      tile_load(A, lda, ta, veca, m0, M, k0 + TK, kend, ra);
+      tile_load(B, ldb, !tb, vecb, n0, N, k0 + TK, kend, rb);
+    }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 16) {
       bf16x8 a[2], b[2];
@@ -282,14 +324,21 @@ struct pdcs_mlp_s {
     int kchunk = (K + splits - 1) / splits;
     kchunk = (kchunk + TK - 1) / TK * TK;
     splits = (K + kchunk - 1) / kchunk;
+    // unsplit products with a plain FP32 result are written in place
+    const bool direct = splits == 1 && !bias && !relu && !mask && out32 && !out16;
     const size_t need = (size_t)splits * M * N * 4;
-    if (need > part_bytes) {
+    if (!direct && need > part_bytes) {
       part.alloc(need);
       part_bytes = need;
     }
-    k_gemm<<<dim3(gx, gy, splits), 256, 0, s>>>(A, lda, ta, Bm, ldb, tb, part.as<float>(), M, N, K, kchunk);
-    k_epilogue<<<lin((int64_t)M * N), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, bias, relu,
-                                                   mask, out32, out16);
+    // 16-byte vector loads need 16-byte aligned operands with row strides in whole vectors
+    const int veca = ((uintptr_t)A % 16 == 0 && lda % 8 == 0) ? 1 : 0;
+    const int vecb = ((uintptr_t)Bm % 16 == 0 && ldb % 8 == 0) ? 1 : 0;
+    k_gemm<<<dim3(gx, gy, splits), 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb,
+                                               direct ? out32 : part.as<float>(), M, N, K, kchunk);
+    if (!direct)
+      k_epilogue<<<lin((int64_t)M * N), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, bias, relu,
+                                                     mask, out32, out16);
   }
 
   void forward(const float* in, int64_t B, hipStream_t s) {
