@@ -114,7 +114,7 @@ struct BandSet {
   int ntile = 0, nslot = 0;
   int64_t R = 0, nent = 0;
   DBuf group, slot, start, row0, nrows, used, tinst, col0, panel, run_start, run_row, run_ext, ext, pk, src;
-  DBuf val32, val64, part32, part64;
+  DBuf val32, val64, part32, part64, part64b;
   DBuf orig32, orig64;  // unscaled values (plain products), filled on first use
   // instance b: rows [r0s[b], r0s[b+1]) gathering from [g0s[b], g0s[b+1])
   void build(const std::vector<int64_t>& r0s, const std::vector<int64_t>& g0s, const std::vector<int32_t>& ptr,

@@ -614,6 +614,7 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
   val64.alloc((size_t)nent * 8);
   part32.alloc((size_t)P * R * 4);
   part64.alloc((size_t)P * R * 8);
+  part64b.alloc((size_t)P * R * 8);
 }
 
 BandTiles BandSet::view() const {
@@ -754,10 +755,12 @@ void Engine::build_schedule() {
     P1 = panels_x > 0 ? panels_x : auto_panels(N);
     P2 = panels_y > 0 ? panels_y : auto_panels(M);
   }
-  prow.P = pcol.P = 1;
-  if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
-  if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
   const bool want_band = layout == PDCS_LAYOUT_BANDS || (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 22));
+  prow.P = pcol.P = 1;
+  if (!want_band) {  // the panel-major CSR copies serve the row layout only
+    if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
+    if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
+  }
   if (want_band && !band1.nslot && !band2.nslot) {
     band1.build(row0, col0, h_rp, h_ci);
     band2.build(col0, row0, h_cp, h_ri);
@@ -848,6 +851,8 @@ KernelCtx Engine::ctx(int probe_passes) const {
     k.bpart64 = band1.part64.as<double>();
     k.bpartT32 = band2.part32.as<float>();
     k.bpartT64 = band2.part64.as<double>();
+    k.bpart64b = band1.part64b.as<double>();
+    k.bpartT64b = band2.part64b.as<double>();
   }
   if (pcol.P > 1) {
     k.pcol = pcol.tiles.view();

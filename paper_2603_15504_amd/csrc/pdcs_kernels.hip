@@ -191,38 +191,39 @@ __global__ __launch_bounds__(kBlock) void k_spmv_part(RowBlocks rb, const int32_
 // pipelined: packed entries and values are loaded two iterations ahead and the
 // gathers one iteration ahead of the accumulation.  Output: part[panel * R + r].
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, const T* __restrict__ val,
-                                                                  const T* __restrict__ x, T* __restrict__ part,
-                                                                  int64_t R, const Inst* __restrict__ inst,
-                                                                  int prec, int need_acc) {
+// Instances a check or evaluation pass works on.
+enum Mode : int { kModeCheck = 0, kModeEvalStart = 1, kModeEvalFinal = 2 };
+
+__device__ __forceinline__ bool mode_selects(const Inst& I, int mode) {
+  if (mode == kModeCheck) return I.status == kActive && I.check_due != 0;
+  if (mode == kModeEvalStart) return I.status == kActive;
+  return I.status == kDone && I.exit_code != 0;
+}
+
+// One wave's band-tile t: part[panel * R + r] = sum over the tile's entries of
+// row r of val * x[col], values TV, gathered vector TX, accumulation and output TA.
+template <typename TV, typename TX, typename TA>
+__device__ __forceinline__ void band_tile_product(const BandTiles& bt, int t, TA* a, const TV* __restrict__ val,
+                                                  const TX* __restrict__ x, TA* __restrict__ part, int64_t R) {
   constexpr int U = kBandUnroll;
-  __shared__ T acc[kBandWaves * kBandSlots];
-  const int g = bt.slot[blockIdx.x];
-  if (g < 0) return;
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int t = bt.group[g * kBandWaves + w];
-  if (t < 0) return;
-  if (inst) {  // solver passes: only instances iterating in this precision (and accepted, for G^T y)
-    const Inst& I = inst[bt.tinst[t]];
-    if (I.status != kActive || I.precision != prec || (need_acc && I.last_acc == 0)) return;
-  }
-  T* a = acc + w * kBandSlots;
+  const int lane = threadIdx.x & (kWave - 1);
   // the sink slot of the padding is never read and stays uninitialized
   const int used = bt.used[t];
-  for (int i = lane; i < used; i += kWave) a[i] = T(0);
-  const T* xs = x + bt.col0[t];
+  for (int i = lane; i < used; i += kWave) a[i] = TA(0);
+  const TX* xs = x + bt.col0[t];
   const int e0 = bt.start[t];
   const int nit = (bt.start[t + 1] - e0) / (U * kWave);
   const uint32_t* pp = bt.pk + e0 + lane;
-  const T* vp = val + e0 + lane;
+  const TV* vp = val + e0 + lane;
   constexpr uint32_t kSlotMask = (1u << kBandSlotBits) - 1u;
   uint32_t pA[U], pB[U], pC[U];
-  T vA[U], vB[U], vC[U], xA[U], xB[U];
+  TV vA[U], vB[U], vC[U];
+  TX xA[U], xB[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     pA[u] = pB[u] = pC[u] = 0u;
-    vA[u] = vB[u] = vC[u] = xA[u] = xB[u] = T(0);
+    vA[u] = vB[u] = vC[u] = TV(0);
+    xA[u] = xB[u] = TX(0);
   }
   if (nit > 0) {
 #pragma unroll
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t sl = pA[u] & kSlotMask;
-      a[sl] = a[sl] + vA[u] * xA[u];
+      a[sl] = a[sl] + (TA)vA[u] * (TA)xA[u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -272,13 +273,74 @@ __global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, 
   // fold the extra slots into their rows (one lane per run, runs own distinct rows)
   for (int r = bt.run_start[t] + lane; r < bt.run_start[t + 1]; r += kWave) {
     const int row = bt.run_row[r];
-    T s = a[row];
+    TA s = a[row];
     for (int q = bt.run_ext[r]; q < bt.run_ext[r + 1]; ++q) s += a[bt.ext[q]];
     a[row] = s;
   }
   const int nr = bt.nrows[t];
-  T* out = part + (size_t)bt.panel[t] * R + bt.row0[t];
+  TA* out = part + (size_t)bt.panel[t] * R + bt.row0[t];
   for (int i = lane; i < nr; i += kWave) out[i] = a[i];
+}
+
+// Trial products (K1: G x_hat, K2: G^T y_hat) in the iterate precision T.
+template <typename T>
+__global__ __launch_bounds__(kBandWaves * kWave) void k_band_spmv(BandTiles bt, const T* __restrict__ val,
+                                                                  const T* __restrict__ x, T* __restrict__ part,
+                                                                  int64_t R, const Inst* __restrict__ inst,
+                                                                  int prec, int need_acc) {
+  __shared__ T acc[kBandWaves * kBandSlots];
+  const int g = bt.slot[blockIdx.x];
+  if (g < 0) return;
+  const int w = threadIdx.x / kWave;
+  const int t = bt.group[g * kBandWaves + w];
+  if (t < 0) return;
+  if (inst) {  // solver passes: only instances iterating in this precision (and accepted, for G^T y)
+    const Inst& I = inst[bt.tinst[t]];
+    if (I.status != kActive || I.precision != prec || (need_acc && I.last_acc == 0)) return;
+  }
+  band_tile_product<T, T, T>(bt, t, acc + w * kBandSlots, val, x, part, R);
+}
+
+// Check / evaluation products with FP64 values of vectors in the iterate
+// precision TX (which = 1: the average candidate, skipped where unused).
+template <typename TX>
+__global__ __launch_bounds__(kBandWaves * kWave) void k_band_cand(BandTiles bt, const double* __restrict__ val,
+                                                                  const TX* __restrict__ x,
+                                                                  double* __restrict__ part, int64_t R,
+                                                                  const Inst* __restrict__ inst, int prec, int mode,
+                                                                  int which) {
+  __shared__ double acc[kBandWaves * kBandSlots];
+  const int g = bt.slot[blockIdx.x];
+  if (g < 0) return;
+  const int w = threadIdx.x / kWave;
+  const int t = bt.group[g * kBandWaves + w];
+  if (t < 0) return;
+  const Inst& I = inst[bt.tinst[t]];
+  if (!mode_selects(I, mode) || I.precision != prec) return;
+  if (which == 1 && mode == kModeCheck && I.use_avg == 0) return;
+  band_tile_product<double, TX, double>(bt, t, acc + w * kBandSlots, val, x, part, R);
+}
+
+// Window sums of the check / evaluation products, per instance.
+__global__ __launch_bounds__(kBlock) void k_band_combine2(Ranges Rg, int P, int64_t R,
+                                                          const double* __restrict__ part0,
+                                                          const double* __restrict__ part1,
+                                                          double* __restrict__ out0, double* __restrict__ out1,
+                                                          const Inst* __restrict__ inst, int mode) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[Rg.blk_inst[b]];
+  if (!mode_selects(I, mode)) return;
+  const bool two = part1 != nullptr && (mode != kModeCheck || I.use_avg != 0);
+  const int r1 = Rg.blk_end[b];
+  for (int r = Rg.blk_start[b] + (int)threadIdx.x; r < r1; r += kBlock) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int p = 0; p < P; ++p) {
+      s0 += part0[(size_t)p * R + r];
+      if (two) s1 += part1[(size_t)p * R + r];
+    }
+    out0[r] = s0;
+    if (two) out1[r] = s1;
+  }
 }
 
 // Sum of the P window partial sums per row (plain product of the band layout).
@@ -482,13 +544,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(const int32_t* __restrict__
 // ===========================================================================
 // Restart / termination check
 // ===========================================================================
-enum Mode : int { kModeCheck = 0, kModeEvalStart = 1, kModeEvalFinal = 2 };
-
-__device__ __forceinline__ bool mode_selects(const Inst& I, int mode) {
-  if (mode == kModeCheck) return I.status == kActive && I.check_due != 0;
-  if (mode == kModeEvalStart) return I.status == kActive;
-  return I.status == kDone && I.exit_code != 0;
-}
 
 // Apply the pending Halpern commit, then form the average candidate S / sum(eta).
 template <typename T>
@@ -1618,7 +1673,30 @@ template <typename T>
 static void launch_cand_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                           const T* x0, const T* x1, const T* y0, const T* y1, int mode) {
   auto blocks = [](int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
-  if (k.P1 > 1) {
+  if (k.use_band) {
+    // band tiles with FP64 values: one pass per vector, then the window sums
+    if (k.band1.nslot > 0) {
+      k_band_cand<T><<<grid1(k.band1.nslot), kBandWaves * kWave, 0, s>>>(k.band1, k.bval64, x0, k.bpart64, k.M,
+                                                                         k.inst, prec, mode, 0);
+      if (x1)
+        k_band_cand<T><<<grid1(k.band1.nslot), kBandWaves * kWave, 0, s>>>(k.band1, k.bval64, x1, k.bpart64b, k.M,
+                                                                           k.inst, prec, mode, 1);
+    }
+    if (k.vrow.nblk > 0)
+      k_band_combine2<<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, k.band1.P, k.M, k.bpart64,
+                                                             x1 ? k.bpart64b : nullptr, k.cgx0, k.cgx1, k.inst, mode);
+    if (k.band2.nslot > 0) {
+      k_band_cand<T><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, k.bvalT64, y0, k.bpartT64, k.N,
+                                                                         k.inst, prec, mode, 0);
+      if (y1)
+        k_band_cand<T><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, k.bvalT64, y1, k.bpartT64b,
+                                                                           k.N, k.inst, prec, mode, 1);
+    }
+    if (k.vcol.nblk > 0)
+      k_band_combine2<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, k.band2.P, k.N, k.bpartT64,
+                                                             y1 ? k.bpartT64b : nullptr, k.cgty0, k.cgty1, k.inst,
+                                                             mode);
+  } else if (k.P1 > 1) {
     if (k.nslot1 > 0)
       k_spmv2_part<T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, k.PA64, x0, x1, k.part64, k.part64b,
                                                           k.inst, prec, mode);
@@ -1628,7 +1706,9 @@ static void launch_cand_t(const KernelCtx& k, hipStream_t s, int prec, const Ite
   } else if (k.brow.nblk > 0) {
     k_spmv2<T><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, k.A64, x0, x1, k.cgx0, k.cgx1, k.inst, prec, mode);
   }
-  if (k.P2 > 1) {
+  if (k.use_band) {
+    // done above
+  } else if (k.P2 > 1) {
     if (k.nslot2 > 0)
       k_spmv2_part<T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, k.PAT64, y0, y1, k.partT64,
                                                           k.partT64b, k.inst, prec, mode);

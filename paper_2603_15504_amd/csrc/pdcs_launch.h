@@ -74,7 +74,7 @@ struct KernelCtx {
   const float *bval32, *bvalT32;
   const double *bval64, *bvalT64;
   float *bpart32, *bpartT32;
-  double *bpart64, *bpartT64;
+  double *bpart64, *bpartT64, *bpart64b, *bpartT64b;  // b: second vector of the check products
 
   // the K1 (K2) product is split into partial sums plus an epilogue pass
   bool split1() const { return use_band || P1 > 1; }
