@@ -58,7 +58,7 @@ struct HostProblem {
 struct Schedule {
   int iter_max = 8;        // passes per lane group in a multi-row wavefront tile
   int block_nnz = 8192;    // work units (nonzeros + 4 per row) per workgroup
-  int vec_per_block = 2048;  // elements per workgroup in elementwise passes
+  int vec_per_block = 1024;  // elements per workgroup in elementwise passes
 };
 
 struct TileSet {
