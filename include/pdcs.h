@@ -107,7 +107,10 @@ typedef struct {
   int64_t compact;            /* 1: a batch of >= 8 LPs rebuilds its schedules over the
                                  still-active instances each time half of them have
                                  finished (results are identical either way)          */
-  int64_t reserved[2];
+  int64_t use_kkt_restart;    /* 0; 1: candidates are compared and the restart rules
+                                 evaluated on KKT_omega instead of the normalized
+                                 duality gap (Section 2.3, option use_kkt_restart)    */
+  int64_t reserved[1];
 } pdcs_options;
 
 /* Per-solve information (result fields of Section 3 plus counters). */

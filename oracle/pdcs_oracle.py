@@ -465,6 +465,7 @@ class Options:
     ruiz_iters: int = 10
     l2_pass: bool = True
     method: str = "auto"             # auto | average | halpern (candidate rule)
+    use_kkt_restart: bool = False    # compare candidates and restart on KKT_omega (Section 2.3)
     check_every: int = 64            # restart / termination check period, in trials
     bisect_rel_eps: float = 1e-6
     max_doublings: int = 64
@@ -607,7 +608,8 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
             # anchor or of the previous candidate that is negative, NaN or has
             # r = 0 switches every comparison of this check to KKT_omega.
             stored = [d["rho"] for d in (metric_anchor, metric_prev) if d is not None]
-            use_kkt = not all(_valid_rho(v) for v in [i["rho"] for i in info.values()] + stored)
+            use_kkt = opts.use_kkt_restart or not all(
+                _valid_rho(v) for v in [i["rho"] for i in info.values()] + stored)
             key = "kkt" if use_kkt else "rho"
             if "cur" in info and "avg" in info:
                 chosen = "cur" if info["cur"][key] <= info["avg"][key] else "avg"

@@ -36,7 +36,8 @@ class pdcs_options(C.Structure):
                 ("polish_switch_tol", C.c_double), ("bisect_rel_eps", C.c_double),
                 ("use_graph", C.c_int64), ("verbose", C.c_int64), ("keep_state", C.c_int64),
                 ("time_kernels", C.c_int64), ("probe_passes", C.c_int64),
-                ("trace_trials", C.c_int64), ("compact", C.c_int64), ("reserved", C.c_int64 * 2)]
+                ("trace_trials", C.c_int64), ("compact", C.c_int64), ("use_kkt_restart", C.c_int64),
+                ("reserved", C.c_int64 * 1)]
 
 
 class pdcs_info(C.Structure):

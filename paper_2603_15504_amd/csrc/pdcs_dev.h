@@ -59,6 +59,7 @@ struct Inst {
   // restart bookkeeping
   double rho_anchor, kkt_anchor, rho_prev, kkt_prev;
   int32_t restart, chosen, optimal, use_kkt;
+  int32_t force_kkt;  // option: restart decisions on KKT_omega instead of the normalized gap
   double best_rel, rel_tol, abs_tol, polish_tol, bisect_eps;
   int64_t stall, stall_checks;
   double best_any;    // lowest relative KKT error of the FP32 phase

@@ -876,6 +876,7 @@ static void validate_options(const pdcs_options& o) {
   if (o.precision < 0 || o.precision > 1) throw Error(PDCS_ERR_INVALID_ARG, "unknown precision");
   if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) throw Error(PDCS_ERR_INVALID_ARG, "ruiz_iters in [0, 1000]");
   if (o.probe_passes < 1 || o.probe_passes > 64) throw Error(PDCS_ERR_INVALID_ARG, "probe_passes in [1, 64]");
+  if (o.use_kkt_restart < 0 || o.use_kkt_restart > 1) throw Error(PDCS_ERR_INVALID_ARG, "use_kkt_restart is 0 or 1");
   if (!(o.bisect_rel_eps > 0)) throw Error(PDCS_ERR_INVALID_ARG, "bisect_rel_eps must be > 0");
   if (std::isnan(o.time_limit)) throw Error(PDCS_ERR_INVALID_ARG, "time_limit is NaN");
 }
@@ -944,6 +945,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     I.check_every = o.check_every;
     I.method = (int32_t)o.method;
     I.use_avg = o.method != PDCS_METHOD_HALPERN ? 1 : 0;
+    I.force_kkt = o.use_kkt_restart ? 1 : 0;
     I.rel_tol = o.rel_tol;
     I.abs_tol = o.abs_tol;
     I.polish_tol = o.polish_switch_tol;

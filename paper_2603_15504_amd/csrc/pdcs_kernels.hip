@@ -994,7 +994,7 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
   }
   if (I.has_anchor && !(I.rho_anchor >= 0.0 && isfinite(I.rho_anchor))) all_valid = false;
   if (I.has_prev && !(I.rho_prev >= 0.0 && isfinite(I.rho_prev))) all_valid = false;
-  const bool use_kkt = !all_valid;
+  const bool use_kkt = I.force_kkt != 0 || !all_valid;
   int ch;
   if (I.method == 1) ch = 1;
   else if (I.method == 2 || nc == 1) ch = 0;

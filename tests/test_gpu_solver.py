@@ -368,3 +368,39 @@ def test_edge_lp_solves(edge_ref, layout, precision):
     prob.set_layout(layout)
     sol = prob.solve(precision=precision, time_limit=60.0)
     _check_solution(inst, sol, ref.pobj)
+
+
+
+@pytest.mark.parametrize("variant", ["average", "halpern", "kkt"])
+@pytest.mark.parametrize("layout", ["rows", "bands"])
+def test_restart_variants_match_oracle(variant, layout):
+    # the candidate rules of Section 2.3 (average only, Halpern only) and the
+    # KKT restart option, each against the oracle run with the same option
+    inst = lpgen.c0_instance(4)
+    lp = O.lpdata_from_instance(inst)
+    kw = dict(use_kkt_restart=True) if variant == "kkt" else dict(method=variant)
+    ref = O.solve(lp, O.Options(time_limit=120, **kw))
+    assert ref.exit_code == 0
+    prob = P.Problem.from_instance(inst)
+    prob.set_layout(layout)
+    gkw = dict(use_kkt_restart=1) if variant == "kkt" else dict(method=variant)
+    sol = prob.solve(precision="fp64", time_limit=60.0, **gkw)
+    print(f"{variant} {layout}: gpu trials {sol.info['iters']} restarts {sol.info['restarts']}, "
+          f"oracle {ref.iters} / {ref.restarts}", flush=True)
+    _check_solution(inst, sol, ref.pobj)
+
+
+@pytest.mark.parametrize("variant", ["average", "halpern", "kkt"])
+def test_restart_variants_first_check_matches_oracle(variant):
+    # deterministic up to the first check: the chosen candidate and restart
+    inst = lpgen.c1_instance(0, m=300, n=600)
+    lp = O.lpdata_from_instance(inst)
+    kw = dict(use_kkt_restart=True) if variant == "kkt" else dict(method=variant)
+    ref = O.solve(lp, O.Options(max_iter=64, check_every=64, **kw))
+    c = ref.checks_log[0]
+    gkw = dict(use_kkt_restart=1) if variant == "kkt" else dict(method=variant)
+    sol = P.Problem.from_instance(inst).solve(precision="fp64", max_iter=64, check_every=64, keep_state=True, **gkw)
+    st = sol.state
+    assert st["chosen"] == (0 if c["chosen"] == "cur" else 1)
+    assert sol.info["restarts"] == ref.restarts
+    assert st["omega"] == pytest.approx(ref.state["omega"], rel=1e-9)

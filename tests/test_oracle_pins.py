@@ -465,6 +465,17 @@ def test_candidate_methods_against_highs(method):
     assert abs(r.pobj - p) / (1 + abs(p)) <= 1e-6
 
 
+def test_kkt_restart_option_against_highs():
+    # restart decisions on KKT_omega (the use_kkt_restart option of Section 3,
+    # the fallback metric of Section 2.3) still reach the optimum
+    lp = _small_lp(7, m=20, n=50, mz=10)
+    p, _, _ = _highs(lp)
+    r = O.solve(lp, O.Options(use_kkt_restart=True, rel_tol=1e-7, abs_tol=1e-7))
+    assert r.exit_code == 0
+    assert all(c["use_kkt"] for c in r.checks_log)
+    assert abs(r.pobj - p) / (1 + abs(p)) <= 1e-6
+
+
 def test_infinite_bounds_and_geq_rows_against_highs():
     rng = np.random.default_rng(21)
     inst = lpgen.planted_lp(lpgen.rng_for(91, 0), 15, 40, per_col=3, m_zero=8)
