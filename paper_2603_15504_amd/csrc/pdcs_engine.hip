@@ -502,11 +502,21 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
   std::vector<int32_t> stamp(kBandSlots, -1), next(kBandSlots, -1);
   int32_t gid = 0;
   std::vector<std::pair<int64_t, int64_t>> bands;  // row ranges, split on slot overflow
+  // Per instance of a batch, bands no taller than needed for about 64 Ki
+  // entries per window, so that tiles of very different instances stay
+  // comparable in work (a single instance keeps the height chosen above).
   for (int b = 0; b < NB; ++b) {
     const int64_t gb = g0s[b], wb = g0s[b + 1] - g0s[b];
     const int64_t W = std::max<int64_t>(1, (wb + Pb[b] - 1) / Pb[b]);
+    int64_t rbb = rb;
+    if (NB > 1) {
+      const int64_t rows_b = r0s[b + 1] - r0s[b];
+      const int64_t nnz_b = rows_b > 0 ? (int64_t)ptr[r0s[b + 1]] - ptr[r0s[b]] : 0;
+      const double per_row = rows_b > 0 ? (double)nnz_b / (double)rows_b / (double)Pb[b] : 1.0;
+      while (rbb > 256 && (double)rbb * per_row > 65536.0) rbb /= 2;
+    }
     std::vector<std::pair<int64_t, int64_t>> todo;
-    for (int64_t r = r0s[b + 1]; r > r0s[b]; r -= rb) todo.push_back({std::max<int64_t>(r0s[b], r - rb), r});
+    for (int64_t r = r0s[b + 1]; r > r0s[b]; r -= rbb) todo.push_back({std::max<int64_t>(r0s[b], r - rbb), r});
     while (!todo.empty()) {
       const auto br = todo.back();
       todo.pop_back();
@@ -540,22 +550,52 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
   std::vector<int32_t> grp;
   std::vector<std::vector<int32_t>> per_xcd(8);
   std::vector<int64_t> load(8, 0);
+  // In a batch, every tile of an instance goes to one XCD (largest instances
+  // first, each to the least loaded XCD), so that the instance's gathered
+  // vector is fetched into one L2 only; instances holding more than 1/16 of
+  // the work are spread over the XCDs like a single problem.
+  std::vector<int> inst_xcd(NB, -1);
+  if (NB > 1) {
+    std::vector<int64_t> iw(NB, 0);
+    int64_t total = 0;
+    for (int t = 0; t < ntile; ++t) {
+      iw[bb.tinst[t]] += bb.work[t] + 1;
+      total += bb.work[t] + 1;
+    }
+    std::vector<int> order(NB);
+    for (int b = 0; b < NB; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return iw[a] > iw[c]; });
+    for (int b : order) {
+      if (iw[b] * 16 > total) continue;
+      int x = 0;
+      for (int q = 1; q < 8; ++q)
+        if (load[q] < load[x]) x = q;
+      inst_xcd[b] = x;
+      load[x] += iw[b];
+    }
+  }
   for (int p = 0; p < P; ++p)
     for (int g = 0; g < ng; ++g) {
       const int gi = (int)(grp.size() / kBandWaves);
       int64_t work = 0;
+      int first = -1;
       for (int w = 0; w < kBandWaves; ++w) {
         const int b = g * kBandWaves + w;
         const int t = b < nb ? b * P + p : -1;
         grp.push_back(t);
-        if (t >= 0) work += bb.work[t];
+        if (t >= 0) {
+          work += bb.work[t];
+          if (first < 0) first = t;
+        }
       }
-      int best = -1;
-      for (int x = 0; x < 8; ++x) {
-        const bool serves = P >= 8 ? (p % 8 == x) : (x % P == p);
-        if (serves && (best < 0 || load[x] < load[best])) best = x;
+      int best = first >= 0 && NB > 1 ? inst_xcd[bb.tinst[first]] : -1;
+      if (best < 0) {
+        for (int x = 0; x < 8; ++x) {
+          const bool serves = NB > 1 || (P >= 8 ? (p % 8 == x) : (x % P == p));
+          if (serves && (best < 0 || load[x] < load[best])) best = x;
+        }
+        load[best] += work + 1;
       }
-      load[best] += work + 1;
       per_xcd[best].push_back(gi);
     }
   size_t depth = 0;
