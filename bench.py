@@ -49,14 +49,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def one_thread():
+    """Context pinning NumPy's BLAS to one thread (the oracle's stated core count)."""
+    try:
+        from threadpoolctl import threadpool_limits
+
+        return threadpool_limits(limits=1)
+    except ImportError:  # pragma: no cover
+        import contextlib
+
+        return contextlib.nullcontext()
+
+
 def oracle_trial_seconds(inst, trials):
-    """Seconds per trial of the FP64 oracle on one instance (no rescaling)."""
+    """Seconds per trial of the FP64 oracle on one instance (no rescaling), one thread."""
     from oracle import pdcs_oracle as O
 
     lp = O.lpdata_from_instance(inst)
-    t0 = time.perf_counter()
-    r = O.solve(lp, O.Options(use_preconditioner=False, max_iter=trials, check_every=1 << 30))
-    return (time.perf_counter() - t0 - r.setup_sec) / max(r.iters, 1)
+    with one_thread():
+        t0 = time.perf_counter()
+        r = O.solve(lp, O.Options(use_preconditioner=False, max_iter=trials, check_every=1 << 30))
+        return (time.perf_counter() - t0 - r.setup_sec) / max(r.iters, 1)
 
 
 def common_fields(args, value, unit, ms, dtype, config, extra=None):
@@ -309,9 +322,10 @@ def cpu_baseline(inst, trials):
     t0 = time.perf_counter()
     lp = O.lpdata_from_instance(inst)
     t_load = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = O.solve(lp, O.Options(use_preconditioner=False, max_iter=trials, check_every=1 << 30))
-    total = time.perf_counter() - t0
+    with one_thread():
+        t0 = time.perf_counter()
+        r = O.solve(lp, O.Options(use_preconditioner=False, max_iter=trials, check_every=1 << 30))
+        total = time.perf_counter() - t0
     sec = total - r.setup_sec
     acc = r.accepted
     nbytes = (acc * trial_bytes(inst.m, inst.n, inst.nnz, 8, True)
