@@ -515,8 +515,23 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
       const double per_row = rows_b > 0 ? (double)nnz_b / (double)rows_b / (double)Pb[b] : 1.0;
       while (rbb > 256 && (double)rbb * per_row > 65536.0) rbb /= 2;
     }
-    std::vector<std::pair<int64_t, int64_t>> todo;
-    for (int64_t r = r0s[b + 1]; r > r0s[b]; r -= rbb) todo.push_back({std::max<int64_t>(r0s[b], r - rbb), r});
+    // Band boundaries with about equal entries (the count of rbb-row bands,
+    // each at most rbb rows): with heavy-tailed row lengths, fixed heights
+    // leave some bands far heavier than others, and the heaviest sets the time.
+    std::vector<std::pair<int64_t, int64_t>> cuts;
+    {
+      const int64_t ra = r0s[b], re = r0s[b + 1];
+      const int64_t nbands = (re - ra + rbb - 1) / rbb;
+      const double target = nbands > 0 ? (double)((int64_t)ptr[re] - ptr[ra]) / (double)nbands : 0.0;
+      int64_t r = ra;
+      while (r < re) {
+        int64_t e = r + 1;
+        while (e < re && e - r < rbb && (double)((int64_t)ptr[e + 1] - ptr[r]) <= target) ++e;
+        cuts.push_back({r, e});
+        r = e;
+      }
+    }
+    std::vector<std::pair<int64_t, int64_t>> todo(cuts.rbegin(), cuts.rend());
     while (!todo.empty()) {
       const auto br = todo.back();
       todo.pop_back();
