@@ -116,7 +116,7 @@ def _bind_hip_runtime_of_torch():
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     _bind_hip_runtime_of_torch()
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -m paper_2603_15504_amd.build` "
+        raise ImportError(f"{path} is missing: build it with `python paper_2603_15504_amd/build.py` "
                           "(there is no CPU fallback)")
     lib = C.CDLL(path)
     for name, (res, args) in PROTOTYPES.items():

@@ -1,6 +1,6 @@
 """Build libpdcs.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-Run as ``python -m paper_2603_15504_amd.build`` or through
+Run as ``python paper_2603_15504_amd/build.py`` or through
 ``__graft_entry__.build()``.  Always recompiles every source.
 """
 from __future__ import annotations
