@@ -419,16 +419,23 @@ struct BandBuild {
 };
 
 // Entries of rows [r0, r1) with gathered index in window p, sorted by gathered
-// index, with accumulator slots assigned per 64-entry group; false if the
-// band needs more than kBandSlots - 1 slots.
-bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t c0, int64_t c1, int inst, const std::vector<int32_t>& ptr,
-                     const std::vector<int32_t>& idx, std::vector<int32_t>& stamp, std::vector<int32_t>& next,
-                     int32_t& gid, BandBuild& out) {
+// index (rotated to start at window offset `shift`), with accumulator slots
+// assigned per 64-entry group; false if the band needs more than
+// kBandSlots - 1 slots.
+bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t c0, int64_t c1, int64_t shift, int inst,
+                     const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx, std::vector<int32_t>& stamp,
+                     std::vector<int32_t>& next, int32_t& gid, BandBuild& out) {
+  // sort key: the index relative to the window start, rotated by `shift`, so
+  // that tiles of one window sweep it from different starting points
+  const int64_t W = std::max<int64_t>(1, c1 - c0);
   std::vector<std::pair<uint64_t, int32_t>> E;
   for (int64_t r = r0; r < r1; ++r)
     for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
       const int64_t c = idx[q];
-      if (c >= c0 && c < c1) E.push_back({((uint64_t)(c - c0) << 20) | (uint64_t)(r - r0), (int32_t)q});
+      if (c >= c0 && c < c1) {
+        const int64_t key = (c - c0 + W - shift) % W;
+        E.push_back({((uint64_t)key << 20) | (uint64_t)(r - r0), (int32_t)q});
+      }
     }
   std::sort(E.begin(), E.end());
   const int nr = (int)(r1 - r0);
@@ -443,7 +450,7 @@ bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t c0, int64_t c1, int 
   out.tinst.push_back(inst);
   for (size_t k = 0; k < E.size(); ++k) {
     if (k % kWave == 0) ++gid;
-    const uint32_t col = (uint32_t)(E[k].first >> 20);
+    const uint32_t col = (uint32_t)(((int64_t)(E[k].first >> 20) + shift) % W);
     int s = (int)(E[k].first & 0xFFFFFu);
     while (stamp[s] == gid) {
       if (next[s] < 0) {
@@ -541,7 +548,13 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
         // window p of instance b (empty beyond its own window count)
         const int64_t c0 = p < Pb[b] ? gb + std::min<int64_t>(wb, p * W) : gb;
         const int64_t c1 = p < Pb[b] ? gb + std::min<int64_t>(wb, (p + 1) * W) : gb;
-        ok = build_band_tile(br.first, br.second, p, c0, c1, b, ptr, idx, stamp, next, gid, bb);
+        // Tiles of one window run at the same time and at about the same pace:
+        // started at the same index they would all gather from the same few
+        // KiB of the window, a handful of L2 channels, at any moment.  Each
+        // band starts its sweep at its own offset, spread over the window.
+        const int64_t rows_b = std::max<int64_t>(1, r0s[b + 1] - r0s[b]);
+        const int64_t shift = c1 > c0 ? (int64_t)((double)(br.first - r0s[b]) / (double)rows_b * (double)(c1 - c0)) % (c1 - c0) : 0;
+        ok = build_band_tile(br.first, br.second, p, c0, c1, shift, b, ptr, idx, stamp, next, gid, bb);
       }
       if (ok) {
         bands.push_back(br);
