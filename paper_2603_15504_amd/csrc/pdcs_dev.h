@@ -17,6 +17,7 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kProbes = 16;        // t values per bisection pass
+constexpr int kCheckCoarsen = 8;   // multisection passes: blocks this many times larger than the trial passes
 constexpr int kMaxCand = 2;        // restart candidates: current PDHG output, average
 
 enum Status : int32_t { kActive = 0, kDone = 1 };
@@ -202,6 +203,36 @@ __device__ __forceinline__ void block_summax_store(double (&v)[NV], double* lds,
 // Reduce the NV-wide records [b0, b1) of one instance inside one workgroup;
 // the first NS fields are summed, the rest take the maximum.  Result is
 // returned to every thread.  Fixed order: deterministic.
+// Sums of NV-value records b0..b1-1 (NV dividing kBlock) into out[0..NV) in
+// LDS: thread t adds value t % NV of every (kBlock / NV)-th record, reading
+// consecutive doubles across threads, then the kBlock / NV partial sums of
+// each value are added in a fixed order.  red: kBlock doubles of LDS.
+template <int NV>
+__device__ __forceinline__ void reduce_records_wide(const double* rec, int b0, int b1, double* red, double* out) {
+  static_assert(kBlock % NV == 0, "record width divides the block");
+  constexpr int R = kBlock / NV;
+  const int i = threadIdx.x % NV;
+  int b = b0 + (int)threadIdx.x / NV;
+  double acc = 0.0;
+  for (; b + 3 * R < b1; b += 4 * R) {
+    const double v0 = rec[(size_t)b * NV + i], v1 = rec[(size_t)(b + R) * NV + i];
+    const double v2 = rec[(size_t)(b + 2 * R) * NV + i], v3 = rec[(size_t)(b + 3 * R) * NV + i];
+    acc += v0;
+    acc += v1;
+    acc += v2;
+    acc += v3;
+  }
+  for (; b < b1; b += R) acc += rec[(size_t)b * NV + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double t = red[threadIdx.x];
+    for (int k = 1; k < R; ++k) t += red[k * NV + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
 template <int NV, int NS>
 __device__ __forceinline__ void reduce_records(const double* rec, int b0, int b1, double* lds,
                                                double (&res)[NV]) {

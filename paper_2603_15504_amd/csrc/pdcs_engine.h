@@ -157,6 +157,7 @@ struct Engine {
   TileSet trow, tcol;
   RowBlockSet brow, bcol;
   RangeSet vrow, vcol;
+  RangeSet crow, ccol;         // coarser blocks for the multisection passes
   PanelSet prow, pcol;         // panel-major G (gathers x) and G^T (gathers y) when split
   std::vector<int32_t> h_ci, h_ri;
   std::vector<double> h_v, h_vt;

@@ -819,6 +819,11 @@ void Engine::build_iteration_schedules(const std::vector<char>* active) {
   bcol.build(h_cp, col0, sched.iter_max * 4, active);
   vrow.build(row0, sched.vec_per_block, active);
   vcol.build(col0, sched.vec_per_block, active);
+  // The multisection passes reduce 32 values per element into per-workgroup
+  // records that one workgroup per instance sums: larger blocks mean fewer
+  // records and fewer block reductions, with the same arithmetic.
+  crow.build(row0, sched.vec_per_block * kCheckCoarsen, active);
+  ccol.build(col0, sched.vec_per_block * kCheckCoarsen, active);
 }
 
 void Engine::build_schedule() {
@@ -871,6 +876,8 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.bcol = bcol.view();
   k.vrow = vrow.view();
   k.vcol = vcol.view();
+  k.crow = crow.view();
+  k.ccol = ccol.view();
   k.inst = d_inst.as<Inst>();
   k.it32 = it32.p;
   k.it64 = it64.p;

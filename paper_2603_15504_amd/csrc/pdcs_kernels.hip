@@ -896,33 +896,42 @@ __global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __rest
 __global__ __launch_bounds__(kBlock) void k_probe_fin(Ranges rc, const double* __restrict__ rec_c,
                                                       Ranges rr, const double* __restrict__ rec_r,
                                                       Inst* __restrict__ inst) {
-  __shared__ double lds[kWavesPerBlock * kProbeNV];
+  __shared__ double red[kBlock];
+  // the bracket update below indexes probes at run time: its inputs live in
+  // LDS (registers indexed at run time would go to scratch memory)
+  __shared__ double s_dist[kMaxCand][kProbes], s_val[kMaxCand][kProbes], s_t[kMaxCand][kProbes];
+  __shared__ double s_cols[kProbeNV], s_rows[kProbeNV];
   const int iid = blockIdx.x;
   Inst& I = inst[iid];
   if (I.status != kActive || I.check_due == 0) return;
   const bool s0 = I.cand[0].phase == kPhaseExp || I.cand[0].phase == kPhaseBisect;
   const bool s1 = I.cand[1].phase == kPhaseExp || I.cand[1].phase == kPhaseBisect;
   if (!s0 && !s1) return;
-  double a[kMaxCand][kProbeNV], bsum[kMaxCand][kProbeNV];
+#pragma unroll
   for (int q = 0; q < kMaxCand; ++q) {
     const bool sq = q == 0 ? s0 : s1;
     if (!sq) continue;  // uniform across the workgroup
-    reduce_records<kProbeNV, kProbeNV>(rec_c + (size_t)q * rc.nblk * kProbeNV, rc.inst_blk0[iid],
-                                       rc.inst_blk0[iid + 1], lds, a[q]);
-    reduce_records<kProbeNV, kProbeNV>(rec_r + (size_t)q * rr.nblk * kProbeNV, rr.inst_blk0[iid],
-                                       rr.inst_blk0[iid + 1], lds, bsum[q]);
+    reduce_records_wide<kProbeNV>(rec_c + (size_t)q * rc.nblk * kProbeNV, rc.inst_blk0[iid], rc.inst_blk0[iid + 1],
+                                  red, s_cols);
+    reduce_records_wide<kProbeNV>(rec_r + (size_t)q * rr.nblk * kProbeNV, rr.inst_blk0[iid], rr.inst_blk0[iid + 1],
+                                  red, s_rows);
+    if (threadIdx.x == 0) {
+      const CandState& C = I.cand[q];
+      for (int p = 0; p < kProbes; ++p) {
+        s_dist[q][p] = sqrt(s_cols[p * 2] + s_rows[p * 2]);
+        s_val[q][p] = s_cols[p * 2 + 1] + s_rows[p * 2 + 1];
+        s_t[q][p] = probe_t(C, p);
+      }
+    }
   }
   if (threadIdx.x != 0) return;
   const double eps = I.bisect_eps;
   for (int q = 0; q < kMaxCand; ++q) {
     CandState& C = I.cand[q];
     if (C.phase != kPhaseExp && C.phase != kPhaseBisect) continue;
-    double dist[kProbes], val[kProbes], tp[kProbes];
-    for (int p = 0; p < kProbes; ++p) {
-      dist[p] = sqrt(a[q][p * 2] + bsum[q][p * 2]);
-      val[p] = a[q][p * 2 + 1] + bsum[q][p * 2 + 1];
-      tp[p] = probe_t(C, p);
-    }
+    const double* dist = s_dist[q];
+    const double* val = s_val[q];
+    const double* tp = s_t[q];
     if (C.phase == kPhaseExp) {
       bool decided = false;
       for (int p = 0; p < kProbes; ++p) {
@@ -1740,11 +1749,11 @@ static void launch_check_pre_t(const KernelCtx& k, hipStream_t s, int prec, cons
 
 template <typename T>
 static void launch_probe_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it) {
-  if (k.vcol.nblk > 0)
-    k_probe_cols<T><<<dim3(k.vcol.nblk, kMaxCand), kBlock, 0, s>>>(k.vcol, it.xh, it.xbar, k.cgty0, k.cgty1, k.d64,
+  if (k.ccol.nblk > 0)
+    k_probe_cols<T><<<dim3(k.ccol.nblk, kMaxCand), kBlock, 0, s>>>(k.ccol, it.xh, it.xbar, k.cgty0, k.cgty1, k.d64,
                                                            k.inst, prec, k.rec_probe_c);
-  if (k.vrow.nblk > 0)
-    k_probe_rows<T><<<dim3(k.vrow.nblk, kMaxCand), kBlock, 0, s>>>(k.vrow, it.yh, it.ybar, k.cgx0, k.cgx1, k.d64,
+  if (k.crow.nblk > 0)
+    k_probe_rows<T><<<dim3(k.crow.nblk, kMaxCand), kBlock, 0, s>>>(k.crow, it.yh, it.ybar, k.cgx0, k.cgx1, k.d64,
                                                            k.inst, prec, k.rec_probe_r);
 }
 
@@ -1766,7 +1775,7 @@ void launch_check(const KernelCtx& k, hipStream_t s, int mask) {
   for (int pass = 0; pass < k.probe_passes; ++pass) {
     if (mask & 1) launch_probe_t<float>(k, s, kFP32, k.it32);
     if (mask & 2) launch_probe_t<double>(k, s, kFP64, k.it64);
-    k_probe_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_probe_c, k.vrow, k.rec_probe_r, k.inst);
+    k_probe_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.ccol, k.rec_probe_c, k.crow, k.rec_probe_r, k.inst);
   }
   k_decide<<<nbt, 64, 0, s>>>(k.inst, k.nb);
   if (mask & 1) launch_restart_t<float>(k, s, kFP32, k.it32);

@@ -43,6 +43,7 @@ struct KernelCtx {
   Tiles trow, tcol;   // CSR of G (rows) and of G^T (columns): wavefront tiles (set-up passes)
   RowBlocks brow, bcol;  // the same structures in row blocks (iteration passes)
   Ranges vrow, vcol;  // elementwise passes over rows and columns
+  Ranges crow, ccol;  // the multisection passes: kCheckCoarsen times larger blocks
   Inst* inst;
   IterPtrs<float> it32;
   IterPtrs<double> it64;
