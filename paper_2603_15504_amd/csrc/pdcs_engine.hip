@@ -821,9 +821,17 @@ void Engine::build_iteration_schedules(const std::vector<char>* active) {
   vcol.build(col0, sched.vec_per_block, active);
   // The multisection passes reduce 32 values per element into per-workgroup
   // records that one workgroup per instance sums: larger blocks mean fewer
-  // records and fewer block reductions, with the same arithmetic.
-  crow.build(row0, sched.vec_per_block * kCheckCoarsen, active);
-  ccol.build(col0, sched.vec_per_block * kCheckCoarsen, active);
+  // records and fewer block reductions, with the same arithmetic.  Blocks
+  // grow up to kCheckCoarsen times, keeping about one block per CU.
+  auto check_block = [&](const std::vector<int64_t>& off) {
+    int64_t total = 0;
+    for (size_t b = 0; b + 1 < off.size(); ++b)
+      if (!active || (*active)[b]) total += off[b + 1] - off[b];
+    const int64_t f = std::max<int64_t>(1, std::min<int64_t>(kCheckCoarsen, total / (256 * (int64_t)sched.vec_per_block)));
+    return (int)(sched.vec_per_block * f);
+  };
+  crow.build(row0, check_block(row0), active);
+  ccol.build(col0, check_block(col0), active);
 }
 
 void Engine::build_schedule() {
