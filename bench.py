@@ -21,7 +21,7 @@ reported is the hot path's algorithmic HBM throughput in GB/s: bytes the
 trials must move (per accepted trial 16 nnz + 76 n + 40 m in FP32, a rejected
 trial without the G^T y pass; restart checks counted as zero bytes) divided by
 the wall time of the steps.  Solves per second for the converging workloads
-are measured by their own scripts.
+are measured with --workload c2 | c3 | c4 (one JSON line each).
 
 Prints one JSON line.
 """

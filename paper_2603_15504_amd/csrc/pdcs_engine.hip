@@ -514,8 +514,8 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
   std::vector<std::pair<int64_t, int64_t>> bands;  // row ranges, split on slot overflow
   // Per instance of a batch, bands no taller than needed for about 32 Ki
   // entries per window, so that tiles of very different instances stay
-  // comparable in work and the last round of tiles is short (a single
-  // instance keeps the height chosen above).  On the 512-LP batch the batched
+  // comparable in work and the tiles still running at the end of a launch
+  // are short (a single instance keeps the height chosen above).  On the 512-LP batch the batched
   // G x_hat took 0.284 ms with 64 Ki, 0.251 with 32 Ki, 0.275 with 16 Ki.
   for (int b = 0; b < NB; ++b) {
     const int64_t gb = g0s[b], wb = g0s[b + 1] - g0s[b];
