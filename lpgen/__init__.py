@@ -31,6 +31,11 @@ __all__ = [
     "zipf_row_lengths",
     "rng_for",
     "dense_runs_instance",
+    "infeasible_sum_row",
+    "infeasible_free_columns",
+    "infeasible_geq_pair",
+    "unbounded_positive_columns",
+    "unbounded_free_pair",
 ]
 
 
@@ -256,3 +261,90 @@ def dense_runs_instance(seed: int = 0, m: int = 256, run: int = 64, coupling: in
     c = rng.uniform(0.0, 1.0, size=n)
     return LPInstance(m, n, m, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, 10.0),
                       name=f"dense_runs_{seed}", x_planted=x0)
+
+
+# ---------------------------------------------------------------------------
+# Infeasible and unbounded variants of the C0 recipe (tests of exit codes 2-5).
+# Each takes a planted feasible LP and adds or changes data so that no
+# feasible point (or no finite optimum) remains; HiGHS confirms the status in
+# the tests.
+# ---------------------------------------------------------------------------
+def _with_rows(inst: LPInstance, rows: np.ndarray, rhs: np.ndarray, equality: bool, name: str) -> LPInstance:
+    """Append dense rows (as zero-cone rows placed after the existing zero rows,
+    or as ">=" rows at the end)."""
+    import scipy.sparse as sp
+
+    G = inst.scipy_csr()
+    R = sp.csr_matrix(np.atleast_2d(rows))
+    if equality:
+        mz = inst.m_zero
+        G2 = sp.vstack([G[:mz], R, G[mz:]]).tocsr()
+        h2 = np.concatenate([inst.h[:mz], rhs, inst.h[mz:]])
+        mz2 = mz + R.shape[0]
+    else:
+        G2 = sp.vstack([G, R]).tocsr()
+        h2 = np.concatenate([inst.h, rhs])
+        mz2 = inst.m_zero
+    G2.sort_indices()
+    return LPInstance(G2.shape[0], inst.n, mz2, G2.indptr.astype(np.int64), G2.indices.astype(np.int32),
+                      G2.data.astype(np.float64), h2, inst.c.copy(), inst.l.copy(), inst.u.copy(), name=name)
+
+
+def infeasible_sum_row(seed: int = 0, m: int = 200, n: int = 500) -> LPInstance:
+    """C0 plus the equality row sum_j x_j = 100 n: beyond reach of 0 <= x <= 10."""
+    base = c0_instance(seed, m, n)
+    return _with_rows(base, np.ones((1, n)), np.array([100.0 * n]), True, f"infeas_sum_m{m}_n{n}_s{seed}")
+
+
+def infeasible_free_columns(seed: int = 0, m: int = 200, n: int = 500, free: int = 50, lower_only: int = 50) -> LPInstance:
+    """C0 with the first ``free`` columns free and the next ``lower_only``
+    without an upper bound, plus the equality row sum_{j >= free+lower_only} x_j
+    = 100 n over the boxed columns only: infeasible, and its Farkas certificate
+    must also respect the infinite bounds (Lambda_j = {0} or R+ there)."""
+    base = c0_instance(seed, m, n)
+    row = np.zeros(n)
+    row[free + lower_only:] = 1.0
+    inst = _with_rows(base, row[None, :], np.array([100.0 * n]), True, f"infeas_free_m{m}_n{n}_s{seed}")
+    inst.l[:free] = -np.inf
+    inst.u[:free] = np.inf
+    inst.u[free:free + lower_only] = np.inf
+    return inst
+
+
+def infeasible_geq_pair(seed: int = 0, m: int = 200, n: int = 500) -> LPInstance:
+    """C0 plus two ">=" rows a^T x >= 1 and -a^T x >= 1 (a ~ N(0,1)): contradictory."""
+    base = c0_instance(seed, m, n)
+    a = rng_for(92, seed).standard_normal(n)
+    return _with_rows(base, np.vstack([a, -a]), np.array([1.0, 1.0]), False, f"infeas_geq_m{m}_n{n}_s{seed}")
+
+
+def unbounded_positive_columns(seed: int = 0, m: int = 200, n: int = 500, k: int = 5) -> LPInstance:
+    """All rows ">=" (planted as C0); the first k columns get |values|, cost -1
+    and no upper bound: raising them keeps Gx >= h and lowers the cost forever."""
+    inst = planted_lp(rng_for(93, seed), m, n, per_col=5, m_zero=0, name=f"unbdd_pos_m{m}_n{n}_s{seed}")
+    cols = inst.col_idx < k
+    inst.val = np.where(cols, np.abs(inst.val), inst.val)
+    inst.c[:k] = -1.0
+    inst.u[:k] = np.inf
+    return inst
+
+
+def unbounded_free_pair(seed: int = 0, m: int = 200, n: int = 500, free: int = 20) -> LPInstance:
+    """C0 with the first ``free`` columns free, column 1 a copy of column 0,
+    c_0 = -1 and c_1 = 0: the direction e_0 - e_1 keeps Gx = h and lowers the
+    cost without bound."""
+    import scipy.sparse as sp
+
+    base = c0_instance(seed, m, n)
+    G = base.scipy_csr().tolil()
+    G[:, 1] = G[:, 0]
+    G = G.tocsr()
+    G.sort_indices()
+    c = base.c.copy()
+    c[0], c[1] = -1.0, 0.0
+    l = base.l.copy()
+    u = base.u.copy()
+    l[:free] = -np.inf
+    u[:free] = np.inf
+    return LPInstance(m, n, base.m_zero, G.indptr.astype(np.int64), G.indices.astype(np.int32),
+                      G.data.astype(np.float64), base.h.copy(), c, l, u, name=f"unbdd_free_m{m}_n{n}_s{seed}")

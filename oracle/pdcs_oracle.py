@@ -22,7 +22,9 @@ PDCS", arXiv 2603.15504):
   three restart conditions with the KKT_omega fallback (Section 2.3), the
   bisection for the normalized duality gap (Algorithm 3, eq. compute_rho,
   compute_zt, compute_zt_2, Section 2.4), the primal weight (Section 2.5) and
-  the termination errors of Section 3 (eq. PDCS_terminate_tolerance_abs/rel).
+  the termination errors of Section 3 (eq. PDCS_terminate_tolerance_abs/rel)
+  and the infeasibility tests of the option list of Section 3 (exit codes 2-5
+  of the exit-code table), read as tests on rays (see ``infeasibility_ratios``).
 
 Everything is float64; products with G use scipy.sparse CSR.  Steps follow the
 paper's order and notation; nothing is fused or reordered.  Where the paper is
@@ -52,6 +54,10 @@ TINY = 1e-10
 
 EXIT_OPTIMAL = 0
 EXIT_MAX_ITER = 1
+EXIT_PRIMAL_INFEASIBLE_LOW_ACC = 2
+EXIT_PRIMAL_INFEASIBLE_HIGH_ACC = 3
+EXIT_DUAL_INFEASIBLE_LOW_ACC = 4
+EXIT_DUAL_INFEASIBLE_HIGH_ACC = 5
 EXIT_TIME_LIMIT = 6
 EXIT_CONTINUE = 7
 EXIT_NUMERICAL_ERROR = 8
@@ -279,6 +285,123 @@ def is_optimal(err: dict, rel_tol: float, abs_tol: float) -> bool:
 
 
 # --------------------------------------------------------------------------
+# Infeasibility tests (Section 3, options eps_{primal,dual}_infeasible_{low,high}_acc;
+# exit codes 2-5 of the exit-code table)
+# --------------------------------------------------------------------------
+def proj_box_recession(d, l, u):
+    """Projection onto the recession cone of [l, u]: 0 where both bounds are finite,
+    R+ where only l is finite, R- where only u is finite, R where neither is."""
+    lf = np.isfinite(l)
+    uf = np.isfinite(u)
+    out = np.array(d, dtype=np.float64, copy=True)
+    out[lf & uf] = 0.0
+    only_l = lf & ~uf
+    only_u = ~lf & uf
+    out[only_l] = np.maximum(out[only_l], 0.0)
+    out[only_u] = np.minimum(out[only_u], 0.0)
+    return out
+
+
+def rounding_bound(count: int) -> float:
+    """gamma_N = N u / (1 - N u) with u = 2^-53: a bound on the relative error of a
+    sum of N floating-point terms (Higham, Accuracy and Stability of Numerical
+    Algorithms, eq. 3.4)."""
+    nu = max(int(count), 1) * 2.0 ** -53
+    return nu / (1.0 - nu)
+
+
+def infeasibility_ratios(lp: LPData, ray_x, ray_y):
+    """The two ratios of the infeasibility options, evaluated on a ray.
+
+    Reading.  Applied literally to an iterate, the primal ratio
+    err_abs,d(lam) / (<y, h> + l^T lam+ - u^T lam-) is 0 for every LP whose
+    variables are all boxed (Lambda = R there, eq. defn_Lambda1), feasible or
+    not.  The tests are therefore read as certificate tests on rays, i.e. on the
+    homogeneous problem (c and h replaced by 0 in the residuals):
+
+    * primal infeasibility: ray_y in K_d, lam = -G^T ray_y;
+      ratio_p = err_abs,d(lam) / f with f = h^T ray_y + l^T lam+ - u^T lam-
+      (finite bounds only).  A ray with f > 0 and err_abs,d(lam) = 0 is a Farkas
+      certificate: every x with Gx - h in K_d*, l <= x <= u would give
+      f <= 0.
+    * dual infeasibility: ray_x in the recession cone of the box; the residual
+      err_rel,p of the homogeneous problem is the Euclidean norm of
+      G ray_x - Proj_{K_d*}(G ray_x) (its denominator 1 + ||h||_1 is 1 there);
+      ratio_d = err_rel,p / (-c^T ray_x).  A ray with -c^T ray_x > 0 and zero
+      residual proves the primal unbounded.
+    * a denominator that is not positive, or not larger than the rounding
+      bound gamma_N of its own sum (N terms, ``rounding_bound``) times the sum
+      of its terms' magnitudes, makes the ratio +inf: the test cannot pass on
+      a denominator that is rounding noise.
+
+    Returns (ratio_p, ratio_d).
+    """
+    lam = -(lp.G.T @ ray_y)
+    num_p = float(np.linalg.norm(lam - proj_Lambda(lam, lp.l, lp.u)))
+    lf = np.isfinite(lp.l)
+    uf = np.isfinite(lp.u)
+    terms = [lp.h * ray_y, lp.l[lf] * np.maximum(lam[lf], 0.0), -lp.u[uf] * np.maximum(-lam[uf], 0.0)]
+    f = float(sum(np.sum(t) for t in terms))
+    mag = float(sum(np.sum(np.abs(t)) for t in terms))
+    nterm = sum(t.size for t in terms)
+    ratio_p = num_p / f if f > rounding_bound(nterm) * mag else math.inf
+    r = lp.G @ ray_x
+    num_d = float(np.linalg.norm(r - proj_Kd_star(r, lp.m_zero)))
+    cx = lp.c * ray_x
+    g = -float(np.sum(cx))
+    ratio_d = num_d / g if g > rounding_bound(cx.size) * float(np.sum(np.abs(cx))) else math.inf
+    return ratio_p, ratio_d
+
+
+TREND_CHECKS = 3
+
+
+class InfeasibilityMonitor:
+    """Low- and high-accuracy infeasibility tests of the option list (Section 3).
+
+    Reading of the trend clause: the low-accuracy primal test passes at a check
+    when ratio_p < eps_primal_infeasible_low_acc and the dual objective of the
+    PDHG output z_hat is strictly larger than at the previous check; it fires
+    once it has passed at TREND_CHECKS consecutive checks.  The dual test is
+    the same with ratio_d and the negated primal objective -c^T x_hat (the
+    primal objective decreases without bound on an unbounded LP).  The
+    high-accuracy tests fire on the ratio alone.  A tolerance of 0 switches its
+    test off.  Priority at one check: high-accuracy primal, high-accuracy dual,
+    low-accuracy primal, low-accuracy dual.
+    """
+
+    def __init__(self, opts):
+        self.eps = (opts.eps_primal_infeasible_low_acc, opts.eps_dual_infeasible_low_acc,
+                    opts.eps_primal_infeasible_high_acc, opts.eps_dual_infeasible_high_acc)
+        self.trend_p = 0
+        self.trend_d = 0
+        self.prev_dobj = None
+        self.prev_negp = None
+
+    @property
+    def enabled(self) -> bool:
+        return any(e > 0.0 for e in self.eps)
+
+    def update(self, ratio_p, ratio_d, pobj, dobj):
+        """Feed one check; returns an exit code (2-5) or None."""
+        lo_p, lo_d, hi_p, hi_d = self.eps
+        up_p = self.prev_dobj is not None and dobj > self.prev_dobj
+        up_d = self.prev_negp is not None and -pobj > self.prev_negp
+        self.prev_dobj, self.prev_negp = dobj, -pobj
+        self.trend_p = self.trend_p + 1 if (ratio_p < lo_p and up_p) else 0
+        self.trend_d = self.trend_d + 1 if (ratio_d < lo_d and up_d) else 0
+        if ratio_p < hi_p:
+            return EXIT_PRIMAL_INFEASIBLE_HIGH_ACC
+        if ratio_d < hi_d:
+            return EXIT_DUAL_INFEASIBLE_HIGH_ACC
+        if self.trend_p >= TREND_CHECKS:
+            return EXIT_PRIMAL_INFEASIBLE_LOW_ACC
+        if self.trend_d >= TREND_CHECKS:
+            return EXIT_DUAL_INFEASIBLE_LOW_ACC
+        return None
+
+
+# --------------------------------------------------------------------------
 # Adaptive step size (Section 2.1, Function 2)
 # --------------------------------------------------------------------------
 def eta_bar(lp: LPData, dx, dy, omega):
@@ -466,9 +589,28 @@ class Options:
     l2_pass: bool = True
     method: str = "auto"             # auto | average | halpern (candidate rule)
     use_kkt_restart: bool = False    # compare candidates and restart on KKT_omega (Section 2.3)
+    use_duality_gap_restart: bool = True  # the normalized duality gap as restart metric (Section 3)
     check_every: int = 64            # restart / termination check period, in trials
+    kkt_restart_freq: int = 0        # check period when KKT_omega is the metric (0: check_every)
+    duality_gap_restart_freq: int = 0  # check period when the gap is the metric (0: check_every)
     bisect_rel_eps: float = 1e-6
     max_doublings: int = 64
+    eps_primal_infeasible_low_acc: float = 1e-12
+    eps_dual_infeasible_low_acc: float = 1e-12
+    eps_primal_infeasible_high_acc: float = 1e-16
+    eps_dual_infeasible_high_acc: float = 1e-16
+
+    def gap_metric(self) -> bool:
+        """Reading of the restart options: the normalized duality gap is the metric
+        unless use_kkt_restart is set or use_duality_gap_restart is cleared, in
+        which case KKT_omega is (and the gap is not computed)."""
+        return bool(self.use_duality_gap_restart) and not self.use_kkt_restart
+
+    def period(self) -> int:
+        """Trials between restart checks: the frequency option of the metric in
+        use, or check_every when that option is 0."""
+        f = self.duality_gap_restart_freq if self.gap_metric() else self.kkt_restart_freq
+        return int(f) if f > 0 else int(self.check_every)
 
 
 @dataclass
@@ -506,7 +648,16 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
     * tau, sigma inside N are eta_hat/omega and eta_hat*omega at the check;
     * the anchor's metric is the candidate's value at the check that restarted;
     * termination is evaluated on the unscaled candidate at each check (and on
-      the start point); the returned point is that candidate.
+      the start point); the returned point is that candidate;
+    * the infeasibility tests (``InfeasibilityMonitor``) run at each check that
+      does not terminate, on the rays Proj(D2 (x_hat - x_start)) and
+      Proj(D1 (y_hat - y_start)) (projections onto the recession cone of the box
+      and onto K_d; z_start is the projected start point z^{0,0}).  On an
+      infeasible or unbounded LP the iterates drift along a certificate, and
+      the displacement since the start grows with the trial count while its
+      error stays bounded, so the ratios fall like 1/kbar; the displacement
+      since the anchor of the current interval would not.  Such an exit
+      returns z_hat.
     """
     opts = opts or Options()
     t_start = time.perf_counter()
@@ -525,6 +676,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
     ys = np.zeros(m) if y0 is None else np.asarray(y0, np.float64) / D1
     x = proj_box(xs, sl.l, sl.u)
     y = proj_Kd(ys, sl.m_zero)
+    x_start, y_start = x.copy(), y.copy()
 
     gmax = float(np.max(np.abs(sl.G.data), initial=0.0))
     eta_hat = 1.0 / gmax if gmax > 0 else 1.0
@@ -543,6 +695,9 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
     metric_prev = None
     trial_log = [] if trace else None
     checks_log = []
+    use_gap = opts.gap_metric()
+    period = opts.period()
+    monitor = InfeasibilityMonitor(opts)
 
     def finish(code, xs_, ys_):
         xu, yu = unscale(xs_, ys_)
@@ -588,7 +743,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
         SH += eta_k
         k += 1
 
-        if kbar % opts.check_every == 0:
+        if kbar % period == 0:
             checks += 1
             tau_c = eta_hat / omega
             sig_c = eta_hat * omega
@@ -600,15 +755,15 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
             info = {}
             for name, (cx, cy) in cands.items():
                 r = n_norm(cx - xa, cy - ya, tau_c, sig_c)
-                rho = normalized_gap(sl, cx, cy, tau_c, sig_c, r, opts.bisect_rel_eps,
-                                     opts.max_doublings)
+                rho = (normalized_gap(sl, cx, cy, tau_c, sig_c, r, opts.bisect_rel_eps,
+                                      opts.max_doublings) if use_gap else math.nan)
                 ep, ed, eg, _, _ = abs_errors_l2(sl, cx, cy)
                 info[name] = dict(rho=rho, kkt=kkt_omega(ep, ed, eg, omega), err=(ep, ed, eg), r=r)
             # Numerical issue (Section 2.3): any gap value of this check, of the
             # anchor or of the previous candidate that is negative, NaN or has
             # r = 0 switches every comparison of this check to KKT_omega.
             stored = [d["rho"] for d in (metric_anchor, metric_prev) if d is not None]
-            use_kkt = opts.use_kkt_restart or not all(
+            use_kkt = not use_gap or not all(
                 _valid_rho(v) for v in [i["rho"] for i in info.values()] + stored)
             key = "kkt" if use_kkt else "rho"
             if "cur" in info and "avg" in info:
@@ -632,6 +787,17 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
                 x, y = cx.copy(), cy.copy()
                 xh, yh = cx.copy(), cy.copy()
                 return finish(EXIT_OPTIMAL, cx, cy)
+            if monitor.enabled:
+                ray_x = proj_box_recession(D2 * (xh - x_start), lp.l, lp.u)
+                ray_y = proj_Kd(D1 * (yh - y_start), lp.m_zero)
+                ratio_p, ratio_d = infeasibility_ratios(lp, ray_x, ray_y)
+                e_h = termination_errors(lp, D2 * xh, D1 * yh)
+                code = monitor.update(ratio_p, ratio_d, e_h["pobj"], e_h["dobj"])
+                checks_log[-1].update(ratio_p=ratio_p, ratio_d=ratio_d)
+                if code is not None:
+                    res = finish(code, xh, yh)
+                    res.state.update(ray_x=ray_x, ray_y=ray_y)
+                    return res
             if restart:
                 # PrimalWeightUpdate(z^{t+1,0}, z^{t,0}, omega^t) and the new anchor.
                 dxn = float(np.linalg.norm(cx - xa))

@@ -514,3 +514,15 @@ def test_max_iter_and_time_limit_exit_codes():
     assert r.exit_code == O.EXIT_MAX_ITER and r.iters == 10
     r = O.solve(lp, O.Options(time_limit=0.0))
     assert r.exit_code == O.EXIT_TIME_LIMIT
+
+
+def test_scaling_hand_example_non_diagonal():
+    # one Ruiz pass and the square-root-of-Euclidean-norm pass on a 2 x 3 matrix,
+    # evaluated by hand in closed form (tests/golden/hand_lps.yaml): a different
+    # L2 formula (the norm itself, the L1 norm) or a pass taken from a stale
+    # matrix gives other numbers
+    g = _load_golden()["scaling_example"]
+    G = sp.csr_matrix(np.array(g["G"], dtype=np.float64))
+    D1, D2 = O.ruiz_l2_scaling(G, int(g["ruiz_iters"]), True)
+    np.testing.assert_allclose(D1, g["D1"], rtol=1e-14)
+    np.testing.assert_allclose(D2, g["D2"], rtol=1e-14)
