@@ -97,8 +97,8 @@ typedef struct {
   double  polish_switch_tol;  /* mixed: switch to FP64 once rel. KKT <= this (0: off)  */
   double  bisect_rel_eps;     /* 1e-6: relative bracket width of the gap bisection     */
   int64_t use_graph;          /* 1: replay each chunk of iterations as a hipGraph      */
-  int64_t verbose;            /* 0: silent; 1: a line about every 2 s for instance 0;
-                                 2: a line per chunk of check_every trials             */
+  int64_t verbose;            /* 0: silent; 1: a line per print_freq trials for
+                                 instance 0 (on stderr); 2: a line per check           */
   int64_t keep_state;         /* 1: keep the internal iterates for pdcs_result_state   */
   int64_t time_kernels;       /* 1: launch without graphs and time every launch of the
                                  SpMV-with-dual-step kernel with HIP events           */
@@ -110,7 +110,35 @@ typedef struct {
   int64_t use_kkt_restart;    /* 0; 1: candidates are compared and the restart rules
                                  evaluated on KKT_omega instead of the normalized
                                  duality gap (Section 2.3, option use_kkt_restart)    */
-  int64_t reserved[1];
+  int64_t use_duality_gap_restart; /* 1: the normalized duality gap is the restart
+                                 metric (with the KKT_omega fallback of Section 2.3);
+                                 0: KKT_omega is, and the gap is not computed.
+                                 use_kkt_restart = 1 also selects KKT_omega          */
+  int64_t kkt_restart_freq;   /* trials between checks while KKT_omega is the metric;
+                                 0 (default): check_every                             */
+  int64_t duality_gap_restart_freq; /* trials between checks while the gap is the
+                                 metric; 0 (default): check_every                     */
+  int64_t print_freq;         /* verbose = 1: one progress line per this many trials
+                                 (2000, as in the option list of Section 3)           */
+  /* Infeasibility tolerances of the option list of Section 3 (exit codes 2-5).
+   * Each test runs at every check that does not terminate, on the rays
+   * r_x = Proj(D2 (x_hat - x_start)) and r_y = Proj(D1 (y_hat - y_start)): the
+   * displacement of the PDHG output from the projected start point, unscaled and
+   * projected onto the recession cone of the box and onto K_d.  With
+   * lam = -G^T r_y and f = h^T r_y + sum_{l finite} l lam+ - sum_{u finite} u lam-:
+   *   ratio_p = ||lam - Proj_Lambda(lam)||_2 / f,
+   *   ratio_d = ||G r_x - Proj_{K_d*}(G r_x)||_2 / (-c^T r_x),
+   * each +inf unless its denominator exceeds the rounding bound gamma_N = Nu/(1-Nu)
+   * of its own sum times the sum of its terms' magnitudes.  High accuracy: exit
+   * 3 (5) when ratio_p (ratio_d) < the tolerance.  Low accuracy: exit 2 (4)
+   * once ratio_p (ratio_d) was below the tolerance at 3 consecutive checks at
+   * which the dual objective (the negated primal objective) of the PDHG output
+   * rose strictly.  0 switches a test off.                                          */
+  double  eps_primal_infeasible_low_acc;   /* 1e-12 */
+  double  eps_dual_infeasible_low_acc;     /* 1e-12 */
+  double  eps_primal_infeasible_high_acc;  /* 1e-16 */
+  double  eps_dual_infeasible_high_acc;    /* 1e-16 */
+  int64_t reserved[4];
 } pdcs_options;
 
 /* Per-solve information (result fields of Section 3 plus counters). */
@@ -141,6 +169,9 @@ typedef struct {
                                  at the last check (Section 2.3)                      */
   double  r_cur, r_avg;       /* their radii ||z_c - z_anchor||_N                      */
   int64_t chosen;             /* candidate taken at the last check: 0 current, 1 average */
+  double  ratio_p, ratio_d;   /* infeasibility ratios of the last check (see
+                                 pdcs_options; NaN when the tests did not run)        */
+  int64_t trend_p, trend_d;   /* consecutive checks passing the low-accuracy tests   */
 } pdcs_state_scalars;
 
 void        pdcs_options_default(pdcs_options* opts);
@@ -209,6 +240,23 @@ int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
 #define PDCS_LAYOUT_BANDS 2
 int  pdcs_problem_set_layout(pdcs_problem p, int64_t layout);
 
+/* pdcs_problem_set_band_schedule: shape of the band tiles of the band layout.
+ *   rows      : tallest band height, a power of two in [256, 8192] (default 8192);
+ *   min_tiles : the height is halved (not below 256) while fewer band-tiles
+ *               (bands x gathered-index windows) would result, so that the
+ *               256 CUs get work (default 384; 1 keeps `rows`);
+ *   entry_cap : in a batch, bands are cut to at most about this many entries
+ *               per window and instance, in [1024, 2^24] (default 32768).
+ * The layout is rebuilt on the host (time proportional to nnz log nnz).
+ * Products are the same up to rounding order.  Errors: PDCS_ERR_INVALID_ARG.
+ * pdcs_problem_band_schedule reads the settings back; *built_rows receives the
+ * band height the current layout of G uses and *windows its number of
+ * gathered-index windows (both 0 when the band layout is not in use); any
+ * pointer may be NULL. */
+int  pdcs_problem_set_band_schedule(pdcs_problem p, int64_t rows, int64_t min_tiles, int64_t entry_cap);
+int  pdcs_problem_band_schedule(pdcs_problem p, int64_t* rows, int64_t* min_tiles, int64_t* entry_cap,
+                                int64_t* built_rows, int64_t* windows);
+
 /* ---- single solve ------------------------------------------------------
  * pdcs_solve: Algorithm 4 (rescale, Algorithm 1, unscale) on one problem.
  *   x0 / y0 : optional host warm start (double[n] / double[m]); NULL = zero
@@ -218,7 +266,28 @@ int  pdcs_problem_set_layout(pdcs_problem p, int64_t layout);
 int  pdcs_solve(pdcs_problem p, const pdcs_options* opts, const double* x0, const double* y0,
                 void* stream, pdcs_result* out);
 
+/* pdcs_solve_device: pdcs_solve with the warm start in device memory, e.g. the
+ * output of the warm-start network (pdcs_mlp_forward) without a trip through
+ * the host.  x0_dev / y0_dev: NULL or device arrays of n / m values, FP64
+ * (warm_dtype = PDCS_PRECISION_FP64) or FP32 (PDCS_PRECISION_MIXED), unscaled,
+ * owned by the caller and only read.  The solver's stream waits for the work
+ * already enqueued on `stream` (NULL: the HIP null stream) before it reads
+ * them; the call is synchronous like pdcs_solve.  A NaN in the warm start
+ * ends the solve with exit code 8 (numerical error).
+ * Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_OOM, PDCS_ERR_HIP. */
+int  pdcs_solve_device(pdcs_problem p, const pdcs_options* opts, const void* x0_dev, const void* y0_dev,
+                       int64_t warm_dtype, void* stream, pdcs_result* out);
+
 int  pdcs_result_info(pdcs_result r, pdcs_info* out);
+/* Device-pointer results (the fields of Section 3 without a host copy): copy
+ * instance r's primal x (n), dual y (m) or dual slack c - G^T y (n), FP64, into
+ * the caller's device buffer of exactly that length, enqueued on `stream`
+ * (NULL: the HIP null stream) and not synchronized.  The result handle must
+ * stay alive until the copy has run.  Errors: PDCS_ERR_INVALID_ARG (null
+ * pointers, length mismatch), PDCS_ERR_HIP. */
+int  pdcs_result_primal_device(pdcs_result r, double* x_dev, int64_t n, void* stream);
+int  pdcs_result_dual_device(pdcs_result r, double* y_dev, int64_t m, void* stream);
+int  pdcs_result_slack_device(pdcs_result r, double* lam_dev, int64_t n, void* stream);
 /* Copy results of instance 0 (single solves) to host buffers of exactly the
  * given length (mismatch: PDCS_ERR_INVALID_ARG). x: primal, y: dual,
  * lam: dual slack c - G^T y (the "slack" field of Section 3). */
@@ -254,6 +323,14 @@ int  pdcs_batch_create(int64_t count, const pdcs_problem* probs, pdcs_batch* out
  * x0s / y0s: NULL or arrays of `count` host pointers (each may be NULL). */
 int  pdcs_batch_solve(pdcs_batch b, const pdcs_options* opts, const double* const* x0s,
                       const double* const* y0s, void* stream, pdcs_result* results);
+/* As pdcs_batch_solve with device warm starts: x0s_dev / y0s_dev are NULL or
+ * host arrays of `count` DEVICE pointers (each may be NULL), instance i's
+ * pointing to n_i / m_i values of warm_dtype (PDCS_PRECISION_FP64: double,
+ * PDCS_PRECISION_MIXED: float), e.g. rows of one [count x (n + m)] network
+ * output.  Ordering and errors as pdcs_solve_device. */
+int  pdcs_batch_solve_device(pdcs_batch b, const pdcs_options* opts, const void* const* x0s_dev,
+                             const void* const* y0s_dev, int64_t warm_dtype, void* stream,
+                             pdcs_result* results);
 /* Autotune the row-tile schedule of this batch: times SpMV schedules with HIP
  * events and keeps the fastest (see pdcs_batch_schedule).  time_budget_ms <= 0
  * uses a default. */
@@ -268,6 +345,10 @@ int  pdcs_batch_set_schedule(pdcs_batch b, int64_t iter_max, int64_t block_nnz,
  * batch (each instance gets its own bands and gathered-index windows).
  * Errors: PDCS_ERR_INVALID_ARG. */
 int  pdcs_batch_set_layout(pdcs_batch b, int64_t layout);
+/* As pdcs_problem_set_band_schedule / pdcs_problem_band_schedule for a batch. */
+int  pdcs_batch_set_band_schedule(pdcs_batch b, int64_t rows, int64_t min_tiles, int64_t entry_cap);
+int  pdcs_batch_band_schedule(pdcs_batch b, int64_t* rows, int64_t* min_tiles, int64_t* entry_cap,
+                              int64_t* built_rows, int64_t* windows);
 void pdcs_batch_destroy(pdcs_batch b);
 
 /* ---- warm-start MLP ----------------------------------------------------

@@ -18,6 +18,8 @@ PDCS_OK = 0
 ERRORS = {-1: "invalid argument", -2: "unsupported", -3: "out of memory", -4: "HIP error",
           -5: "size", -6: "state"}
 EXIT_OPTIMAL, EXIT_MAX_ITER, EXIT_TIME_LIMIT, EXIT_CONTINUE, EXIT_NUMERICAL_ERROR = 0, 1, 6, 7, 8
+EXIT_PRIMAL_INFEASIBLE_LOW_ACC, EXIT_PRIMAL_INFEASIBLE_HIGH_ACC = 2, 3
+EXIT_DUAL_INFEASIBLE_LOW_ACC, EXIT_DUAL_INFEASIBLE_HIGH_ACC = 4, 5
 METHOD = {"auto": 0, "average": 1, "halpern": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 
@@ -37,7 +39,11 @@ class pdcs_options(C.Structure):
                 ("use_graph", C.c_int64), ("verbose", C.c_int64), ("keep_state", C.c_int64),
                 ("time_kernels", C.c_int64), ("probe_passes", C.c_int64),
                 ("trace_trials", C.c_int64), ("compact", C.c_int64), ("use_kkt_restart", C.c_int64),
-                ("reserved", C.c_int64 * 1)]
+                ("use_duality_gap_restart", C.c_int64), ("kkt_restart_freq", C.c_int64),
+                ("duality_gap_restart_freq", C.c_int64), ("print_freq", C.c_int64),
+                ("eps_primal_infeasible_low_acc", C.c_double), ("eps_dual_infeasible_low_acc", C.c_double),
+                ("eps_primal_infeasible_high_acc", C.c_double), ("eps_dual_infeasible_high_acc", C.c_double),
+                ("reserved", C.c_int64 * 4)]
 
 
 class pdcs_info(C.Structure):
@@ -55,7 +61,9 @@ class pdcs_state_scalars(C.Structure):
                 ("eta", C.c_double), ("beta", C.c_double), ("sum_eta", C.c_double),
                 ("kbar", C.c_int64), ("k", C.c_int64), ("t", C.c_int64), ("accepted", C.c_int64),
                 ("precision", C.c_int64), ("rho_cur", C.c_double), ("rho_avg", C.c_double),
-                ("r_cur", C.c_double), ("r_avg", C.c_double), ("chosen", C.c_int64)]
+                ("r_cur", C.c_double), ("r_avg", C.c_double), ("chosen", C.c_int64),
+                ("ratio_p", C.c_double), ("ratio_d", C.c_double), ("trend_p", C.c_int64),
+                ("trend_d", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -74,11 +82,21 @@ PROTOTYPES = {
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
     "pdcs_problem_set_panels": (C.c_int, [_P, _I64, _I64]),
     "pdcs_problem_set_layout": (C.c_int, [_P, _I64]),
+    "pdcs_problem_set_band_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
+    "pdcs_problem_band_schedule": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64),
+                                             C.POINTER(_I64), C.POINTER(_I64)]),
+    "pdcs_batch_set_band_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
+    "pdcs_batch_band_schedule": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64),
+                                           C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, C.POINTER(_P)]),
+    "pdcs_solve_device": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _I64, _P, C.POINTER(_P)]),
     "pdcs_result_info": (C.c_int, [_P, C.POINTER(pdcs_info)]),
     "pdcs_result_primal": (C.c_int, [_P, _P, _I64]),
     "pdcs_result_dual": (C.c_int, [_P, _P, _I64]),
     "pdcs_result_slack": (C.c_int, [_P, _P, _I64]),
+    "pdcs_result_primal_device": (C.c_int, [_P, _P, _I64, _P]),
+    "pdcs_result_dual_device": (C.c_int, [_P, _P, _I64, _P]),
+    "pdcs_result_slack_device": (C.c_int, [_P, _P, _I64, _P]),
     "pdcs_result_scaling": (C.c_int, [_P, _P, _I64, _P, _I64]),
     "pdcs_result_state": (C.c_int, [_P, C.POINTER(pdcs_state_scalars), _P, _P, _P, _P, _P, _P]),
     "pdcs_result_products": (C.c_int, [_P, _P, _P]),
@@ -86,6 +104,7 @@ PROTOTYPES = {
     "pdcs_result_destroy": (None, [_P]),
     "pdcs_batch_create": (C.c_int, [_I64, _P, C.POINTER(_P)]),
     "pdcs_batch_solve": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _P, _P]),
+    "pdcs_batch_solve_device": (C.c_int, [_P, C.POINTER(pdcs_options), _P, _P, _I64, _P, _P]),
     "pdcs_batch_autotune": (C.c_int, [_P, C.c_double]),
     "pdcs_batch_schedule": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_batch_set_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
@@ -221,6 +240,31 @@ def pdcs_problem_set_layout(p, layout: int):
     _check(lib.pdcs_problem_set_layout(p, int(layout)), "pdcs_problem_set_layout")
 
 
+def pdcs_problem_set_band_schedule(p, rows: int, min_tiles: int, entry_cap: int):
+    _check(lib.pdcs_problem_set_band_schedule(p, int(rows), int(min_tiles), int(entry_cap)),
+           "pdcs_problem_set_band_schedule")
+
+
+def _band_schedule(fn, h, name):
+    v = [C.c_int64() for _ in range(5)]
+    _check(fn(h, *[C.byref(x) for x in v]), name)
+    return dict(rows=v[0].value, min_tiles=v[1].value, entry_cap=v[2].value, built_rows=v[3].value,
+                windows=v[4].value)
+
+
+def pdcs_problem_band_schedule(p) -> dict:
+    return _band_schedule(lib.pdcs_problem_band_schedule, p, "pdcs_problem_band_schedule")
+
+
+def pdcs_batch_set_band_schedule(b, rows: int, min_tiles: int, entry_cap: int):
+    _check(lib.pdcs_batch_set_band_schedule(b, int(rows), int(min_tiles), int(entry_cap)),
+           "pdcs_batch_set_band_schedule")
+
+
+def pdcs_batch_band_schedule(b) -> dict:
+    return _band_schedule(lib.pdcs_batch_band_schedule, b, "pdcs_batch_band_schedule")
+
+
 def pdcs_solve(p, opts: pdcs_options | None = None, x0=None, y0=None, stream: int = 0) -> C.c_void_p:
     m, n, _ = pdcs_problem_dims(p)
     x0 = _f64(x0, n)
@@ -228,6 +272,17 @@ def pdcs_solve(p, opts: pdcs_options | None = None, x0=None, y0=None, stream: in
     out = C.c_void_p()
     _check(lib.pdcs_solve(p, C.byref(opts) if opts is not None else None, _ptr(x0), _ptr(y0),
                           C.c_void_p(stream) if stream else None, C.byref(out)), "pdcs_solve")
+    return out
+
+
+def pdcs_solve_device(p, opts: pdcs_options | None, x0_dev: int, y0_dev: int, warm_dtype: int,
+                      stream: int = 0) -> C.c_void_p:
+    """Warm start from device pointers (0 = none); warm_dtype 0 = FP64, 1 = FP32."""
+    out = C.c_void_p()
+    _check(lib.pdcs_solve_device(p, C.byref(opts) if opts is not None else None,
+                                 C.c_void_p(x0_dev) if x0_dev else None, C.c_void_p(y0_dev) if y0_dev else None,
+                                 int(warm_dtype), C.c_void_p(stream) if stream else None, C.byref(out)),
+           "pdcs_solve_device")
     return out
 
 
@@ -253,6 +308,21 @@ def pdcs_result_dual(r, m):
 
 def pdcs_result_slack(r, n):
     return _get_vec(lib.pdcs_result_slack, r, n, "pdcs_result_slack")
+
+
+def pdcs_result_primal_device(r, x_dev: int, n: int, stream: int = 0):
+    _check(lib.pdcs_result_primal_device(r, C.c_void_p(x_dev), int(n), C.c_void_p(stream) if stream else None),
+           "pdcs_result_primal_device")
+
+
+def pdcs_result_dual_device(r, y_dev: int, m: int, stream: int = 0):
+    _check(lib.pdcs_result_dual_device(r, C.c_void_p(y_dev) if y_dev else None, int(m),
+                                       C.c_void_p(stream) if stream else None), "pdcs_result_dual_device")
+
+
+def pdcs_result_slack_device(r, lam_dev: int, n: int, stream: int = 0):
+    _check(lib.pdcs_result_slack_device(r, C.c_void_p(lam_dev), int(n), C.c_void_p(stream) if stream else None),
+           "pdcs_result_slack_device")
 
 
 def pdcs_result_scaling(r, m, n):
@@ -296,25 +366,52 @@ def pdcs_batch_create(problems) -> C.c_void_p:
     return out
 
 
-def pdcs_batch_solve(b, count, opts=None, x0s=None, y0s=None, stream: int = 0):
+def pdcs_batch_solve(b, count, opts=None, x0s=None, y0s=None, stream: int = 0, dims=None):
+    """dims: the (m, n) of every instance; each warm-start entry must have n (x)
+    or m (y) values, since the library reads exactly that many."""
     keep = []
+    if dims is None:
+        raise ValueError("pdcs_batch_solve needs the (m, n) of every instance")
+    if len(dims) != count:
+        raise ValueError(f"expected {count} instance sizes, got {len(dims)}")
 
-    def ptr_array(vs):
+    def ptr_array(vs, side):
         if vs is None:
             return None
+        if len(vs) != count:
+            raise ValueError(f"expected {count} warm-start entries, got {len(vs)}")
         arr = (C.c_void_p * count)()
         for i, v in enumerate(vs):
             if v is not None:
-                a = _f64(v)
+                a = _f64(v, dims[i][side])
                 keep.append(a)
                 arr[i] = a.ctypes.data
         keep.append(arr)
         return C.cast(arr, C.c_void_p)
 
     res = (C.c_void_p * count)()
-    _check(lib.pdcs_batch_solve(b, C.byref(opts) if opts is not None else None, ptr_array(x0s),
-                                ptr_array(y0s), C.c_void_p(stream) if stream else None,
+    _check(lib.pdcs_batch_solve(b, C.byref(opts) if opts is not None else None, ptr_array(x0s, 1),
+                                ptr_array(y0s, 0), C.c_void_p(stream) if stream else None,
                                 C.cast(res, C.c_void_p)), "pdcs_batch_solve")
+    return [C.c_void_p(res[i]) for i in range(count)]
+
+
+def pdcs_batch_solve_device(b, count, opts, x0s_dev, y0s_dev, warm_dtype: int, stream: int = 0):
+    """x0s_dev / y0s_dev: None or `count` device addresses (0 = no warm start for that instance)."""
+    def ptr_array(vs):
+        if vs is None:
+            return None
+        if len(vs) != count:
+            raise ValueError(f"expected {count} warm-start pointers, got {len(vs)}")
+        return (C.c_void_p * count)(*[int(v) if v else None for v in vs])
+
+    xa, ya = ptr_array(x0s_dev), ptr_array(y0s_dev)
+    res = (C.c_void_p * count)()
+    _check(lib.pdcs_batch_solve_device(b, C.byref(opts) if opts is not None else None,
+                                       C.cast(xa, C.c_void_p) if xa is not None else None,
+                                       C.cast(ya, C.c_void_p) if ya is not None else None, int(warm_dtype),
+                                       C.c_void_p(stream) if stream else None, C.cast(res, C.c_void_p)),
+           "pdcs_batch_solve_device")
     return [C.c_void_p(res[i]) for i in range(count)]
 
 
@@ -374,11 +471,21 @@ class Problem:
         return cls(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx, inst.val, inst.h, inst.c,
                    inst.l, inst.u)
 
-    def solve(self, x0=None, y0=None, with_scaling=False, **opts) -> Solution:
+    def solve(self, x0=None, y0=None, with_scaling=False, device_out=False, **opts) -> Solution:
+        """Host warm start (arrays) or, for torch tensors on the GPU, the device
+        warm-start call (float64 or float32, read on torch's current stream).
+        device_out=True returns x, y, lam as float64 torch tensors filled by the
+        device-pointer result calls."""
         o = pdcs_options_default(**opts)
-        r = pdcs_solve(self.handle, o, x0, y0)
+        dev = _is_device_tensor(x0) or _is_device_tensor(y0)
+        if dev:
+            dtype = _warm_dtype(x0, y0, {"x0": (x0, self.n), "y0": (y0, self.m)})
+            r = pdcs_solve_device(self.handle, o, _dev_ptr(x0), _dev_ptr(y0), dtype, _torch_stream())
+        else:
+            r = pdcs_solve(self.handle, o, x0, y0)
         try:
-            return _collect(r, self.m, self.n, with_scaling, bool(o.keep_state), int(o.trace_trials))
+            return _collect(r, self.m, self.n, with_scaling, bool(o.keep_state), int(o.trace_trials),
+                            device_out=device_out)
         finally:
             pdcs_result_destroy(r)
 
@@ -388,6 +495,12 @@ class Problem:
     def set_layout(self, layout="auto"):
         """Matrix storage for the trial SpMVs: "auto", "rows" or "bands"."""
         pdcs_problem_set_layout(self.handle, LAYOUTS[layout] if isinstance(layout, str) else layout)
+
+    def set_band_schedule(self, rows=8192, min_tiles=384, entry_cap=32768):
+        pdcs_problem_set_band_schedule(self.handle, rows, min_tiles, entry_cap)
+
+    def band_schedule(self) -> dict:
+        return pdcs_problem_band_schedule(self.handle)
 
     def spmv(self, x_dev, out_dev, transpose=False, precision="fp64", stream=0):
         pdcs_problem_spmv(self.handle, 1 if transpose else 0, PRECISION[precision], x_dev, out_dev, stream)
@@ -404,10 +517,67 @@ class Problem:
             pass
 
 
-def _collect(r, m, n, with_scaling, with_state, trace=0) -> Solution:
+def _is_device_tensor(a) -> bool:
+    return a is not None and hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _dev_ptr(a) -> int:
+    return 0 if a is None else int(a.data_ptr())
+
+
+def _torch_stream() -> int:
+    import torch
+
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _warm_dtype(x0, y0, want) -> int:
+    """Check the device warm-start tensors (contiguous, one dtype, right length)
+    and return the dtype code of the C ABI (0: float64, 1: float32)."""
+    import torch
+
+    codes = set()
+    for name, (t, length) in want.items():
+        if t is None:
+            continue
+        if not _is_device_tensor(t) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous GPU tensor when the other one is")
+        if t.numel() != length:
+            raise ValueError(f"{name}: expected {length} entries, got {t.numel()}")
+        if t.dtype == torch.float64:
+            codes.add(0)
+        elif t.dtype == torch.float32:
+            codes.add(1)
+        else:
+            raise ValueError(f"{name} must be float64 or float32, got {t.dtype}")
+    if len(codes) != 1:
+        raise ValueError("x0 and y0 must share one dtype")
+    return codes.pop()
+
+
+def _device_vectors(r, m, n):
+    import torch
+
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    lam = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = _torch_stream()
+    pdcs_result_primal_device(r, x.data_ptr(), n, st)
+    pdcs_result_dual_device(r, y.data_ptr() if m > 0 else 0, m, st)
+    pdcs_result_slack_device(r, lam.data_ptr(), n, st)
+    # the copies are enqueued on torch's stream; the result handle is destroyed
+    # right after, so wait for them here
+    torch.cuda.current_stream().synchronize()
+    return x, y, lam
+
+
+def _collect(r, m, n, with_scaling, with_state, trace=0, device_out=False) -> Solution:
     info = _info_dict(pdcs_result_info(r))
-    sol = Solution(pdcs_result_primal(r, n), pdcs_result_dual(r, m) if m > 0 else np.zeros(0),
-                   pdcs_result_slack(r, n), info)
+    if device_out:
+        sol = Solution(*_device_vectors(r, m, n), info)
+    else:
+        sol = Solution(pdcs_result_primal(r, n), pdcs_result_dual(r, m) if m > 0 else np.zeros(0),
+                       pdcs_result_slack(r, n), info)
     if with_scaling:
         sol.D1, sol.D2 = pdcs_result_scaling(r, m, n)
     if with_state:
@@ -432,14 +602,36 @@ class Batch:
         self.problems = list(problems)
         self.handle = pdcs_batch_create([p.handle for p in self.problems])
 
-    def solve(self, x0s=None, y0s=None, with_scaling=False, **opts):
+    def solve(self, x0s=None, y0s=None, with_scaling=False, device_out=False, **opts):
+        """x0s / y0s: None or one entry per instance (None, a host array, or a
+        GPU tensor; GPU tensors select the device warm-start call, one dtype for
+        all of them)."""
         o = pdcs_options_default(**opts)
-        rs = pdcs_batch_solve(self.handle, len(self.problems), o, x0s, y0s)
+        count = len(self.problems)
+        entries = [v for vs in (x0s, y0s) if vs is not None for v in vs if v is not None]
+        if any(_is_device_tensor(v) for v in entries):
+            for vs in (x0s, y0s):
+                if vs is not None and len(vs) != count:
+                    raise ValueError(f"expected {count} warm-start entries, got {len(vs)}")
+            dtypes = set()
+            for i, p in enumerate(self.problems):
+                xi = x0s[i] if x0s is not None else None
+                yi = y0s[i] if y0s is not None else None
+                if xi is not None or yi is not None:
+                    dtypes.add(_warm_dtype(xi, yi, {f"x0s[{i}]": (xi, p.n), f"y0s[{i}]": (yi, p.m)}))
+            if len(dtypes) != 1:
+                raise ValueError("device warm starts must share one dtype")
+            rs = pdcs_batch_solve_device(self.handle, count, o,
+                                         None if x0s is None else [_dev_ptr(v) for v in x0s],
+                                         None if y0s is None else [_dev_ptr(v) for v in y0s],
+                                         dtypes.pop(), _torch_stream())
+        else:
+            rs = pdcs_batch_solve(self.handle, count, o, x0s, y0s, dims=[(p.m, p.n) for p in self.problems])
         out = []
         try:
             for i, (r, p) in enumerate(zip(rs, self.problems)):
                 out.append(_collect(r, p.m, p.n, with_scaling, bool(o.keep_state),
-                                    int(o.trace_trials) if i == 0 else 0))
+                                    int(o.trace_trials) if i == 0 else 0, device_out=device_out))
         finally:
             for r in rs:
                 pdcs_result_destroy(r)
@@ -458,6 +650,12 @@ class Batch:
     def set_layout(self, layout="auto"):
         """Matrix storage for the trial SpMVs of every instance: "auto", "rows" or "bands"."""
         pdcs_batch_set_layout(self.handle, LAYOUTS[layout] if isinstance(layout, str) else layout)
+
+    def set_band_schedule(self, rows=8192, min_tiles=384, entry_cap=32768):
+        pdcs_batch_set_band_schedule(self.handle, rows, min_tiles, entry_cap)
+
+    def band_schedule(self) -> dict:
+        return pdcs_batch_band_schedule(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

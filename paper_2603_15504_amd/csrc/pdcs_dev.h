@@ -69,9 +69,16 @@ struct Inst {
   double pobj, dobj, abs_p, abs_d, abs_gap, rel_p, rel_d, rel_gap;
   CandState cand[kMaxCand];
   double chk_rho[kMaxCand], chk_r[kMaxCand];  // values of the last restart check
+  // infeasibility tests of the option list of Section 3 (exit codes 2-5)
+  double eps_inf[4];        // tolerances: primal low, dual low, primal high, dual high
+  double ratio_p, ratio_d;  // ratios of the last check (NaN: not evaluated)
+  double prev_dobj, prev_negp;  // dual objective and -(primal objective) of z_hat at the previous check
+  int32_t infeas_on, ray_due, trend_p, trend_d;
+  int32_t has_prev_obj, stop_max_iter, pad_inf0, pad_inf1;
   double* trace;            // per-trial scalars of the first trace_cap trials (or null)
   int64_t trace_cap;
 };
+constexpr int kTrendChecks = 3;  // consecutive checks the low-accuracy infeasibility tests must pass
 constexpr int kTraceStride = 16;  // kbar, eta, eta_bar, dx2, dy2, dy^T G dx, accepted, eta', beta, k,
                                   // then for accepted trials: c^T x_hat, h^T y_hat, sum l lam+, sum u lam-, err_p^2, err_d^2
 

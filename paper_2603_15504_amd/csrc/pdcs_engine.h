@@ -106,6 +106,15 @@ struct PanelSet {
   void build_slots();
 };
 
+// Shape of the band tiles: the tallest band height (a power of two, at most
+// kBandRows), halved while fewer than min_tiles band-tiles would result; in a
+// batch, bands are further cut to at most about entry_cap entries per window.
+struct BandSchedule {
+  int rows = kBandRows;
+  int min_tiles = 384;
+  int entry_cap = 32768;
+};
+
 // Band-tile layout of a CSR-like structure (see BandTiles), per instance of a
 // batch.  src maps every packed entry to its position in
 // the CSR order (-1 for padding), so the scaled values can be filled in.
@@ -117,8 +126,10 @@ struct BandSet {
   DBuf val32, val64, part32, part64, part64b;
   DBuf orig32, orig64;  // unscaled values (plain products), filled on first use
   // instance b: rows [r0s[b], r0s[b+1]) gathering from [g0s[b], g0s[b+1])
+  int band_rows = 0;  // band height chosen by build
+  void reset();       // back to the unbuilt state, device memory released
   void build(const std::vector<int64_t>& r0s, const std::vector<int64_t>& g0s, const std::vector<int32_t>& ptr,
-             const std::vector<int32_t>& idx);
+             const std::vector<int32_t>& idx, const BandSchedule& bs);
   BandTiles view() const;
 };
 
@@ -137,6 +148,18 @@ struct OutBlock {
   DBuf st[2][8];  // [fp64, fp32] x [x, y, x_hat, y_hat, x_a, y_a, G^T y_hat, G x_hat]
 };
 
+// Where a solve's warm start comes from: host arrays (hx / hy) or device
+// pointers (dx / dy, FP64 when dtype is 0, FP32 when 1) that become readable
+// once the work enqueued on `caller` has run.  All null: no warm start.
+struct WarmStart {
+  const double* const* hx = nullptr;
+  const double* const* hy = nullptr;
+  const void* const* dx = nullptr;
+  const void* const* dy = nullptr;
+  int dtype = 0;
+  hipStream_t caller = nullptr;
+};
+
 struct Engine {
   int B = 0;
   int64_t M = 0, N = 0, NNZ = 0;
@@ -150,6 +173,10 @@ struct Engine {
   DBuf rec_primal, rec_dual, rec_lam, rec_cand_c, rec_cand_r, rec_probe_c, rec_probe_r;
   DBuf rec_nc, rec_nr, rec_nm;
   DBuf d_inst, d_summary, warm_x, warm_y, d_trace;
+  DBuf d_row0i, d_col0i, warm_ptr, d_flag;       // instance offsets, device warm-start pointer table
+  DBuf xs0, ys0, rx, ry, rgx, rgty;              // infeasibility rays (FP64)
+  bool any_unbounded = false;                    // some column has an infinite bound
+  int infeas_on = 0;                             // the running solve runs the infeasibility tests
   int32_t* h_summary = nullptr;
   IterBufs<float> it32;
   IterBufs<double> it64;
@@ -167,6 +194,7 @@ struct Engine {
   bool use_band = false;
   bool band_suspended = false;      // auto layout: the active instances of a batch fell below the band threshold
   BandSet band1, band2;             // band tiles of G (gathers x) and G^T (gathers y)
+  BandSchedule bsched;              // shape of both band layouts
   hipStream_t stream = nullptr;
   std::map<int64_t, hipGraphExec_t> graphs;
   std::vector<hipEvent_t> events;
@@ -184,9 +212,10 @@ struct Engine {
   KernelCtx ctx(int probe_passes) const;
   void enqueue_chunk(const KernelCtx& k, int mask, int64_t K, bool timed);
   void harvest_events();
-  std::vector<struct pdcs_result_s*> solve(const pdcs_options& o, const double* const* x0s,
-                                           const double* const* y0s);
+  std::vector<struct pdcs_result_s*> solve(const pdcs_options& o, const WarmStart& ws);
   double time_dual(int prec, int reps);
+  double time_band_trial(int reps);
+  void rebuild_bands();
   void autotune(double budget_ms);
 };
 

@@ -482,7 +482,7 @@ bool build_band_tile(int64_t r0, int64_t r1, int p, int64_t c0, int64_t c1, int6
 }  // namespace
 
 void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>& g0s, const std::vector<int32_t>& ptr,
-                    const std::vector<int32_t>& idx) {
+                    const std::vector<int32_t>& idx, const BandSchedule& bs) {
   const int NB = (int)r0s.size() - 1;
   R = r0s[NB];
   const int64_t G = g0s[NB];
@@ -496,24 +496,26 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
   }
   // band height: as tall as possible (better gather locality, fewer
   // iterations' worth of fixed cost per tile) while keeping at least about
-  // 384 band-tiles to spread over the 256 CUs.  On the m = 2e5, n = 5e5 LP
-  // (nnz 5e6) a trial took 0.131 / 0.105 / 0.112 / 0.130 ms with at least
-  // 192 / 384 / 768 / 1536 tiles; larger problems reach 8192-row bands anyway.
+  // bs.min_tiles (384 by default) band-tiles to spread over the 256 CUs.  On
+  // the m = 2e5, n = 5e5 LP (nnz 5e6) a trial took 0.131 / 0.105 / 0.112 /
+  // 0.130 ms with at least 192 / 384 / 768 / 1536 tiles; larger problems reach
+  // 8192-row bands anyway.
   auto tiles_for = [&](int64_t rb) {
     int64_t t = 0;
     for (int b = 0; b < NB; ++b) t += ((r0s[b + 1] - r0s[b] + rb - 1) / rb) * P;
     return t;
   };
-  int64_t rb = kBandRows;
-  while (rb > 256 && tiles_for(rb) < 384) rb /= 2;
+  int64_t rb = std::min<int64_t>(bs.rows, kBandRows);
+  while (rb > 256 && tiles_for(rb) < bs.min_tiles) rb /= 2;
+  band_rows = (int)rb;
   BandBuild bb;
   bb.run_start.push_back(0);
   bb.run_ext.push_back(0);
   std::vector<int32_t> stamp(kBandSlots, -1), next(kBandSlots, -1);
   int32_t gid = 0;
   std::vector<std::pair<int64_t, int64_t>> bands;  // row ranges, split on slot overflow
-  // Per instance of a batch, bands no taller than needed for about 32 Ki
-  // entries per window, so that tiles of very different instances stay
+  // Per instance of a batch, bands no taller than needed for about
+  // bs.entry_cap (32 Ki) entries per window, so that tiles of very different instances stay
   // comparable in work and the tiles still running at the end of a launch
   // are short (a single instance keeps the height chosen above).  On the 512-LP batch the batched
   // G x_hat took 0.284 ms with 64 Ki, 0.251 with 32 Ki, 0.275 with 16 Ki.
@@ -525,7 +527,7 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
       const int64_t rows_b = r0s[b + 1] - r0s[b];
       const int64_t nnz_b = rows_b > 0 ? (int64_t)ptr[r0s[b + 1]] - ptr[r0s[b]] : 0;
       const double per_row = rows_b > 0 ? (double)nnz_b / (double)rows_b / (double)Pb[b] : 1.0;
-      while (rbb > 256 && (double)rbb * per_row > 32768.0) rbb /= 2;
+      while (rbb > 256 && (double)rbb * per_row > (double)bs.entry_cap) rbb /= 2;
     }
     // Band boundaries with about equal entries (the count of rbb-row bands,
     // each at most rbb rows): with heavy-tailed row lengths, fixed heights
@@ -690,6 +692,16 @@ void BandSet::build(const std::vector<int64_t>& r0s, const std::vector<int64_t>&
   part64b.alloc((size_t)P * R * 8);
 }
 
+void BandSet::reset() {
+  P = 1;
+  ntile = nslot = 0;
+  R = nent = 0;
+  band_rows = 0;
+  for (DBuf* d : {&group, &slot, &start, &row0, &nrows, &used, &tinst, &col0, &panel, &run_start, &run_row, &run_ext,
+                  &ext, &pk, &src, &val32, &val64, &part32, &part64, &part64b, &orig32, &orig64})
+    d->release();
+}
+
 BandTiles BandSet::view() const {
   BandTiles b{};
   b.group = group.as<int32_t>();
@@ -795,6 +807,12 @@ Engine::Engine(const std::vector<const HostProblem*>& probs) {
   for (DBuf* bf : {&c32, &l32, &u32}) bf->alloc((size_t)N * 4);
   d_inst.alloc(sizeof(Inst) * (size_t)std::max(B, 1));
   d_summary.alloc(16);
+  {
+    std::vector<int32_t> r0i(row0.begin(), row0.end()), c0i(col0.begin(), col0.end());
+    upload(d_row0i, r0i);
+    upload(d_col0i, c0i);
+  }
+  for (int64_t j = 0; j < N && !any_unbounded; ++j) any_unbounded = !std::isfinite(l[j]) || !std::isfinite(u[j]);
   HIP_OK(hipHostMalloc((void**)&h_summary, 16, hipHostMallocDefault));
   build_schedule();
 }
@@ -848,8 +866,8 @@ void Engine::build_schedule() {
     if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
   }
   if (want_band && !band1.nslot && !band2.nslot) {
-    band1.build(row0, col0, h_rp, h_ci);
-    band2.build(col0, row0, h_cp, h_ri);
+    band1.build(row0, col0, h_rp, h_ci, bsched);
+    band2.build(col0, row0, h_cp, h_ri, bsched);
   }
   use_band = want_band;
   rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
@@ -916,6 +934,14 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.P2 = pcol.P;
   k.rec_dual_epi = rec_dual_epi.as<double>();
   k.rec_lam_epi = rec_lam_epi.as<double>();
+  k.infeas = infeas_on;
+  k.ray_x = any_unbounded ? 1 : 0;
+  k.xs0 = xs0.as<double>();
+  k.ys0 = ys0.as<double>();
+  k.rx = rx.as<double>();
+  k.ry = ry.as<double>();
+  k.rgx = rgx.as<double>();
+  k.rgty = rgty.as<double>();
   if (prow.P > 1) {
     k.prow = prow.tiles.view();
     k.bprow = prow.blocks.view();
@@ -967,6 +993,24 @@ static void validate_options(const pdcs_options& o) {
   if (o.use_kkt_restart < 0 || o.use_kkt_restart > 1) throw Error(PDCS_ERR_INVALID_ARG, "use_kkt_restart is 0 or 1");
   if (!(o.bisect_rel_eps > 0)) throw Error(PDCS_ERR_INVALID_ARG, "bisect_rel_eps must be > 0");
   if (std::isnan(o.time_limit)) throw Error(PDCS_ERR_INVALID_ARG, "time_limit is NaN");
+  if (o.use_duality_gap_restart < 0 || o.use_duality_gap_restart > 1)
+    throw Error(PDCS_ERR_INVALID_ARG, "use_duality_gap_restart is 0 or 1");
+  if (o.kkt_restart_freq < 0 || o.kkt_restart_freq > 100000 || o.duality_gap_restart_freq < 0 ||
+      o.duality_gap_restart_freq > 100000)
+    throw Error(PDCS_ERR_INVALID_ARG, "restart frequencies in [0, 1e5]");
+  if (o.print_freq < 1) throw Error(PDCS_ERR_INVALID_ARG, "print_freq must be >= 1");
+  for (double e : {o.eps_primal_infeasible_low_acc, o.eps_dual_infeasible_low_acc, o.eps_primal_infeasible_high_acc,
+                   o.eps_dual_infeasible_high_acc})
+    if (!(e >= 0.0) || !std::isfinite(e)) throw Error(PDCS_ERR_INVALID_ARG, "infeasibility tolerances must be finite and >= 0");
+}
+
+// Restart metric and check period (option list of Section 3): the normalized
+// duality gap unless use_kkt_restart is set or use_duality_gap_restart is
+// cleared; the period is the metric's frequency option, or check_every when 0.
+static bool gap_metric(const pdcs_options& o) { return o.use_duality_gap_restart != 0 && o.use_kkt_restart == 0; }
+static int64_t check_period(const pdcs_options& o) {
+  const int64_t f = gap_metric(o) ? o.duality_gap_restart_freq : o.kkt_restart_freq;
+  return f > 0 ? f : o.check_every;
 }
 
 void Engine::enqueue_chunk(const KernelCtx& k, int mask, int64_t K, bool timed) {
@@ -1003,8 +1047,21 @@ void Engine::harvest_events() {
   ev_used = 0;
 }
 
-std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* const* x0s, const double* const* y0s) {
+std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const WarmStart& ws) {
   validate_options(o);
+  const double* const* x0s = ws.hx;
+  const double* const* y0s = ws.hy;
+  const bool gap = gap_metric(o);
+  const int64_t period = check_period(o);
+  const int probe_passes = gap ? (int)o.probe_passes : 0;
+  infeas_on = (o.eps_primal_infeasible_low_acc > 0 || o.eps_dual_infeasible_low_acc > 0 ||
+               o.eps_primal_infeasible_high_acc > 0 || o.eps_dual_infeasible_high_acc > 0)
+                  ? 1
+                  : 0;
+  if (infeas_on && !rx.p) {
+    for (DBuf* bf : {&xs0, &rx, &rgty}) bf->alloc((size_t)N * 8);
+    for (DBuf* bf : {&ys0, &ry, &rgx}) bf->alloc((size_t)M * 8);
+  }
   HIP_OK(hipGetLastError());
   const auto t_start = std::chrono::steady_clock::now();
   if (band_suspended) {  // left over from a solve that ended early
@@ -1030,10 +1087,16 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     I.status = kActive;
     I.exit_code = PDCS_EXIT_CONTINUE;
     I.max_iter = o.max_iter;
-    I.check_every = o.check_every;
+    I.check_every = period;
     I.method = (int32_t)o.method;
     I.use_avg = o.method != PDCS_METHOD_HALPERN ? 1 : 0;
-    I.force_kkt = o.use_kkt_restart ? 1 : 0;
+    I.force_kkt = gap ? 0 : 1;
+    I.infeas_on = infeas_on;
+    I.eps_inf[0] = o.eps_primal_infeasible_low_acc;
+    I.eps_inf[1] = o.eps_dual_infeasible_low_acc;
+    I.eps_inf[2] = o.eps_primal_infeasible_high_acc;
+    I.eps_inf[3] = o.eps_dual_infeasible_high_acc;
+    I.ratio_p = I.ratio_d = std::numeric_limits<double>::quiet_NaN();
     I.rel_tol = o.rel_tol;
     I.abs_tol = o.abs_tol;
     I.polish_tol = o.polish_switch_tol;
@@ -1085,7 +1148,42 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     }
     HIP_OK(hipStreamSynchronize(stream));
   }
-  KernelCtx k = ctx((int)o.probe_passes);
+  if (ws.dx || ws.dy) {
+    // device warm starts: wait for the caller's work on its stream, then pack
+    // the per-instance arrays into the FP64 start vectors (NaN is rejected)
+    hipEvent_t ready;
+    HIP_OK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipError_t e1 = hipEventRecord(ready, ws.caller);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(stream, ready, 0) : e1;
+    (void)hipEventDestroy(ready);
+    HIP_OK(e2);
+    if (!d_flag.p) d_flag.alloc(256);
+    HIP_OK(hipMemsetAsync(d_flag.p, 0, 4, stream));
+    if (!warm_ptr.p) warm_ptr.alloc(sizeof(void*) * (size_t)B);
+    int64_t maxc = 0, maxr = 0;
+    for (int b = 0; b < B; ++b) {
+      maxc = std::max<int64_t>(maxc, col0[b + 1] - col0[b]);
+      maxr = std::max<int64_t>(maxr, row0[b + 1] - row0[b]);
+    }
+    for (int side = 0; side < 2; ++side) {
+      const void* const* src = side == 0 ? ws.dx : ws.dy;
+      if (!src) continue;
+      std::vector<const void*> tbl(src, src + B);
+      HIP_OK(hipMemcpyAsync(warm_ptr.p, tbl.data(), sizeof(void*) * (size_t)B, hipMemcpyHostToDevice, stream));
+      DBuf& dst = side == 0 ? warm_x : warm_y;
+      dst.alloc((size_t)(side == 0 ? N : M) * 8);
+      launch_pack_warm(warm_ptr.as<const void*>(), (side == 0 ? d_col0i : d_row0i).as<int32_t>(), B,
+                       side == 0 ? maxc : maxr, ws.dtype, dst.as<double>(), d_flag.as<int32_t>(), stream);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipStreamSynchronize(stream));  // the pointer table is reused by the other side
+      if (side == 0) dx0 = warm_x.as<double>();
+      else dy0 = warm_y.as<double>();
+    }
+    int32_t nan_seen = 0;
+    HIP_OK(hipMemcpy(&nan_seen, d_flag.p, 4, hipMemcpyDeviceToHost));
+    if (nan_seen) throw Error(PDCS_ERR_INVALID_ARG, "NaN in the device warm start");
+  }
+  KernelCtx k = ctx(probe_passes);
   SetupCtx su{};
   su.precondition = o.use_preconditioner ? 1 : 0;
   su.ruiz_iters = (int)o.ruiz_iters;
@@ -1139,7 +1237,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
   ev_used = 0;
   launch_summary(k, stream, d_summary.as<int32_t>());
   int64_t chunks = 0;
-  auto last_print = std::chrono::steady_clock::now();
+  int64_t printed = 0;  // progress lines written (verbose = 1: one per print_freq trials)
   // Retire-and-compact: when the active instances of a batch have halved
   // since the schedules were built, rebuild the iteration schedules over the
   // active ones only, so finished instances stop costing workgroups.
@@ -1150,9 +1248,9 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     HIP_OK(hipStreamSynchronize(stream));
     if (timed) harvest_events();
     const int a32 = h_summary[0], a64 = h_summary[1];
-    const double since = std::chrono::duration<double>(std::chrono::steady_clock::now() - last_print).count();
-    if (o.verbose && chunks > 0 && (since >= 2.0 || o.verbose > 1)) {
-      last_print = std::chrono::steady_clock::now();
+    const bool print_now = o.verbose > 1 || (o.verbose == 1 && chunks * period / o.print_freq > printed);
+    if (o.verbose && chunks > 0 && print_now) {
+      printed = chunks * period / o.print_freq;
       Inst I0;
       HIP_OK(hipMemcpy(&I0, d_inst.p, sizeof(Inst), hipMemcpyDeviceToHost));
       std::fprintf(stderr,
@@ -1177,7 +1275,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
       // the automatic layout choice, made again for the instances still running:
       // few large tiles would leave most of the chip idle, compacted row blocks do not
       if (layout == PDCS_LAYOUT_AUTO && act_nnz < ((int64_t)1 << 22)) band_suspended = true;
-      k = ctx((int)o.probe_passes);
+      k = ctx(probe_passes);
       active_built = a32 + a64;
       compacted = true;
     }
@@ -1188,12 +1286,13 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     }
     const int mask = (a32 ? 1 : 0) | (a64 ? 2 : 0);
     if (use_graph) {
-      const int64_t key = ((int64_t)mask << 40) ^ (o.check_every << 8) ^ o.probe_passes;
+      // everything that changes the captured launch sequence is in the key
+      const int64_t key = ((int64_t)mask << 48) | ((int64_t)infeas_on << 47) | (period << 8) | probe_passes;
       auto it = graphs.find(key);
       if (it == graphs.end()) {
         hipGraph_t g;
         HIP_OK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        enqueue_chunk(k, mask, o.check_every, false);
+        enqueue_chunk(k, mask, period, false);
         HIP_OK(hipStreamEndCapture(stream, &g));
         hipGraphExec_t ge;
         HIP_OK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -1202,7 +1301,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
       }
       HIP_OK(hipGraphLaunch(it->second, stream));
     } else {
-      enqueue_chunk(k, mask, o.check_every, timed);
+      enqueue_chunk(k, mask, period, timed);
     }
     HIP_OK(hipGetLastError());
     ++chunks;
@@ -1210,7 +1309,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
   if (compacted) {  // the final evaluation covers every instance
     build_iteration_schedules(nullptr);
     band_suspended = false;
-    k = ctx((int)o.probe_passes);
+    k = ctx(probe_passes);
   }
   // final point of instances that stopped without an optimal candidate
   launch_eval(k, stream, alloc_mask, 1);
@@ -1302,6 +1401,10 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     r->st.r_cur = I.chk_r[0];
     r->st.r_avg = I.chk_r[1];
     r->st.chosen = I.chosen;
+    r->st.ratio_p = I.ratio_p;
+    r->st.ratio_d = I.ratio_d;
+    r->st.trend_p = I.trend_p;
+    r->st.trend_d = I.trend_d;
     r->has_state = o.keep_state != 0;
     if (b == 0 && o.trace_trials > 0) {
       const int64_t rows = std::min<int64_t>(o.trace_trials, I.kbar);
@@ -1312,6 +1415,15 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const double* cons
     res[b] = r;
   }
   return res;
+}
+
+// Rebuild both band layouts with the current band schedule (the scaled band
+// values are filled in by the next solve's set-up).
+void Engine::rebuild_bands() {
+  clear_graphs();
+  band1.reset();
+  band2.reset();
+  build_schedule();
 }
 
 // Time `reps` launches of the SpMV-with-dual-step kernel on the current state.
@@ -1379,6 +1491,14 @@ void pdcs_options_default(pdcs_options* o) {
   o->time_kernels = 0;
   o->probe_passes = 7;
   o->compact = 1;
+  o->use_duality_gap_restart = 1;
+  o->kkt_restart_freq = 0;
+  o->duality_gap_restart_freq = 0;
+  o->print_freq = 2000;
+  o->eps_primal_infeasible_low_acc = 1e-12;
+  o->eps_dual_infeasible_low_acc = 1e-12;
+  o->eps_primal_infeasible_high_acc = 1e-16;
+  o->eps_dual_infeasible_high_acc = 1e-16;
 }
 
 const char* pdcs_status_string(int code) {
@@ -1508,7 +1628,33 @@ int pdcs_solve(pdcs_problem p, const pdcs_options* opts, const double* x0, const
     const double* xs[1] = {x0};
     const double* ys[1] = {y0};
     (void)stream;
-    auto r = p->eng->solve(o, x0 ? xs : nullptr, y0 ? ys : nullptr);
+    WarmStart ws;
+    ws.hx = x0 ? xs : nullptr;
+    ws.hy = y0 ? ys : nullptr;
+    auto r = p->eng->solve(o, ws);
+    *out = r[0];
+    return PDCS_OK;
+  });
+}
+
+int pdcs_solve_device(pdcs_problem p, const pdcs_options* opts, const void* x0_dev, const void* y0_dev,
+                      int64_t warm_dtype, void* stream, pdcs_result* out) {
+  return guarded([&]() {
+    if (!p || !out) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    if (warm_dtype != PDCS_PRECISION_FP64 && warm_dtype != PDCS_PRECISION_MIXED)
+      throw Error(PDCS_ERR_INVALID_ARG, "warm_dtype must be PDCS_PRECISION_FP64 or PDCS_PRECISION_MIXED");
+    *out = nullptr;
+    pdcs_options o;
+    if (opts) o = *opts;
+    else pdcs_options_default(&o);
+    const void* xs[1] = {x0_dev};
+    const void* ys[1] = {y0_dev};
+    WarmStart ws;
+    ws.dx = x0_dev ? xs : nullptr;
+    ws.dy = y0_dev ? ys : nullptr;
+    ws.dtype = warm_dtype == PDCS_PRECISION_MIXED ? 1 : 0;
+    ws.caller = (hipStream_t)stream;
+    auto r = p->eng->solve(o, ws);
     *out = r[0];
     return PDCS_OK;
   });
@@ -1526,6 +1672,38 @@ static void copy_out(const DBuf& src, int64_t off, int64_t len, double* dst, int
   if (!dst) throw Error(PDCS_ERR_INVALID_ARG, "destination is null");
   if (want != len) throw Error(PDCS_ERR_INVALID_ARG, "length mismatch");
   if (len > 0) HIP_OK(hipMemcpy(dst, src.as<double>() + off, (size_t)len * 8, hipMemcpyDeviceToHost));
+}
+
+static void copy_out_device(const DBuf& src, int64_t off, int64_t len, double* dst, int64_t want, void* stream) {
+  if (!dst) throw Error(PDCS_ERR_INVALID_ARG, "destination is null");
+  if (want != len) throw Error(PDCS_ERR_INVALID_ARG, "length mismatch");
+  if (len > 0)
+    HIP_OK(hipMemcpyAsync(dst, src.as<double>() + off, (size_t)len * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+}
+
+int pdcs_result_primal_device(pdcs_result r, double* x_dev, int64_t n, void* stream) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    copy_out_device(r->out->x, r->col0, r->n, x_dev, n, stream);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_dual_device(pdcs_result r, double* y_dev, int64_t m, void* stream) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    if (r->m == 0 && m == 0) return PDCS_OK;
+    copy_out_device(r->out->y, r->row0, r->m, y_dev, m, stream);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_result_slack_device(pdcs_result r, double* lam_dev, int64_t n, void* stream) {
+  return guarded([&]() {
+    if (!r) throw Error(PDCS_ERR_INVALID_ARG, "result is null");
+    copy_out_device(r->out->lam, r->col0, r->n, lam_dev, n, stream);
+    return PDCS_OK;
+  });
 }
 
 int pdcs_result_primal(pdcs_result r, double* x, int64_t n) {
@@ -1653,7 +1831,30 @@ int pdcs_batch_solve(pdcs_batch b, const pdcs_options* opts, const double* const
     if (opts) o = *opts;
     else pdcs_options_default(&o);
     (void)stream;
-    auto r = b->eng->solve(o, x0s, y0s);
+    WarmStart ws;
+    ws.hx = x0s;
+    ws.hy = y0s;
+    auto r = b->eng->solve(o, ws);
+    for (size_t i = 0; i < r.size(); ++i) results[i] = r[i];
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_solve_device(pdcs_batch b, const pdcs_options* opts, const void* const* x0s_dev,
+                            const void* const* y0s_dev, int64_t warm_dtype, void* stream, pdcs_result* results) {
+  return guarded([&]() {
+    if (!b || !results) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    if (warm_dtype != PDCS_PRECISION_FP64 && warm_dtype != PDCS_PRECISION_MIXED)
+      throw Error(PDCS_ERR_INVALID_ARG, "warm_dtype must be PDCS_PRECISION_FP64 or PDCS_PRECISION_MIXED");
+    pdcs_options o;
+    if (opts) o = *opts;
+    else pdcs_options_default(&o);
+    WarmStart ws;
+    ws.dx = x0s_dev;
+    ws.dy = y0s_dev;
+    ws.dtype = warm_dtype == PDCS_PRECISION_MIXED ? 1 : 0;
+    ws.caller = (hipStream_t)stream;
+    auto r = b->eng->solve(o, ws);
     for (size_t i = 0; i < r.size(); ++i) results[i] = r[i];
     return PDCS_OK;
   });
@@ -1692,6 +1893,58 @@ int pdcs_batch_set_layout(pdcs_batch b, int64_t layout) {
   });
 }
 
+static void set_band_schedule(Engine& e, int64_t rows, int64_t min_tiles, int64_t entry_cap) {
+  if (rows < 256 || rows > kBandRows || (rows & (rows - 1)) != 0)
+    throw Error(PDCS_ERR_INVALID_ARG, "band rows must be a power of two in [256, 8192]");
+  if (min_tiles < 1 || min_tiles > (1 << 20)) throw Error(PDCS_ERR_INVALID_ARG, "min_tiles in [1, 2^20]");
+  if (entry_cap < 1024 || entry_cap > (1 << 24)) throw Error(PDCS_ERR_INVALID_ARG, "entry_cap in [1024, 2^24]");
+  e.bsched = BandSchedule{(int)rows, (int)min_tiles, (int)entry_cap};
+  e.rebuild_bands();
+}
+
+static void get_band_schedule(const Engine& e, int64_t* rows, int64_t* min_tiles, int64_t* entry_cap,
+                              int64_t* built_rows, int64_t* windows) {
+  if (rows) *rows = e.bsched.rows;
+  if (min_tiles) *min_tiles = e.bsched.min_tiles;
+  if (entry_cap) *entry_cap = e.bsched.entry_cap;
+  if (built_rows) *built_rows = e.use_band ? e.band1.band_rows : 0;
+  if (windows) *windows = e.use_band ? e.band1.P : 0;
+}
+
+int pdcs_problem_set_band_schedule(pdcs_problem p, int64_t rows, int64_t min_tiles, int64_t entry_cap) {
+  return guarded([&]() {
+    if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
+    set_band_schedule(*p->eng, rows, min_tiles, entry_cap);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_set_band_schedule(pdcs_batch b, int64_t rows, int64_t min_tiles, int64_t entry_cap) {
+  return guarded([&]() {
+    if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
+    set_band_schedule(*b->eng, rows, min_tiles, entry_cap);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_problem_band_schedule(pdcs_problem p, int64_t* rows, int64_t* min_tiles, int64_t* entry_cap,
+                               int64_t* built_rows, int64_t* windows) {
+  return guarded([&]() {
+    if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
+    get_band_schedule(*p->eng, rows, min_tiles, entry_cap, built_rows, windows);
+    return PDCS_OK;
+  });
+}
+
+int pdcs_batch_band_schedule(pdcs_batch b, int64_t* rows, int64_t* min_tiles, int64_t* entry_cap,
+                             int64_t* built_rows, int64_t* windows) {
+  return guarded([&]() {
+    if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
+    get_band_schedule(*b->eng, rows, min_tiles, entry_cap, built_rows, windows);
+    return PDCS_OK;
+  });
+}
+
 int pdcs_batch_autotune(pdcs_batch b, double time_budget_ms) {
   return guarded([&]() {
     if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
@@ -1716,7 +1969,7 @@ void Engine::autotune(double budget_ms) {
   o.max_iter = 1;
   o.use_graph = 0;
   {
-    auto rs = solve(o, nullptr, nullptr);
+    auto rs = solve(o, WarmStart{});
     for (auto* r : rs) delete r;
   }
   // re-activate every instance so that the timed kernels do their full work

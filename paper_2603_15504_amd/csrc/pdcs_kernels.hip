@@ -23,6 +23,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace pdcs {
 
 // ===========================================================================
@@ -192,12 +194,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_part(RowBlocks rb, const int32_
 // gathers one iteration ahead of the accumulation.  Output: part[panel * R + r].
 // ---------------------------------------------------------------------------
 // Instances a check or evaluation pass works on.
-enum Mode : int { kModeCheck = 0, kModeEvalStart = 1, kModeEvalFinal = 2 };
+// kModeRay: the infeasibility rays of a check, FP64 vectors whatever the
+// instance's iterate precision.
+enum Mode : int { kModeCheck = 0, kModeEvalStart = 1, kModeEvalFinal = 2, kModeRay = 3 };
 
 __device__ __forceinline__ bool mode_selects(const Inst& I, int mode) {
   if (mode == kModeCheck) return I.status == kActive && I.check_due != 0;
   if (mode == kModeEvalStart) return I.status == kActive;
+  if (mode == kModeRay) return I.status == kActive && I.check_due != 0 && I.ray_due != 0;
   return I.status == kDone && I.exit_code != 0;
+}
+
+// Precision filter of the check products: the ray pass serves every instance.
+__device__ __forceinline__ bool prec_selects(const Inst& I, int mode, int prec) {
+  return mode == kModeRay || I.precision == prec;
 }
 
 // One wave's band-tile t: part[panel * R + r] = sum over the tile's entries of
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(kBandWaves * kWave) void k_band_cand(BandTiles bt, 
   const int t = bt.group[g * kBandWaves + w];
   if (t < 0) return;
   const Inst& I = inst[bt.tinst[t]];
-  if (!mode_selects(I, mode) || I.precision != prec) return;
+  if (!mode_selects(I, mode) || !prec_selects(I, mode, prec)) return;
   if (which == 1 && mode == kModeCheck && I.use_avg == 0) return;
   band_tile_product<double, TX, double>(bt, t, acc + w * kBandSlots, val, x, part, R);
 }
@@ -586,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv2(RowBlocks rb, MatPtrs<double> 
   __shared__ double lds[2 * kRowBlockCap + kWavesPerBlock * 2];
   const int b = blockIdx.x;
   const Inst& I = inst[rb.blk_inst[b]];
-  if (!mode_selects(I, mode) || I.precision != prec) return;
+  if (!mode_selects(I, mode) || !prec_selects(I, mode, prec)) return;
   const bool two = (in1 != nullptr) && (mode != kModeCheck || I.use_avg != 0);
   if (two) {
     const T* const xs[2] = {in0, in1};
@@ -613,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv2_part(RowBlocks rb, const int32
   const int b = slot[blockIdx.x];
   if (b < 0) return;
   const Inst& I = inst[0];
-  if (!mode_selects(I, mode) || I.precision != prec) return;
+  if (!mode_selects(I, mode) || !prec_selects(I, mode, prec)) return;
   const bool two = (in1 != nullptr) && (mode != kModeCheck || I.use_avg != 0);
   if (two) {
     const T* const xs[2] = {in0, in1};
@@ -786,8 +796,8 @@ __global__ __launch_bounds__(kBlock) void k_cand_fin(Ranges rc, const double* __
     C.doublings = 0;
     C.bracketed = 0;
     C.last_dist = -1.0;
-    if (mode != kModeCheck) {
-      C.phase = kPhaseOff;
+    if (mode != kModeCheck || I.force_kkt) {
+      C.phase = kPhaseOff;  // KKT_omega is the restart metric: no bisection
     } else if (!(C.r > 0.0) || !isfinite(C.r)) {
       C.phase = kPhaseDone;  // invalid radius: numerical issue
     } else if (C.scale == 0.0) {
@@ -986,13 +996,15 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
   Inst& I = inst[iid];
   if (I.status != kActive || I.check_due == 0) return;
   I.checks += 1;
+  I.ray_due = 0;
   const int nc = I.use_avg ? 2 : 1;
   bool all_valid = true;
   for (int q = 0; q < nc; ++q) {
     CandState& C = I.cand[q];
     if (C.phase == kPhaseBisect) C.phase = kPhaseDone;  // pass budget spent: take t_lo
     if (C.phase == kPhaseExp) C.phase = kPhaseDone;
-    if (!(C.r > 0.0) || !isfinite(C.r)) C.rho = NAN;
+    if (I.force_kkt) C.rho = NAN;  // the gap is not computed
+    else if (!(C.r > 0.0) || !isfinite(C.r)) C.rho = NAN;
     else if (C.scale == 0.0) C.rho = 0.0;
     else C.rho = C.val_lo / C.r;
     if (!(C.rho >= 0.0) || !isfinite(C.rho)) all_valid = false;
@@ -1072,6 +1084,7 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
     return;
   }
   I.restart = restart ? 1 : 0;
+  I.ray_due = I.infeas_on;
   if (restart) {
     const double dx = sqrt(C.dxa2), dy = sqrt(C.dya2);
     double w = I.omega;
@@ -1091,10 +1104,9 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
     I.kkt_prev = C.kkt;
     I.has_prev = 1;
   }
-  if (I.kbar >= I.max_iter) {  // trial budget spent: stop after this check
-    I.status = kDone;
-    I.exit_code = 1;
-  }
+  // trial budget spent: stop after this check (k_check_end), once the
+  // infeasibility tests of the check have run
+  if (I.kbar >= I.max_iter) I.stop_max_iter = 1;
 }
 
 // Apply a restart (anchor <- candidate, products refreshed from the FP64-value
@@ -1186,6 +1198,10 @@ __global__ void k_check_end(Inst* __restrict__ inst, int nb) {
     I.status = kDone;
     I.exit_code = 0;
   }
+  if (I.stop_max_iter && I.status == kActive) {
+    I.status = kDone;
+    I.exit_code = 1;
+  }
   if (I.switch_fp64 && I.status == kActive) {
     I.precision = kFP64;
     I.switch_fp64 = 0;
@@ -1196,6 +1212,185 @@ __global__ void k_check_end(Inst* __restrict__ inst, int nb) {
   }
   I.check_due = 0;
   I.restart = 0;
+  I.ray_due = 0;
+}
+
+// ===========================================================================
+// Infeasibility tests (option list of Section 3; exit codes 2-5)
+// ===========================================================================
+// The tests run on rays: the displacement of the PDHG output z_hat from the
+// projected start point, r_x = Proj_rec(x_hat - x_start) onto the recession
+// cone of the box and r_y = Proj_Kd(y_hat - y_start), in the rescaled space
+// (both projections commute with the positive diagonal scaling).  Unscaled,
+// G^T (D1 r_y) = D2^{-1} G_hat^T r_y and G (D2 r_x) = D1^{-1} G_hat r_x.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ray_vec_cols(Ranges R, const T* __restrict__ xh,
+                                                         const double* __restrict__ xs0, DataPtrs<double> d,
+                                                         double* __restrict__ rx, const Inst* __restrict__ inst,
+                                                         int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, kModeRay) || I.precision != prec) return;
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    double v = (double)xh[j] - xs0[j];
+    const bool lf = isfinite(d.l[j]), uf = isfinite(d.u[j]);
+    if (lf && uf) v = 0.0;
+    else if (lf) v = fmax(v, 0.0);
+    else if (uf) v = fmin(v, 0.0);
+    rx[j] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ray_vec_rows(Ranges R, const T* __restrict__ yh,
+                                                         const double* __restrict__ ys0, double* __restrict__ ry,
+                                                         const Inst* __restrict__ inst, int prec) {
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, kModeRay) || I.precision != prec) return;
+  const int mz_end = I.row0 + I.m_zero;
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double v = (double)yh[i] - ys0[i];
+    ry[i] = i < mz_end ? v : fmax(v, 0.0);
+  }
+}
+
+// Column terms, with lam = -(G_hat^T r_y)_j / D2_j (the unscaled -G^T r_y) and
+// the unscaled bounds l_j = l_hat_j D2_j, u_j = u_hat_j D2_j:
+//   [0] ||lam - Proj_Lambda lam||^2   [1] sum l lam+ - u lam- (finite bounds)
+//   [2] its terms' magnitudes          [3] number of those terms
+//   [4] c^T r_x (= c_hat^T r_x)         [5] its terms' magnitudes
+constexpr int kRayColsNV = 6;
+__global__ __launch_bounds__(kBlock) void k_ray_cols(Ranges R, const double* __restrict__ rx,
+                                                     const double* __restrict__ rgty, DataPtrs<double> d,
+                                                     const double* __restrict__ D2, const Inst* __restrict__ inst,
+                                                     double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * kRayColsNV];
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, kModeRay)) return;
+  double acc[kRayColsNV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int j1 = R.blk_end[b];
+  for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
+    const double dj = D2[j];
+    const double lam = -rgty[j] / dj;
+    const double lo = d.l[j], hi = d.u[j];
+    const bool lf = isfinite(lo), uf = isfinite(hi);
+    double viol;
+    if (!lf && !uf) viol = lam;               // Lambda_j = {0}
+    else if (!lf) viol = fmax(lam, 0.0);      // R-
+    else if (!uf) viol = fmin(lam, 0.0);      // R+
+    else viol = 0.0;                          // R
+    acc[0] += viol * viol;
+    if (lf) {
+      const double t = (lo * dj) * fmax(lam, 0.0);
+      acc[1] += t;
+      acc[2] += fabs(t);
+      acc[3] += 1.0;
+    }
+    if (uf) {
+      const double t = -(hi * dj) * fmax(-lam, 0.0);
+      acc[1] += t;
+      acc[2] += fabs(t);
+      acc[3] += 1.0;
+    }
+    const double cx = rx ? d.c[j] * rx[j] : 0.0;
+    acc[4] += cx;
+    acc[5] += fabs(cx);
+  }
+  block_sum_store<kRayColsNV>(acc, lds, rec + (size_t)b * kRayColsNV);
+}
+
+// Row terms: [0] h^T r_y (= h_hat^T r_y), [1] its terms' magnitudes,
+// [2] ||G r_x - Proj_Kd*(G r_x)||^2 with (G r_x)_i = (G_hat r_x)_i / D1_i
+// (zero when no instance has a nonzero primal ray: rgx null).
+constexpr int kRayRowsNV = 3;
+__global__ __launch_bounds__(kBlock) void k_ray_rows(Ranges R, const double* __restrict__ ry,
+                                                     const double* __restrict__ rgx, DataPtrs<double> d,
+                                                     const double* __restrict__ D1, const Inst* __restrict__ inst,
+                                                     double* __restrict__ rec) {
+  __shared__ double lds[kWavesPerBlock * kRayRowsNV];
+  const int b = blockIdx.x;
+  const Inst& I = inst[R.blk_inst[b]];
+  if (!mode_selects(I, kModeRay)) return;
+  const int mz_end = I.row0 + I.m_zero;
+  double acc[kRayRowsNV] = {0.0, 0.0, 0.0};
+  const int i1 = R.blk_end[b];
+  for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    const double t = d.h[i] * ry[i];
+    acc[0] += t;
+    acc[1] += fabs(t);
+    if (rgx) {
+      const double r = rgx[i] / D1[i];
+      const double res = i < mz_end ? r : fmin(r, 0.0);
+      acc[2] += res * res;
+    }
+  }
+  block_sum_store<kRayRowsNV>(acc, lds, rec + (size_t)b * kRayRowsNV);
+}
+
+// gamma_N = N u / (1 - N u), u = 2^-53: relative error bound of a sum of N terms.
+__device__ __forceinline__ double rounding_bound(double count) {
+  const double nu = fmax(count, 1.0) * 0x1p-53;
+  return nu / (1.0 - nu);
+}
+
+// Ratios, trend counters and the exit decision of the infeasibility tests.
+// Priority: high-accuracy primal (3), high-accuracy dual (5), low-accuracy
+// primal (2), low-accuracy dual (4); a tolerance of 0 never passes.
+__global__ __launch_bounds__(kBlock) void k_ray_fin(Ranges rc, const double* __restrict__ rec_c, Ranges rr,
+                                                    const double* __restrict__ rec_r, Inst* __restrict__ inst) {
+  __shared__ double lds[kWavesPerBlock * kRayColsNV];
+  const int iid = blockIdx.x;
+  Inst& I = inst[iid];
+  if (!mode_selects(I, kModeRay)) return;
+  double cs[kRayColsNV], rs[kRayRowsNV];
+  reduce_records<kRayColsNV, kRayColsNV>(rec_c, rc.inst_blk0[iid], rc.inst_blk0[iid + 1], lds, cs);
+  reduce_records<kRayRowsNV, kRayRowsNV>(rec_r, rr.inst_blk0[iid], rr.inst_blk0[iid + 1], lds, rs);
+  if (threadIdx.x != 0) return;
+  const double f = rs[0] + cs[1];
+  const double fmag = rs[1] + cs[2];
+  const double ratio_p = f > rounding_bound((double)I.rows + cs[3]) * fmag ? sqrt(cs[0]) / f : (double)INFINITY;
+  const double g = -cs[4];
+  const double ratio_d = g > rounding_bound((double)I.cols) * cs[5] ? sqrt(rs[2]) / g : (double)INFINITY;
+  const double pobj = I.cand[0].pobj, dobj = I.cand[0].dobj;
+  const bool up_p = I.has_prev_obj && dobj > I.prev_dobj;
+  const bool up_d = I.has_prev_obj && -pobj > I.prev_negp;
+  I.prev_dobj = dobj;
+  I.prev_negp = -pobj;
+  I.has_prev_obj = 1;
+  I.trend_p = (ratio_p < I.eps_inf[0] && up_p) ? I.trend_p + 1 : 0;
+  I.trend_d = (ratio_d < I.eps_inf[1] && up_d) ? I.trend_d + 1 : 0;
+  I.ratio_p = ratio_p;
+  I.ratio_d = ratio_d;
+  int code = 0;
+  if (ratio_p < I.eps_inf[2]) code = 3;
+  else if (ratio_d < I.eps_inf[3]) code = 5;
+  else if (I.trend_p >= kTrendChecks) code = 2;
+  else if (I.trend_d >= kTrendChecks) code = 4;
+  if (code) {
+    I.status = kDone;
+    I.exit_code = code;
+    I.restart = 0;
+    I.switch_fp64 = 0;
+  }
+}
+
+// Device warm starts into the packed FP64 start vector.
+template <typename TW>
+__global__ void k_pack_warm(const void* const* __restrict__ src, const int32_t* __restrict__ off, int B,
+                            double* __restrict__ out, int32_t* __restrict__ nan_flag) {
+  for (int b = blockIdx.y; b < B; b += gridDim.y) {
+    const int o0 = off[b], len = off[b + 1] - off[b];
+    const TW* sp = static_cast<const TW*>(src[b]);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) {
+      const double v = sp ? (double)sp[e] : 0.0;
+      if (isnan(v)) *nan_flag = 1;
+      out[o0 + e] = v;
+    }
+  }
 }
 
 // Evaluated point (start point or final point): termination test and output.
@@ -1523,7 +1718,8 @@ __global__ __launch_bounds__(kBlock) void k_init_inst(Ranges rc, const double* _
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_start_cols(Ranges R, const double* __restrict__ x0,
                                                        const double* __restrict__ D2, DataPtrs<double> d,
-                                                       IterPtrs<T> it, const Inst* __restrict__ inst, int prec) {
+                                                       IterPtrs<T> it, double* __restrict__ xs0,
+                                                       const Inst* __restrict__ inst, int prec) {
   const int b = blockIdx.x;
   const Inst& I = inst[R.blk_inst[b]];
   if (I.precision != prec) return;
@@ -1531,6 +1727,7 @@ __global__ __launch_bounds__(kBlock) void k_start_cols(Ranges R, const double* _
   for (int j = R.blk_start[b] + (int)threadIdx.x; j < j1; j += kBlock) {
     const double v = x0 ? x0[j] / D2[j] : 0.0;
     const T x = (T)clampd(v, d.l[j], d.u[j]);
+    if (xs0) xs0[j] = (double)x;
     it.x[j] = x;
     it.xa[j] = x;
     it.xh[j] = x;
@@ -1541,7 +1738,8 @@ __global__ __launch_bounds__(kBlock) void k_start_cols(Ranges R, const double* _
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_start_rows(Ranges R, const double* __restrict__ y0,
                                                        const double* __restrict__ D1, IterPtrs<T> it,
-                                                       const Inst* __restrict__ inst, int prec) {
+                                                       double* __restrict__ ys0, const Inst* __restrict__ inst,
+                                                       int prec) {
   const int b = blockIdx.x;
   const Inst& I = inst[R.blk_inst[b]];
   if (I.precision != prec) return;
@@ -1550,6 +1748,7 @@ __global__ __launch_bounds__(kBlock) void k_start_rows(Ranges R, const double* _
   for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
     const double v = y0 ? y0[i] / D1[i] : 0.0;
     const T y = (T)(i < mz_end ? v : fmax(v, 0.0));
+    if (ys0) ys0[i] = (double)y;
     it.y[i] = y;
     it.ya[i] = y;
     it.yh[i] = y;
@@ -1767,6 +1966,74 @@ static void launch_restart_t(const KernelCtx& k, hipStream_t s, int prec, const 
                                                              k.inst, prec);
 }
 
+// Products of the rays with FP64 values (every selected instance, whatever
+// its precision): rgty = G_hat^T r_y, and rgx = G_hat r_x when some instance
+// has an unbounded column.
+static void launch_ray_products(const KernelCtx& k, hipStream_t s) {
+  auto blocks = [](int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
+  if (k.use_band) {
+    if (k.band2.nslot > 0)
+      k_band_cand<double><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, k.bvalT64, k.ry, k.bpartT64,
+                                                                              k.N, k.inst, kFP64, kModeRay, 0);
+    if (k.vcol.nblk > 0)
+      k_band_combine2<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, k.band2.P, k.N, k.bpartT64, nullptr, k.rgty,
+                                                             nullptr, k.inst, kModeRay);
+    if (k.ray_x) {
+      if (k.band1.nslot > 0)
+        k_band_cand<double><<<grid1(k.band1.nslot), kBandWaves * kWave, 0, s>>>(k.band1, k.bval64, k.rx, k.bpart64,
+                                                                                k.M, k.inst, kFP64, kModeRay, 0);
+      if (k.vrow.nblk > 0)
+        k_band_combine2<<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, k.band1.P, k.M, k.bpart64, nullptr, k.rgx,
+                                                               nullptr, k.inst, kModeRay);
+    }
+    return;
+  }
+  if (k.P2 > 1) {
+    if (k.nslot2 > 0)
+      k_spmv2_part<double><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, k.PAT64, k.ry, nullptr, k.partT64,
+                                                               nullptr, k.inst, kFP64, kModeRay);
+    if (k.N > 0)
+      k_combine2<<<blocks(k.N), kBlock, 0, s>>>(k.N, k.P2, k.partT64, nullptr, k.rgty, nullptr, k.inst, kModeRay);
+  } else if (k.bcol.nblk > 0) {
+    k_spmv2<double><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, k.AT64, k.ry, nullptr, k.rgty, nullptr, k.inst,
+                                                           kFP64, kModeRay);
+  }
+  if (!k.ray_x) return;
+  if (k.P1 > 1) {
+    if (k.nslot1 > 0)
+      k_spmv2_part<double><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, k.PA64, k.rx, nullptr, k.part64,
+                                                               nullptr, k.inst, kFP64, kModeRay);
+    if (k.M > 0)
+      k_combine2<<<blocks(k.M), kBlock, 0, s>>>(k.M, k.P1, k.part64, nullptr, k.rgx, nullptr, k.inst, kModeRay);
+  } else if (k.brow.nblk > 0) {
+    k_spmv2<double><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, k.A64, k.rx, nullptr, k.rgx, nullptr, k.inst,
+                                                           kFP64, kModeRay);
+  }
+}
+
+template <typename T>
+static void launch_ray_vec_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it) {
+  if (k.vcol.nblk > 0 && k.ray_x)
+    k_ray_vec_cols<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it.xh, k.xs0, k.d64, k.rx, k.inst, prec);
+  if (k.vrow.nblk > 0)
+    k_ray_vec_rows<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it.yh, k.ys0, k.ry, k.inst, prec);
+}
+
+// The infeasibility tests of one check (instances selected by k_decide).
+static void launch_ray(const KernelCtx& k, hipStream_t s, int mask) {
+  if (mask & 1) launch_ray_vec_t<float>(k, s, kFP32, k.it32);
+  if (mask & 2) launch_ray_vec_t<double>(k, s, kFP64, k.it64);
+  launch_ray_products(k, s);
+  // the candidate records are free once k_cand_fin has run
+  if (k.vcol.nblk > 0)
+    k_ray_cols<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, k.ray_x ? k.rx : nullptr, k.rgty, k.d64, k.D2, k.inst,
+                                                      k.rec_cand_c);
+  if (k.vrow.nblk > 0)
+    k_ray_rows<<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, k.ry, k.ray_x ? k.rgx : nullptr, k.d64, k.D1, k.inst,
+                                                      k.rec_cand_r);
+  k_ray_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_cand_c, k.vrow, k.rec_cand_r, k.inst);
+}
+
 void launch_check(const KernelCtx& k, hipStream_t s, int mask) {
   const int nbt = (k.nb + 63) / 64;
   if (mask & 1) launch_check_pre_t<float>(k, s, kFP32, k.it32);
@@ -1778,6 +2045,7 @@ void launch_check(const KernelCtx& k, hipStream_t s, int mask) {
     k_probe_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.ccol, k.rec_probe_c, k.crow, k.rec_probe_r, k.inst);
   }
   k_decide<<<nbt, 64, 0, s>>>(k.inst, k.nb);
+  if (k.infeas) launch_ray(k, s, mask);
   if (mask & 1) launch_restart_t<float>(k, s, kFP32, k.it32);
   if (mask & 2) launch_restart_t<double>(k, s, kFP64, k.it64);
   k_check_end<<<nbt, 64, 0, s>>>(k.inst, k.nb);
@@ -1884,15 +2152,17 @@ void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mas
   // start point and its products
   if (mask & 1) {
     if (k.vcol.nblk > 0)
-      k_start_cols<float><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.x0, k.D2, k.d64, k.it32, k.inst, kFP32);
+      k_start_cols<float><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.x0, k.D2, k.d64, k.it32, k.xs0, k.inst,
+                                                                 kFP32);
     if (k.vrow.nblk > 0)
-      k_start_rows<float><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.y0, k.D1, k.it32, k.inst, kFP32);
+      k_start_rows<float><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.y0, k.D1, k.it32, k.ys0, k.inst, kFP32);
   }
   if (mask & 2) {
     if (k.vcol.nblk > 0)
-      k_start_cols<double><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.x0, k.D2, k.d64, k.it64, k.inst, kFP64);
+      k_start_cols<double><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, su.x0, k.D2, k.d64, k.it64, k.xs0, k.inst,
+                                                                  kFP64);
     if (k.vrow.nblk > 0)
-      k_start_rows<double><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.y0, k.D1, k.it64, k.inst, kFP64);
+      k_start_rows<double><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, su.y0, k.D1, k.it64, k.ys0, k.inst, kFP64);
   }
   // FP64-value products of the start point: eval mode computes cgx0 = G x_hat, cgty0 = G^T y_hat
   launch_eval(k, s, mask, 0);
@@ -1938,6 +2208,14 @@ void launch_band_plain(const BandTiles& bt, int prec, const void* val, const voi
 
 void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* o64, float* o32, hipStream_t s) {
   if (n > 0) k_band_vals<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, v64, o64, o32);
+}
+
+void launch_pack_warm(const void* const* src, const int32_t* off, int B, int64_t maxlen, int dtype, double* out,
+                      int32_t* nan_flag, hipStream_t s) {
+  if (B <= 0 || maxlen <= 0) return;
+  const dim3 g((unsigned)std::min<int64_t>((maxlen + 255) / 256, 1024), (unsigned)std::min(B, 4096));
+  if (dtype == 0) k_pack_warm<double><<<g, 256, 0, s>>>(src, off, B, out, nan_flag);
+  else k_pack_warm<float><<<g, 256, 0, s>>>(src, off, B, out, nan_flag);
 }
 
 void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec) {

@@ -67,6 +67,11 @@ struct KernelCtx {
   float *part32, *partT32;
   double *part64, *partT64, *part64b, *partT64b;
   double *rec_dual_epi, *rec_lam_epi;
+  // Infeasibility tests: projected start point (FP64, rescaled space), the
+  // two rays and their products G_hat r_x (rows) and G_hat^T r_y (columns).
+  int infeas;   // some instance runs the tests
+  int ray_x;    // some instance has a column with an infinite bound (else r_x = 0)
+  double *xs0, *ys0, *rx, *ry, *rgx, *rgty;
   // Band-tile layout (single instances): when use_band is set, the two SpMVs of
   // a trial run on band1 (G, windows over x) and band2 (G^T, windows over y),
   // writing band1.P (band2.P) partial sums per row that the epilogues combine.
@@ -116,6 +121,11 @@ void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec);
 void launch_band_plain(const BandTiles& bt, int prec, const void* val, const void* in, void* part, int64_t R,
                        void* out, hipStream_t s);
 void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* o64, float* o32, hipStream_t s);
+// Warm starts from device pointers: out[off[b] + e] = src[b][e] (FP64 or FP32
+// source, dtype 0 / 1; a null src[b] gives zeros), e < off[b + 1] - off[b];
+// *nan_flag is set to 1 when a value is NaN.
+void launch_pack_warm(const void* const* src, const int32_t* off, int B, int64_t maxlen, int dtype, double* out,
+                      int32_t* nan_flag, hipStream_t s);
 
 // Trial split for kernel timing: K3, K1, and the rest of the trial.
 void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part);

@@ -105,3 +105,47 @@ def test_null_handles_are_rejected():
     assert P.lib.pdcs_problem_dims(None, None, None, None) == -1
     assert P.lib.pdcs_batch_create(0, None, None) == -1
     assert P.lib.pdcs_mlp_create(0, 1, 1, 0, None) == -1
+
+
+def test_new_option_defaults_follow_the_paper():
+    # option list of Section 3: infeasibility tolerances, the duality-gap
+    # restart switch and the print frequency
+    import paper_2603_15504_amd as P
+
+    o = P.pdcs_options_default()
+    assert o.eps_primal_infeasible_low_acc == 1e-12 and o.eps_dual_infeasible_low_acc == 1e-12
+    assert o.eps_primal_infeasible_high_acc == 1e-16 and o.eps_dual_infeasible_high_acc == 1e-16
+    assert o.use_duality_gap_restart == 1 and o.use_kkt_restart == 0
+    assert o.print_freq == 2000
+    # 0: the check period falls back to check_every
+    assert o.kkt_restart_freq == 0 and o.duality_gap_restart_freq == 0
+    assert P.pdcs_status_string(2) == "primal_infeasible_low_acc"
+    assert P.pdcs_status_string(5) == "dual_infeasible_high_acc"
+
+
+def test_state_struct_matches_header():
+    import paper_2603_15504_amd as P
+
+    hdr = open(os.path.join(ROOT, "include", "pdcs.h")).read()
+    end = hdr.index("} pdcs_state_scalars;")
+    body = hdr[hdr.rindex("typedef struct {", 0, end):end]
+    n = 0
+    for decl in re.findall(r"^\s*(?:int64_t|double)\s+([^;]+);", body, re.M):
+        n += len(decl.split(","))
+    assert ctypes.sizeof(P.pdcs_state_scalars) == 8 * n
+
+
+def test_batch_warm_start_lengths_checked_before_the_call():
+    # the library reads exactly n_b / m_b values per instance, so the binding
+    # refuses other lengths (and a wrong entry count) before calling it
+    import paper_2603_15504_amd as P
+
+    dims = [(3, 5), (2, 4)]
+    with pytest.raises(ValueError):
+        P.pdcs_batch_solve(None, 2, None, x0s=[np.zeros(4), None], dims=dims)
+    with pytest.raises(ValueError):
+        P.pdcs_batch_solve(None, 2, None, y0s=[np.zeros(3), np.zeros(3)], dims=dims)
+    with pytest.raises(ValueError):
+        P.pdcs_batch_solve(None, 2, None, x0s=[np.zeros(5)], dims=dims)
+    with pytest.raises(ValueError):
+        P.pdcs_batch_solve(None, 2, None, dims=dims[:1])
