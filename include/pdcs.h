@@ -214,6 +214,26 @@ int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
 int  pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision,
                        const void* in_dev, void* out_dev, void* stream);
 
+/* pdcs_problem_spmv_noalloc: pdcs_problem_spmv for callers that cannot
+ * allocate device memory (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * pdcs_problem_spmv; the call allocates nothing, host or device.
+ *   - The band layout's window partial sums go to a file-scope device array
+ *     of 64 MiB (one per GPU, held until the process ends) instead of the
+ *     problem's own buffer.  A product that needs more (P windows x R output
+ *     rows x 4 B in FP32, x 8 B in FP64) fails with PDCS_ERR_SIZE.  The row
+ *     layout uses no partial sums.
+ *   - Every call on one GPU shares that array, which keeps the last call's
+ *     contents: calls that overlap on one GPU race (use one stream, or order
+ *     them).  Nothing in it needs clearing: each call overwrites every
+ *     partial sum it reads.
+ *   - The problem's device must be the current device (PDCS_ERR_INVALID_ARG
+ *     otherwise).  The first call on a device resolves the array's address;
+ *     make that call outside stream capture.
+ * Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_SIZE, PDCS_ERR_HIP. */
+int  pdcs_problem_spmv_noalloc(pdcs_problem p, int64_t transpose, int64_t precision,
+                               const void* in_dev, void* out_dev, void* stream);
+
 /* pdcs_problem_set_panels: column-panel split of the two SpMVs of a single
  * problem.  px panels split the columns gathered by G x, py the rows gathered
  * by G^T y; each panel's workgroups are routed to a fixed subset of the 8 XCDs

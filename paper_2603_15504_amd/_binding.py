@@ -80,6 +80,7 @@ PROTOTYPES = {
     "pdcs_problem_destroy": (None, [_P]),
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
+    "pdcs_problem_spmv_noalloc": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
     "pdcs_problem_set_panels": (C.c_int, [_P, _I64, _I64]),
     "pdcs_problem_set_layout": (C.c_int, [_P, _I64]),
     "pdcs_problem_set_band_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
@@ -227,6 +228,12 @@ def pdcs_problem_spmv(p, transpose: int, precision: int, in_dev: int, out_dev: i
     _check(lib.pdcs_problem_spmv(p, int(transpose), int(precision), C.c_void_p(in_dev),
                                  C.c_void_p(out_dev), C.c_void_p(stream) if stream else None),
            "pdcs_problem_spmv")
+
+
+def pdcs_problem_spmv_noalloc(p, transpose: int, precision: int, in_dev: int, out_dev: int, stream: int = 0):
+    _check(lib.pdcs_problem_spmv_noalloc(p, int(transpose), int(precision), C.c_void_p(in_dev),
+                                         C.c_void_p(out_dev), C.c_void_p(stream) if stream else None),
+           "pdcs_problem_spmv_noalloc")
 
 
 def pdcs_problem_set_panels(p, px: int, py: int):

@@ -124,7 +124,7 @@ struct BandSet {
   int64_t R = 0, nent = 0;
   DBuf group, slot, start, row0, nrows, used, tinst, col0, panel, run_start, run_row, run_ext, ext, pk, src;
   DBuf val32, val64, part32, part64, part64b;
-  DBuf orig32, orig64;  // unscaled values (plain products), filled on first use
+  DBuf orig32, orig64;  // unscaled values (plain products), filled by Engine::prepare_plain
   // instance b: rows [r0s[b], r0s[b+1]) gathering from [g0s[b], g0s[b+1])
   int band_rows = 0;  // band height chosen by build
   void reset();       // back to the unbuilt state, device memory released
@@ -162,6 +162,7 @@ struct WarmStart {
 
 struct Engine {
   int B = 0;
+  int device = 0;                                // HIP device current at creation
   int64_t M = 0, N = 0, NNZ = 0;
   std::vector<int64_t> row0, col0, mzero;
   std::vector<int32_t> h_rp, h_cp;
@@ -216,6 +217,8 @@ struct Engine {
   double time_dual(int prec, int reps);
   double time_band_trial(int reps);
   void rebuild_bands();
+  // unscaled values in the storage order of the current layout (plain products)
+  void prepare_plain();
   void autotune(double budget_ms);
 };
 

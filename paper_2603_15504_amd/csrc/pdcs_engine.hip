@@ -12,6 +12,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -746,6 +747,7 @@ template struct IterBufs<float>;
 template struct IterBufs<double>;
 
 Engine::Engine(const std::vector<const HostProblem*>& probs) {
+  HIP_OK(hipGetDevice(&device));
   HIP_OK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   B = (int)probs.size();
   row0.assign(B + 1, 0);
@@ -1537,6 +1539,7 @@ int pdcs_problem_create(int64_t m, int64_t n, int64_t m_zero, const int64_t* row
     p->hp.build(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u);
     std::vector<const HostProblem*> v{&p->hp};
     p->eng = std::make_unique<Engine>(v);
+    p->eng->prepare_plain();
     *out = p.release();
     return PDCS_OK;
   });
@@ -1554,6 +1557,50 @@ int pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz) {
   });
 }
 
+// Unscaled values in the storage order of the current layout, for the plain
+// products: FP32 copies of the CSR / CSC values, and with band tiles the FP64
+// and FP32 values in band-entry order.  Made once per layout, so that the plain
+// products themselves allocate nothing.
+void Engine::prepare_plain() {
+  if (NNZ > 0 && !orig32.p) {
+    orig32.alloc((size_t)NNZ * 4);
+    origT32.alloc((size_t)NNZ * 4);
+    launch_to_f32(d_v.as<double>(), orig32.as<float>(), NNZ, stream);
+    launch_to_f32(d_vt.as<double>(), origT32.as<float>(), NNZ, stream);
+  }
+  if (use_band) {
+    for (int tr = 0; tr < 2; ++tr) {
+      BandSet& bs = tr ? band2 : band1;
+      if (bs.nent > 0 && !bs.orig64.p) {
+        bs.orig64.alloc((size_t)bs.nent * 8);
+        bs.orig32.alloc((size_t)bs.nent * 4);
+        launch_band_vals(bs.src.as<int32_t>(), bs.nent, tr ? d_vt.as<double>() : d_v.as<double>(),
+                         bs.orig64.as<double>(), bs.orig32.as<float>(), stream);
+      }
+    }
+  }
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(stream));
+}
+
+// One plain product with the unscaled values; `part` receives the band
+// layout's window partial sums (P x R values of the product's precision).
+static void plain_spmv(Engine& e, bool transpose, bool f32, const void* in_dev, void* out_dev, void* part,
+                       hipStream_t s) {
+  if (e.use_band) {
+    BandSet& bs = transpose ? e.band2 : e.band1;
+    if (bs.nent > 0 && !bs.orig64.p) throw Error(PDCS_ERR_STATE, "band values not prepared");
+    launch_band_plain(bs.view(), f32 ? kFP32 : kFP64, f32 ? bs.orig32.p : bs.orig64.p, in_dev, part, bs.R, out_dev, s);
+  } else if (!transpose) {
+    launch_spmv_plain(e.brow.view(), f32 ? kFP32 : kFP64, e.d_rp.as<int32_t>(), e.d_ci.as<int32_t>(),
+                      f32 ? e.orig32.p : e.d_v.p, in_dev, out_dev, s);
+  } else {
+    launch_spmv_plain(e.bcol.view(), f32 ? kFP32 : kFP64, e.d_cp.as<int32_t>(), e.d_ri.as<int32_t>(),
+                      f32 ? e.origT32.p : e.d_vt.p, in_dev, out_dev, s);
+  }
+  HIP_OK(hipGetLastError());
+}
+
 int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, const void* in_dev, void* out_dev,
                       void* stream) {
   return guarded([&]() {
@@ -1561,35 +1608,60 @@ int pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision, cons
     if (precision != PDCS_PRECISION_FP64 && precision != PDCS_PRECISION_MIXED)
       throw Error(PDCS_ERR_INVALID_ARG, "unknown precision");
     Engine& e = *p->eng;
-    hipStream_t s = (hipStream_t)stream;  // NULL: the HIP null stream
     const bool f32 = precision == PDCS_PRECISION_MIXED;
-    if (f32 && !e.orig32.p) {
-      std::vector<float> a(e.NNZ), at(e.NNZ);
-      for (int64_t q = 0; q < e.NNZ; ++q) {
-        a[q] = (float)p->hp.v[q];
-        at[q] = (float)p->hp.vt[q];
-      }
-      upload(e.orig32, a);
-      upload(e.origT32, at);
-    }
+    BandSet& bs = transpose ? e.band2 : e.band1;
+    plain_spmv(e, transpose != 0, f32, in_dev, out_dev, f32 ? bs.part32.p : bs.part64.p, (hipStream_t)stream);
+    return PDCS_OK;
+  });
+}
+
+// Scratch memory of pdcs_problem_spmv_noalloc: the band layout's window
+// partial sums.  A file-scope device array, one copy per GPU, held until the
+// process ends; every call on one GPU shares it.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];  // device address of `scratch`, per device
+
+// The device address of `scratch` on device `dev` (current), resolved once per
+// device: the array's name in host code is a host-side stand-in, not a device
+// address.
+static void* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Error(PDCS_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !ptr)
+      throw Error(PDCS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(err));
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+int pdcs_problem_spmv_noalloc(pdcs_problem p, int64_t transpose, int64_t precision, const void* in_dev,
+                              void* out_dev, void* stream) {
+  return guarded([&]() {
+    if (!p || !in_dev || !out_dev) throw Error(PDCS_ERR_INVALID_ARG, "null argument");
+    if (precision != PDCS_PRECISION_FP64 && precision != PDCS_PRECISION_MIXED)
+      throw Error(PDCS_ERR_INVALID_ARG, "unknown precision");
+    Engine& e = *p->eng;
+    int cur = -1;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != e.device) throw Error(PDCS_ERR_INVALID_ARG, "the problem's device is not the current device");
+    const bool f32 = precision == PDCS_PRECISION_MIXED;
+    void* part = nullptr;
     if (e.use_band) {
-      BandSet& bs = transpose ? e.band2 : e.band1;
-      if (!bs.orig64.p) {
-        bs.orig64.alloc((size_t)bs.nent * 8);
-        bs.orig32.alloc((size_t)bs.nent * 4);
-        launch_band_vals(bs.src.as<int32_t>(), bs.nent, transpose ? e.d_vt.as<double>() : e.d_v.as<double>(),
-                         bs.orig64.as<double>(), bs.orig32.as<float>(), s);
-      }
-      launch_band_plain(bs.view(), f32 ? kFP32 : kFP64, f32 ? bs.orig32.p : bs.orig64.p, in_dev,
-                        f32 ? bs.part32.p : bs.part64.p, bs.R, out_dev, s);
-    } else if (!transpose) {
-      launch_spmv_plain(e.brow.view(), f32 ? kFP32 : kFP64, e.d_rp.as<int32_t>(), e.d_ci.as<int32_t>(),
-                        f32 ? e.orig32.p : e.d_v.p, in_dev, out_dev, s);
-    } else {
-      launch_spmv_plain(e.bcol.view(), f32 ? kFP32 : kFP64, e.d_cp.as<int32_t>(), e.d_ri.as<int32_t>(),
-                        f32 ? e.origT32.p : e.d_vt.p, in_dev, out_dev, s);
+      const BandSet& bs = transpose ? e.band2 : e.band1;
+      const size_t need = (size_t)bs.P * (size_t)bs.R * (f32 ? 4 : 8);
+      if (need > kNoAllocScratchBytes)
+        throw Error(PDCS_ERR_SIZE, "window partial sums (" + std::to_string(need) + " B) exceed the " +
+                                       std::to_string(kNoAllocScratchBytes) + " B scratch array");
+      part = noalloc_scratch(cur);
     }
-    HIP_OK(hipGetLastError());
+    plain_spmv(e, transpose != 0, f32, in_dev, out_dev, part, (hipStream_t)stream);
     return PDCS_OK;
   });
 }
@@ -1601,6 +1673,7 @@ int pdcs_problem_set_layout(pdcs_problem p, int64_t layout) {
       throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
     p->eng->layout = (int)layout;
     p->eng->build_schedule();
+    p->eng->prepare_plain();
     return PDCS_OK;
   });
 }
@@ -1915,6 +1988,7 @@ int pdcs_problem_set_band_schedule(pdcs_problem p, int64_t rows, int64_t min_til
   return guarded([&]() {
     if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
     set_band_schedule(*p->eng, rows, min_tiles, entry_cap);
+    p->eng->prepare_plain();
     return PDCS_OK;
   });
 }

@@ -2210,6 +2210,15 @@ void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* 
   if (n > 0) k_band_vals<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, v64, o64, o32);
 }
 
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n > 0) k_to_f32<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, s>>>(in, out, n);
+}
+
 void launch_pack_warm(const void* const* src, const int32_t* off, int B, int64_t maxlen, int dtype, double* out,
                       int32_t* nan_flag, hipStream_t s) {
   if (B <= 0 || maxlen <= 0) return;

@@ -121,6 +121,8 @@ void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec);
 void launch_band_plain(const BandTiles& bt, int prec, const void* val, const void* in, void* part, int64_t R,
                        void* out, hipStream_t s);
 void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* o64, float* o32, hipStream_t s);
+// out[i] = (float)in[i], i < n
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // Warm starts from device pointers: out[off[b] + e] = src[b][e] (FP64 or FP32
 // source, dtype 0 / 1; a null src[b] gives zeros), e < off[b + 1] - off[b];
 // *nan_flag is set to 1 when a value is NaN.
