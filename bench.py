@@ -13,15 +13,25 @@ SpMV G x_hat with the dual step, line-search decision, SpMV G^T y_hat with the
 dual-slack pass, reflection parameter), then one restart check with its
 termination test.  The timed region is one solve call that runs exactly
 `steps` chunks from a cold start (rescaling included) on the HBM-resident
-problem; the warm-up is one such call of `warmup` chunks.
+problem, each chunk replayed as a hipGraph as in production; the warm-up is
+one such call of `warmup` chunks.  The dominant kernel's launch time comes
+from a second solve of the same length whose chunks are launched eagerly
+with HIP events around every G x_hat launch on the solver's stream.
 
 The method does not reach relative KKT 1e-6 on this instance within minutes
 (the FP64 oracle shows the same slow tail on the same family), so the figure
 reported is the hot path's algorithmic HBM throughput in GB/s: bytes the
 trials must move (per accepted trial 16 nnz + 76 n + 40 m in FP32, a rejected
 trial without the G^T y pass; restart checks counted as zero bytes) divided by
-the wall time of the steps.  Solves per second for the converging workloads
-are measured with --workload c2 | c3 | c4 (one JSON line each).
+the wall time of the steps.
+
+Solves per second at relative KKT 1e-6 are measured on the batched workload
+(512 LPs, m log-uniform in [1e3, 5e4], n = 2m, 8 nonzeros per column) in the
+same run and reported under config.solves: one batched mixed-precision solve,
+one batched FP64 solve, and a sample of unbatched FP64 solves extrapolated to
+the batch (labelled as such); the FP64 oracle's termination test re-checks a
+random sample of the returned (x, y).  --no-solves skips it.  The other
+workloads run alone with --workload c2 | c3 | c4 (one JSON line each).
 
 Prints one JSON line.
 """
@@ -144,6 +154,81 @@ def run_c2(args, P, np):
         "sum_nnz": int(sum(i.nnz for i in insts)), "optimal": int(ok), "trials_median": int(np.median(its)),
         "trials_max": int(its.max()), "schedule": list(sched), "fp64_batched": f64},
         {"roofline": roof, "cpu_baseline": cpu})
+
+
+def c2_solves(P, np, count=512, sample_single=8, check_oracle=4):
+    """Solves per second at relative KKT 1e-6 on the 512-LP batch: mixed
+    batched, FP64 batched, and unbatched FP64 (a sample of single solves,
+    extrapolated to the batch); the oracle's termination test on a sample of
+    the mixed answers."""
+    import lpgen
+    from oracle import pdcs_oracle as O
+
+    t = time.perf_counter()
+    insts = lpgen.c2_batch(count=count)
+    probs = [P.Problem.from_instance(i) for i in insts]
+    batch = P.Batch(probs)
+    t_setup = time.perf_counter() - t
+    log(f"solves: {len(insts)} LPs (sum nnz {sum(i.nnz for i in insts)}) generated and uploaded in {t_setup:.1f}s")
+    t = time.perf_counter()
+    sched = batch.autotune(2000.0)
+    t_tune = time.perf_counter() - t
+    out = {"workload": f"{len(insts)} LPs m~logU[1e3,5e4], n=2m, 8 nnz/col, rel. KKT 1e-6",
+           "sum_nnz": int(sum(i.nnz for i in insts)), "autotune_s": round(t_tune, 2),
+           "schedule": list(sched), "band_schedule": batch.band_schedule()}
+    res = {}
+    for prec in ("mixed", "fp64"):
+        torch_sync()
+        t0 = time.perf_counter()
+        sols = batch.solve(precision=prec, time_limit=300.0)
+        wall = time.perf_counter() - t0
+        its = np.array([s.info["iters"] for s in sols])
+        f64_its = np.array([s.info["fp64_iters"] for s in sols])
+        res[prec] = sols
+        out[f"batched_{prec}"] = {
+            "solves_per_s": round(len(insts) / wall, 3), "seconds": round(wall, 2),
+            "optimal": int(sum(s.info["exit_code"] == 0 for s in sols)),
+            "trials_median": int(np.median(its)), "trials_max": int(its.max()),
+            "fp64_trial_fraction": round(float(f64_its.sum()) / max(float(its.sum()), 1.0), 4)}
+        log(f"solves: batched {prec}: {wall:.2f}s, {out[f'batched_{prec}']['optimal']} optimal")
+    obj = [abs(a.info["pobj"] - b.info["pobj"]) / (1 + abs(b.info["pobj"])) for a, b in zip(res["mixed"], res["fp64"])]
+    out["obj_rel_diff_mixed_vs_fp64_max"] = float(max(obj))
+    # unbatched plain FP64: single-problem solves of a random sample
+    rng = np.random.default_rng(1)
+    pick = rng.choice(len(insts), size=min(sample_single, len(insts)), replace=False)
+    secs, ok = [], 0
+    for i in pick:
+        torch_sync()
+        t0 = time.perf_counter()
+        s1 = probs[i].solve(precision="fp64", time_limit=300.0)
+        secs.append(time.perf_counter() - t0)
+        ok += int(s1.info["exit_code"] == 0)
+    est = float(np.mean(secs)) * len(insts)
+    out["unbatched_fp64"] = {"solves_per_s": round(len(insts) / est, 3), "optimal_in_sample": ok,
+                             "note": (f"extrapolated: {len(pick)} single-problem FP64 solves of random members, "
+                                      f"mean {np.mean(secs):.3f}s each, times {len(insts)}")}
+    out["speedup_mixed_batched_vs_unbatched_fp64"] = round(out["batched_mixed"]["solves_per_s"] /
+                                                           out["unbatched_fp64"]["solves_per_s"], 2)
+    # the oracle's termination test on a sample of the mixed answers
+    chk = rng.choice(len(insts), size=min(check_oracle, len(insts)), replace=False)
+    worst = 0.0
+    for i in chk:
+        s = res["mixed"][i]
+        e = O.termination_errors(O.lpdata_from_instance(insts[i]), s.x, s.y)
+        worst = max(worst, e["rel_p"], e["rel_d"], e["rel_gap"])
+    out["oracle_rel_kkt_max_of_sample"] = worst
+    out["oracle_sample"] = [int(i) for i in chk]
+    log(f"solves: unbatched FP64 {out['unbatched_fp64']['solves_per_s']} solves/s (extrapolated); "
+        f"oracle rel KKT on {len(chk)} answers <= {worst:.2e}")
+    for p in probs:
+        p.close()
+    return out
+
+
+def torch_sync():
+    import torch
+
+    torch.cuda.synchronize()
 
 
 def run_c4(args, P, np):
@@ -400,8 +485,10 @@ def main():
     ap.add_argument("--cpu-trials", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and plain-SpMV side measurements")
-    ap.add_argument("--graph-replay", action="store_true",
-                    help="c1: replay chunks as hipGraphs in the timed region (kernel events from a separate solve)")
+    ap.add_argument("--eager", action="store_true",
+                    help="c1: launch the timed chunks eagerly with kernel events (default: hipGraph replay, "
+                         "kernel events from a second solve)")
+    ap.add_argument("--no-solves", action="store_true", help="c1: skip the batched solves/s record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build solves on one GPU only (the multi-GPU sharding is a design note); "
@@ -437,12 +524,11 @@ def main():
     if args.warmup > 0:
         w = prob.solve(max_iter=args.warmup * CHUNK, **base)
         log(f"warmup: {w.info['iters']} trials in {w.info['time_sec']:.3f}s")
-    # The timed region launches its chunks eagerly with HIP events around every
-    # G x_hat launch on the solver's stream (time_kernels), so the dominant
-    # kernel's duration comes from the timed steps themselves;
-    # --graph-replay times hipGraph-replayed chunks instead (events then come
-    # from a separate solve).
-    timed_opts = dict(base, time_kernels=0 if args.graph_replay else 1)
+    # The timed region replays each chunk as a hipGraph (the production path);
+    # the dominant kernel's launch time comes from a second solve of the same
+    # length with eager launches and HIP events around every G x_hat launch on
+    # the solver's stream.  --eager times that event-instrumented solve instead.
+    timed_opts = dict(base, time_kernels=1 if args.eager else 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sol = prob.solve(max_iter=args.steps * CHUNK, **timed_opts)
@@ -457,14 +543,16 @@ def main():
     value = path_bytes / wall / 1e9
 
     # dominant kernel: the band SpMV G x_hat, event-timed launch by launch on the solver's stream
-    kt = sol if not args.graph_replay else prob.solve(max_iter=16 * CHUNK, time_kernels=1, **base)
+    kt = sol if args.eager else prob.solve(max_iter=args.steps * CHUNK, **dict(base, time_kernels=1))
     ms = kt.info["spmv_avg_ms"]
     per_launch = spmv_bytes(m, n, nnz, 4)
     achieved = per_launch / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(),
             "kernel": "k_band_spmv<float> (G x_hat, band tiles)", "avg_launch_ms": round(ms, 5),
-            "algorithmic_bytes_per_launch": int(per_launch), "launches_timed": int(kt.info["spmv_launches"])}
+            "algorithmic_bytes_per_launch": int(per_launch), "launches_timed": int(kt.info["spmv_launches"]),
+            "timing": ("HIP events around each launch in the timed solve" if args.eager else
+                       "HIP events around each launch in an eager solve of the same length after the timed one")}
     log(f"k_band_spmv<float>: {ms:.4f} ms per launch, {achieved:.0f} GB/s")
 
     extras = {}
@@ -474,6 +562,9 @@ def main():
         extras["fp64_trials_per_s"] = round(f64_tps, 1)
         extras["plain_spmv"] = plain_spmv(prob, inst, torch)
         log(f"fp64: {f64_tps:.0f} trials/s; plain SpMV {extras['plain_spmv']['gbs']} GB/s")
+
+    if not args.no_solves:
+        extras["solves"] = c2_solves(P, np)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -498,7 +589,7 @@ def main():
             "workload": desc,
             "m": m, "n": n, "nnz": nnz,
             "step": "64 trials + 1 restart/termination check",
-            "timed_region": "hipGraph replay" if args.graph_replay else "eager launches, HIP events around G x_hat",
+            "timed_region": "eager launches, HIP events around G x_hat" if args.eager else "hipGraph replay",
             "trials": int(info["iters"]), "accepted": int(acc),
             "trials_per_s": round(info["iters"] / wall, 1),
             "rel_kkt_at_end": max(info["rel_p"], info["rel_d"], info["rel_gap"]),
