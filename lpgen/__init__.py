@@ -263,6 +263,30 @@ def dense_runs_instance(seed: int = 0, m: int = 256, run: int = 64, coupling: in
                       name=f"dense_runs_{seed}", x_planted=x0)
 
 
+
+def dense_columns_instance(seed: int = 0, m: int = 5000, n: int = 600_000, per_col: int = 2,
+                           dense: int = 3) -> LPInstance:
+    """Edge-case LP for chunked layouts: ``per_col`` uniform random rows per
+    column over more than 2^18 columns (several gathered-index windows), plus
+    ``dense`` columns spread over the index range that hold an entry in every
+    row (thousands of entries of one gathered index within one band).  Values
+    N(0,1), planted as in ``planted_lp``."""
+    rng = rng_for(91, seed)
+    row_a, col_a = _distinct_rows_per_column(rng, m, n, per_col)
+    dcols = np.linspace(n // (2 * dense), n - 1 - n // (2 * dense), dense).astype(np.int64)
+    row_b = np.tile(np.arange(m, dtype=np.int64), dense)
+    col_b = np.repeat(dcols, m)
+    keep = ~np.isin(col_a, dcols)
+    row = np.concatenate([row_a[keep], row_b])
+    col = np.concatenate([col_a[keep], col_b])
+    val = rng.standard_normal(row.size)
+    row_ptr, col_idx, val = csr_from_columns(m, n, row, col, val)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    h = _csr_matvec(row_ptr, col_idx, val, x0)
+    c = rng.uniform(0.0, 1.0, size=n)
+    return LPInstance(m, n, m, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, 10.0),
+                      name=f"dense_columns_{seed}", x_planted=x0)
+
 # ---------------------------------------------------------------------------
 # Infeasible and unbounded variants of the C0 recipe (tests of exit codes 2-5).
 # Each takes a planted feasible LP and adds or changes data so that no

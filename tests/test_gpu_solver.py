@@ -314,7 +314,7 @@ def test_band_layout_solves_dense_runs():
     _check_solution(inst, sol, ref.pobj)
 
 
-@pytest.mark.parametrize("maker", ["c1", "dense_runs", "c1_wide"])
+@pytest.mark.parametrize("maker", ["c1", "dense_runs", "c1_wide", "dense_cols"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_band_layout_spmv_elementwise(maker, precision):
     # The band SpMV itself, both directions, against scipy.  Each row is summed
@@ -326,6 +326,8 @@ def test_band_layout_spmv_elementwise(maker, precision):
         inst = lpgen.c1_instance(3, m=5000, n=10000)
     elif maker == "c1_wide":      # more than 2^18 gathered columns: several windows
         inst = lpgen.c1_instance(4, m=20000, n=600000, max_len=400)
+    elif maker == "dense_cols":   # one gathered index with more entries per band than a chunk holds
+        inst = lpgen.dense_columns_instance(0)
     else:
         inst = lpgen.dense_runs_instance(2)
     A = inst.scipy_csr()
@@ -404,3 +406,4 @@ def test_restart_variants_first_check_matches_oracle(variant):
     assert st["chosen"] == (0 if c["chosen"] == "cur" else 1)
     assert sol.info["restarts"] == ref.restarts
     assert st["omega"] == pytest.approx(ref.state["omega"], rel=1e-9)
+
