@@ -56,6 +56,7 @@ class LPInstance:
     name: str = "lp"
     x_planted: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    soc: tuple = ()  # dimensions of second-order-cone row blocks (the last rows)
 
     @property
     def nnz(self) -> int:
@@ -286,6 +287,34 @@ def dense_columns_instance(seed: int = 0, m: int = 5000, n: int = 600_000, per_c
     c = rng.uniform(0.0, 1.0, size=n)
     return LPInstance(m, n, m, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, 10.0),
                       name=f"dense_columns_{seed}", x_planted=x0)
+
+
+def soc_instance(seed: int = 0, m_zero: int = 60, n: int = 300, blocks=(3, 5, 8, 16, 40), per_col: int = 3,
+                 upper: float = 10.0) -> LPInstance:
+    """Conic variant of the C0 recipe with second-order-cone rows (the socG
+    option): ``m_zero`` equality rows followed by one block per entry of
+    ``blocks``, (G x - h)_block = (t, w) with ||w|| <= t.  Each column gets
+    ``per_col`` distinct uniform rows over all rows, values N(0,1); x0 ~ U[0,5]
+    is planted strictly feasible: h = G x0 on the equality rows and
+    h = G x0 - s0 on a block, with s0 = (||w|| + 1 + |N(0,1)|, w), w ~ N(0, I);
+    c ~ U[0,1]; 0 <= x <= upper."""
+    rng = rng_for(92, seed)
+    blocks = tuple(int(d) for d in blocks)
+    m = m_zero + sum(blocks)
+    row, col = _distinct_rows_per_column(rng, m, n, per_col)
+    val = rng.standard_normal(row.size)
+    row_ptr, col_idx, val = csr_from_columns(m, n, row, col, val)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    h = _csr_matvec(row_ptr, col_idx, val, x0)
+    r = m_zero
+    for d in blocks:
+        w = rng.standard_normal(d - 1)
+        s0 = np.concatenate([[np.linalg.norm(w) + 1.0 + abs(rng.standard_normal())], w])
+        h[r:r + d] -= s0
+        r += d
+    c = rng.uniform(0.0, 1.0, size=n)
+    return LPInstance(m, n, m_zero, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, upper),
+                      name=f"soc_{seed}", x_planted=x0, soc=blocks)
 
 # ---------------------------------------------------------------------------
 # Infeasible and unbounded variants of the C0 recipe (tests of exit codes 2-5).

@@ -9,10 +9,14 @@ in ``lpgen``.
 What it computes (paper: "A Technical Note on the Implementation and Use of
 PDCS", arXiv 2603.15504):
 
-* the LP restriction of the conic problem of Section 1.1 (eq. prob_cp): every
-  variable is box-bounded (n2 = 0), rows are zero-cone (equality) rows followed
-  by nonnegative-cone (>=) rows, so K_d* = {0}^m_zero x R+^m_nonneg and
-  K_d = R^m_zero x R+^m_nonneg;
+* the conic problem of Section 1.1 (eq. prob_cp) with every variable
+  box-bounded (n2 = 0) and row cones in the paper's order: zero-cone
+  (equality) rows, nonnegative-cone (>=) rows, then second-order-cone blocks
+  (the socG option of Section 3), so K_d* = {0}^m_zero x R+^m_nonneg x K_soc x
+  ... and K_d = R^m_zero x R+^m_nonneg x K_soc x ... (the second-order cone is
+  self-dual); after diagonal rescaling the blocks become rescaled cones
+  (Section 2.6), projected onto by a one-dimensional root find
+  (``proj_scaled_soc``);
 * Algorithm "PDCS with preconditioning" (Section 2.6): diagonal rescaling, the
   PDCS loop of Algorithm 1 (Section 2) on the rescaled data, then unscaling;
 * inside it: OnePDHG (eq. PDHG, Section 1.2), AdaptiveStepPDHG (Function 2,
@@ -68,7 +72,14 @@ EXIT_NUMERICAL_ERROR = 8
 # --------------------------------------------------------------------------
 @dataclass
 class LPData:
-    """min c^T x  s.t.  Gx - h in K_d*,  l <= x <= u   (eq. prob_cp, LP case)."""
+    """min c^T x  s.t.  Gx - h in K_d*,  l <= x <= u   (eq. prob_cp, boxed variables).
+
+    Rows: m_zero zero-cone rows, then nonnegative-cone rows, then the
+    second-order-cone blocks of dimensions ``soc`` (each block (t, w) with
+    ||w|| <= t).  ``cone_scale`` (None = all ones) holds positive row factors e
+    of rescaled data: its K_d* blocks are diag(e) K_soc and its K_d blocks
+    diag(1/e) K_soc (the cones of Gx - h and y after rows are multiplied by e,
+    Section 2.6)."""
 
     G: sp.csr_matrix
     h: np.ndarray
@@ -76,6 +87,8 @@ class LPData:
     l: np.ndarray
     u: np.ndarray
     m_zero: int
+    soc: tuple = ()
+    cone_scale: np.ndarray | None = None
 
     @property
     def m(self) -> int:
@@ -85,17 +98,26 @@ class LPData:
     def n(self) -> int:
         return self.G.shape[1]
 
+    def proj_Kd(self, y):
+        return proj_Kd(y, self.m_zero, self.soc, self.cone_scale)
 
-def lpdata_from_arrays(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u) -> LPData:
+    def proj_Kd_star(self, v):
+        return proj_Kd_star(v, self.m_zero, self.soc, self.cone_scale)
+
+
+def lpdata_from_arrays(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u, soc=()) -> LPData:
     G = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col_idx), np.asarray(row_ptr)),
                       shape=(int(m), int(n)))
+    soc = tuple(int(d) for d in soc)
+    if any(d < 1 for d in soc) or int(m_zero) + sum(soc) > int(m):
+        raise ValueError("second-order-cone blocks must have dimension >= 1 and fit after the zero rows")
     return LPData(G, np.asarray(h, np.float64), np.asarray(c, np.float64),
-                  np.asarray(l, np.float64), np.asarray(u, np.float64), int(m_zero))
+                  np.asarray(l, np.float64), np.asarray(u, np.float64), int(m_zero), soc)
 
 
 def lpdata_from_instance(inst) -> LPData:
     return lpdata_from_arrays(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx,
-                              inst.val, inst.h, inst.c, inst.l, inst.u)
+                              inst.val, inst.h, inst.c, inst.l, inst.u, getattr(inst, "soc", ()))
 
 
 # --------------------------------------------------------------------------
@@ -106,18 +128,97 @@ def proj_box(x, l, u):
     return np.minimum(np.maximum(x, l), u)
 
 
-def proj_Kd(y, m_zero):
-    """Projection onto K_d = R^m_zero x R+^m_nonneg (dual variables of the rows)."""
-    out = np.array(y, dtype=np.float64, copy=True)
-    out[m_zero:] = np.maximum(out[m_zero:], 0.0)
+def proj_soc(v):
+    """Projection onto the second-order cone {(t, w): ||w|| <= t} (closed form)."""
+    v = np.asarray(v, dtype=np.float64)
+    t, w = v[0], v[1:]
+    nw = float(np.linalg.norm(w))
+    if nw <= t:
+        return v.copy()
+    if nw <= -t:
+        return np.zeros_like(v)
+    a = 0.5 * (t + nw)
+    return np.concatenate([[a], (a / nw) * w])
+
+
+def proj_scaled_soc(v, e):
+    """Projection onto the rescaled cone E K_soc = {E z : z in K_soc}, E = diag(e) > 0
+    (Section 2.6: after diagonal rescaling the projection is a root find).
+
+    Derivation (KKT conditions of min ||p - v||^2 s.t. ||p_bar / e_bar|| <= p0 / e0):
+    v itself if it lies in the cone; 0 if v lies in the polar cone -E^{-1} K_soc
+    (||v_bar * e_bar|| <= -v0 e0); otherwise the constraint is active with
+    multiplier mu > 0, s = p0 / e0 = v0 / e0 + mu / e0^2 and
+    p_i = v_i e_i^2 s / (e_i^2 s + mu), where mu is the root of
+        f(mu) = sum_i v_i^2 e_i^2 / (e_i^2 s(mu) + mu)^2 - 1,
+    strictly decreasing on mu > max(0, -v0 e0), positive at that left end and
+    non-positive at mu = ||v_bar * e_bar||.  The root is found by bisection to
+    the resolution of the floating-point numbers.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    v0, vb = float(v[0]), v[1:]
+    e0, eb = float(e[0]), e[1:]
+    if float(np.linalg.norm(vb / eb)) <= v0 / e0:
+        return v.copy()
+    if float(np.linalg.norm(vb * eb)) <= -v0 * e0:
+        return np.zeros_like(v)
+    q = vb * vb * eb * eb
+    e2 = eb * eb
+
+    def f(mu):
+        s = v0 / e0 + mu / (e0 * e0)
+        return float(np.sum(q / (e2 * s + mu) ** 2)) - 1.0
+
+    lo = max(0.0, -v0 * e0)
+    hi = max(lo, float(np.linalg.norm(vb * eb)))
+    while f(hi) > 0.0:  # only by rounding at the right end
+        hi = 2.0 * hi + 1e-300
+    for _ in range(2000):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if f(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    mu = 0.5 * (lo + hi)
+    s = v0 / e0 + mu / (e0 * e0)
+    return np.concatenate([[e0 * s], vb * e2 * s / (e2 * s + mu)])
+
+
+def _soc_blocks(m, soc):
+    """(start, end) row ranges of the second-order-cone blocks (the last rows)."""
+    r = m - sum(soc)
+    out = []
+    for d in soc:
+        out.append((r, r + d))
+        r += d
     return out
 
 
-def proj_Kd_star(v, m_zero):
-    """Projection onto K_d* = {0}^m_zero x R+^m_nonneg."""
+def proj_Kd(y, m_zero, soc=(), scale=None):
+    """Projection onto K_d = R^m_zero x R+^m_nonneg x K_soc x ... (dual variables of
+    the rows); with row factors ``scale`` the blocks are diag(1/scale) K_soc."""
+    out = np.array(y, dtype=np.float64, copy=True)
+    m = out.size
+    m_cone = m - sum(soc)
+    out[m_zero:m_cone] = np.maximum(out[m_zero:m_cone], 0.0)
+    for a, b in _soc_blocks(m, soc):
+        out[a:b] = proj_soc(out[a:b]) if scale is None else proj_scaled_soc(out[a:b], 1.0 / scale[a:b])
+    return out
+
+
+def proj_Kd_star(v, m_zero, soc=(), scale=None):
+    """Projection onto K_d* = {0}^m_zero x R+^m_nonneg x K_soc x ...; with row factors
+    ``scale`` the blocks are diag(scale) K_soc."""
     out = np.array(v, dtype=np.float64, copy=True)
+    m = out.size
+    m_cone = m - sum(soc)
     out[:m_zero] = 0.0
-    out[m_zero:] = np.maximum(out[m_zero:], 0.0)
+    out[m_zero:m_cone] = np.maximum(out[m_zero:m_cone], 0.0)
+    for a, b in _soc_blocks(m, soc):
+        out[a:b] = proj_soc(out[a:b]) if scale is None else proj_scaled_soc(out[a:b], scale[a:b])
     return out
 
 
@@ -180,9 +281,12 @@ def ruiz_l2_scaling(G: sp.csr_matrix, ruiz_iters: int = 10, l2_pass: bool = True
 
 
 def rescale(lp: LPData, D1, D2) -> LPData:
-    """Rescaled data of eq. rescaled_prob: G^=D1 G D2, c^=D2 c, h^=D1 h, l^=l/D2, u^=u/D2."""
+    """Rescaled data of eq. rescaled_prob: G^=D1 G D2, c^=D2 c, h^=D1 h, l^=l/D2, u^=u/D2;
+    the row cones become diag(D1) K_d* (and diag(1/D1) K_d for y)."""
     Gs = (sp.diags(D1) @ lp.G @ sp.diags(D2)).tocsr()
-    return LPData(Gs, D1 * lp.h, D2 * lp.c, lp.l / D2, lp.u / D2, lp.m_zero)
+    scale = D1 if lp.cone_scale is None else lp.cone_scale * D1
+    return LPData(Gs, D1 * lp.h, D2 * lp.c, lp.l / D2, lp.u / D2, lp.m_zero, lp.soc,
+                  np.asarray(scale, np.float64) if lp.soc else None)
 
 
 # --------------------------------------------------------------------------
@@ -190,7 +294,7 @@ def rescale(lp: LPData, D1, D2) -> LPData:
 # --------------------------------------------------------------------------
 def one_pdhg(lp: LPData, x, y, tau, sigma):
     xh = proj_box(x - tau * (lp.c - lp.G.T @ y), lp.l, lp.u)
-    yh = proj_Kd(y + sigma * (lp.h - lp.G @ (2.0 * xh - x)), lp.m_zero)
+    yh = lp.proj_Kd(y + sigma * (lp.h - lp.G @ (2.0 * xh - x)))
     return xh, yh
 
 
@@ -216,7 +320,7 @@ def abs_errors_l2(lp: LPData, x, y):
     Returns (err_p, err_d, err_gap, pobj, dobj).
     """
     r = lp.G @ x - lp.h
-    err_p = float(np.linalg.norm(r - proj_Kd_star(r, lp.m_zero)))
+    err_p = float(np.linalg.norm(r - lp.proj_Kd_star(r)))
     lam = lp.c - lp.G.T @ y
     err_d = float(np.linalg.norm(lam - proj_Lambda(lam, lp.l, lp.u)))
     pobj = float(np.dot(lp.c, x))
@@ -260,7 +364,7 @@ def termination_errors(lp: LPData, x, y):
     """
     Gx = lp.G @ x
     r = Gx - lp.h
-    pr = proj_Kd_star(r, lp.m_zero)
+    pr = lp.proj_Kd_star(r)
     abs_p = float(np.max(np.abs(r - pr), initial=0.0))
     GTy = lp.G.T @ y
     lam = lp.c - GTy
@@ -346,7 +450,7 @@ def infeasibility_ratios(lp: LPData, ray_x, ray_y):
     nterm = sum(t.size for t in terms)
     ratio_p = num_p / f if f > rounding_bound(nterm) * mag else math.inf
     r = lp.G @ ray_x
-    num_d = float(np.linalg.norm(r - proj_Kd_star(r, lp.m_zero)))
+    num_d = float(np.linalg.norm(r - lp.proj_Kd_star(r)))
     cx = lp.c * ray_x
     g = -float(np.sum(cx))
     ratio_d = num_d / g if g > rounding_bound(cx.size) * float(np.sum(np.abs(cx))) else math.inf
@@ -454,7 +558,7 @@ def adaptive_step_pdhg(lp: LPData, x, y, omega, eta, kbar, trace=None, max_kbar=
 # --------------------------------------------------------------------------
 def z_of_t(lp: LPData, x, y, b1, b2, tau, sigma, t):
     """z(t) of eq. compute_zt_2: (Proj_X(x + t tau b1), Proj_Y(y + t sigma b2))."""
-    return proj_box(x + t * tau * b1, lp.l, lp.u), proj_Kd(y + t * sigma * b2, lp.m_zero)
+    return proj_box(x + t * tau * b1, lp.l, lp.u), lp.proj_Kd(y + t * sigma * b2)
 
 
 def n_norm(dx, dy, tau, sigma):
@@ -675,7 +779,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
     xs = np.zeros(n) if x0 is None else np.asarray(x0, np.float64) / D2
     ys = np.zeros(m) if y0 is None else np.asarray(y0, np.float64) / D1
     x = proj_box(xs, sl.l, sl.u)
-    y = proj_Kd(ys, sl.m_zero)
+    y = sl.proj_Kd(ys)
     x_start, y_start = x.copy(), y.copy()
 
     gmax = float(np.max(np.abs(sl.G.data), initial=0.0))
@@ -789,7 +893,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
                 return finish(EXIT_OPTIMAL, cx, cy)
             if monitor.enabled:
                 ray_x = proj_box_recession(D2 * (xh - x_start), lp.l, lp.u)
-                ray_y = proj_Kd(D1 * (yh - y_start), lp.m_zero)
+                ray_y = lp.proj_Kd(D1 * (yh - y_start))
                 ratio_p, ratio_d = infeasibility_ratios(lp, ray_x, ray_y)
                 e_h = termination_errors(lp, D2 * xh, D1 * yh)
                 code = monitor.update(ratio_p, ratio_d, e_h["pobj"], e_h["dobj"])
