@@ -1,13 +1,16 @@
 /*
  * pdcs.h -- C ABI of the MI355X (gfx950) PDCS linear-programming solver.
  *
- * Problem solved (Section 1.1, eq. prob_cp, restricted to linear programs):
+ * Problem solved (Section 1.1, eq. prob_cp, with box-bounded variables):
  *
  *     min  c^T x   s.t.  (G x - h)_i  = 0   for i <  m_zero      (zero cone)
- *                        (G x - h)_i >= 0   for i >= m_zero      (nonnegative cone)
+ *                        (G x - h)_i >= 0   for the next rows     (nonnegative cone)
+ *                        (G x - h)_B in K_soc for each second-order-cone block B
+ *                                           of the last rows (pdcs_problem_create_conic)
  *                        l <= x <= u                            (box, +-inf allowed)
  *
- * with its dual (eq. dual_conic): max h^T y + l^T lam+ - u^T lam-, lam = c - G^T y.
+ * with its dual (eq. dual_conic): max h^T y + l^T lam+ - u^T lam-, lam = c - G^T y,
+ * y in K_d = R^m_zero x R+^... x K_soc x ... (the second-order cone is self-dual).
  * The method is "PDCS with preconditioning" (Section 2.6): diagonal rescaling,
  * then the restarted, line-searched, reflected-Halpern PDHG loop of Algorithm 1
  * (Function 2 for the step size, Section 2.2 for the reflection parameter,
@@ -42,7 +45,7 @@ extern "C" {
 /* ---- error codes ------------------------------------------------------- */
 #define PDCS_OK               0
 #define PDCS_ERR_INVALID_ARG (-1)  /* null pointer, malformed CSR, NaN, l > u, bad sizes */
-#define PDCS_ERR_UNSUPPORTED (-2)  /* cone types other than zero / nonnegative rows     */
+#define PDCS_ERR_UNSUPPORTED (-2)  /* a request this library does not implement        */
 #define PDCS_ERR_OOM         (-3)  /* device or host allocation failed                  */
 #define PDCS_ERR_HIP         (-4)  /* a HIP runtime call failed                          */
 #define PDCS_ERR_SIZE        (-5)  /* problem too large for 32-bit device indexing       */
@@ -197,6 +200,22 @@ int  pdcs_problem_create(int64_t m, int64_t n, int64_t m_zero,
                          const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                          const double* h, const double* c, const double* l, const double* u,
                          pdcs_problem* out);
+/* pdcs_problem_create_conic: as pdcs_problem_create, with second-order-cone
+ * row blocks (the socG option of Section 3): after the m_zero zero-cone rows
+ * and the nonnegative-cone rows come n_soc blocks, block q holding the next
+ * soc_dims[q] rows, with (G x - h)_block = (t, w) in K_soc = {||w|| <= t}
+ * (Section 1.1, eq. prob_cp); the dual rows y_block lie in K_soc too (the cone
+ * is self-dual).  After the diagonal rescaling a block's cones are
+ * diag(D1) K_soc and diag(1/D1) K_soc, projected onto by a one-dimensional
+ * root find (Section 2.6).  soc_dims is a host array of n_soc dimensions >= 1
+ * with m_zero + sum(soc_dims) <= m, copied.  Problems with cone blocks always
+ * take the band layout.  Errors: PDCS_ERR_INVALID_ARG as pdcs_problem_create,
+ * and for a bad block list. */
+int  pdcs_problem_create_conic(int64_t m, int64_t n, int64_t m_zero, int64_t n_soc,
+                               const int64_t* soc_dims, const int64_t* row_ptr,
+                               const int32_t* col_idx, const double* val,
+                               const double* h, const double* c, const double* l,
+                               const double* u, pdcs_problem* out);
 void pdcs_problem_destroy(pdcs_problem p);
 int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
 

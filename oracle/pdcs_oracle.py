@@ -152,8 +152,9 @@ def proj_scaled_soc(v, e):
     p_i = v_i e_i^2 s / (e_i^2 s + mu), where mu is the root of
         f(mu) = sum_i v_i^2 e_i^2 / (e_i^2 s(mu) + mu)^2 - 1,
     strictly decreasing on mu > max(0, -v0 e0), positive at that left end and
-    non-positive at mu = ||v_bar * e_bar||.  The root is found by bisection to
-    the resolution of the floating-point numbers.
+    non-positive at mu = ||v_bar * e_bar||.  The root is found by bisection
+    until the bracket is narrower than 2^-52 of its right end (the resolution
+    of a float64 mu).
     """
     v = np.asarray(v, dtype=np.float64)
     e = np.asarray(e, dtype=np.float64)
@@ -176,7 +177,7 @@ def proj_scaled_soc(v, e):
         hi = 2.0 * hi + 1e-300
     for _ in range(2000):
         mid = 0.5 * (lo + hi)
-        if mid <= lo or mid >= hi:
+        if mid <= lo or mid >= hi or hi - lo <= 2.0 ** -52 * hi:
             break
         if f(mid) > 0.0:
             lo = mid

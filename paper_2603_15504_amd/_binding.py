@@ -77,6 +77,7 @@ PROTOTYPES = {
     "pdcs_last_error": (C.c_char_p, []),
     "pdcs_device_count": (C.c_int, []),
     "pdcs_problem_create": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+    "pdcs_problem_create_conic": (C.c_int, [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
     "pdcs_problem_destroy": (None, [_P]),
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
@@ -211,6 +212,23 @@ def pdcs_problem_create(m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=Non
     _check(lib.pdcs_problem_create(int(m), int(n), int(m_zero), _ptr(row_ptr), _ptr(col_idx), _ptr(val),
                                    _ptr(h), _ptr(c), _ptr(l), _ptr(u), C.byref(out)),
            "pdcs_problem_create")
+    return out
+
+
+def pdcs_problem_create_conic(m, n, m_zero, soc_dims, row_ptr, col_idx, val, h, c, l=None, u=None) -> C.c_void_p:
+    soc = np.ascontiguousarray(np.asarray(soc_dims, dtype=np.int64).reshape(-1))
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    val = _f64(val)
+    h = _f64(h, m) if m > 0 else np.zeros(1)
+    c = _f64(c, n)
+    l = _f64(l, n)
+    u = _f64(u, n)
+    out = C.c_void_p()
+    _check(lib.pdcs_problem_create_conic(int(m), int(n), int(m_zero), int(soc.size), _ptr(soc) if soc.size else None,
+                                         _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(h), _ptr(c), _ptr(l),
+                                         _ptr(u), C.byref(out)),
+           "pdcs_problem_create_conic")
     return out
 
 
@@ -469,14 +487,18 @@ def _info_dict(info: pdcs_info) -> dict:
 class Problem:
     """An LP uploaded to the GPU (pdcs_problem)."""
 
-    def __init__(self, m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=None):
+    def __init__(self, m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=None, soc=()):
+        """soc: dimensions of second-order-cone row blocks (the last rows)."""
         self.m, self.n = int(m), int(n)
-        self.handle = pdcs_problem_create(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u)
+        if len(soc):
+            self.handle = pdcs_problem_create_conic(m, n, m_zero, soc, row_ptr, col_idx, val, h, c, l, u)
+        else:
+            self.handle = pdcs_problem_create(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u)
 
     @classmethod
     def from_instance(cls, inst):
         return cls(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx, inst.val, inst.h, inst.c,
-                   inst.l, inst.u)
+                   inst.l, inst.u, getattr(inst, "soc", ()))
 
     def solve(self, x0=None, y0=None, with_scaling=False, device_out=False, **opts) -> Solution:
         """Host warm start (arrays) or, for torch tensors on the GPU, the device

@@ -74,7 +74,9 @@ struct Inst {
   double ratio_p, ratio_d;  // ratios of the last check (NaN: not evaluated)
   double prev_dobj, prev_negp;  // dual objective and -(primal objective) of z_hat at the previous check
   int32_t infeas_on, ray_due, trend_p, trend_d;
-  int32_t has_prev_obj, stop_max_iter, pad_inf0, pad_inf1;
+  int32_t has_prev_obj, stop_max_iter;
+  int32_t soc_start;        // first second-order-cone row (row0 + rows when none)
+  int32_t pad_inf1;
   double* trace;            // per-trial scalars of the first trace_cap trials (or null)
   int64_t trace_cap;
 };
@@ -145,11 +147,18 @@ struct BandTiles {
 };
 
 // Schedule of an elementwise pass: contiguous element ranges per workgroup.
+// Row ranges never split a second-order-cone block: the blocks inside range b
+// are [blk_soc0[b], blk_soc1[b]) of the table (soc_r0: first row, soc_dim:
+// dimension); all four are null when no instance has such blocks.
 struct Ranges {
   const int32_t* blk_start;
   const int32_t* blk_end;
   const int32_t* blk_inst;
   const int32_t* inst_blk0;    // per instance: first workgroup (B+1 entries)
+  const int32_t* blk_soc0;
+  const int32_t* blk_soc1;
+  const int32_t* soc_r0;
+  const int32_t* soc_dim;
   int32_t nblk;
 };
 

@@ -50,8 +50,10 @@ struct HostProblem {
   int64_t m = 0, n = 0, m_zero = 0, nnz = 0;
   std::vector<int32_t> rp, ci, cp, ri;
   std::vector<double> v, vt, h, c, l, u;
+  std::vector<int32_t> soc;  // second-order-cone block dimensions (the last rows)
   void build(int64_t m, int64_t n, int64_t mz, const int64_t* row_ptr, const int32_t* col_idx,
-             const double* val, const double* h, const double* c, const double* l, const double* u);
+             const double* val, const double* h, const double* c, const double* l, const double* u,
+             int64_t n_soc = 0, const int64_t* soc_dims = nullptr);
 };
 
 // Tile schedule parameters (chosen by pdcs_batch_autotune or set explicitly).
@@ -82,9 +84,18 @@ struct RowBlockSet {
   RowBlocks view() const;
 };
 
+// Second-order-cone row blocks of all instances: first (absolute) row and
+// dimension of each block, in row order.
+struct SocTable {
+  std::vector<int32_t> r0, dim;
+  DBuf r0_d, dim_d;
+  bool empty() const { return r0.empty(); }
+};
+
 struct RangeSet {
-  DBuf start, end, binst_d, iblk0_d;
+  DBuf start, end, binst_d, iblk0_d, soc0_d, soc1_d;
   int nblk = 0;
+  const SocTable* soc = nullptr;  // set for row ranges that must not split cone blocks
   void build(const std::vector<int64_t>& inst_off, int per_block, const std::vector<char>* active = nullptr);
   Ranges view() const;
 };
@@ -164,7 +175,7 @@ struct Engine {
   int B = 0;
   int device = 0;                                // HIP device current at creation
   int64_t M = 0, N = 0, NNZ = 0;
-  std::vector<int64_t> row0, col0, mzero;
+  std::vector<int64_t> row0, col0, mzero, socstart;  // socstart: first cone row per instance
   std::vector<int32_t> h_rp, h_cp;
   DBuf d_rp, d_ci, d_v, d_cp, d_ri, d_vt, d_h, d_c, d_l, d_u;
   DBuf orig32, origT32;
@@ -184,6 +195,7 @@ struct Engine {
   Schedule sched;
   TileSet trow, tcol;
   RowBlockSet brow, bcol;
+  SocTable soc;                // second-order-cone row blocks (absolute rows)
   RangeSet vrow, vcol;
   RangeSet crow, ccol;         // coarser blocks for the multisection passes
   PanelSet prow, pcol;         // panel-major G (gathers x) and G^T (gathers y) when split

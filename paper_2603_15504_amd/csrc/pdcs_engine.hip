@@ -62,9 +62,18 @@ static void upload(DBuf& d, const std::vector<T>& h) {
 // ---------------------------------------------------------------------------
 void HostProblem::build(int64_t m_, int64_t n_, int64_t mz, const int64_t* row_ptr, const int32_t* col_idx,
                         const double* val, const double* h_, const double* c_, const double* l_,
-                        const double* u_) {
+                        const double* u_, int64_t n_soc, const int64_t* soc_dims) {
   if (m_ < 0 || n_ < 1) throw Error(PDCS_ERR_INVALID_ARG, "need m >= 0 and n >= 1");
   if (mz < 0 || mz > m_) throw Error(PDCS_ERR_INVALID_ARG, "m_zero must lie in [0, m]");
+  if (n_soc < 0 || (n_soc > 0 && !soc_dims)) throw Error(PDCS_ERR_INVALID_ARG, "bad second-order-cone list");
+  soc.clear();
+  int64_t soc_rows = 0;
+  for (int64_t q = 0; q < n_soc; ++q) {
+    if (soc_dims[q] < 1) throw Error(PDCS_ERR_INVALID_ARG, "second-order-cone dimensions must be >= 1");
+    soc_rows += soc_dims[q];
+    if (soc_rows > m_ - mz) throw Error(PDCS_ERR_INVALID_ARG, "second-order-cone rows exceed the rows after m_zero");
+    soc.push_back((int32_t)soc_dims[q]);
+  }
   if (m_ >= INT32_MAX || n_ >= INT32_MAX) throw Error(PDCS_ERR_SIZE, "m and n must be < 2^31 - 1");
   if (!row_ptr) throw Error(PDCS_ERR_INVALID_ARG, "row_ptr is null");
   if (!c_) throw Error(PDCS_ERR_INVALID_ARG, "c is null");
@@ -298,16 +307,36 @@ RowBlocks RowBlockSet::view() const {
 }
 
 void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block, const std::vector<char>* active) {
-  std::vector<int32_t> st, en, bi, iblk0;
+  std::vector<int32_t> st, en, bi, iblk0, s0, s1;
   const int B = (int)inst_off.size() - 1;
+  const bool cones = soc && !soc->empty();
+  size_t q = 0;  // next cone block (cone blocks are in row order)
   iblk0.push_back(0);
   for (int b = 0; b < B; ++b) {
     const int64_t stop = (active && !(*active)[b]) ? inst_off[b] : inst_off[b + 1];
-    for (int64_t s = inst_off[b]; s < stop; s += per_block) {
+    if (cones)
+      while (q < soc->r0.size() && soc->r0[q] < inst_off[b]) ++q;
+    int64_t s = inst_off[b];
+    while (s < stop) {
+      int64_t e = std::min<int64_t>(s + per_block, stop);
+      const size_t q0 = q;
+      if (cones) {
+        // a range ends at a cone block boundary: blocks starting inside it are
+        // taken whole, and a range that reaches a block's rows takes the block
+        while (q < soc->r0.size() && soc->r0[q] < e && soc->r0[q] < stop) {
+          e = std::max<int64_t>(e, (int64_t)soc->r0[q] + soc->dim[q]);
+          ++q;
+        }
+      }
       st.push_back((int32_t)s);
-      en.push_back((int32_t)std::min<int64_t>(s + per_block, stop));
+      en.push_back((int32_t)e);
       bi.push_back(b);
+      s0.push_back((int32_t)q0);
+      s1.push_back((int32_t)q);
+      s = e;
     }
+    if (cones)  // cone blocks of an inactive instance
+      while (q < soc->r0.size() && soc->r0[q] < inst_off[b + 1]) ++q;
     iblk0.push_back((int32_t)st.size());
   }
   nblk = (int)st.size();
@@ -315,6 +344,13 @@ void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block, const 
   upload(end, en);
   upload(binst_d, bi);
   upload(iblk0_d, iblk0);
+  if (cones) {
+    upload(soc0_d, s0);
+    upload(soc1_d, s1);
+  } else {
+    soc0_d.release();
+    soc1_d.release();
+  }
 }
 
 Ranges RangeSet::view() const {
@@ -323,6 +359,11 @@ Ranges RangeSet::view() const {
   r.blk_end = end.as<int32_t>();
   r.blk_inst = binst_d.as<int32_t>();
   r.inst_blk0 = iblk0_d.as<int32_t>();
+  const bool cones = soc && !soc->empty() && soc0_d.p;
+  r.blk_soc0 = cones ? soc0_d.as<int32_t>() : nullptr;
+  r.blk_soc1 = cones ? soc1_d.as<int32_t>() : nullptr;
+  r.soc_r0 = cones ? soc->r0_d.as<int32_t>() : nullptr;
+  r.soc_dim = cones ? soc->dim_d.as<int32_t>() : nullptr;
   r.nblk = nblk;
   return r;
 }
@@ -815,6 +856,24 @@ Engine::Engine(const std::vector<const HostProblem*>& probs) {
     upload(d_col0i, c0i);
   }
   for (int64_t j = 0; j < N && !any_unbounded; ++j) any_unbounded = !std::isfinite(l[j]) || !std::isfinite(u[j]);
+  // second-order-cone blocks: the last rows of each instance, in row order
+  for (int b = 0; b < B; ++b) {
+    int64_t rows = 0;
+    for (int32_t d : probs[b]->soc) rows += d;
+    int64_t r = row0[b + 1] - rows;
+    socstart.push_back(r);
+    for (int32_t d : probs[b]->soc) {
+      soc.r0.push_back((int32_t)r);
+      soc.dim.push_back(d);
+      r += d;
+    }
+  }
+  if (!soc.empty()) {
+    upload(soc.r0_d, soc.r0);
+    upload(soc.dim_d, soc.dim);
+  }
+  vrow.soc = &soc;
+  crow.soc = &soc;
   HIP_OK(hipHostMalloc((void**)&h_summary, 16, hipHostMallocDefault));
   build_schedule();
 }
@@ -861,7 +920,10 @@ void Engine::build_schedule() {
     P1 = panels_x > 0 ? panels_x : auto_panels(N);
     P2 = panels_y > 0 ? panels_y : auto_panels(M);
   }
-  const bool want_band = layout == PDCS_LAYOUT_BANDS || (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 22));
+  // cone blocks are projected in the row epilogues of the split dual pass,
+  // which the band layout always takes
+  const bool want_band = layout == PDCS_LAYOUT_BANDS || !soc.empty() ||
+                         (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 22));
   prow.P = pcol.P = 1;
   if (!want_band) {  // the panel-major CSR copies serve the row layout only
     if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
@@ -1085,6 +1147,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const WarmStart& w
     I.col0 = (int32_t)col0[b];
     I.cols = (int32_t)(col0[b + 1] - col0[b]);
     I.m_zero = (int32_t)mzero[b];
+    I.soc_start = (int32_t)socstart[b];
     I.precision = mixed ? kFP32 : kFP64;
     I.status = kActive;
     I.exit_code = PDCS_EXIT_CONTINUE;
@@ -1276,7 +1339,7 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const WarmStart& w
       build_iteration_schedules(&act);
       // the automatic layout choice, made again for the instances still running:
       // few large tiles would leave most of the chip idle, compacted row blocks do not
-      if (layout == PDCS_LAYOUT_AUTO && act_nnz < ((int64_t)1 << 22)) band_suspended = true;
+      if (layout == PDCS_LAYOUT_AUTO && soc.empty() && act_nnz < ((int64_t)1 << 22)) band_suspended = true;
       k = ctx(probe_passes);
       active_built = a32 + a64;
       compacted = true;
@@ -1537,6 +1600,22 @@ int pdcs_problem_create(int64_t m, int64_t n, int64_t m_zero, const int64_t* row
     *out = nullptr;
     auto p = std::make_unique<pdcs_problem_s>();
     p->hp.build(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u);
+    std::vector<const HostProblem*> v{&p->hp};
+    p->eng = std::make_unique<Engine>(v);
+    p->eng->prepare_plain();
+    *out = p.release();
+    return PDCS_OK;
+  });
+}
+
+int pdcs_problem_create_conic(int64_t m, int64_t n, int64_t m_zero, int64_t n_soc, const int64_t* soc_dims,
+                              const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* h,
+                              const double* c, const double* l, const double* u, pdcs_problem* out) {
+  return guarded([&]() {
+    if (!out) throw Error(PDCS_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    auto p = std::make_unique<pdcs_problem_s>();
+    p->hp.build(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u, n_soc, soc_dims);
     std::vector<const HostProblem*> v{&p->hp};
     p->eng = std::make_unique<Engine>(v);
     p->eng->prepare_plain();

@@ -28,6 +28,86 @@
 namespace pdcs {
 
 // ===========================================================================
+// Second-order-cone row blocks (socG option of Section 3, rescaled cones of
+// Section 2.6)
+// ===========================================================================
+// Projection of one block v (element i read by ld(i)) onto diag(e) K_soc,
+// K_soc = {(t, w): ||w|| <= t}, e_i = ef(i) > 0, by one wave; element i of the
+// result goes to st(i, p_i), each by the lane that read v_i.  From the KKT
+// conditions: v itself inside the cone; 0 inside the polar cone -diag(1/e)
+// K_soc (||w e_w|| <= -t e_t); otherwise the multiplier mu > 0 is the root of
+//   f(mu) = sum_i v_i^2 e_i^2 / (e_i^2 s + mu)^2 - 1,  s = v_0 / e_0 + mu / e_0^2
+// (sum over i >= 1), which is convex and decreasing, positive at
+// max(0, -v_0 e_0) and non-positive at ||w e_w||: Newton steps kept inside the
+// bracket (bisection when a step leaves it), then p_0 = e_0 s and
+// p_i = v_i e_i^2 s / (e_i^2 s + mu).  FP64 throughout.
+template <class LD, class EF, class ST>
+__device__ __forceinline__ void wave_proj_soc(int d, const LD& ld, const EF& ef, const ST& st) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double v0 = ld(0), e0 = ef(0);
+  double in_w = 0.0, po_w = 0.0;
+  for (int i = 1 + lane; i < d; i += kWave) {
+    const double v = ld(i), e = ef(i);
+    in_w += (v / e) * (v / e);
+    po_w += (v * e) * (v * e);
+  }
+  in_w = wave_sum(in_w);
+  po_w = wave_sum(po_w);
+  if (sqrt(in_w) <= v0 / e0) {
+    for (int i = lane; i < d; i += kWave) st(i, ld(i));
+    return;
+  }
+  if (sqrt(po_w) <= -v0 * e0) {
+    for (int i = lane; i < d; i += kWave) st(i, 0.0);
+    return;
+  }
+  const double ie02 = 1.0 / (e0 * e0);
+  double lo = fmax(0.0, -v0 * e0), hi = fmax(lo, sqrt(po_w));
+  double mu = lo;
+  for (int it = 0; it < 200; ++it) {
+    const double sv = v0 / e0 + mu * ie02;
+    double f = 0.0, df = 0.0;
+    for (int i = 1 + lane; i < d; i += kWave) {
+      const double v = ld(i), e = ef(i), e2 = e * e;
+      const double den = e2 * sv + mu, q = v * v * e2;
+      f += q / (den * den);
+      df -= 2.0 * q * (e2 * ie02 + 1.0) / (den * den * den);
+    }
+    f = wave_sum(f) - 1.0;
+    df = wave_sum(df);
+    if (f > 0.0) lo = mu;
+    else hi = mu;
+    if (f == 0.0 || !(hi > lo)) break;
+    double next = mu - f / df;
+    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    if (fabs(next - mu) <= 4e-16 * next) {
+      mu = next;
+      break;
+    }
+    mu = next;
+  }
+  const double sv = v0 / e0 + mu * ie02;
+  for (int i = lane; i < d; i += kWave) {
+    if (i == 0) {
+      st(0, e0 * sv);
+    } else {
+      const double v = ld(i), e = ef(i), e2 = e * e;
+      st(i, v * e2 * sv / (e2 * sv + mu));
+    }
+  }
+}
+
+// The cone blocks of row range b are handled by the waves of its workgroup,
+// block q by wave (q - first) mod kWavesPerBlock; fn(first row, dimension).
+template <class FN>
+__device__ __forceinline__ void for_cone_blocks(const Ranges& R, int b, const FN& fn) {
+  if (!R.blk_soc0) return;
+  const int wave = threadIdx.x / kWave;
+  const int q0 = R.blk_soc0[b], q1 = R.blk_soc1[b];
+  for (int q = q0 + wave; q < q1; q += kWavesPerBlock) fn(R.soc_r0[q], R.soc_dim[q]);
+}
+
+// ===========================================================================
 // Iteration kernels
 // ===========================================================================
 
@@ -76,7 +156,7 @@ struct DualEpilogue {
   DataPtrs<T> d;
   bool commit, avg;
   double ca, cb, beta, etak, sigma;
-  int mz_end;
+  int mz_end, soc_start;
   __device__ __forceinline__ void operator()(int r, double s, double (&acc)[4]) const {
     double y = (double)it.y[r];
     double gx = (double)it.gx[r];
@@ -92,6 +172,11 @@ struct DualEpilogue {
     const double hv = (double)d.h[r];
     const double gxn = (double)(T)s;
     const double v = y + sigma * (hv - 2.0 * gxn + gx);
+    if (r >= soc_start) {  // cone block row: projected with its block afterwards
+      it.yh[r] = (T)v;
+      it.gxh[r] = (T)gxn;
+      return;
+    }
     const bool zero_row = r < mz_end;
     const double yn = (double)(T)(zero_row ? v : fmax(v, 0.0));
     it.yh[r] = (T)yn;
@@ -120,6 +205,7 @@ __device__ __forceinline__ DualEpilogue<T> make_dual_epilogue(const Inst& I, con
   e.etak = I.eta_k;
   e.sigma = I.eta * I.omega;
   e.mz_end = I.row0 + I.m_zero;
+  e.soc_start = I.soc_start;
   return e;
 }
 
@@ -379,8 +465,8 @@ __global__ void k_band_vals(const int32_t* __restrict__ src, int64_t n, const do
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restrict__ part, int P,
                                                      int64_t M, IterPtrs<T> it, DataPtrs<T> d,
-                                                     Inst* __restrict__ inst, int prec,
-                                                     double* __restrict__ rec) {
+                                                     const double* __restrict__ D1, Inst* __restrict__ inst,
+                                                     int prec, double* __restrict__ rec) {
   __shared__ double lds[kWavesPerBlock * 4];
   const int b = blockIdx.x;
   const Inst& I = inst[R.blk_inst[b]];
@@ -392,6 +478,31 @@ __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restri
     double s = 0.0;
     for (int p = 0; p < P; ++p) s += (double)part[(size_t)p * M + r];
     epi(r, s, acc);
+  }
+  if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
+    __syncthreads();  // the blocks' unprojected values and committed iterates are in memory
+    for_cone_blocks(R, b, [&](int r0, int dim) {
+      // y_hat = Proj onto diag(1/D1) K_soc of the stored value, with the line-search terms
+      wave_proj_soc(
+          dim, [&](int i) { return (double)it.yh[r0 + i]; }, [&](int i) { return 1.0 / D1[r0 + i]; },
+          [&](int i, double p) {
+            const int r = r0 + i;
+            const double yn = (double)(T)p;
+            it.yh[r] = (T)yn;
+            const double dy = yn - (double)it.y[r];
+            acc[0] += dy * dy;
+            acc[1] += dy * ((double)it.gxh[r] - (double)it.gx[r]);
+            acc[3] += (double)d.h[r] * yn;
+          });
+      // primal residual of the reflection parameter: (G x_hat - h) against diag(D1) K_soc
+      wave_proj_soc(
+          dim, [&](int i) { return (double)it.gxh[r0 + i] - (double)d.h[r0 + i]; },
+          [&](int i) { return D1[r0 + i]; },
+          [&](int i, double p) {
+            const double pr = ((double)it.gxh[r0 + i] - (double)d.h[r0 + i]) - p;
+            acc[2] += pr * pr;
+          });
+    });
   }
   block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
 }
@@ -730,6 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
   for (int i = 0; i < kCandRowsNV; ++i) acc[i] = 0.0;
   const int i1 = R.blk_end[b];
   for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    if (i >= I.soc_start) continue;  // cone block rows: below
     const double h = d.h[i], di = D1[i];
     const double yav = (double)ya[i];
     const bool zero_row = i < mz_end;
@@ -751,6 +863,37 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
       acc[8 + q * 3 + 2] = fmax(acc[8 + q * 3 + 2], proj / di);
     }
   }
+  // cone blocks: the same terms, with the residual r = G x - h projected onto
+  // diag(D1) K_soc for the scaled L2 term and, unscaled (r / D1), onto K_soc for
+  // the infinity-norm termination terms
+  for_cone_blocks(R, b, [&](int r0, int dim) {
+    for (int q = 0; q < nc; ++q) {
+      const T* yq = q == 0 ? y0 : y1;
+      const double* gq = q == 0 ? g0 : g1;
+      for (int i = (int)(threadIdx.x & (kWave - 1)); i < dim; i += kWave) {
+        const int r = r0 + i;
+        const double yc = (double)yq[r], gx = gq[r], h = d.h[r];
+        const double dya = yc - (double)ya[r], res = gx - h;
+        acc[q * 4 + 0] += dya * dya;
+        acc[q * 4 + 1] += res * res;
+        acc[q * 4 + 3] += h * yc;
+        acc[8 + q * 3 + 1] = fmax(acc[8 + q * 3 + 1], fabs(gx) / D1[r]);
+      }
+      wave_proj_soc(
+          dim, [&](int i) { return gq[r0 + i] - d.h[r0 + i]; }, [&](int i) { return D1[r0 + i]; },
+          [&](int i, double p) {
+            const double pr = (gq[r0 + i] - d.h[r0 + i]) - p;
+            acc[q * 4 + 2] += pr * pr;
+          });
+      wave_proj_soc(
+          dim, [&](int i) { return (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; }, [](int) { return 1.0; },
+          [&](int i, double p) {
+            const double ru = (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i];
+            acc[8 + q * 3 + 0] = fmax(acc[8 + q * 3 + 0], fabs(ru - p));
+            acc[8 + q * 3 + 2] = fmax(acc[8 + q * 3 + 2], fabs(p));
+          });
+    }
+  });
   block_summax_store<kCandRowsNV, kCandRowsNS>(acc, lds, rec + (size_t)b * kCandRowsNV);
 }
 
@@ -865,8 +1008,9 @@ __global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __rest
                                                        const T* __restrict__ y1,
                                                        const double* __restrict__ g0,
                                                        const double* __restrict__ g1,
-                                                       DataPtrs<double> d, const Inst* __restrict__ inst,
-                                                       int prec, double* __restrict__ rec) {
+                                                       DataPtrs<double> d, const double* __restrict__ D1,
+                                                       const Inst* __restrict__ inst, int prec,
+                                                       double* __restrict__ rec) {
   __shared__ double lds[kWavesPerBlock * kProbeNV];
   const int b = blockIdx.x;
   const int q = blockIdx.y;
@@ -887,6 +1031,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __rest
   const double* gs = q == 0 ? g0 : g1;
   const int i1 = R.blk_end[b];
   for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    if (i >= I.soc_start) continue;  // cone block rows: below
     const bool zero_row = i < mz_end;
     const double yc = (double)ys[i];
     const double b2 = d.h[i] - gs[i];
@@ -898,6 +1043,25 @@ __global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __rest
       acc[p * 2 + 1] += b2 * dy;
     }
   }
+  // cone blocks: y(t) = Proj onto diag(1/D1) K_soc of y + t sigma b2, per probe
+  for_cone_blocks(R, b, [&](int r0, int dim) {
+#pragma unroll
+    for (int p = 0; p < kProbes; ++p) {
+      const double tp = tq[p];
+      double dd = 0.0, bd = 0.0;
+      wave_proj_soc(
+          dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
+          [&](int i) { return 1.0 / D1[r0 + i]; },
+          [&](int i, double pv) {
+            const double yc = (double)ys[r0 + i];
+            const double dy = pv - yc;
+            dd += dy * dy;
+            bd += (d.h[r0 + i] - gs[r0 + i]) * dy;
+          });
+      acc[p * 2 + 0] += dd * inv_sigma;
+      acc[p * 2 + 1] += bd;
+    }
+  });
   block_sum_store<kProbeNV>(acc, lds, rec + ((size_t)q * R.nblk + b) * kProbeNV);
 }
 
@@ -1244,17 +1408,26 @@ __global__ __launch_bounds__(kBlock) void k_ray_vec_cols(Ranges R, const T* __re
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ray_vec_rows(Ranges R, const T* __restrict__ yh,
-                                                         const double* __restrict__ ys0, double* __restrict__ ry,
-                                                         const Inst* __restrict__ inst, int prec) {
+                                                         const double* __restrict__ ys0, const double* __restrict__ D1,
+                                                         double* __restrict__ ry, const Inst* __restrict__ inst,
+                                                         int prec) {
   const int b = blockIdx.x;
   const Inst& I = inst[R.blk_inst[b]];
   if (!mode_selects(I, kModeRay) || I.precision != prec) return;
   const int mz_end = I.row0 + I.m_zero;
   const int i1 = R.blk_end[b];
   for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    if (i >= I.soc_start) continue;  // cone block rows: below
     const double v = (double)yh[i] - ys0[i];
     ry[i] = i < mz_end ? v : fmax(v, 0.0);
   }
+  // cone blocks: the unscaled ray D1 (y_hat - y_start) projected onto K_soc,
+  // stored scaled back by 1 / D1 like the other rows
+  for_cone_blocks(R, b, [&](int r0, int dim) {
+    wave_proj_soc(
+        dim, [&](int i) { return D1[r0 + i] * ((double)yh[r0 + i] - ys0[r0 + i]); }, [](int) { return 1.0; },
+        [&](int i, double p) { ry[r0 + i] = p / D1[r0 + i]; });
+  });
 }
 
 // Column terms, with lam = -(G_hat^T r_y)_j / D2_j (the unscaled -G^T r_y) and
@@ -1322,12 +1495,22 @@ __global__ __launch_bounds__(kBlock) void k_ray_rows(Ranges R, const double* __r
     const double t = d.h[i] * ry[i];
     acc[0] += t;
     acc[1] += fabs(t);
-    if (rgx) {
+    if (rgx && i < I.soc_start) {
       const double r = rgx[i] / D1[i];
       const double res = i < mz_end ? r : fmin(r, 0.0);
       acc[2] += res * res;
     }
   }
+  // cone blocks: the unscaled G r_x against K_soc
+  if (rgx)
+    for_cone_blocks(R, b, [&](int r0, int dim) {
+      wave_proj_soc(
+          dim, [&](int i) { return rgx[r0 + i] / D1[r0 + i]; }, [](int) { return 1.0; },
+          [&](int i, double p) {
+            const double res = rgx[r0 + i] / D1[r0 + i] - p;
+            acc[2] += res * res;
+          });
+    });
   block_sum_store<kRayRowsNV>(acc, lds, rec + (size_t)b * kRayRowsNV);
 }
 
@@ -1746,6 +1929,7 @@ __global__ __launch_bounds__(kBlock) void k_start_rows(Ranges R, const double* _
   const int mz_end = I.row0 + I.m_zero;
   const int i1 = R.blk_end[b];
   for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
+    if (i >= I.soc_start) continue;  // cone block rows: below
     const double v = y0 ? y0[i] / D1[i] : 0.0;
     const T y = (T)(i < mz_end ? v : fmax(v, 0.0));
     if (ys0) ys0[i] = (double)y;
@@ -1754,6 +1938,20 @@ __global__ __launch_bounds__(kBlock) void k_start_rows(Ranges R, const double* _
     it.yh[i] = y;
     it.sy[i] = (T)0;
   }
+  // cone blocks: y0 / D1 projected onto diag(1/D1) K_soc
+  for_cone_blocks(R, b, [&](int r0, int dim) {
+    wave_proj_soc(
+        dim, [&](int i) { return y0 ? y0[r0 + i] / D1[r0 + i] : 0.0; }, [&](int i) { return 1.0 / D1[r0 + i]; },
+        [&](int i, double p) {
+          const int r = r0 + i;
+          const T y = (T)p;
+          if (ys0) ys0[r] = (double)y;
+          it.y[r] = y;
+          it.ya[r] = y;
+          it.yh[r] = y;
+          it.sy[r] = (T)0;
+        });
+  });
 }
 
 // Copy FP64 products into the maintained products of the start point.
@@ -1822,7 +2020,7 @@ static void launch_dual_epi_t(const KernelCtx& k, hipStream_t s, int prec, const
                               const DataPtrs<T>& d, const T* part) {
   if (k.split1() && k.vrow.nblk > 0)
     k_dual_epi<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, part, k.use_band ? k.band1.P : k.P1, k.M, it, d,
-                                                         k.inst, prec, k.rec_dual_epi);
+                                                         k.D1, k.inst, prec, k.rec_dual_epi);
 }
 
 template <typename T>
@@ -1953,7 +2151,7 @@ static void launch_probe_t(const KernelCtx& k, hipStream_t s, int prec, const It
                                                            k.inst, prec, k.rec_probe_c);
   if (k.crow.nblk > 0)
     k_probe_rows<T><<<dim3(k.crow.nblk, kMaxCand), kBlock, 0, s>>>(k.crow, it.yh, it.ybar, k.cgx0, k.cgx1, k.d64,
-                                                           k.inst, prec, k.rec_probe_r);
+                                                                    k.D1, k.inst, prec, k.rec_probe_r);
 }
 
 template <typename T>
@@ -2016,7 +2214,7 @@ static void launch_ray_vec_t(const KernelCtx& k, hipStream_t s, int prec, const 
   if (k.vcol.nblk > 0 && k.ray_x)
     k_ray_vec_cols<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, it.xh, k.xs0, k.d64, k.rx, k.inst, prec);
   if (k.vrow.nblk > 0)
-    k_ray_vec_rows<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it.yh, k.ys0, k.ry, k.inst, prec);
+    k_ray_vec_rows<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, it.yh, k.ys0, k.D1, k.ry, k.inst, prec);
 }
 
 // The infeasibility tests of one check (instances selected by k_decide).
