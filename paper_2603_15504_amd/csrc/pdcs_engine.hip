@@ -2139,6 +2139,12 @@ void Engine::autotune(double budget_ms) {
   const Cand cands[] = {{4, 4096}, {8, 4096}, {8, 8192}, {8, 16384}, {16, 8192}, {16, 16384}, {32, 16384},
                         {32, 32768}};
   const auto t0 = std::chrono::steady_clock::now();
+  auto spent = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
+  // Row blocks: the layout of small batches, and of a band batch's tail once
+  // compaction leaves fewer than 2^22 nonzeros running (timed with the bands
+  // set aside).
+  const bool band = use_band;
+  band_suspended = band;
   Schedule best = sched;
   double best_t = 1e300;
   for (const Cand& c : cands) {
@@ -2150,10 +2156,36 @@ void Engine::autotune(double budget_ms) {
       best_t = t;
       best = sched;
     }
-    if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > budget_ms) break;
+    if (spent() > (band ? 0.25 : 1.0) * budget_ms) break;
   }
   sched = best;
   build_schedule();
+  band_suspended = false;
+  if (!band) return;
+  // Band tiles: band height, tile minimum and, in a batch, the per-window entry
+  // cap of an instance's bands, timed on the trial product G x_hat (each
+  // candidate rebuilds both band layouts on the host).  The candidates bracket
+  // the defaults by a factor of 2.
+  const BandSchedule base = bsched;
+  const BandSchedule bc[] = {base,
+                             {base.rows, base.min_tiles, std::max(1024, base.entry_cap / 2)},
+                             {base.rows, base.min_tiles, base.entry_cap * 2},
+                             {base.rows, base.min_tiles * 2, base.entry_cap},
+                             {std::max(256, base.rows / 2), base.min_tiles, base.entry_cap}};
+  BandSchedule bbest = base;
+  double bbest_t = 1e300;
+  for (const BandSchedule& c : bc) {
+    if (&c != &bc[0] && spent() > budget_ms) break;
+    bsched = c;
+    rebuild_bands();
+    const double t = time_dual(kFP32, 5);
+    if (t < bbest_t) {
+      bbest_t = t;
+      bbest = c;
+    }
+  }
+  bsched = bbest;
+  rebuild_bands();
 }
 
 }  // namespace pdcs

@@ -96,6 +96,28 @@ def test_batch_autotuned_schedule_still_matches(refs):
         _check(inst, sol, r.pobj)
 
 
+def test_batch_band_schedule_autotuned_still_matches(refs):
+    # with band tiles the autotuner also times band height, tile minimum and
+    # entry cap (rebuilding the band layouts); the chosen one is a candidate and
+    # the batch still solves to the oracle's answers
+    insts, rs = refs
+    b = P.Batch([P.Problem.from_instance(i) for i in insts])
+    b.set_layout("bands")
+    before = b.band_schedule()
+    b.autotune(60000.0)
+    after = b.band_schedule()
+    cands = {(before["rows"], before["min_tiles"], before["entry_cap"]),
+             (before["rows"], before["min_tiles"], max(1024, before["entry_cap"] // 2)),
+             (before["rows"], before["min_tiles"], before["entry_cap"] * 2),
+             (before["rows"], before["min_tiles"] * 2, before["entry_cap"]),
+             (max(256, before["rows"] // 2), before["min_tiles"], before["entry_cap"])}
+    assert (after["rows"], after["min_tiles"], after["entry_cap"]) in cands
+    assert after["built_rows"] > 0
+    sols = b.solve(precision="mixed", time_limit=120.0)
+    for inst, sol, r in zip(insts, sols, rs):
+        _check(inst, sol, r.pobj)
+
+
 @pytest.mark.parametrize("sched", [(1, 1024, 256), (64, 65536, 8192)])
 def test_batch_schedule_extremes(refs, sched):
     insts, rs = refs
