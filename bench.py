@@ -171,7 +171,7 @@ def c2_solves(P, np, count=512, sample_single=8, check_oracle=4):
     t_setup = time.perf_counter() - t
     log(f"solves: {len(insts)} LPs (sum nnz {sum(i.nnz for i in insts)}) generated and uploaded in {t_setup:.1f}s")
     t = time.perf_counter()
-    sched = batch.autotune(2000.0)
+    sched = batch.autotune(30000.0)
     t_tune = time.perf_counter() - t
     out = {"workload": f"{len(insts)} LPs m~logU[1e3,5e4], n=2m, 8 nnz/col, rel. KKT 1e-6",
            "sum_nnz": int(sum(i.nnz for i in insts)), "autotune_s": round(t_tune, 2),
@@ -351,6 +351,56 @@ def run_c3(args, P, np):
         {"roofline": roof, "cpu_baseline": None})
 
 
+def mlp_step_bytes(B, d_in, w, d_out):
+    """Algorithmic HBM bytes of one fused training step of the warm-start MLP:
+    Adam reads the FP32 weight, both moments and writes all three plus the BF16
+    copy (26 B per weight; biases 28 B with their stored gradient); W1 is read
+    once as BF16, W2 and W3 twice (forward and backward products); the input is
+    read (FP32), written and read twice as BF16; the target is read (FP32) and
+    the BF16 loss gradient written once and read twice.  Hidden-layer traffic
+    (batch x width) is left out."""
+    nw = w * d_in + w * w + d_out * w
+    nb = 2 * w + d_out
+    return (26 * nw + 28 * nb + 2 * w * d_in + 4 * w * w + 4 * d_out * w
+            + B * d_in * (4 + 2 + 2 + 2) + B * d_out * (4 + 2 + 2 + 2))
+
+
+def run_c3_mlp(args, P, np):
+    """The warm-start network's training step at the LP family's shape
+    (inputs h, c and outputs x, y: 6e4 -> 512 -> 512 -> 6e4), random data:
+    K asynchronous steps between two events on the network's stream."""
+    import torch
+
+    d = 20000 + 40000
+    B = args.mlp_batch
+    net = P.MLP(d, 512, d, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    u = torch.randn((B, d), device="cuda", generator=g)
+    t = torch.randn((B, d), device="cuda", generator=g)
+    for _ in range(max(args.warmup, 1)):
+        net.train_step(u, t, 1e-4, wait=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        net.train_step(u, t, 1e-4, wait=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = mlp_step_bytes(B, d, 512, d)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    flops = 3 * 2 * B * (d * 512 + 512 * 512 + 512 * d)
+    log(f"mlp step batch {B}: {ms:.3f} ms, {nbytes / 1e9:.3f} GB algorithmic -> {gbs:.0f} GB/s, "
+        f"{flops / (ms * 1e-3) / 1e12:.1f} TFLOP/s")
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(gbs / 8000.0, 4), "traffic": None,
+            "kernel": f"MLP training step (BF16 MFMA products, loss and Adam in their epilogues), batch {B}",
+            "bytes_per_step": int(nbytes), "tflops": round(flops / (ms * 1e-3) / 1e12, 2)}
+    return common_fields(args, round(gbs, 1), "GB/s", ms, "bf16 (FP32 accumulate, FP32 Adam)", {
+        "workload": f"warm-start MLP training step, 60000 -> 512 -> 512 -> 60000, batch {B}, random inputs"},
+        {"roofline": roof, "cpu_baseline": None})
+
+
 def workload(name: str):
     import lpgen
 
@@ -474,7 +524,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed chunks of 64 trials + restart check")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c1_nnz_matched", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c1_nnz_matched", "c2", "c3", "c3_mlp", "c4"])
+    ap.add_argument("--mlp-batch", type=int, default=256, help="c3_mlp: training batch")
     ap.add_argument("--c2-count", type=int, default=512)
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "bands"],
                     help="c2: matrix layout of the batch (profiling)")
@@ -506,6 +557,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
 
+    if args.workload == "c3_mlp":
+        print(json.dumps(run_c3_mlp(args, P, np)), flush=True)
+        return
     if args.workload in ("c2", "c3", "c4"):
         if args.steps == 200 and args.warmup == 20:   # the C1 defaults: one step each here
             args.steps, args.warmup = 1, 0

@@ -268,15 +268,24 @@ int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
  *   PDCS_LAYOUT_BANDS: band tiles: row bands x gathered-index windows, entries
  *                      sorted by gathered index and summed per row in LDS, then
  *                      one partial sum per window combined by the epilogues;
+ *   PDCS_LAYOUT_WORKGROUP: CSR row blocks, with every chunk of trials between
+ *                      two restart checks run by one kernel that gives each
+ *                      instance one workgroup: the passes of a trial are
+ *                      separated by workgroup barriers instead of kernel
+ *                      launches (latency-bound small instances);
  *   PDCS_LAYOUT_AUTO : bands for problems (and batches, see
- *                      pdcs_batch_set_layout) with at least 2^22 nonzeros.
- * Both layouts compute the same products up to rounding order.  Building the
- * band tiles takes host time proportional to nnz log nnz and 20 bytes of device
- * memory per nonzero of each of G and G^T.
+ *                      pdcs_batch_set_layout) with at least 2^22 nonzeros,
+ *                      the workgroup layout when every instance has at most
+ *                      2^15 nonzeros and no cone blocks, else rows.
+ * All layouts compute the same products up to rounding order; rows and
+ * workgroup produce bit-identical iterates.  Building the band tiles takes host
+ * time proportional to nnz log nnz and 20 bytes of device memory per nonzero of
+ * each of G and G^T.  Cone blocks always take the band layout.
  * Errors: PDCS_ERR_INVALID_ARG for an unknown layout. */
 #define PDCS_LAYOUT_AUTO  0
 #define PDCS_LAYOUT_ROWS  1
 #define PDCS_LAYOUT_BANDS 2
+#define PDCS_LAYOUT_WORKGROUP 3
 int  pdcs_problem_set_layout(pdcs_problem p, int64_t layout);
 
 /* pdcs_problem_set_band_schedule: shape of the band tiles of the band layout.
@@ -370,9 +379,14 @@ int  pdcs_batch_solve(pdcs_batch b, const pdcs_options* opts, const double* cons
 int  pdcs_batch_solve_device(pdcs_batch b, const pdcs_options* opts, const void* const* x0s_dev,
                              const void* const* y0s_dev, int64_t warm_dtype, void* stream,
                              pdcs_result* results);
-/* Autotune the row-tile schedule of this batch: times SpMV schedules with HIP
- * events and keeps the fastest (see pdcs_batch_schedule).  time_budget_ms <= 0
- * uses a default. */
+/* Autotune this batch's SpMV schedules: times candidates with HIP events and
+ * keeps the fastest.  Row blocks (pdcs_batch_schedule; the layout of small
+ * batches and of a band batch's tail after compaction) are tuned first; with
+ * band tiles, band height, tile minimum and per-window entry cap
+ * (pdcs_batch_band_schedule) are then tuned on the trial product G x_hat, each
+ * candidate rebuilding the band layouts on the host.  Candidates beyond
+ * time_budget_ms are skipped (<= 0: 2000 ms); the current schedules are always
+ * among those timed. */
 int  pdcs_batch_autotune(pdcs_batch b, double time_budget_ms);
 /* Current schedule: iter_max (row-group iterations per wavefront tile),
  * block_nnz (nonzeros per workgroup), vec_per_block (elements per workgroup). */
@@ -393,14 +407,30 @@ void pdcs_batch_destroy(pdcs_batch b);
 /* ---- warm-start MLP ----------------------------------------------------
  * 3-layer perceptron v = W3 relu(W2 relu(W1 u + b1) + b2) + b3 with BF16
  * weights (FP32 master copy) and FP32 accumulation on MFMA units.  Inputs and
- * outputs are device float32 row-major [batch x d]. */
+ * outputs are device float32 row-major [batch x d].  pdcs_mlp_create: sizes in
+ * [1, 2^26] for d_in and d_out, [1, 8192] for width, and fewer than 2^30
+ * entries in each weight matrix (width x d_in, width x d_out); Glorot-uniform
+ * weights from `seed`, zero biases.  Errors: PDCS_ERR_INVALID_ARG,
+ * PDCS_ERR_OOM, PDCS_ERR_HIP. */
 int  pdcs_mlp_create(int64_t d_in, int64_t width, int64_t d_out, uint64_t seed, pdcs_mlp* out);
 int  pdcs_mlp_forward(pdcs_mlp net, const float* in_dev, float* out_dev, int64_t batch,
                       void* stream);
-/* One Adam step on the mean squared error; *loss_out (host) receives the loss
- * of the batch before the step. */
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the mean
+ * squared error, enqueued on `stream`.  The weight updates run inside the
+ * weight-gradient products.  With loss_out non-NULL the call waits for the
+ * step and *loss_out (host) receives the loss of the batch before the step;
+ * with loss_out NULL it returns at once (the step runs asynchronously on
+ * `stream`; in_dev and target_dev must stay valid until it has run). */
 int  pdcs_mlp_train_step(pdcs_mlp net, const float* in_dev, const float* target_dev,
                          int64_t batch, float lr, float* loss_out, void* stream);
+/* Read back one activation of the last forward, gradient or training call as
+ * host float[count], count = batch x features: which = 0 the network input as
+ * the first product sees it (standardized, BF16), 1 / 2 the hidden layers
+ * after ReLU (BF16), 3 the loss gradient dL/dv (BF16), 4 / 5 the ReLU-masked
+ * gradients dL/dz2 / dL/dz1 (BF16).  3-5 exist only after a gradient or
+ * training call.  BF16 values are widened exactly.  The call waits for the
+ * device to be idle.  Errors: PDCS_ERR_INVALID_ARG. */
+int  pdcs_mlp_activation(pdcs_mlp net, int64_t which, float* host_out, int64_t count);
 /* Gradients of the MSE loss at the current weights without updating them, as
  * FP32 device arrays laid out like the weights (W1[width x d_in], b1[width],
  * W2[width x width], b2[width], W3[d_out x width], b3[d_out]). */

@@ -12,7 +12,9 @@ GPU, the GEMM operands (inputs, weights, hidden activations, output gradients)
 to bfloat16 before multiplying, and accumulates in float64.
 
 Parity pinning: the analytic gradients are checked against central finite
-differences of the FP64 loss (tests), and Adam against its textbook update.
+differences of the FP64 loss, the per-layer products (layer_products) against
+the same finite differences, the standardized forms against hand-computed
+values, and Adam against its textbook first step (tests).
 """
 from __future__ import annotations
 
@@ -86,6 +88,30 @@ def loss_and_grad(params, u, t, d_in, w, d_out, bf16=False):
     gb1 = dz1.sum(axis=0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
     return loss, g
+
+
+def layer_products(params, acts, d_in, w, d_out):
+    """Every product of one forward and backward pass, in float64, from the
+    activations that pass fed its products: acts = dict(U, h1, h2, dv, dz2, dz1)
+    of arrays [batch x features] (the GPU's BF16 values, widened).  Weights are
+    rounded to BF16 like the GPU's copies.
+
+    Returns z1 = U W1^T + b1, z2 = h1 W2^T + b2, v = h2 W3^T + b3, the backward
+    products dh2 = dv W3 and dh1 = dz2 W2 (before the ReLU masks), the weight
+    gradients gW1 = dz1^T U, gW2 = dz2^T h1, gW3 = dv^T h2, and under the same
+    names with suffix "_abs" each product taken over absolute values (biases
+    included), the scale that bounds a sum's rounding error."""
+    P = split_params(params, d_in, w, d_out)
+    W1, W2, W3 = (bf16_round(P[k]) for k in ("W1", "W2", "W3"))
+    a = {k: np.asarray(acts[k], np.float64) for k in ("U", "h1", "h2", "dv", "dz2", "dz1")}
+    out = {}
+    for name, x, y, b in (("z1", a["U"], W1.T, P["b1"]), ("z2", a["h1"], W2.T, P["b2"]),
+                          ("v", a["h2"], W3.T, P["b3"]), ("dh2", a["dv"], W3, None),
+                          ("dh1", a["dz2"], W2, None), ("gW1", a["dz1"].T, a["U"], None),
+                          ("gW2", a["dz2"].T, a["h1"], None), ("gW3", a["dv"].T, a["h2"], None)):
+        out[name] = x @ y + (b if b is not None else 0.0)
+        out[name + "_abs"] = np.abs(x) @ np.abs(y) + (np.abs(b) if b is not None else 0.0)
+    return out
 
 
 def adam_step(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -116,6 +116,7 @@ PROTOTYPES = {
     "pdcs_mlp_forward": (C.c_int, [_P, _P, _P, _I64, _P]),
     "pdcs_mlp_train_step": (C.c_int, [_P, _P, _P, _I64, C.c_float, C.POINTER(C.c_float), _P]),
     "pdcs_mlp_gradients": (C.c_int, [_P, _P, _P, _I64, _P, C.POINTER(C.c_float), _P]),
+    "pdcs_mlp_activation": (C.c_int, [_P, _I64, _P, _I64]),
     "pdcs_mlp_set_normalization": (C.c_int, [_P, _P, _P, _P, _P]),
     "pdcs_mlp_num_params": (C.c_int, [_P, C.POINTER(_I64)]),
     "pdcs_mlp_get_params": (C.c_int, [_P, _P]),
@@ -258,7 +259,7 @@ def pdcs_problem_set_panels(p, px: int, py: int):
     _check(lib.pdcs_problem_set_panels(p, int(px), int(py)), "pdcs_problem_set_panels")
 
 
-LAYOUTS = {"auto": 0, "rows": 1, "bands": 2}
+LAYOUTS = {"auto": 0, "rows": 1, "bands": 2, "workgroup": 3}
 
 
 def pdcs_problem_set_layout(p, layout: int):
@@ -712,11 +713,21 @@ def pdcs_mlp_forward(net, in_dev: int, out_dev: int, batch: int, stream: int = 0
                                 C.c_void_p(stream) if stream else None), "pdcs_mlp_forward")
 
 
-def pdcs_mlp_train_step(net, in_dev: int, target_dev: int, batch: int, lr: float, stream: int = 0) -> float:
+def pdcs_mlp_train_step(net, in_dev: int, target_dev: int, batch: int, lr: float, stream: int = 0,
+                        wait: bool = True):
+    """One Adam step; returns the loss before the step, or None (and does not
+    wait for the step) when wait is False."""
     loss = C.c_float()
     _check(lib.pdcs_mlp_train_step(net, C.c_void_p(in_dev), C.c_void_p(target_dev), int(batch), float(lr),
-                                   C.byref(loss), C.c_void_p(stream) if stream else None), "pdcs_mlp_train_step")
-    return loss.value
+                                   C.byref(loss) if wait else None, C.c_void_p(stream) if stream else None),
+           "pdcs_mlp_train_step")
+    return loss.value if wait else None
+
+
+def pdcs_mlp_activation(net, which: int, batch: int, features: int) -> np.ndarray:
+    out = np.empty((int(batch), int(features)), dtype=np.float32)
+    _check(lib.pdcs_mlp_activation(net, int(which), _ptr(out), out.size), "pdcs_mlp_activation")
+    return out
 
 
 def pdcs_mlp_gradients(net, in_dev: int, target_dev: int, batch: int, grad_dev: int, stream: int = 0) -> float:
@@ -773,11 +784,19 @@ class MLP:
                          torch.cuda.current_stream().cuda_stream)
         return out
 
-    def train_step(self, u, t, lr):
+    def train_step(self, u, t, lr, wait=True):
         import torch
 
         return pdcs_mlp_train_step(self.handle, u.data_ptr(), t.data_ptr(), u.shape[0], lr,
-                                   torch.cuda.current_stream().cuda_stream)
+                                   torch.cuda.current_stream().cuda_stream, wait)
+
+    ACTIVATIONS = ("input", "h1", "h2", "dv", "dz2", "dz1")
+
+    def activation(self, name, batch):
+        """BF16 activation `name` (ACTIVATIONS) of the last call, widened to float32."""
+        which = self.ACTIVATIONS.index(name)
+        feats = (self.d_in, self.width, self.width, self.d_out, self.width, self.width)[which]
+        return pdcs_mlp_activation(self.handle, which, batch, feats)
 
     def gradients(self, u, t):
         import torch

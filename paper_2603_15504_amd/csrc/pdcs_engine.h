@@ -205,6 +205,7 @@ struct Engine {
   int panels_x = 0, panels_y = 0;   // 0: automatic
   int layout = PDCS_LAYOUT_AUTO;
   bool use_band = false;
+  bool wg_trials = false;           // chunks of trials by one workgroup per instance
   bool band_suspended = false;      // auto layout: the active instances of a batch fell below the band threshold
   BandSet band1, band2;             // band tiles of G (gathers x) and G^T (gathers y)
   BandSchedule bsched;              // shape of both band layouts

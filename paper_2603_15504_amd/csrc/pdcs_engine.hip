@@ -916,7 +916,7 @@ void Engine::build_iteration_schedules(const std::vector<char>* active) {
 void Engine::build_schedule() {
   build_iteration_schedules(nullptr);
   int P1 = 1, P2 = 1;
-  if (B == 1) {
+  if (B == 1 && layout != PDCS_LAYOUT_WORKGROUP) {
     P1 = panels_x > 0 ? panels_x : auto_panels(N);
     P2 = panels_y > 0 ? panels_y : auto_panels(M);
   }
@@ -934,6 +934,12 @@ void Engine::build_schedule() {
     band2.build(col0, row0, h_cp, h_ri, bsched);
   }
   use_band = want_band;
+  // one workgroup per instance for whole chunks of trials: forced, or small
+  // instances (every one at most 2^15 nonzeros) on row blocks without panels
+  int64_t max_nnz = 0;
+  for (int b = 0; b < B; ++b) max_nnz = std::max<int64_t>(max_nnz, h_rp[row0[b + 1]] - h_rp[row0[b]]);
+  wg_trials = !want_band && prow.P == 1 && pcol.P == 1 &&
+              (layout == PDCS_LAYOUT_WORKGROUP || (layout == PDCS_LAYOUT_AUTO && max_nnz <= ((int64_t)1 << 15)));
   rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
   rec_lam_epi.alloc((size_t)std::max(vcol.nblk, 1) * 3 * 8);
   const int nr = std::max(brow.nblk, 1), nc = std::max(bcol.nblk, 1);
@@ -996,6 +1002,7 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.probe_passes = probe_passes;
   k.P1 = prow.P;
   k.P2 = pcol.P;
+  k.wg_trials = wg_trials ? 1 : 0;
   k.rec_dual_epi = rec_dual_epi.as<double>();
   k.rec_lam_epi = rec_lam_epi.as<double>();
   k.infeas = infeas_on;
@@ -1078,6 +1085,12 @@ static int64_t check_period(const pdcs_options& o) {
 }
 
 void Engine::enqueue_chunk(const KernelCtx& k, int mask, int64_t K, bool timed) {
+  if (k.wg_trials && !k.use_band && !timed) {  // timed runs keep the per-pass launches
+    launch_trials_wg(k, stream, mask, (int)K);
+    launch_check(k, stream, mask);
+    launch_summary(k, stream, d_summary.as<int32_t>());
+    return;
+  }
   for (int64_t s = 0; s < K; ++s) {
     launch_trial_part(k, stream, mask, 0);
     if (timed) {
@@ -1748,8 +1761,7 @@ int pdcs_problem_spmv_noalloc(pdcs_problem p, int64_t transpose, int64_t precisi
 int pdcs_problem_set_layout(pdcs_problem p, int64_t layout) {
   return guarded([&]() {
     if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
-    if (layout != PDCS_LAYOUT_AUTO && layout != PDCS_LAYOUT_ROWS && layout != PDCS_LAYOUT_BANDS)
-      throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
+    if (layout < PDCS_LAYOUT_AUTO || layout > PDCS_LAYOUT_WORKGROUP) throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
     p->eng->layout = (int)layout;
     p->eng->build_schedule();
     p->eng->prepare_plain();
@@ -2037,8 +2049,7 @@ int pdcs_batch_set_schedule(pdcs_batch b, int64_t iter_max, int64_t block_nnz, i
 int pdcs_batch_set_layout(pdcs_batch b, int64_t layout) {
   return guarded([&]() {
     if (!b) throw Error(PDCS_ERR_INVALID_ARG, "batch is null");
-    if (layout != PDCS_LAYOUT_AUTO && layout != PDCS_LAYOUT_ROWS && layout != PDCS_LAYOUT_BANDS)
-      throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
+    if (layout < PDCS_LAYOUT_AUTO || layout > PDCS_LAYOUT_WORKGROUP) throw Error(PDCS_ERR_INVALID_ARG, "unknown layout");
     b->eng->layout = (int)layout;
     b->eng->build_schedule();
     return PDCS_OK;

@@ -112,12 +112,12 @@ __device__ __forceinline__ void for_cone_blocks(const Ranges& R, int b, const FN
 // ===========================================================================
 
 // K3: primal step over the columns of the instance.
+// The five passes of a trial are device functions of the workgroup's range or
+// instance, so that k_trials_wg can run them back to back inside one workgroup.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_primal(Ranges R, IterPtrs<T> it, DataPtrs<T> d,
-                                                   Inst* __restrict__ inst, int prec,
-                                                   double* __restrict__ rec) {
+__device__ __forceinline__ void primal_body(int b, const Ranges& R, const IterPtrs<T>& it, const DataPtrs<T>& d,
+                                            Inst* inst, int prec, double* rec) {
   __shared__ double lds[kWavesPerBlock * 2];
-  const int b = blockIdx.x;
   const Inst& I = inst[R.blk_inst[b]];
   if (I.status != kActive || I.precision != prec) return;
   const bool commit = I.pending != 0;
@@ -146,6 +146,13 @@ __global__ __launch_bounds__(kBlock) void k_primal(Ranges R, IterPtrs<T> it, Dat
     acc[1] += c * xn;
   }
   block_sum_store<2>(acc, lds, rec + (size_t)b * 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_primal(Ranges R, IterPtrs<T> it, DataPtrs<T> d,
+                                                   Inst* __restrict__ inst, int prec,
+                                                   double* __restrict__ rec) {
+  primal_body<T>(blockIdx.x, R, it, d, inst, prec, rec);
 }
 
 // K1: CSR SpMV G x_hat with the fused dual step.  Record: ||dy||^2,
@@ -228,11 +235,9 @@ __device__ __forceinline__ void lam_epilogue(int j, double s, const IterPtrs<T>&
 }
 
 template <typename T, typename TM>
-__global__ __launch_bounds__(kBlock) void k_dual(RowBlocks rb, MatPtrs<TM> A, IterPtrs<T> it,
-                                                 DataPtrs<T> d, Inst* __restrict__ inst, int prec,
-                                                 double* __restrict__ rec) {
+__device__ __forceinline__ void dual_body(int b, const RowBlocks& rb, const MatPtrs<TM>& A, const IterPtrs<T>& it,
+                                          const DataPtrs<T>& d, Inst* inst, int prec, double* rec) {
   __shared__ double lds[kRowBlockCap + kWavesPerBlock * 4];
-  const int b = blockIdx.x;
   const Inst& I = inst[rb.blk_inst[b]];
   if (I.status != kActive || I.precision != prec) return;
   const DualEpilogue<T> epi = make_dual_epilogue(I, it, d);
@@ -242,6 +247,13 @@ __global__ __launch_bounds__(kBlock) void k_dual(RowBlocks rb, MatPtrs<TM> A, It
                 [&](int r, const double* s) { epi(r, s[0], acc); });
   __syncthreads();
   block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
+}
+
+template <typename T, typename TM>
+__global__ __launch_bounds__(kBlock) void k_dual(RowBlocks rb, MatPtrs<TM> A, IterPtrs<T> it,
+                                                 DataPtrs<T> d, Inst* __restrict__ inst, int prec,
+                                                 double* __restrict__ rec) {
+  dual_body<T, TM>(blockIdx.x, rb, A, it, d, inst, prec, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -529,13 +541,9 @@ __global__ __launch_bounds__(kBlock) void k_lam_epi(Ranges R, const T* __restric
 }
 
 // F1: line-search decision of Function 2, one workgroup per instance.
-__global__ __launch_bounds__(kBlock) void k_fin_ls(const int32_t* __restrict__ iblk_p,
-                                                   const double* __restrict__ rec_p,
-                                                   const int32_t* __restrict__ iblk_d,
-                                                   const double* __restrict__ rec_d,
-                                                   Inst* __restrict__ inst) {
+__device__ __forceinline__ void fin_ls_body(int iid, const int32_t* iblk_p, const double* rec_p,
+                                            const int32_t* iblk_d, const double* rec_d, Inst* inst) {
   __shared__ double lds[kWavesPerBlock * 4];
-  const int iid = blockIdx.x;
   Inst& I = inst[iid];
   if (I.status != kActive) return;
   double p[2], q[4];
@@ -594,14 +602,20 @@ __global__ __launch_bounds__(kBlock) void k_fin_ls(const int32_t* __restrict__ i
   I.eta = eta_next;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fin_ls(const int32_t* __restrict__ iblk_p,
+                                                   const double* __restrict__ rec_p,
+                                                   const int32_t* __restrict__ iblk_d,
+                                                   const double* __restrict__ rec_d,
+                                                   Inst* __restrict__ inst) {
+  fin_ls_body(blockIdx.x, iblk_p, rec_p, iblk_d, rec_d, inst);
+}
+
 // K2: transposed SpMV G^T y_hat over the columns with the dual-slack epilogue.
 // Record: ||lam - Proj_Lambda lam||^2, sum l lam+, sum u lam- (finite bounds).
 template <typename T, typename TM>
-__global__ __launch_bounds__(kBlock) void k_lam(RowBlocks rb, MatPtrs<TM> AT, IterPtrs<T> it,
-                                                DataPtrs<T> d, Inst* __restrict__ inst, int prec,
-                                                double* __restrict__ rec) {
+__device__ __forceinline__ void lam_body(int b, const RowBlocks& rb, const MatPtrs<TM>& AT, const IterPtrs<T>& it,
+                                         const DataPtrs<T>& d, Inst* inst, int prec, double* rec) {
   __shared__ double lds[kRowBlockCap + kWavesPerBlock * 3];
-  const int b = blockIdx.x;
   const Inst& I = inst[rb.blk_inst[b]];
   if (I.status != kActive || I.precision != prec || I.last_acc == 0) return;
   double acc[3] = {0.0, 0.0, 0.0};
@@ -612,13 +626,17 @@ __global__ __launch_bounds__(kBlock) void k_lam(RowBlocks rb, MatPtrs<TM> AT, It
   block_sum_store<3>(acc, lds, rec + (size_t)b * 3);
 }
 
+template <typename T, typename TM>
+__global__ __launch_bounds__(kBlock) void k_lam(RowBlocks rb, MatPtrs<TM> AT, IterPtrs<T> it,
+                                                DataPtrs<T> d, Inst* __restrict__ inst, int prec,
+                                                double* __restrict__ rec) {
+  lam_body<T, TM>(blockIdx.x, rb, AT, it, d, inst, prec, rec);
+}
+
 // F2: reflection parameter at z_hat (eq. adaptive_reflection with the relative
 // errors of eq. tolerance-2), then schedule the Halpern commit.
-__global__ __launch_bounds__(kBlock) void k_fin_beta(const int32_t* __restrict__ iblk_l,
-                                                     const double* __restrict__ rec_l,
-                                                     Inst* __restrict__ inst) {
+__device__ __forceinline__ void fin_beta_body(int iid, const int32_t* iblk_l, const double* rec_l, Inst* inst) {
   __shared__ double lds[kWavesPerBlock * 3];
-  const int iid = blockIdx.x;
   Inst& I = inst[iid];
   if (I.status != kActive || I.last_acc == 0) return;
   double q[3];
@@ -659,6 +677,46 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(const int32_t* __restrict__
   if (!I.check_due && I.kbar >= I.max_iter) {
     I.status = kDone;
     I.exit_code = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_beta(const int32_t* __restrict__ iblk_l,
+                                                     const double* __restrict__ rec_l,
+                                                     Inst* __restrict__ inst) {
+  fin_beta_body(blockIdx.x, iblk_l, rec_l, inst);
+}
+
+// A chunk of K trials of one instance per workgroup (small instances, row
+// blocks): the passes of k_primal, k_dual, k_fin_ls, k_lam and k_fin_beta in
+// order over the instance's blocks, separated by workgroup barriers instead
+// of kernel boundaries.  All waves of the workgroup share one CU and its L1,
+// so a barrier makes every global write of the previous pass visible.  The
+// decisions are read from the instance record after each barrier, the same
+// for every thread, so every barrier is reached by the whole workgroup.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_trials_wg(Ranges vcol, RowBlocks brow, RowBlocks bcol, MatPtrs<T> A,
+                                                      MatPtrs<T> AT, IterPtrs<T> it, DataPtrs<T> d,
+                                                      Inst* __restrict__ inst, int prec, double* rec_p,
+                                                      double* rec_d, double* rec_l, int K) {
+  const int iid = blockIdx.x;
+  const int p0 = vcol.inst_blk0[iid], p1 = vcol.inst_blk0[iid + 1];
+  const int d0 = brow.inst_blk0[iid], d1 = brow.inst_blk0[iid + 1];
+  const int l0 = bcol.inst_blk0[iid], l1 = bcol.inst_blk0[iid + 1];
+  for (int s = 0; s < K; ++s) {
+    {
+      const Inst& I = inst[iid];
+      if (I.status != kActive || I.precision != prec) break;
+    }
+    for (int b = p0; b < p1; ++b) primal_body<T>(b, vcol, it, d, inst, prec, rec_p);
+    __syncthreads();
+    for (int b = d0; b < d1; ++b) dual_body<T, T>(b, brow, A, it, d, inst, prec, rec_d);
+    __syncthreads();
+    fin_ls_body(iid, vcol.inst_blk0, rec_p, brow.inst_blk0, rec_d, inst);
+    __syncthreads();
+    for (int b = l0; b < l1; ++b) lam_body<T, T>(b, bcol, AT, it, d, inst, prec, rec_l);
+    __syncthreads();
+    fin_beta_body(iid, bcol.inst_blk0, rec_l, inst);
+    __syncthreads();
   }
 }
 
@@ -2067,6 +2125,16 @@ void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
   if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.PAT64, k.use_band ? k.bpartT64 : k.partT64);
   k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(s2 ? k.vcol.inst_blk0 : k.bcol.inst_blk0,
                                              s2 ? k.rec_lam_epi : k.rec_lam, k.inst);
+}
+
+void launch_trials_wg(const KernelCtx& k, hipStream_t s, int mask, int K) {
+  if (k.nb < 1 || K < 1) return;
+  if (mask & 1)
+    k_trials_wg<float><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A32, k.AT32, k.it32, k.d32, k.inst, kFP32,
+                                               k.rec_primal, k.rec_dual, k.rec_lam, K);
+  if (mask & 2)
+    k_trials_wg<double><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A64, k.AT64, k.it64, k.d64, k.inst, kFP64,
+                                                k.rec_primal, k.rec_dual, k.rec_lam, K);
 }
 
 void launch_trial(const KernelCtx& k, hipStream_t s, int mask) {

@@ -82,6 +82,9 @@ struct KernelCtx {
   float *bpart32, *bpartT32;
   double *bpart64, *bpartT64, *bpart64b, *bpartT64b;  // b: second vector of the check products
 
+  // chunks of trials run by k_trials_wg (row blocks, no split, no bands)
+  int wg_trials;
+
   // the K1 (K2) product is split into partial sums plus an epilogue pass
   bool split1() const { return use_band || P1 > 1; }
   bool split2() const { return use_band || P2 > 1; }
@@ -109,6 +112,8 @@ struct SetupCtx {
 
 void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mask);
 void launch_trial(const KernelCtx& k, hipStream_t s, int mask);
+// K trials of every instance, one workgroup per instance (k.wg_trials layouts)
+void launch_trials_wg(const KernelCtx& k, hipStream_t s, int mask, int K);
 void launch_check(const KernelCtx& k, hipStream_t s, int mask);
 void launch_summary(const KernelCtx& k, hipStream_t s, int32_t* out);
 void launch_timeout(const KernelCtx& k, hipStream_t s);

@@ -5,8 +5,11 @@
 // the Adam updates.  Every GEMM is C = op(A) op(B) with row-major operands,
 // tiled 128 x 128 x 32 per workgroup (four wavefronts of 64 x 64), split along
 // K when M x N alone cannot fill the chip; split partials are summed in a fixed
-// order by the epilogue kernels (bias, ReLU, BF16 copies), so results are
-// deterministic.
+// order, so results are deterministic.  The products' epilogues do the rest of
+// a training step where the data already sits in registers: bias and ReLU in
+// the forward pass, the loss and its gradient in the output layer, the ReLU
+// mask in the backward pass, and Adam in the weight-gradient products, so FP32
+// weight gradients never travel through HBM during training.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,30 +28,33 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int TM = 128, TN = 128, TK = 32, LDK = TK + 8;  // LDS row stride: 80 B (16 B aligned)
+constexpr int TM = 128, TN = 128;
 
 __device__ __forceinline__ bf16 to_bf16(float v) { return (bf16)v; }
 
-// One operand tile (128 rows of op(X) x TK) staged through registers.  op(X)
+// One operand tile (128 rows of op(X) x KT) staged through registers.  op(X)
 // row r, column k lives at X[k * ld + r] when trans, else X[r * ld + k].  Each
-// thread owns two 8-element vectors of the tile: along k when the source is
+// thread owns KT / 16 8-element vectors of the tile: along k when the source is
 // k-contiguous (not trans), along r otherwise.  vec: the launch guarantees
 // 16-byte alignment of the source and ld % 8 == 0, so whole vectors inside the
 // bounds load with one 16-byte access; anything else loads element by element.
+// The LDS copy has rows of KT + 8 elements (16-byte aligned, staggered banks).
+template <int KT>
 struct TileRegs {
-  bf16x8 v[2];
+  bf16x8 v[KT / 16];
 };
 
+template <int KT>
 __device__ __forceinline__ void tile_load(const bf16* __restrict__ X, int ld, int trans, int vec, int r0, int R,
-                                          int k0, int kend, TileRegs& t) {
+                                          int k0, int kend, TileRegs<KT>& t) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = tid + q * 256;  // vector index in the tile: 512 vectors of 8
+  for (int q = 0; q < KT / 16; ++q) {
+    const int e = tid + q * 256;  // vector index in the tile: 16 KT vectors of 8
     int rr, kk;
     if (!trans) {
-      rr = e / (TK / 8);
-      kk = (e % (TK / 8)) * 8;
+      rr = e / (KT / 8);
+      kk = (e % (KT / 8)) * 8;
     } else {
       kk = e / (TM / 8);
       rr = (e % (TM / 8)) * 8;
@@ -74,13 +80,14 @@ __device__ __forceinline__ void tile_load(const bf16* __restrict__ X, int ld, in
   }
 }
 
-__device__ __forceinline__ void tile_store(bf16 (*S)[LDK], int trans, const TileRegs& t) {
+template <int KT>
+__device__ __forceinline__ void tile_store(bf16 (*S)[KT + 8], int trans, const TileRegs<KT>& t) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < KT / 16; ++q) {
     const int e = tid + q * 256;
     if (!trans) {
-      const int rr = e / (TK / 8), kk = (e % (TK / 8)) * 8;
+      const int rr = e / (KT / 8), kk = (e % (KT / 8)) * 8;
       *reinterpret_cast<bf16x8*>(&S[rr][kk]) = t.v[q];
     } else {
       const int kk = e / (TM / 8), rr = (e % (TM / 8)) * 8;
@@ -90,17 +97,120 @@ __device__ __forceinline__ void tile_store(bf16 (*S)[LDK], int trans, const Tile
   }
 }
 
-// C_part[z] = op(A)[m0:m0+128, kz] * op(B)[kz, n0:n0+128]
+// How a GEMM output element is used once its FP32 sum s is known.
+//   EPI_STORE: C[z][row][col] = s (split partials, or a plain FP32 product)
+//   EPI_ACT  : s (+ bias[col]), ReLU, times (mask[idx] > 0) -- the derivative of
+//              ReLU read from the BF16 activation it produced -- stored as FP32
+//              and/or BF16
+//   EPI_ADAM : s is the gradient of weight idx: Adam on the FP32 master weight
+//              and its moments, and the BF16 copy the next products read, so the
+//              gradient itself never reaches memory
+//   EPI_MSE  : s + bias[col] is the network output; with the target t
+//              (standardized per column when tmu is set) the loss gradient
+//              g = 2 (v - t) * gscale goes out as BF16, and each workgroup leaves
+//              one loss partial (FP64) and per-column sums of g for its row tile
+enum { EPI_STORE = 0, EPI_ACT = 1, EPI_ADAM = 2, EPI_MSE = 3 };
+
+struct Epi {
+  const float* bias = nullptr;
+  int relu = 0;
+  const bf16* mask = nullptr;
+  float* out32 = nullptr;
+  bf16* out16 = nullptr;
+  float *p = nullptr, *m = nullptr, *v = nullptr;
+  bf16* w16 = nullptr;
+  float lr = 0, b1 = 0, b2 = 0, eps = 0, c1 = 1, c2 = 1;
+  const float* t = nullptr;
+  const float* tmu = nullptr;
+  const float* tinv = nullptr;
+  float gscale = 0;
+  int vec4 = 0;  // EPI_ADAM: N % 4 == 0, p / m / v 16-byte and w16 8-byte aligned
+  float* colpart = nullptr;
+  double* lossp = nullptr;
+};
+
+__device__ __forceinline__ void epi_act(const Epi& e, size_t idx, int col, float s) {
+  if (e.bias) s += e.bias[col];
+  if (e.relu) s = fmaxf(s, 0.0f);
+  if (e.mask) s = (float)e.mask[idx] > 0.0f ? s : 0.0f;
+  if (e.out32) e.out32[idx] = s;
+  if (e.out16) e.out16[idx] = to_bf16(s);
+}
+
+// Raw buffer access (vector memory instructions with a uniform resource):
+// 32-bit byte offsets, per lane plus uniform.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  const i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+}
+__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float4 x) {
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  const i32x4 v = {__float_as_int(x.x), __float_as_int(x.y), __float_as_int(x.z), __float_as_int(x.w)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore_2x32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t lo,
+                                            uint32_t hi) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  const i32x2 v = {(int)lo, (int)hi};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, bf16 x) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, (int)voff, (int)soff, 0);
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// C = op(A)[M x K] op(B)[K x N] by 128 x 128 output tiles, split into
+// gridDim.x / (gx * gy) K-chunks of kchunk:
 //   op(A)[m][k] = ta ? A[k * lda + m] : A[m * lda + k]
 //   op(B)[k][n] = tb ? B[n * ldb + k] : B[k * ldb + n]
 // (op(B) is staged as its transpose, rows n, so both tiles are row x k.)
+// Workgroups are dispatched to the 8 XCDs round-robin by linear index; the
+// index is remapped so that consecutive logical tiles share an XCD, and the
+// tile order runs fastest along the shorter grid side, so the tiles that read
+// the same operand panel (the same K-chunk of a split product, the same row or
+// column panel otherwise) meet in one L2.
+template <int KIND, int KT>
 __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int lda, int ta, int veca,
                                               const bf16* __restrict__ B, int ldb, int tb, int vecb,
-                                              float* __restrict__ C, int M, int N, int K, int kchunk) {
-  __shared__ __attribute__((aligned(16))) bf16 As[TM][LDK];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[TN][LDK];
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int kbeg = blockIdx.z * kchunk;
+                                              float* __restrict__ C, int M, int N, int K, int kchunk, int gx,
+                                              int gy, Epi e) {
+  // operand tiles for the K-loop; the Adam epilogue reuses the same LDS to
+  // stage the FP32 output tile (rows padded by 4 floats)
+  constexpr int kTileBytes = (TM + TN) * (KT + 8) * 2;
+  constexpr int kStageBytes = KIND == EPI_ADAM ? TM * (TN + 4) * 4 : 0;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kTileBytes > kStageBytes ? kTileBytes : kStageBytes];
+  bf16(*As)[KT + 8] = reinterpret_cast<bf16(*)[KT + 8]>(smem);
+  bf16(*Bs)[KT + 8] = reinterpret_cast<bf16(*)[KT + 8]>(smem + TM * (KT + 8) * 2);
+  const int L = blockIdx.x, total = gridDim.x;
+  const int full = total & ~7;
+  const int Q = L < full ? (L & 7) * (full >> 3) + (L >> 3) : L;
+  const int tiles = gx * gy;
+  const int z = Q / tiles, tq = Q - z * tiles;
+  int bx, by;
+  if (gx <= gy) {
+    bx = tq % gx;
+    by = tq / gx;
+  } else {
+    by = tq % gy;
+    bx = tq / gy;
+  }
+  const int m0 = by * TM, n0 = bx * TN;
+  const int kbeg = z * kchunk;
   const int kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -111,21 +221,21 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-  TileRegs ra, rb;
+  TileRegs<KT> ra, rb;
   if (kbeg < kend) {
-    tile_load(A, lda, ta, veca, m0, M, kbeg, kend, ra);
-    tile_load(B, ldb, !tb, vecb, n0, N, kbeg, kend, rb);
+    tile_load<KT>(A, lda, ta, veca, m0, M, kbeg, kend, ra);
+    tile_load<KT>(B, ldb, !tb, vecb, n0, N, kbeg, kend, rb);
   }
-  for (int k0 = kbeg; k0 < kend; k0 += TK) {
-    tile_store(As, ta, ra);
-    tile_store(Bs, !tb, rb);
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    tile_store<KT>(As, ta, ra);
+    tile_store<KT>(Bs, !tb, rb);
     __syncthreads();
-    if (k0 + TK < kend) {  // prefetch the next tile while the matrix cores work
-      tile_load(A, lda, ta, veca, m0, M, k0 + TK, kend, ra);
-      tile_load(B, ldb, !tb, vecb, n0, N, k0 + TK, kend, rb);
+    if (k0 + KT < kend) {  // prefetch the next tile while the matrix cores work
+      tile_load<KT>(A, lda, ta, veca, m0, M, k0 + KT, kend, ra);
+      tile_load<KT>(B, ldb, !tb, vecb, n0, N, k0 + KT, kend, rb);
     }
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 16) {
+    for (int kk = 0; kk < KT; kk += 16) {
       bf16x8 a[2], b[2];
       const int ko = kk + (lane >> 5) * 8;
 #pragma unroll
@@ -139,33 +249,262 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
     }
     __syncthreads();
   }
-  float* Cz = C + (size_t)blockIdx.z * M * N;
+  // accumulator element r of acc[i][j] holds output (row0 + i*32 + (r/4)*8 + r%4, col0 + j*32)
+  const int row0 = m0 + wm + (lane >> 5) * 4, col0 = n0 + wn + (lane & 31);
+  if constexpr (KIND == EPI_STORE) {
+    float* Cz = C + (size_t)z * M * N;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm + i * 32 + (r / 4) * 8 + (lane >> 5) * 4 + (r % 4);
-        const int col = n0 + wn + j * 32 + (lane & 31);
-        if (row < M && col < N) Cz[(size_t)row * N + col] = acc[i][j][r];
+        for (int r = 0; r < 16; ++r) {
+          const int row = row0 + i * 32 + (r / 4) * 8 + (r % 4), col = col0 + j * 32;
+          if (row < M && col < N) Cz[(size_t)row * N + col] = acc[i][j][r];
+        }
+  } else if constexpr (KIND == EPI_ACT) {
+    // per 16-element group: the bias (one column) and the masks are loaded
+    // before the first store, so the loads are all in flight together
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = col0 + j * 32;
+        const float bv = (e.bias && col < N) ? e.bias[col] : 0.0f;
+        float mk[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = row0 + i * 32 + (r / 4) * 8 + (r % 4);
+          mk[r] = (e.mask && row < M && col < N) ? (float)e.mask[(size_t)row * N + col] : 1.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = row0 + i * 32 + (r / 4) * 8 + (r % 4);
+          if (row < M && col < N) {
+            float s = acc[i][j][r] + bv;
+            if (e.relu) s = fmaxf(s, 0.0f);
+            if (!(mk[r] > 0.0f)) s = 0.0f;
+            const size_t idx = (size_t)row * N + col;
+            if (e.out32) e.out32[idx] = s;
+            if (e.out16) e.out16[idx] = to_bf16(s);
+          }
+        }
       }
+  } else if constexpr (KIND == EPI_ADAM) {
+    // Element offsets are 32-bit (each weight matrix holds < 2^30 entries).
+    // Interior tiles address the moments and weights through buffer resources:
+    // one per-lane byte offset per column half plus a uniform row offset, so an
+    // element costs no address registers.  The 64 accumulators go in 8 groups
+    // of 8; the loads of group q+1 are issued before group q is updated and
+    // stored, so they are in flight meanwhile.  Tiles that stick out of the
+    // matrix take the guarded loop.
+    if (e.vec4 && m0 + TM <= M && n0 + TN <= N) {
+      // The tile goes through LDS so that each thread updates whole 16-byte
+      // runs of a row: thread t takes columns 4 (t % 32) .. +3 of rows
+      // t / 32 + 8 q (q < 16), in 4 groups of 4 rows; the first group's
+      // weights and moments are requested before the tile is staged, and each
+      // next group's before the current one is updated.
+      float(*S)[TN + 4] = reinterpret_cast<float(*)[TN + 4]>(smem);
+      const int lr = threadIdx.x >> 5, lc = (threadIdx.x & 31) * 4;
+      // buffer resources: one per-lane offset, the row step as a uniform offset
+      const uint32_t bytes = (uint32_t)M * (uint32_t)N * 4u;
+      const __amdgpu_buffer_rsrc_t rp = make_rsrc(e.p, bytes), rm = make_rsrc(e.m, bytes),
+                                   rv = make_rsrc(e.v, bytes), rw = make_rsrc(e.w16, bytes / 2);
+      const uint32_t vo = (uint32_t)(m0 + lr) * (uint32_t)N + (uint32_t)(n0 + lc);  // element offset
+      const uint32_t s8 = 8u * (uint32_t)N;                                          // elements per 8 rows
+      float4 cp[4], cm[4], cv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        cp[u] = bload4(rp, vo * 4u, (uint32_t)u * s8 * 4u);
+        cm[u] = bload4(rm, vo * 4u, (uint32_t)u * s8 * 4u);
+        cv[u] = bload4(rv, vo * 4u, (uint32_t)u * s8 * 4u);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            S[wm + i * 32 + (r / 4) * 8 + (lane >> 5) * 4 + (r % 4)][wn + j * 32 + (lane & 31)] = acc[i][j][r];
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float4 np_[4], nm[4], nv[4];
+        if (g + 1 < 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t so = (uint32_t)(4 * (g + 1) + u) * s8 * 4u;
+            np_[u] = bload4(rp, vo * 4u, so);
+            nm[u] = bload4(rm, vo * 4u, so);
+            nv[u] = bload4(rv, vo * 4u, so);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = 4 * g + u;
+          const uint32_t so = (uint32_t)q * s8;
+          const float4 g4 = *reinterpret_cast<const float4*>(&S[lr + 8 * q][lc]);
+          const float gg[4] = {g4.x, g4.y, g4.z, g4.w};
+          const float pp[4] = {cp[u].x, cp[u].y, cp[u].z, cp[u].w};
+          const float mm[4] = {cm[u].x, cm[u].y, cm[u].z, cm[u].w};
+          const float vv[4] = {cv[u].x, cv[u].y, cv[u].z, cv[u].w};
+          float po[4], mo[4], vq[4];
+          unsigned short wo[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            mo[k] = e.b1 * mm[k] + (1.0f - e.b1) * gg[k];
+            vq[k] = e.b2 * vv[k] + (1.0f - e.b2) * gg[k] * gg[k];
+            po[k] = pp[k] - e.lr * (mo[k] / e.c1) / (sqrtf(vq[k] / e.c2) + e.eps);
+            wo[k] = __builtin_bit_cast(unsigned short, to_bf16(po[k]));
+          }
+          bstore4(rm, vo * 4u, so * 4u, make_float4(mo[0], mo[1], mo[2], mo[3]));
+          bstore4(rv, vo * 4u, so * 4u, make_float4(vq[0], vq[1], vq[2], vq[3]));
+          bstore4(rp, vo * 4u, so * 4u, make_float4(po[0], po[1], po[2], po[3]));
+          bstore_2x32(rw, vo * 2u, so * 2u, (uint32_t)wo[0] | ((uint32_t)wo[1] << 16),
+                      (uint32_t)wo[2] | ((uint32_t)wo[3] << 16));
+        }
+        if (g + 1 < 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            cp[u] = np_[u];
+            cm[u] = nm[u];
+            cv[u] = nv[u];
+          }
+        }
+      }
+    } else if (m0 + TM <= M && n0 + TN <= N) {
+      const uint32_t bytes = (uint32_t)M * (uint32_t)N * 4u;
+      const __amdgpu_buffer_rsrc_t rp = make_rsrc(e.p, bytes), rm = make_rsrc(e.m, bytes),
+                                   rv = make_rsrc(e.v, bytes), rw = make_rsrc(e.w16, bytes / 2);
+      const uint32_t un = (uint32_t)N;
+      const uint32_t vbase = (uint32_t)row0 * un + (uint32_t)col0;  // element offset of (row0, col0)
+      auto soff = [&](int q, int rr) {  // uniform element offset of group q, element rr
+        const int i = q >> 2, h = q & 1;
+        return (uint32_t)(i * 32 + h * 16 + (rr / 4) * 8 + (rr % 4)) * un;
+      };
+      float cp[8], cm[8], cv[8];
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const uint32_t s = soff(0, rr) * 4u, v = vbase * 4u;
+        cp[rr] = bload(rp, v, s);
+        cm[rr] = bload(rm, v, s);
+        cv[rr] = bload(rv, v, s);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float np_[8], nm[8], nv[8];
+        if (q + 1 < 8) {
+          const uint32_t v = (vbase + (uint32_t)((((q + 1) >> 1) & 1) * 32)) * 4u;
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            const uint32_t s = soff(q + 1, rr) * 4u;
+            np_[rr] = bload(rp, v, s);
+            nm[rr] = bload(rm, v, s);
+            nv[rr] = bload(rv, v, s);
+          }
+        }
+        const int i = q >> 2, j = (q >> 1) & 1, h = q & 1;
+        const uint32_t ve = vbase + (uint32_t)(j * 32);
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+          const uint32_t s = soff(q, rr);
+          const float g = acc[i][j][h * 8 + rr];
+          const float mi = e.b1 * cm[rr] + (1.0f - e.b1) * g;
+          const float vi = e.b2 * cv[rr] + (1.0f - e.b2) * g * g;
+          const float pi = cp[rr] - e.lr * (mi / e.c1) / (sqrtf(vi / e.c2) + e.eps);
+          bstore(rm, ve * 4u, s * 4u, mi);
+          bstore(rv, ve * 4u, s * 4u, vi);
+          bstore(rp, ve * 4u, s * 4u, pi);
+          bstore16(rw, ve * 2u, s * 2u, to_bf16(pi));
+        }
+        if (q + 1 < 8) {
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            cp[rr] = np_[rr];
+            cm[rr] = nm[rr];
+            cv[rr] = nv[rr];
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = row0 + i * 32 + (r / 4) * 8 + (r % 4), col = col0 + j * 32;
+            if (row < M && col < N) {
+              const uint32_t o = (uint32_t)row * (uint32_t)N + (uint32_t)col;
+              const float g = acc[i][j][r];
+              const float mi = e.b1 * e.m[o] + (1.0f - e.b1) * g;
+              const float vi = e.b2 * e.v[o] + (1.0f - e.b2) * g * g;
+              const float pi = e.p[o] - e.lr * (mi / e.c1) / (sqrtf(vi / e.c2) + e.eps);
+              e.m[o] = mi;
+              e.v[o] = vi;
+              e.p[o] = pi;
+              e.w16[o] = to_bf16(pi);
+            }
+          }
+    }
+  } else {
+    static_assert(KIND == EPI_MSE, "unknown epilogue");
+    __shared__ float csum[2][TN];
+    __shared__ double lsum[4];
+    float cs[2] = {0.0f, 0.0f};
+    double e2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = col0 + j * 32;
+        const bool cok = col < N;
+        const float bv = cok ? e.bias[col] : 0.0f;
+        const float mu = (cok && e.tmu) ? e.tmu[col] : 0.0f;
+        const float inv = (cok && e.tmu) ? e.tinv[col] : 1.0f;
+        float tv[16];  // targets of the group, loaded before the first store
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = row0 + i * 32 + (r / 4) * 8 + (r % 4);
+          tv[r] = (row < M && cok) ? e.t[(size_t)row * N + col] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = row0 + i * 32 + (r / 4) * 8 + (r % 4);
+          if (row < M && cok) {
+            const float vo = acc[i][j][r] + bv;
+            const float tt = e.tmu ? (tv[r] - mu) * inv : tv[r];
+            const float d = vo - tt;
+            e2 += (double)d * (double)d;
+            const float g = 2.0f * d * e.gscale;
+            e.out16[(size_t)row * N + col] = to_bf16(g);
+            cs[j] += g;
+          }
+        }
+      }
+    // column sums: the two row halves of the wave, then the two waves of a column half
+#pragma unroll
+    for (int j = 0; j < 2; ++j) cs[j] += __shfl_xor(cs[j], 32, 64);
+    if (lane < 32) {
+      csum[wave >> 1][wn + lane] = cs[0];
+      csum[wave >> 1][wn + 32 + lane] = cs[1];
+    }
+    e2 = wave_sum64(e2);
+    if (lane == 0) lsum[wave] = e2;
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < TN && n0 + c < N) e.colpart[(size_t)by * N + n0 + c] = csum[0][c] + csum[1][c];
+    if (threadIdx.x == 0) e.lossp[(size_t)by * gx + bx] = ((lsum[0] + lsum[1]) + lsum[2]) + lsum[3];
+  }
 }
 
-// out = sum_z part[z] (+ bias[col]) then optional ReLU; FP32 and/or BF16 copies.
-// grad_mask: when non-null, out = sum * (mask > 0) (derivative of ReLU at mask).
-__global__ void k_epilogue(const float* __restrict__ part, int splits, int64_t MN, int N,
-                           const float* __restrict__ bias, int relu, const float* __restrict__ grad_mask,
-                           float* __restrict__ out32, bf16* __restrict__ out16) {
+// Split products: out = sum_z part[z] in a fixed order, then the EPI_ACT use.
+__global__ void k_epilogue(const float* __restrict__ part, int splits, int64_t MN, int N, Epi e) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= MN) return;
   float s = 0.0f;
   for (int z = 0; z < splits; ++z) s += part[(size_t)z * MN + i];
-  if (bias) s += bias[i % N];
-  if (relu) s = fmaxf(s, 0.0f);
-  if (grad_mask) s = grad_mask[i] > 0.0f ? s : 0.0f;
-  if (out32) out32[i] = s;
-  if (out16) out16[i] = to_bf16(s);
+  epi_act(e, (size_t)i, (int)(i % N), s);
 }
 
 __global__ void k_to_bf16(const float* __restrict__ in, bf16* __restrict__ out, int64_t n) {
@@ -173,17 +512,37 @@ __global__ void k_to_bf16(const float* __restrict__ in, bf16* __restrict__ out, 
   if (i < n) out[i] = to_bf16(in[i]);
 }
 
-// Standardized BF16 input: (u - mean) / scale per feature (identity when mean is null).
+// Standardized BF16 input: (u - mean) / scale per feature (identity when mean
+// is null).  Four consecutive elements per thread (one 16-byte load, one
+// 8-byte store) when vec4 (n % 4 == 0 and both arrays 16 / 8-byte aligned).
 __global__ void k_in_norm(const float* __restrict__ in, const float* __restrict__ mu,
-                          const float* __restrict__ inv_scale, int64_t n, int d, bf16* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float v = in[i];
+                          const float* __restrict__ inv_scale, int64_t n, int d, int vec4, bf16* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec4) {
+    if (4 * t >= n) return;
+    const float4 v4 = reinterpret_cast<const float4*>(in)[t];
+    float v[4] = {v4.x, v4.y, v4.z, v4.w};
+    if (mu) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = (int)((4 * t + k) % d);
+        v[k] = (v[k] - mu[j]) * inv_scale[j];
+      }
+    }
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    bf16x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = to_bf16(v[k]);
+    reinterpret_cast<bf16x4*>(out)[t] = o;
+    return;
+  }
+  if (t >= n) return;
+  float v = in[t];
   if (mu) {
-    const int j = (int)(i % d);
+    const int j = (int)(t % d);
     v = (v - mu[j]) * inv_scale[j];
   }
-  out[i] = to_bf16(v);
+  out[t] = to_bf16(v);
 }
 
 // Network output in the caller's units: z * scale + mean per feature.
@@ -197,36 +556,6 @@ __global__ void k_out_denorm(const float* __restrict__ z, const float* __restric
     v = v * scale[j] + mu[j];
   }
   out[i] = v;
-}
-
-// Per-block partial sums of (v - t)^2 with t standardized like the outputs
-// ((t - mean) / scale per feature when mean is non-null); dv = 2 (v - t) / count;
-// BF16 copy of dv.
-__global__ void k_mse(const float* __restrict__ v, const float* __restrict__ t, int64_t n, float scale,
-                      const float* __restrict__ tmu, const float* __restrict__ tinv, int d,
-                      float* __restrict__ dv, bf16* __restrict__ dv16, double* __restrict__ part) {
-  __shared__ double red[256];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double e2 = 0.0;
-  if (i < n) {
-    float ti = t[i];
-    if (tmu) {
-      const int j = (int)(i % d);
-      ti = (ti - tmu[j]) * tinv[j];
-    }
-    const float d = v[i] - ti;
-    e2 = (double)d * (double)d;
-    const float g = 2.0f * d * scale;
-    dv[i] = g;
-    dv16[i] = to_bf16(g);
-  }
-  red[threadIdx.x] = e2;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 __global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, float* __restrict__ out) {
@@ -251,7 +580,33 @@ __global__ void k_colsum(const float* __restrict__ g, int rows, int cols, float*
   out[c] = s;
 }
 
-// Adam step on the FP32 master weights; BF16 copies of the weight matrices.
+// First level of a column sum over many rows: workgroup (x, y) adds rows
+// [y * chunk, (y + 1) * chunk) of 64 columns, wave w taking every fourth row
+// from w with four independent partial sums; part[y][col] = the waves' sums in
+// order.  Fixed order: deterministic.
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ g, int rows, int cols, int chunk,
+                                                     float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  if (c < cols) {
+    int r = r0 + wave;
+    for (; r + 12 < r1; r += 16) {
+      s0 += g[(size_t)r * cols + c];
+      s1 += g[(size_t)(r + 4) * cols + c];
+      s2 += g[(size_t)(r + 8) * cols + c];
+      s3 += g[(size_t)(r + 12) * cols + c];
+    }
+    for (; r < r1; r += 4) s0 += g[(size_t)r * cols + c];
+  }
+  red[wave][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (wave == 0 && c < cols) part[(size_t)blockIdx.y * cols + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// Adam step on FP32 parameters (the biases; weights are updated inside their gradient products).
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
                        float c2) {
@@ -279,9 +634,14 @@ struct pdcs_mlp_s {
   const float* imu() const { return norm_in ? in_mu.as<float>() : nullptr; }
   const float* omu() const { return norm_out ? out_mu.as<float>() : nullptr; }
   int64_t step = 0;
-  int64_t cap = 0;  // batch capacity of the activation buffers
-  DBuf u16, z1, h1_16, z2, h2_16, vout, dv, dv16, dh, dz16a, dz16b, part, lossp, lossv;
-  size_t part_bytes = 0;
+  int64_t cap = 0;    // batch capacity of the activation buffers
+  int64_t last = 0;   // batch of the last forward / gradient / training call
+  bool have_grad_acts = false;  // the last call computed the backward activations
+  // activations: BF16 operands of the products (input, h1, h2, dL/dv, dL/dz2,
+  // dL/dz1), the FP32 output, FP32 masked hidden gradients (bias sums), the
+  // loss gradient's per-row-tile column sums and the loss partials
+  DBuf u16, h1_16, h2_16, vout, dv16, dz16a, dz16b, dh, colpart, part, cspart, lossp, lossv;
+  size_t part_bytes = 0, cs_bytes = 0;
   hipStream_t stream = nullptr;
 
   bf16* W1() const { return wbf.as<bf16>(); }
@@ -289,6 +649,8 @@ struct pdcs_mlp_s {
   bf16* W3() const { return wbf.as<bf16>() + w * din + w * w; }
   float* P(int64_t off) const { return params.as<float>() + off; }
   float* G(int64_t off) const { return grads.as<float>() + off; }
+  float* Mo(int64_t off) const { return adam_m.as<float>() + off; }
+  float* Vo(int64_t off) const { return adam_v.as<float>() + off; }
 
   void refresh_bf16(hipStream_t s) {
     k_to_bf16<<<lin(w * din), 256, 0, s>>>(P(off_w1), W1(), w * din);
@@ -299,80 +661,207 @@ struct pdcs_mlp_s {
   void ensure(int64_t B) {
     if (B <= cap) return;
     cap = B;
+    const int64_t rt = (B + TM - 1) / TM;  // row tiles of the output layer
     u16.alloc(B * din * 2);
-    z1.alloc(B * w * 4);
     h1_16.alloc(B * w * 2);
-    z2.alloc(B * w * 4);
     h2_16.alloc(B * w * 2);
     vout.alloc(B * dout * 4);
-    dv.alloc(B * dout * 4);
     dv16.alloc(B * dout * 2);
-    dh.alloc(B * w * 4);
     dz16a.alloc(B * w * 2);
     dz16b.alloc(B * w * 2);
-    lossp.alloc(((B * dout + 255) / 256) * 8);
+    dh.alloc(B * w * 4);
+    colpart.alloc(rt * dout * 4);
+    lossp.alloc(rt * ((dout + TN - 1) / TN) * 8);
     lossv.alloc(8);
   }
 
-  // C[M x N] (+bias, relu | grad mask) <- op(A) op(B); split along K as needed.
-  void gemm(const bf16* A, int lda, int ta, const bf16* Bm, int ldb, int tb, int M, int N, int K,
-            const float* bias, int relu, const float* mask, float* out32, bf16* out16, hipStream_t s) {
+  // op(A)[M x K] op(B)[K x N] with epilogue `kind`.  Products whose output tiles
+  // alone cannot fill the chip are split along K (EPI_STORE / EPI_ACT only);
+  // the partials are then summed in a fixed order.  EPI_STORE writes e.out32.
+  // The tile depth grows with the K-range of a workgroup: each step of the
+  // K-loop costs about one memory latency, so long ranges take deep steps.
+  void gemm(int kind, const bf16* A, int lda, int ta, const bf16* Bm, int ldb, int tb, int M, int N, int K,
+            Epi e, hipStream_t s) {
     const int gx = (N + TN - 1) / TN, gy = (M + TM - 1) / TM;
-    int splits = 1;
     const int tiles = gx * gy;
-    while (tiles * splits < 512 && K / (splits * 2) >= 256) splits *= 2;
+    if (kind == EPI_ADAM) e.vec4 = adam_vec4(e, N);
+    int splits = 1;
+    if (kind == EPI_STORE || kind == EPI_ACT)
+      while (tiles * splits < 512 && K / (splits * 2) >= 256) splits *= 2;
     int kchunk = (K + splits - 1) / splits;
-    kchunk = (kchunk + TK - 1) / TK * TK;
+    const int kt = kchunk >= 512 ? 128 : (kchunk >= 128 ? 64 : 32);
+    kchunk = (kchunk + kt - 1) / kt * kt;
     splits = (K + kchunk - 1) / kchunk;
-    // unsplit products with a plain FP32 result are written in place
-    const bool direct = splits == 1 && !bias && !relu && !mask && out32 && !out16;
-    const size_t need = (size_t)splits * M * N * 4;
-    if (!direct && need > part_bytes) {
-      part.alloc(need);
-      part_bytes = need;
+    if (splits < 1) splits = 1;
+    if (splits > 1) {
+      const size_t need = (size_t)splits * M * N * 4;
+      if (need > part_bytes) {
+        part.alloc(need);
+        part_bytes = need;
+      }
+      launch(EPI_STORE, kt, A, lda, ta, Bm, ldb, tb, part.as<float>(), M, N, K, kchunk, gx, gy, splits, e, s);
+      k_epilogue<<<lin((int64_t)M * N), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, e);
+      return;
     }
+    launch(kind, kt, A, lda, ta, Bm, ldb, tb, kind == EPI_STORE ? e.out32 : nullptr, M, N, K, kchunk, gx, gy, 1, e, s);
+  }
+
+  template <int KIND>
+  static void launch_kt(int kt, dim3 grid, const bf16* A, int lda, int ta, int veca, const bf16* Bm, int ldb, int tb,
+                        int vecb, float* C, int M, int N, int K, int kchunk, int gx, int gy, const Epi& e,
+                        hipStream_t s) {
+    if (kt == 128)
+      k_gemm<KIND, 128><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e);
+    else if (kt == 64)
+      k_gemm<KIND, 64><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e);
+    else
+      k_gemm<KIND, 32><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e);
+  }
+
+  static void launch(int kind, int kt, const bf16* A, int lda, int ta, const bf16* Bm, int ldb, int tb, float* C, int M,
+                     int N, int K, int kchunk, int gx, int gy, int splits, const Epi& e, hipStream_t s) {
     // 16-byte vector loads need 16-byte aligned operands with row strides in whole vectors
     const int veca = ((uintptr_t)A % 16 == 0 && lda % 8 == 0) ? 1 : 0;
     const int vecb = ((uintptr_t)Bm % 16 == 0 && ldb % 8 == 0) ? 1 : 0;
-    k_gemm<<<dim3(gx, gy, splits), 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb,
-                                               direct ? out32 : part.as<float>(), M, N, K, kchunk);
-    if (!direct)
-      k_epilogue<<<lin((int64_t)M * N), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, bias, relu,
-                                                     mask, out32, out16);
+    const dim3 grid((unsigned)(gx * gy * splits));
+    switch (kind) {
+      case EPI_STORE:
+        launch_kt<EPI_STORE>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        break;
+      case EPI_ACT:
+        launch_kt<EPI_ACT>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        break;
+      case EPI_ADAM:
+        launch_kt<EPI_ADAM>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        break;
+      default:
+        launch_kt<EPI_MSE>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+    }
+  }
+
+  // Column sums of g [rows x cols] into out (fixed order): one pass for a few
+  // rows, else 32-row partial sums by many workgroups, then their sum.
+  void colsum(const float* g, int64_t rows, int64_t cols, float* out, hipStream_t s) {
+    if (rows <= 32) {
+      k_colsum<<<lin(cols), 256, 0, s>>>(g, (int)rows, (int)cols, out);
+      return;
+    }
+    const int chunk = 32;
+    const int64_t ny = (rows + chunk - 1) / chunk;
+    const size_t need = (size_t)ny * cols * 4;
+    if (need > cs_bytes) {
+      cspart.alloc(need);
+      cs_bytes = need;
+    }
+    k_colsum_part<<<dim3((unsigned)((cols + 63) / 64), (unsigned)ny), 256, 0, s>>>(g, (int)rows, (int)cols, chunk,
+                                                                                  cspart.as<float>());
+    k_colsum<<<lin(cols), 256, 0, s>>>(cspart.as<float>(), (int)ny, (int)cols, out);
+  }
+
+  static Epi act(const float* bias, int relu, const bf16* mask, float* out32, bf16* out16) {
+    Epi e;
+    e.bias = bias;
+    e.relu = relu;
+    e.mask = mask;
+    e.out32 = out32;
+    e.out16 = out16;
+    return e;
+  }
+
+  // Adam (step `step`, learning rate lr) on the weights at offset off: the
+  // weight-gradient product's epilogue when `adam`, else the gradient is stored.
+  Epi wgrad(bool adam, int64_t off, bf16* w16, float lr) const {
+    Epi e;
+    if (!adam) {
+      e.out32 = G(off);
+      return e;
+    }
+    e.p = P(off);
+    e.m = Mo(off);
+    e.v = Vo(off);
+    e.w16 = w16;
+    e.lr = lr;
+    e.b1 = 0.9f;
+    e.b2 = 0.999f;
+    e.eps = 1e-8f;
+    e.c1 = 1.0f - std::pow(e.b1, (float)step);
+    e.c2 = 1.0f - std::pow(e.b2, (float)step);
+    return e;
+  }
+
+  // 16-byte runs of weight rows: the Adam epilogue's staged path
+  static int adam_vec4(const Epi& e, int64_t N) {
+    return (N % 4 == 0 && (uintptr_t)e.p % 16 == 0 && (uintptr_t)e.m % 16 == 0 && (uintptr_t)e.v % 16 == 0 &&
+            (uintptr_t)e.w16 % 8 == 0)
+               ? 1
+               : 0;
+  }
+
+  // Standardized BF16 input and the two hidden layers (BF16, after ReLU).
+  void hidden(const float* in, int64_t B, hipStream_t s) {
+    ensure(B);
+    last = B;
+    const int64_t n = B * din;
+    const int vec4 = (n % 4 == 0 && (uintptr_t)in % 16 == 0 && (uintptr_t)u16.p % 8 == 0) ? 1 : 0;
+    k_in_norm<<<lin(vec4 ? n / 4 : n), 256, 0, s>>>(in, imu(), in_inv.as<float>(), n, (int)din, vec4, u16.as<bf16>());
+    gemm(EPI_ACT, u16.as<bf16>(), din, 0, W1(), din, 1, B, w, din, act(P(off_b1), 1, nullptr, nullptr, h1_16.as<bf16>()),
+         s);
+    gemm(EPI_ACT, h1_16.as<bf16>(), w, 0, W2(), w, 1, B, w, w, act(P(off_b2), 1, nullptr, nullptr, h2_16.as<bf16>()),
+         s);
   }
 
   void forward(const float* in, int64_t B, hipStream_t s) {
-    ensure(B);
-    k_in_norm<<<lin(B * din), 256, 0, s>>>(in, imu(), in_inv.as<float>(), B * din, (int)din, u16.as<bf16>());
-    gemm(u16.as<bf16>(), din, 0, W1(), din, 1, B, w, din, P(off_b1), 1, nullptr, z1.as<float>(), h1_16.as<bf16>(), s);
-    gemm(h1_16.as<bf16>(), w, 0, W2(), w, 1, B, w, w, P(off_b2), 1, nullptr, z2.as<float>(), h2_16.as<bf16>(), s);
-    gemm(h2_16.as<bf16>(), w, 0, W3(), w, 1, B, dout, w, P(off_b3), 0, nullptr, vout.as<float>(), nullptr, s);
+    hidden(in, B, s);
+    have_grad_acts = false;
+    gemm(EPI_ACT, h2_16.as<bf16>(), w, 0, W3(), w, 1, B, dout, w, act(P(off_b3), 0, nullptr, vout.as<float>(), nullptr),
+         s);
   }
 
-  // Gradients of the mean squared error into `grads`; loss (host) returned.
-  float backward(const float* target, int64_t B, hipStream_t s) {
+  // Forward and backward of the mean squared error; the weight gradients are
+  // stored in `grads`, or, when `adam`, applied as an Adam step inside the
+  // weight-gradient products (each layer's BF16 weights are read by the
+  // backward product before its own update rewrites them).  Bias gradients go
+  // to `grads` either way; the loss stays on the device (lossv).
+  void train(const float* in, const float* target, int64_t B, bool adam, float lr, hipStream_t s) {
+    hidden(in, B, s);
+    have_grad_acts = true;
     const int64_t n = B * dout;
-    const int nb = (int)((n + 255) / 256);
-    k_mse<<<nb, 256, 0, s>>>(vout.as<float>(), target, n, 1.0f / (float)n, omu(), out_inv.as<float>(), (int)dout,
-                             dv.as<float>(), dv16.as<bf16>(), lossp.as<double>());
-    k_sum_parts<<<1, 256, 0, s>>>(lossp.as<double>(), nb, 1.0 / (double)n, lossv.as<float>());
-    // layer 3: dW3 = dV^T H2, db3 = colsum dV, dH2 = dV W3, dZ2 = dH2 * (z2 > 0)
-    gemm(dv16.as<bf16>(), dout, 1, h2_16.as<bf16>(), w, 0, dout, w, B, nullptr, 0, nullptr, G(off_w3), nullptr, s);
-    k_colsum<<<lin(dout), 256, 0, s>>>(dv.as<float>(), B, dout, G(off_b3));
-    gemm(dv16.as<bf16>(), dout, 0, W3(), w, 0, B, w, dout, nullptr, 0, z2.as<float>(), dh.as<float>(),
-         dz16a.as<bf16>(), s);
-    // layer 2
-    gemm(dz16a.as<bf16>(), w, 1, h1_16.as<bf16>(), w, 0, w, w, B, nullptr, 0, nullptr, G(off_w2), nullptr, s);
-    k_colsum<<<lin(w), 256, 0, s>>>(dh.as<float>(), B, w, G(off_b2));
-    gemm(dz16a.as<bf16>(), w, 0, W2(), w, 0, B, w, w, nullptr, 0, z1.as<float>(), dh.as<float>(), dz16b.as<bf16>(),
-         s);
-    // layer 1
-    gemm(dz16b.as<bf16>(), w, 1, u16.as<bf16>(), din, 0, w, din, B, nullptr, 0, nullptr, G(off_w1), nullptr, s);
-    k_colsum<<<lin(w), 256, 0, s>>>(dh.as<float>(), B, w, G(off_b1));
-    float loss = 0.0f;
-    HIP_OK(hipMemcpyAsync(&loss, lossv.p, 4, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    return loss;
+    const int rt = (int)((B + TM - 1) / TM), ct = (int)((dout + TN - 1) / TN);
+    // output layer fused with the loss: dv16 = BF16 dL/dv, column sums, loss partials
+    Epi mse;
+    mse.bias = P(off_b3);
+    mse.t = target;
+    mse.tmu = omu();
+    mse.tinv = out_inv.as<float>();
+    mse.gscale = 1.0f / (float)n;
+    mse.out16 = dv16.as<bf16>();
+    mse.colpart = colpart.as<float>();
+    mse.lossp = lossp.as<double>();
+    gemm(EPI_MSE, h2_16.as<bf16>(), w, 0, W3(), w, 1, B, dout, w, mse, s);
+    k_sum_parts<<<1, 256, 0, s>>>(lossp.as<double>(), rt * ct, 1.0 / (double)n, lossv.as<float>());
+    colsum(colpart.as<float>(), rt, dout, G(off_b3), s);
+    // layer 3: dZ2 = (dV W3) * (h2 > 0) before W3 changes, then dW3 = dV^T H2
+    gemm(EPI_ACT, dv16.as<bf16>(), dout, 0, W3(), w, 0, B, w, dout,
+         act(nullptr, 0, h2_16.as<bf16>(), dh.as<float>(), dz16a.as<bf16>()), s);
+    gemm(adam ? EPI_ADAM : EPI_STORE, dv16.as<bf16>(), dout, 1, h2_16.as<bf16>(), w, 0, dout, w, B,
+         wgrad(adam, off_w3, W3(), lr), s);
+    colsum(dh.as<float>(), B, w, G(off_b2), s);
+    // layer 2: dZ1 = (dZ2 W2) * (h1 > 0), then dW2 = dZ2^T H1
+    gemm(EPI_ACT, dz16a.as<bf16>(), w, 0, W2(), w, 0, B, w, w,
+         act(nullptr, 0, h1_16.as<bf16>(), dh.as<float>(), dz16b.as<bf16>()), s);
+    gemm(adam ? EPI_ADAM : EPI_STORE, dz16a.as<bf16>(), w, 1, h1_16.as<bf16>(), w, 0, w, w, B,
+         wgrad(adam, off_w2, W2(), lr), s);
+    colsum(dh.as<float>(), B, w, G(off_b1), s);
+    // layer 1: dW1 = dZ1^T U
+    gemm(adam ? EPI_ADAM : EPI_STORE, dz16b.as<bf16>(), w, 1, u16.as<bf16>(), din, 0, w, din, B,
+         wgrad(adam, off_w1, W1(), lr), s);
+    if (adam) {  // the biases: FP32 only, one small pass each
+      const Epi e = wgrad(true, off_b1, nullptr, lr);
+      const int64_t offs[3] = {off_b1, off_b2, off_b3}, cnt[3] = {w, w, dout};
+      for (int q = 0; q < 3; ++q)
+        k_adam<<<lin(cnt[q]), 256, 0, s>>>(P(offs[q]), G(offs[q]), Mo(offs[q]), Vo(offs[q]), cnt[q], lr, e.b1, e.b2,
+                                           e.eps, e.c1, e.c2);
+    }
   }
 };
 
@@ -380,8 +869,9 @@ extern "C" {
 
 int pdcs_mlp_create(int64_t d_in, int64_t width, int64_t d_out, uint64_t seed, pdcs_mlp* out) {
   try {
-    if (!out || d_in < 1 || width < 1 || d_out < 1 || d_in > (1 << 26) || d_out > (1 << 26) || width > 8192)
-      throw Error(PDCS_ERR_INVALID_ARG, "bad MLP sizes");
+    if (!out || d_in < 1 || width < 1 || d_out < 1 || d_in > (1 << 26) || d_out > (1 << 26) || width > 8192 ||
+        width * d_in >= ((int64_t)1 << 30) || width * d_out >= ((int64_t)1 << 30))
+      throw Error(PDCS_ERR_INVALID_ARG, "bad MLP sizes (each weight matrix must hold fewer than 2^30 entries)");
     *out = nullptr;
     auto net = new pdcs_mlp_s();
     std::unique_ptr<pdcs_mlp_s> guard(net);
@@ -454,9 +944,11 @@ int pdcs_mlp_gradients(pdcs_mlp net, const float* in_dev, const float* target_de
   try {
     if (!net || !in_dev || !target_dev || batch < 1) throw Error(PDCS_ERR_INVALID_ARG, "bad gradient arguments");
     hipStream_t s = pick(net, stream);
-    net->forward(in_dev, batch, s);
-    const float loss = net->backward(target_dev, batch, s);
+    net->train(in_dev, target_dev, batch, false, 0.0f, s);
     if (grad_dev) HIP_OK(hipMemcpyAsync(grad_dev, net->grads.p, net->np * 4, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipGetLastError());
+    float loss = 0.0f;
+    HIP_OK(hipMemcpyAsync(&loss, net->lossv.p, 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (loss_out) *loss_out = loss;
     return PDCS_OK;
@@ -472,17 +964,39 @@ int pdcs_mlp_train_step(pdcs_mlp net, const float* in_dev, const float* target_d
     if (!net || !in_dev || !target_dev || batch < 1 || !(lr > 0.0f))
       throw Error(PDCS_ERR_INVALID_ARG, "bad train arguments");
     hipStream_t s = pick(net, stream);
-    net->forward(in_dev, batch, s);
-    const float loss = net->backward(target_dev, batch, s);
     net->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.0f - std::pow(b1, (float)net->step), c2 = 1.0f - std::pow(b2, (float)net->step);
-    k_adam<<<lin(net->np), 256, 0, s>>>(net->params.as<float>(), net->grads.as<float>(), net->adam_m.as<float>(),
-                                        net->adam_v.as<float>(), net->np, lr, b1, b2, eps, c1, c2);
-    net->refresh_bf16(s);
+    net->train(in_dev, target_dev, batch, true, lr, s);
     HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(s));
-    if (loss_out) *loss_out = loss;
+    if (loss_out) {  // without a loss pointer the step stays asynchronous on `stream`
+      float loss = 0.0f;
+      HIP_OK(hipMemcpyAsync(&loss, net->lossv.p, 4, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      *loss_out = loss;
+    }
+    return PDCS_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  }
+}
+
+int pdcs_mlp_activation(pdcs_mlp net, int64_t which, float* host_out, int64_t count) {
+  try {
+    if (!net || !host_out || which < 0 || which > 5) throw Error(PDCS_ERR_INVALID_ARG, "bad activation arguments");
+    if (net->last < 1 || (which >= 3 && !net->have_grad_acts))
+      throw Error(PDCS_ERR_INVALID_ARG, "no activation of that kind from the last call");
+    const int64_t B = net->last;
+    const bf16* src[6] = {net->u16.as<bf16>(), net->h1_16.as<bf16>(), net->h2_16.as<bf16>(),
+                          net->dv16.as<bf16>(), net->dz16a.as<bf16>(), net->dz16b.as<bf16>()};
+    const int64_t dim[6] = {net->din, net->w, net->w, net->dout, net->w, net->w};
+    if (count != B * dim[which]) throw Error(PDCS_ERR_INVALID_ARG, "count must be batch x features");
+    HIP_OK(hipDeviceSynchronize());
+    std::vector<uint16_t> raw(count);
+    HIP_OK(hipMemcpy(raw.data(), src[which], count * 2, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count; ++i) {
+      const uint32_t bits = (uint32_t)raw[i] << 16;
+      std::memcpy(&host_out[i], &bits, 4);
+    }
     return PDCS_OK;
   } catch (const Error& e) {
     set_last_error(e.what());

@@ -37,7 +37,7 @@ def _warm(inst, seed=0, noise=0.05):
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 def test_device_warm_start_equals_host_warm_start(dtype, layout):
     inst = lpgen.c0_instance(5)
     x0, y0 = _warm(inst)
@@ -110,7 +110,7 @@ def test_host_batch_warm_start_lengths_checked():
         batch.solve(x0s=[np.zeros(insts[0].n)])
 
 
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 def test_device_results_equal_host_results(layout):
     inst = lpgen.c0_instance(7)
     prob = P.Problem.from_instance(inst)

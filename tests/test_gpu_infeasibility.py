@@ -37,7 +37,7 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_exit_codes_match_oracle(name, layout, precision):
     gen, kw, allowed = CASES[name]
@@ -55,7 +55,7 @@ def test_exit_codes_match_oracle(name, layout, precision):
 
 
 @pytest.mark.parametrize("name", ["free_columns", "free_pair", "sum_row"])
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 def test_first_check_ratios_match_oracle(name, layout):
     gen, kw, _ = CASES[name]
     inst = gen(1)
@@ -74,7 +74,7 @@ def test_first_check_ratios_match_oracle(name, layout):
             assert got == pytest.approx(want, rel=1e-9, abs=1e-300), key
 
 
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_feasible_lps_with_unbounded_columns_stay_optimal(layout, precision):
     # the tests are on by default: feasible LPs with free, one-sided and boxed

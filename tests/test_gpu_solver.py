@@ -105,7 +105,7 @@ def _edge_lp():
     return lpgen.LPInstance(inst.m, inst.n, inst.m_zero, rp, ci.astype(np.int32), v, h, c, l, u, name="edge")
 
 
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 @pytest.mark.parametrize("mz", [None, 60, "edge"])
 def test_first_trials_match_oracle_elementwise(mz, layout):
     # Before the first restart check the iteration is deterministic: after N
@@ -362,7 +362,7 @@ def edge_ref():
     return inst, ref
 
 
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_edge_lp_solves(edge_ref, layout, precision):
     inst, ref = edge_ref
@@ -374,7 +374,7 @@ def test_edge_lp_solves(edge_ref, layout, precision):
 
 
 @pytest.mark.parametrize("variant", ["average", "halpern", "kkt"])
-@pytest.mark.parametrize("layout", ["rows", "bands"])
+@pytest.mark.parametrize("layout", ["rows", "bands", "workgroup"])
 def test_restart_variants_match_oracle(variant, layout):
     # the candidate rules of Section 2.3 (average only, Halpern only) and the
     # KKT restart option, each against the oracle run with the same option
@@ -407,3 +407,36 @@ def test_restart_variants_first_check_matches_oracle(variant):
     assert sol.info["restarts"] == ref.restarts
     assert st["omega"] == pytest.approx(ref.state["omega"], rel=1e-9)
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workgroup_layout_is_bit_identical_to_rows(precision):
+    # the single-workgroup chunk kernel runs the same passes over the same
+    # blocks as the row-block kernels, only separated by barriers instead of
+    # launches: every iterate agrees bit for bit, across restart checks too
+    inst = lpgen.c0_instance(3)
+    states = {}
+    for layout in ("rows", "workgroup"):
+        prob = P.Problem.from_instance(inst)
+        prob.set_layout(layout)
+        sol = prob.solve(precision=precision, max_iter=700, check_every=64, keep_state=True)
+        states[layout] = sol
+    a, b = states["rows"], states["workgroup"]
+    assert a.info["iters"] == b.info["iters"] and a.info["restarts"] == b.info["restarts"]
+    for key in ("x", "y", "x_hat", "y_hat", "x_a", "y_a"):
+        assert np.array_equal(a.state[key], b.state[key]), key
+
+
+def test_workgroup_layout_batch_matches_oracle():
+    # uneven small instances, one workgroup each, with restarts and compaction
+    insts = [lpgen.planted_lp(lpgen.rng_for(90, s), m, 2 * m, per_col=4, m_zero=m // 3)
+             for s, m in enumerate((30, 75, 160, 240))]
+    b = P.Batch([P.Problem.from_instance(i) for i in insts])
+    b.set_layout("workgroup")
+    for inst, sol in zip(insts, b.solve(precision="fp64", time_limit=60.0)):
+        lp = O.lpdata_from_instance(inst)
+        ref = O.solve(lp, O.Options(rel_tol=1e-9, abs_tol=1e-9, time_limit=300))
+        err = O.termination_errors(lp, sol.x, sol.y)
+        assert sol.info["exit_code"] == 0, sol.info
+        assert max(err["rel_p"], err["rel_d"], err["rel_gap"]) <= 1e-6 * 1.0001
+        assert abs(err["pobj"] - ref.pobj) / (1 + abs(ref.pobj)) <= 2e-6
