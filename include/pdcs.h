@@ -275,8 +275,12 @@ int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
  *                      launches (latency-bound small instances);
  *   PDCS_LAYOUT_AUTO : bands for problems (and batches, see
  *                      pdcs_batch_set_layout) with at least 2^22 nonzeros,
- *                      the workgroup layout when every instance has at most
- *                      2^15 nonzeros and no cone blocks, else rows.
+ *                      the workgroup layout when every instance (iterates,
+ *                      data and both CSR copies, FP64) fits in the LDS of one
+ *                      workgroup (about 120 KiB: e.g. 200 rows, 500 columns,
+ *                      2500 nonzeros) and has no cone blocks, else rows.
+ *                      Instances that fit run their trials out of LDS; forced,
+ *                      the layout works on global memory for larger ones.
  * All layouts compute the same products up to rounding order; rows and
  * workgroup produce bit-identical iterates.  Building the band tiles takes host
  * time proportional to nnz log nnz and 20 bytes of device memory per nonzero of

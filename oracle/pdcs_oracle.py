@@ -823,7 +823,7 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
         return finish(EXIT_OPTIMAL, x, y)
 
     while True:
-        # ---- AdaptiveStepPDHG (Algorithm 1, line 4) ----
+        # ---- AdaptiveStepPDHG (Algorithm 1: the PDHG step with line search) ----
         out = adaptive_step_pdhg(sl, x, y, omega, eta_hat, kbar, trial_log, opts.max_iter)
         xh_new, yh_new, eta_k, eta_p, kbar, _ = out
         if xh_new is None:  # trial budget ran out during rejections
@@ -833,16 +833,16 @@ def solve(lp: LPData, opts: Options | None = None, x0=None, y0=None, trace: bool
         xh, yh = xh_new, yh_new
         eta_hat = eta_p
         accepted += 1
-        # ---- beta at z_hat (line 5) ----
+        # ---- reflection parameter beta at z_hat (Algorithm 1) ----
         beta = reflection_parameter(max_err(sl, xh, yh))
         if trial_log is not None:
             trial_log[-1]["beta"] = beta
-        # ---- reflected Halpern (line 6) ----
+        # ---- reflected Halpern update (Algorithm 1) ----
         a = (k + 1.0) / (k + 2.0)
         bcoef = 1.0 / (k + 2.0)
         x = a * ((1.0 + beta) * xh - beta * x) + bcoef * xa
         y = a * ((1.0 + beta) * yh - beta * y) + bcoef * ya
-        # ---- eta-weighted average of the PDHG outputs (line 7) ----
+        # ---- eta-weighted average of the PDHG outputs (Algorithm 1) ----
         Sx = Sx + eta_k * xh
         Sy = Sy + eta_k * yh
         SH += eta_k

@@ -78,7 +78,7 @@ struct TileSet {
 struct RowBlockSet {
   DBuf r0, r1, binst_d, iblk0_d;
   int nblk = 0;
-  std::vector<int32_t> h_binst;
+  std::vector<int32_t> h_binst, h_iblk0;  // host copies: block -> instance, instance -> first block
   void build(const std::vector<int32_t>& ptr, const std::vector<int64_t>& inst_r0, int red_max,
              const std::vector<char>* active = nullptr);
   RowBlocks view() const;
@@ -95,6 +95,7 @@ struct SocTable {
 struct RangeSet {
   DBuf start, end, binst_d, iblk0_d, soc0_d, soc1_d;
   int nblk = 0;
+  std::vector<int32_t> h_iblk0;  // host copy: instance -> first block
   const SocTable* soc = nullptr;  // set for row ranges that must not split cone blocks
   void build(const std::vector<int64_t>& inst_off, int per_block, const std::vector<char>* active = nullptr);
   Ranges view() const;
@@ -206,6 +207,8 @@ struct Engine {
   int layout = PDCS_LAYOUT_AUTO;
   bool use_band = false;
   bool wg_trials = false;           // chunks of trials by one workgroup per instance
+  size_t lds_bytes[2] = {0, 0};     // FP32 / FP64: dynamic LDS of the LDS-resident chunk kernel (0: not used)
+  void plan_lds_trials();
   bool band_suspended = false;      // auto layout: the active instances of a batch fell below the band threshold
   BandSet band1, band2;             // band tiles of G (gathers x) and G^T (gathers y)
   BandSchedule bsched;              // shape of both band layouts

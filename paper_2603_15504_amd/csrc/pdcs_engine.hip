@@ -290,6 +290,7 @@ void RowBlockSet::build(const std::vector<int32_t>& ptr, const std::vector<int64
   }
   nblk = (int)a.size();
   h_binst = bi;
+  h_iblk0 = iblk0;
   upload(r0, a);
   upload(r1, e);
   upload(binst_d, bi);
@@ -340,6 +341,7 @@ void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block, const 
     iblk0.push_back((int32_t)st.size());
   }
   nblk = (int)st.size();
+  h_iblk0 = iblk0;
   upload(start, st);
   upload(end, en);
   upload(binst_d, bi);
@@ -934,12 +936,14 @@ void Engine::build_schedule() {
     band2.build(col0, row0, h_cp, h_ri, bsched);
   }
   use_band = want_band;
-  // one workgroup per instance for whole chunks of trials: forced, or small
-  // instances (every one at most 2^15 nonzeros) on row blocks without panels
-  int64_t max_nnz = 0;
-  for (int b = 0; b < B; ++b) max_nnz = std::max<int64_t>(max_nnz, h_rp[row0[b + 1]] - h_rp[row0[b]]);
+  // one workgroup per instance for whole chunks of trials: forced, or
+  // automatically when every instance fits in LDS in FP64 (the workgroup then
+  // runs its trials out of LDS; on global memory it would be slower than the
+  // row-block kernels), on row blocks without panels
+  plan_lds_trials();
   wg_trials = !want_band && prow.P == 1 && pcol.P == 1 &&
-              (layout == PDCS_LAYOUT_WORKGROUP || (layout == PDCS_LAYOUT_AUTO && max_nnz <= ((int64_t)1 << 15)));
+              (layout == PDCS_LAYOUT_WORKGROUP || (layout == PDCS_LAYOUT_AUTO && lds_bytes[1] > 0));
+  if (!wg_trials) lds_bytes[0] = lds_bytes[1] = 0;
   rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
   rec_lam_epi.alloc((size_t)std::max(vcol.nblk, 1) * 3 * 8);
   const int nr = std::max(brow.nblk, 1), nc = std::max(bcol.nblk, 1);
@@ -954,6 +958,30 @@ void Engine::build_schedule() {
   rec_nc.alloc((size_t)vc * 3 * 8);
   rec_nr.alloc((size_t)vr * 3 * 8);
   rec_nm.alloc((size_t)std::max(trow.nblk, 1) * 8);
+}
+
+// Dynamic LDS of k_trials_lds for the largest instance, per precision (0 when
+// some instance does not fit next to the kernel's static LDS: the chunk kernel
+// then works on global memory).  The block tables are those of the full
+// schedule; compaction only removes blocks, and inactive instances exit before
+// touching LDS.
+void Engine::plan_lds_trials() {
+  lds_bytes[0] = lds_bytes[1] = 0;
+  if (!soc.empty()) return;
+  size_t need[2] = {0, 0};
+  for (int b = 0; b < B; ++b) {
+    const int64_t m = row0[b + 1] - row0[b], n = col0[b + 1] - col0[b];
+    const int64_t nnz = h_rp[row0[b + 1]] - h_rp[row0[b]];
+    const int64_t np = vcol.h_iblk0[b + 1] - vcol.h_iblk0[b];
+    const int64_t nd = brow.h_iblk0[b + 1] - brow.h_iblk0[b];
+    const int64_t nl = bcol.h_iblk0[b + 1] - bcol.h_iblk0[b];
+    need[0] = std::max(need[0], lds_layout(m, n, nnz, np, nd, nl, 4).total);
+    need[1] = std::max(need[1], lds_layout(m, n, nnz, np, nd, nl, 8).total);
+  }
+  for (int pi = 0; pi < 2; ++pi) {
+    const size_t avail = trials_lds_capacity(pi == 0 ? kFP32 : kFP64);
+    lds_bytes[pi] = need[pi] <= avail ? need[pi] : 0;
+  }
 }
 
 void Engine::ensure_iter(int prec) {
@@ -1003,6 +1031,8 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.P1 = prow.P;
   k.P2 = pcol.P;
   k.wg_trials = wg_trials ? 1 : 0;
+  k.lds_trials32 = (int)lds_bytes[0];
+  k.lds_trials64 = (int)lds_bytes[1];
   k.rec_dual_epi = rec_dual_epi.as<double>();
   k.rec_lam_epi = rec_lam_epi.as<double>();
   k.infeas = infeas_on;

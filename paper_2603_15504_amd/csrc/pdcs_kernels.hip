@@ -1,8 +1,8 @@
 // HIP kernels of the PDCS LP solver for gfx950.
 //
 // One trial of AdaptiveStepPDHG (Function 2) is five launches:
-//   k_primal   : deferred reflected-Halpern commit of x and of G^T y (Algorithm 1,
-//                lines 6-7), then x_hat = Proj_[l,u](x - tau (c - G^T y))   (eq. PDHG)
+//   k_primal   : deferred reflected-Halpern commit of x and of G^T y (Algorithm 1:
+//                reflection and averaging), then x_hat = Proj_[l,u](x - tau (c - G^T y))   (eq. PDHG)
 //   k_dual     : CSR SpMV G x_hat with the dual step fused into the row epilogue:
 //                Halpern commit of y and of G x, then
 //                y_hat = Proj_Kd(y + sigma (h - 2 G x_hat + G x))          (eq. PDHG)
@@ -717,6 +717,157 @@ __global__ __launch_bounds__(kBlock) void k_trials_wg(Ranges vcol, RowBlocks bro
     __syncthreads();
     fin_beta_body(iid, bcol.inst_blk0, rec_l, inst);
     __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_copy(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
+}
+
+// k_trials_wg with the instance resident in LDS: the kernel copies its
+// iterates, data, matrix rows and columns, schedule tables and Inst record
+// into LDS, runs the chunk's K trials there (pointers into LDS, offset so that
+// the device functions keep using global indices), then writes back what the
+// trials change.  Every dependent step of a trial is then an LDS access
+// instead of an HBM round trip.  The host launches it only when the largest
+// instance fits (dynamic LDS of lds_layout(...).total bytes).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_trials_lds(Ranges vcol, RowBlocks brow, RowBlocks bcol, MatPtrs<T> A,
+                                                       MatPtrs<T> AT, IterPtrs<T> it, DataPtrs<T> d,
+                                                       Inst* __restrict__ inst, int prec, int K) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  __shared__ Inst Ish;
+  __shared__ int32_t iblk[6];
+  const int iid = blockIdx.x;
+  {
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(&inst[iid]);
+    uint64_t* t = reinterpret_cast<uint64_t*>(&Ish);
+    for (int i = threadIdx.x; i < (int)(sizeof(Inst) / 8); i += kBlock) t[i] = s[i];
+    if (threadIdx.x == 0) {
+      iblk[0] = vcol.inst_blk0[iid];
+      iblk[1] = vcol.inst_blk0[iid + 1];
+      iblk[2] = brow.inst_blk0[iid];
+      iblk[3] = brow.inst_blk0[iid + 1];
+      iblk[4] = bcol.inst_blk0[iid];
+      iblk[5] = bcol.inst_blk0[iid + 1];
+    }
+  }
+  __syncthreads();
+  if (Ish.status != kActive || Ish.precision != prec || K < 1) return;
+  const int r0 = Ish.row0, m = Ish.rows, c0 = Ish.col0, n = Ish.cols;
+  const int p0 = iblk[0], np = iblk[1] - p0, d0 = iblk[2], nd = iblk[3] - d0, l0 = iblk[4], nl = iblk[5] - l0;
+  const int q0 = A.ptr[r0], nnz = A.ptr[r0 + m] - q0;
+  const int t0 = AT.ptr[c0];
+  const LdsLayout L = lds_layout(m, n, nnz, np, nd, nl, sizeof(T));
+  T* vec = reinterpret_cast<T*>(dyn + L.vec);
+  T* dat = reinterpret_cast<T*>(dyn + L.dat);
+  // iterates (x-like: n values each, then y-like: m values each)
+  T* const xs[7] = {it.x, it.xa, it.xh, it.gty, it.gtya, it.gtyh, it.sx};
+  T* const ys[7] = {it.y, it.ya, it.yh, it.gx, it.gxa, it.gxh, it.sy};
+  for (int v = 0; v < 7; ++v) lds_copy(vec + (size_t)v * n, xs[v] + c0, n);
+  for (int v = 0; v < 7; ++v) lds_copy(vec + (size_t)7 * n + (size_t)v * m, ys[v] + r0, m);
+  lds_copy(dat, d.c + c0, n);
+  lds_copy(dat + n, d.l + c0, n);
+  lds_copy(dat + 2 * n, d.u + c0, n);
+  lds_copy(dat + 3 * n, d.h + r0, m);
+  int32_t* rp = reinterpret_cast<int32_t*>(dyn + L.rp);
+  int32_t* ci = reinterpret_cast<int32_t*>(dyn + L.ci);
+  T* va = reinterpret_cast<T*>(dyn + L.va);
+  int32_t* cp = reinterpret_cast<int32_t*>(dyn + L.cp);
+  int32_t* ri = reinterpret_cast<int32_t*>(dyn + L.ri);
+  T* vt = reinterpret_cast<T*>(dyn + L.vt);
+  lds_copy(rp, A.ptr + r0, m + 1);
+  lds_copy(ci, A.idx + q0, nnz);
+  lds_copy(va, A.val + q0, nnz);
+  lds_copy(cp, AT.ptr + c0, n + 1);
+  lds_copy(ri, AT.idx + t0, nnz);
+  lds_copy(vt, AT.val + t0, nnz);
+  double* recp = reinterpret_cast<double*>(dyn + L.rec);
+  double* recd = recp + 2 * np;
+  double* recl = recd + 4 * nd;
+  int32_t* bt = reinterpret_cast<int32_t*>(dyn + L.blk);
+  lds_copy(bt, vcol.blk_start + p0, np);
+  lds_copy(bt + np, vcol.blk_end + p0, np);
+  lds_copy(bt + 2 * np, vcol.blk_inst + p0, np);
+  int32_t* bd = bt + 3 * np;
+  lds_copy(bd, brow.blk_row0 + d0, nd);
+  lds_copy(bd + nd, brow.blk_row1 + d0, nd);
+  lds_copy(bd + 2 * nd, brow.blk_inst + d0, nd);
+  int32_t* bl = bd + 3 * nd;
+  lds_copy(bl, bcol.blk_row0 + l0, nl);
+  lds_copy(bl + nl, bcol.blk_row1 + l0, nl);
+  lds_copy(bl + 2 * nl, bcol.blk_inst + l0, nl);
+  __syncthreads();
+  // the same structures over LDS, indexed with global row, column, entry,
+  // block and instance numbers
+  IterPtrs<T> li = it;
+  T* const lx[7] = {vec, vec + n, vec + 2 * n, vec + 3 * n, vec + 4 * n, vec + 5 * n, vec + 6 * n};
+  T* const ly0 = vec + (size_t)7 * n;
+  li.x = lx[0] - c0;
+  li.xa = lx[1] - c0;
+  li.xh = lx[2] - c0;
+  li.gty = lx[3] - c0;
+  li.gtya = lx[4] - c0;
+  li.gtyh = lx[5] - c0;
+  li.sx = lx[6] - c0;
+  li.y = ly0 - r0;
+  li.ya = ly0 + m - r0;
+  li.yh = ly0 + 2 * m - r0;
+  li.gx = ly0 + 3 * m - r0;
+  li.gxa = ly0 + 4 * m - r0;
+  li.gxh = ly0 + 5 * m - r0;
+  li.sy = ly0 + 6 * m - r0;
+  const DataPtrs<T> ld{dat - c0, dat + n - c0, dat + 2 * n - c0, dat + 3 * n - r0};
+  const MatPtrs<T> LA{rp - r0, ci - q0, va - q0};
+  const MatPtrs<T> LAT{cp - c0, ri - t0, vt - t0};
+  Ranges lv = vcol;
+  lv.blk_start = bt - p0;
+  lv.blk_end = bt + np - p0;
+  lv.blk_inst = bt + 2 * np - p0;
+  lv.inst_blk0 = iblk - iid;
+  RowBlocks lr = brow;
+  lr.blk_row0 = bd - d0;
+  lr.blk_row1 = bd + nd - d0;
+  lr.blk_inst = bd + 2 * nd - d0;
+  lr.inst_blk0 = iblk + 2 - iid;
+  RowBlocks lc = bcol;
+  lc.blk_row0 = bl - l0;
+  lc.blk_row1 = bl + nl - l0;
+  lc.blk_inst = bl + 2 * nl - l0;
+  lc.inst_blk0 = iblk + 4 - iid;
+  Inst* li_inst = &Ish - iid;
+  double* rp_ = recp - 2 * (size_t)p0;
+  double* rd_ = recd - 4 * (size_t)d0;
+  double* rl_ = recl - 3 * (size_t)l0;
+  for (int s = 0; s < K; ++s) {
+    if (Ish.status != kActive || Ish.precision != prec) break;
+    for (int b = p0; b < p0 + np; ++b) primal_body<T>(b, lv, li, ld, li_inst, prec, rp_);
+    __syncthreads();
+    for (int b = d0; b < d0 + nd; ++b) dual_body<T, T>(b, lr, LA, li, ld, li_inst, prec, rd_);
+    __syncthreads();
+    fin_ls_body(iid, lv.inst_blk0, rp_, lr.inst_blk0, rd_, li_inst);
+    __syncthreads();
+    for (int b = l0; b < l0 + nl; ++b) lam_body<T, T>(b, lc, LAT, li, ld, li_inst, prec, rl_);
+    __syncthreads();
+    fin_beta_body(iid, lc.inst_blk0, rl_, li_inst);
+    __syncthreads();
+  }
+  // write back what trials change: x, x_hat, G^T y, G^T y_hat, S_x and the row
+  // counterparts (anchors and data are read-only here), then the record
+  const int wx[5] = {0, 2, 3, 5, 6};
+  for (int v = 0; v < 5; ++v) {
+    const T* src = vec + (size_t)wx[v] * n;
+    T* dst = xs[wx[v]] + c0;
+    for (int i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
+    const T* sy_ = ly0 + (size_t)wx[v] * m;
+    T* dy_ = ys[wx[v]] + r0;
+    for (int i = threadIdx.x; i < m; i += kBlock) dy_[i] = sy_[i];
+  }
+  {
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(&Ish);
+    uint64_t* t = reinterpret_cast<uint64_t*>(&inst[iid]);
+    for (int i = threadIdx.x; i < (int)(sizeof(Inst) / 8); i += kBlock) t[i] = s[i];
   }
 }
 
@@ -2127,14 +2278,54 @@ void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
                                              s2 ? k.rec_lam_epi : k.rec_lam, k.inst);
 }
 
+// Dynamic LDS the LDS-resident chunk kernel can take: the device's LDS per
+// workgroup less the kernel's static LDS; the first call per precision also
+// raises the kernel's dynamic-LDS limit to that size.
+template <typename T>
+static size_t lds_capacity_t() {
+  static size_t cap = 0;
+  static bool done = false;
+  if (!done) {
+    done = true;
+    int dev = 0, max_lds = 0, optin = 0;
+    hipFuncAttributes fa{};
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+      if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess)
+        max_lds = std::max(max_lds, optin);
+    }
+    if (max_lds > 0 && hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_trials_lds<T>)) == hipSuccess &&
+        (size_t)max_lds > fa.sharedSizeBytes + 1024) {
+      const size_t c = (size_t)max_lds - fa.sharedSizeBytes - 1024;
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trials_lds<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)c) == hipSuccess)
+        cap = c;
+    }
+    (void)hipGetLastError();
+  }
+  return cap;
+}
+
+size_t trials_lds_capacity(int prec) { return prec == kFP32 ? lds_capacity_t<float>() : lds_capacity_t<double>(); }
+
 void launch_trials_wg(const KernelCtx& k, hipStream_t s, int mask, int K) {
   if (k.nb < 1 || K < 1) return;
-  if (mask & 1)
-    k_trials_wg<float><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A32, k.AT32, k.it32, k.d32, k.inst, kFP32,
-                                               k.rec_primal, k.rec_dual, k.rec_lam, K);
-  if (mask & 2)
-    k_trials_wg<double><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A64, k.AT64, k.it64, k.d64, k.inst, kFP64,
-                                                k.rec_primal, k.rec_dual, k.rec_lam, K);
+  if (mask & 1) {
+    if (k.lds_trials32 > 0)
+      k_trials_lds<float><<<k.nb, kBlock, k.lds_trials32, s>>>(k.vcol, k.brow, k.bcol, k.A32, k.AT32, k.it32, k.d32,
+                                                              k.inst, kFP32, K);
+    else
+      k_trials_wg<float><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A32, k.AT32, k.it32, k.d32, k.inst, kFP32,
+                                                 k.rec_primal, k.rec_dual, k.rec_lam, K);
+  }
+  if (mask & 2) {
+    if (k.lds_trials64 > 0)
+      k_trials_lds<double><<<k.nb, kBlock, k.lds_trials64, s>>>(k.vcol, k.brow, k.bcol, k.A64, k.AT64, k.it64,
+                                                               k.d64, k.inst, kFP64, K);
+    else
+      k_trials_wg<double><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A64, k.AT64, k.it64, k.d64, k.inst, kFP64,
+                                                  k.rec_primal, k.rec_dual, k.rec_lam, K);
+  }
 }
 
 void launch_trial(const KernelCtx& k, hipStream_t s, int mask) {

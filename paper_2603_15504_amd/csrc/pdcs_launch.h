@@ -37,6 +37,31 @@ struct MatPtrs {
   const TM* val;
 };
 
+// LDS footprint of one instance in k_trials_lds: the 14 iterate vectors the
+// trials touch, c, l, u, h, both CSR copies of the instance's part of G and
+// the three per-block record arrays.  Shared by the host (choice of kernel,
+// dynamic LDS size) and the kernel (carving), so both agree.
+struct LdsLayout {
+  size_t vec, dat, rp, ci, va, cp, ri, vt, rec, blk, total;
+};
+__host__ __device__ inline size_t lds_align16(size_t b) { return (b + 15) & ~(size_t)15; }
+__host__ __device__ inline LdsLayout lds_layout(int64_t m, int64_t n, int64_t nnz, int64_t nb_p, int64_t nb_d,
+                                                int64_t nb_l, size_t s) {
+  LdsLayout L;
+  L.vec = 0;                                            // x xa xh gty gtya gtyh sx | y ya yh gx gxa gxh sy
+  L.dat = L.vec + lds_align16((size_t)(7 * n + 7 * m) * s);  // c l u | h
+  L.rp = L.dat + lds_align16((size_t)(3 * n + m) * s);
+  L.ci = L.rp + lds_align16((size_t)(m + 1) * 4);
+  L.va = L.ci + lds_align16((size_t)nnz * 4);
+  L.cp = L.va + lds_align16((size_t)nnz * s);
+  L.ri = L.cp + lds_align16((size_t)(n + 1) * 4);
+  L.vt = L.ri + lds_align16((size_t)nnz * 4);
+  L.rec = L.vt + lds_align16((size_t)nnz * s);
+  L.blk = L.rec + lds_align16((size_t)(2 * nb_p + 4 * nb_d + 3 * nb_l) * 8);
+  L.total = L.blk + lds_align16((size_t)(3 * nb_p + 3 * nb_d + 3 * nb_l) * 4);
+  return L;
+}
+
 struct KernelCtx {
   int nb;
   int64_t M, N;
@@ -82,8 +107,10 @@ struct KernelCtx {
   float *bpart32, *bpartT32;
   double *bpart64, *bpartT64, *bpart64b, *bpartT64b;  // b: second vector of the check products
 
-  // chunks of trials run by k_trials_wg (row blocks, no split, no bands)
+  // chunks of trials run by k_trials_wg (row blocks, no split, no bands), by
+  // k_trials_lds with this many bytes of dynamic LDS when nonzero
   int wg_trials;
+  int lds_trials32, lds_trials64;
 
   // the K1 (K2) product is split into partial sums plus an epilogue pass
   bool split1() const { return use_band || P1 > 1; }
@@ -114,6 +141,8 @@ void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mas
 void launch_trial(const KernelCtx& k, hipStream_t s, int mask);
 // K trials of every instance, one workgroup per instance (k.wg_trials layouts)
 void launch_trials_wg(const KernelCtx& k, hipStream_t s, int mask, int K);
+// LDS left for the instance data of the LDS-resident chunk kernel (bytes)
+size_t trials_lds_capacity(int prec);
 void launch_check(const KernelCtx& k, hipStream_t s, int mask);
 void launch_summary(const KernelCtx& k, hipStream_t s, int32_t* out);
 void launch_timeout(const KernelCtx& k, hipStream_t s);

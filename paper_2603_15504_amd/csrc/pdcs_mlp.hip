@@ -174,8 +174,8 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// C = op(A)[M x K] op(B)[K x N] by 128 x 128 output tiles, split into
-// gridDim.x / (gx * gy) K-chunks of kchunk:
+// C = op(A)[M x K] op(B)[K x N] by 128 x 128 output tiles, split S =
+// gridDim.x / (gx * gy) ways along K (split z takes every S-th K-tile):
 //   op(A)[m][k] = ta ? A[k * lda + m] : A[m * lda + k]
 //   op(B)[k][n] = tb ? B[n * ldb + k] : B[k * ldb + n]
 // (op(B) is staged as its transpose, rows n, so both tiles are row x k.)
@@ -187,7 +187,7 @@ __device__ __forceinline__ double wave_sum64(double v) {
 template <int KIND, int KT>
 __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int lda, int ta, int veca,
                                               const bf16* __restrict__ B, int ldb, int tb, int vecb,
-                                              float* __restrict__ C, int M, int N, int K, int kchunk, int gx,
+                                              float* __restrict__ C, int M, int N, int K, int gx,
                                               int gy, Epi e) {
   // operand tiles for the K-loop; the Adam epilogue reuses the same LDS to
   // stage the FP32 output tile (rows padded by 4 floats)
@@ -210,8 +210,10 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
     bx = tq / gy;
   }
   const int m0 = by * TM, n0 = bx * TN;
-  const int kbeg = z * kchunk;
-  const int kend = min(K, kbeg + kchunk);
+  // K-tiles z, z + S, z + 2S, ... of the S-way split: the workgroups of one
+  // output tile read adjacent K-tiles at about the same time, so each row of an
+  // operand is fetched in long runs rather than one K-tile at a time
+  const int S = total / tiles, kstep = S * KT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   f32x16 acc[2][2];
@@ -222,17 +224,18 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
   TileRegs<KT> ra, rb;
-  if (kbeg < kend) {
-    tile_load<KT>(A, lda, ta, veca, m0, M, kbeg, kend, ra);
-    tile_load<KT>(B, ldb, !tb, vecb, n0, N, kbeg, kend, rb);
+  if (z * KT < K) {
+    tile_load<KT>(A, lda, ta, veca, m0, M, z * KT, min(K, z * KT + KT), ra);
+    tile_load<KT>(B, ldb, !tb, vecb, n0, N, z * KT, min(K, z * KT + KT), rb);
   }
-  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+  for (int k0 = z * KT; k0 < K; k0 += kstep) {
     tile_store<KT>(As, ta, ra);
     tile_store<KT>(Bs, !tb, rb);
     __syncthreads();
-    if (k0 + KT < kend) {  // prefetch the next tile while the matrix cores work
-      tile_load<KT>(A, lda, ta, veca, m0, M, k0 + KT, kend, ra);
-      tile_load<KT>(B, ldb, !tb, vecb, n0, N, k0 + KT, kend, rb);
+    const int kn = k0 + kstep;
+    if (kn < K) {  // prefetch the next tile while the matrix cores work
+      tile_load<KT>(A, lda, ta, veca, m0, M, kn, min(K, kn + KT), ra);
+      tile_load<KT>(B, ldb, !tb, vecb, n0, N, kn, min(K, kn + KT), rb);
     }
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 16) {
@@ -699,43 +702,43 @@ struct pdcs_mlp_s {
         part.alloc(need);
         part_bytes = need;
       }
-      launch(EPI_STORE, kt, A, lda, ta, Bm, ldb, tb, part.as<float>(), M, N, K, kchunk, gx, gy, splits, e, s);
+      launch(EPI_STORE, kt, A, lda, ta, Bm, ldb, tb, part.as<float>(), M, N, K, gx, gy, splits, e, s);
       k_epilogue<<<lin((int64_t)M * N), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, e);
       return;
     }
-    launch(kind, kt, A, lda, ta, Bm, ldb, tb, kind == EPI_STORE ? e.out32 : nullptr, M, N, K, kchunk, gx, gy, 1, e, s);
+    launch(kind, kt, A, lda, ta, Bm, ldb, tb, kind == EPI_STORE ? e.out32 : nullptr, M, N, K, gx, gy, 1, e, s);
   }
 
   template <int KIND>
   static void launch_kt(int kt, dim3 grid, const bf16* A, int lda, int ta, int veca, const bf16* Bm, int ldb, int tb,
-                        int vecb, float* C, int M, int N, int K, int kchunk, int gx, int gy, const Epi& e,
+                        int vecb, float* C, int M, int N, int K, int gx, int gy, const Epi& e,
                         hipStream_t s) {
     if (kt == 128)
-      k_gemm<KIND, 128><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e);
+      k_gemm<KIND, 128><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e);
     else if (kt == 64)
-      k_gemm<KIND, 64><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e);
+      k_gemm<KIND, 64><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e);
     else
-      k_gemm<KIND, 32><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e);
+      k_gemm<KIND, 32><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e);
   }
 
   static void launch(int kind, int kt, const bf16* A, int lda, int ta, const bf16* Bm, int ldb, int tb, float* C, int M,
-                     int N, int K, int kchunk, int gx, int gy, int splits, const Epi& e, hipStream_t s) {
+                     int N, int K, int gx, int gy, int splits, const Epi& e, hipStream_t s) {
     // 16-byte vector loads need 16-byte aligned operands with row strides in whole vectors
     const int veca = ((uintptr_t)A % 16 == 0 && lda % 8 == 0) ? 1 : 0;
     const int vecb = ((uintptr_t)Bm % 16 == 0 && ldb % 8 == 0) ? 1 : 0;
     const dim3 grid((unsigned)(gx * gy * splits));
     switch (kind) {
       case EPI_STORE:
-        launch_kt<EPI_STORE>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        launch_kt<EPI_STORE>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e, s);
         break;
       case EPI_ACT:
-        launch_kt<EPI_ACT>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        launch_kt<EPI_ACT>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e, s);
         break;
       case EPI_ADAM:
-        launch_kt<EPI_ADAM>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        launch_kt<EPI_ADAM>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e, s);
         break;
       default:
-        launch_kt<EPI_MSE>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, kchunk, gx, gy, e, s);
+        launch_kt<EPI_MSE>(kt, grid, A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e, s);
     }
   }
 

@@ -410,11 +410,17 @@ def test_restart_variants_first_check_matches_oracle(variant):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_workgroup_layout_is_bit_identical_to_rows(precision):
+@pytest.mark.parametrize("size", ["lds", "global"])
+def test_workgroup_layout_is_bit_identical_to_rows(precision, size):
     # the single-workgroup chunk kernel runs the same passes over the same
     # blocks as the row-block kernels, only separated by barriers instead of
-    # launches: every iterate agrees bit for bit, across restart checks too
-    inst = lpgen.c0_instance(3)
+    # launches: every iterate agrees bit for bit, across restart checks too.
+    # C0 fits in LDS (the LDS-resident kernel); the m = 2000 instance does
+    # not (the kernel on global memory)
+    if size == "lds":
+        inst = lpgen.c0_instance(3)
+    else:
+        inst = lpgen.planted_lp(lpgen.rng_for(5, 0), 2000, 4000, per_col=8, m_zero=600)
     states = {}
     for layout in ("rows", "workgroup"):
         prob = P.Problem.from_instance(inst)
