@@ -34,34 +34,43 @@ __device__ __forceinline__ bf16 to_bf16(float v) { return (bf16)v; }
 
 // One operand tile (128 rows of op(X) x KT) staged through registers.  op(X)
 // row r, column k lives at X[k * ld + r] when trans, else X[r * ld + k].  Each
-// thread owns KT / 16 8-element vectors of the tile: along k when the source is
-// k-contiguous (not trans), along r otherwise.  vec: the launch guarantees
-// 16-byte alignment of the source and ld % 8 == 0, so whole vectors inside the
-// bounds load with one 16-byte access; anything else loads element by element.
-// The LDS copy has rows of KT + 8 elements (16-byte aligned, staggered banks).
+// thread loads KT / 16 8-element vectors, each along the source's contiguous
+// direction:
+//   not trans: vector e = tid + 256 q holds row e / (KT/8), k-block e % (KT/8);
+//   trans    : thread t holds rows 8 (t % 16) .. +7 for the KT/16 consecutive
+//              k = (t / 16) KT/16 + q, one vector per k; lanes 0-15 of a k read
+//              256 contiguous bytes.  The store transposes these in registers so
+//              that each row goes to LDS as one run of KT/16 k-values.
+// vec: the launch guarantees 16-byte alignment of the source and ld % 8 == 0,
+// so whole vectors inside the bounds load with one 16-byte access; anything
+// else loads element by element.
+//
+// LDS holds 128 rows of KT + 8 elements.  The 16-byte blocks of a row are
+// swizzled by the row's group of eight (block b of row r sits at block
+// b ^ ((r / 8) mod KT/8)): the transposed stores of 16 lanes (rows eight apart)
+// and the MFMA reads of 32 lanes (32 consecutive rows) then fall on different
+// banks.
 template <int KT>
 struct TileRegs {
   bf16x8 v[KT / 16];
 };
 
 template <int KT>
+__device__ __forceinline__ int swz(int row, int blk) {
+  return blk ^ ((row >> 3) & (KT / 8 - 1));
+}
+
+template <int KT>
 __device__ __forceinline__ void tile_load(const bf16* __restrict__ X, int ld, int trans, int vec, int r0, int R,
                                           int k0, int kend, TileRegs<KT>& t) {
   const int tid = threadIdx.x;
+  constexpr int KQ = KT / 16;
 #pragma unroll
-  for (int q = 0; q < KT / 16; ++q) {
-    const int e = tid + q * 256;  // vector index in the tile: 16 KT vectors of 8
-    int rr, kk;
-    if (!trans) {
-      rr = e / (KT / 8);
-      kk = (e % (KT / 8)) * 8;
-    } else {
-      kk = e / (TM / 8);
-      rr = (e % (TM / 8)) * 8;
-    }
-    const int gr = r0 + rr, gk = k0 + kk;
+  for (int q = 0; q < KQ; ++q) {
     bf16x8 v;
     if (!trans) {
+      const int e = tid + q * 256;
+      const int gr = r0 + e / (KT / 8), gk = k0 + (e % (KT / 8)) * 8;
       if (vec && gr < R && gk + 8 <= kend) {
         v = *reinterpret_cast<const bf16x8*>(X + (size_t)gr * ld + gk);
       } else {
@@ -69,6 +78,7 @@ __device__ __forceinline__ void tile_load(const bf16* __restrict__ X, int ld, in
         for (int i = 0; i < 8; ++i) v[i] = (gr < R && gk + i < kend) ? X[(size_t)gr * ld + gk + i] : to_bf16(0.0f);
       }
     } else {
+      const int gr = r0 + (tid & 15) * 8, gk = k0 + (tid >> 4) * KQ + q;
       if (vec && gk < kend && gr + 8 <= R) {
         v = *reinterpret_cast<const bf16x8*>(X + (size_t)gk * ld + gr);
       } else {
@@ -83,16 +93,24 @@ __device__ __forceinline__ void tile_load(const bf16* __restrict__ X, int ld, in
 template <int KT>
 __device__ __forceinline__ void tile_store(bf16 (*S)[KT + 8], int trans, const TileRegs<KT>& t) {
   const int tid = threadIdx.x;
+  constexpr int KQ = KT / 16;
+  if (!trans) {
 #pragma unroll
-  for (int q = 0; q < KT / 16; ++q) {
-    const int e = tid + q * 256;
-    if (!trans) {
-      const int rr = e / (KT / 8), kk = (e % (KT / 8)) * 8;
-      *reinterpret_cast<bf16x8*>(&S[rr][kk]) = t.v[q];
-    } else {
-      const int kk = e / (TM / 8), rr = (e % (TM / 8)) * 8;
+    for (int q = 0; q < KQ; ++q) {
+      const int e = tid + q * 256;
+      const int rr = e / (KT / 8), blk = e % (KT / 8);
+      *reinterpret_cast<bf16x8*>(&S[rr][swz<KT>(rr, blk) * 8]) = t.v[q];
+    }
+  } else {
+    typedef __bf16 bf16xq __attribute__((ext_vector_type(KQ)));
+    const int rb = (tid & 15) * 8, kq = (tid >> 4) * KQ;  // k-run kq .. kq + KQ - 1: within one 8-block
 #pragma unroll
-      for (int i = 0; i < 8; ++i) S[rr + i][kk] = t.v[q][i];
+    for (int i = 0; i < 8; ++i) {
+      bf16xq w;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) w[q] = t.v[q][i];
+      const int row = rb + i;
+      *reinterpret_cast<bf16xq*>(&S[row][swz<KT>(row, kq >> 3) * 8 + (kq & 7)]) = w;
     }
   }
 }
@@ -240,11 +258,17 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 16) {
       bf16x8 a[2], b[2];
-      const int ko = kk + (lane >> 5) * 8;
+      const int kb = (kk >> 3) + (lane >> 5);  // 16-byte block of k-values kk + 8 (lane / 32) ..
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 32 + (lane & 31)][ko]);
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + i * 32 + (lane & 31);
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[row][swz<KT>(row, kb) * 8]);
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 32 + (lane & 31)][ko]);
+      for (int j = 0; j < 2; ++j) {
+        const int row = wn + j * 32 + (lane & 31);
+        b[j] = *reinterpret_cast<const bf16x8*>(&Bs[row][swz<KT>(row, kb) * 8]);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
