@@ -208,6 +208,7 @@ struct Engine {
   bool use_band = false;
   bool wg_trials = false;           // chunks of trials by one workgroup per instance
   size_t lds_bytes[2] = {0, 0};     // FP32 / FP64: dynamic LDS of the LDS-resident chunk kernel (0: not used)
+  bool lds_rowwise = false;         // its dual and dual-slack passes take one thread per row
   void plan_lds_trials();
   bool band_suspended = false;      // auto layout: the active instances of a batch fell below the band threshold
   BandSet band1, band2;             // band tiles of G (gathers x) and G^T (gathers y)

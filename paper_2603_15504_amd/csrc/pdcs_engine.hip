@@ -982,6 +982,12 @@ void Engine::plan_lds_trials() {
     const size_t avail = trials_lds_capacity(pi == 0 ? kFP32 : kFP64);
     lds_bytes[pi] = need[pi] <= avail ? need[pi] : 0;
   }
+  // short rows and columns everywhere: one thread per row in the dual and
+  // dual-slack passes (long ones keep the block schedule's lanes per row)
+  int64_t longest = 0;
+  for (int64_t r = 0; r < M; ++r) longest = std::max<int64_t>(longest, h_rp[r + 1] - h_rp[r]);
+  for (int64_t c = 0; c < N; ++c) longest = std::max<int64_t>(longest, h_cp[c + 1] - h_cp[c]);
+  lds_rowwise = longest <= kLdsRowMax;
 }
 
 void Engine::ensure_iter(int prec) {
@@ -1033,6 +1039,7 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.wg_trials = wg_trials ? 1 : 0;
   k.lds_trials32 = (int)lds_bytes[0];
   k.lds_trials64 = (int)lds_bytes[1];
+  k.lds_rowwise = lds_rowwise ? 1 : 0;
   k.rec_dual_epi = rec_dual_epi.as<double>();
   k.rec_lam_epi = rec_lam_epi.as<double>();
   k.infeas = infeas_on;

@@ -541,8 +541,11 @@ __global__ __launch_bounds__(kBlock) void k_lam_epi(Ranges R, const T* __restric
 }
 
 // F1: line-search decision of Function 2, one workgroup per instance.
+// pf: when non-null, pf[0] = (kbar + 1)^-0.3 and pf[1] = (kbar + 1)^-0.6 for the
+// kbar this trial reaches, computed beforehand by an otherwise idle thread
 __device__ __forceinline__ void fin_ls_body(int iid, const int32_t* iblk_p, const double* rec_p,
-                                            const int32_t* iblk_d, const double* rec_d, Inst* inst) {
+                                            const int32_t* iblk_d, const double* rec_d, Inst* inst,
+                                            const double* pf = nullptr) {
   __shared__ double lds[kWavesPerBlock * 4];
   Inst& I = inst[iid];
   if (I.status != kActive) return;
@@ -560,7 +563,8 @@ __device__ __forceinline__ void fin_ls_body(int iid, const int32_t* iblk_p, cons
   const double den = fabs(dydg);
   const double etabar = den > 0.0 ? num / den : (double)INFINITY;
   const double kb1 = (double)I.kbar + 1.0;
-  const double eta_next = fmin((1.0 - pow(kb1, -0.3)) * etabar, (1.0 + pow(kb1, -0.6)) * eta);
+  const double p3 = pf ? pf[0] : pow(kb1, -0.3), p6 = pf ? pf[1] : pow(kb1, -0.6);
+  const double eta_next = fmin((1.0 - p3) * etabar, (1.0 + p6) * eta);
   if (!isfinite(num) || isnan(etabar) || isnan(q[2]) || isnan(q[3]) || isnan(p[1]) ||
       !(eta_next > 0.0) || !isfinite(eta_next)) {
     I.status = kDone;
@@ -720,6 +724,41 @@ __global__ __launch_bounds__(kBlock) void k_trials_wg(Ranges vcol, RowBlocks bro
   }
 }
 
+// Row-wise passes of the LDS-resident chunk kernel (instances whose rows and
+// columns hold at most kLdsRowMax entries): one thread per row of G (dual
+// step) or of G^T (dual slack), the dot product in FP64 in entry order, and one
+// record for the whole instance.
+template <typename T>
+__device__ __forceinline__ void dual_rows_lds(int r0, int r1, const MatPtrs<T>& A, const IterPtrs<T>& it,
+                                              const DataPtrs<T>& d, const Inst& I, double* rec) {
+  __shared__ double lds[kWavesPerBlock * 4];
+  if (I.status != kActive) return;
+  const DualEpilogue<T> epi = make_dual_epilogue(I, it, d);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+    double s = 0.0;
+    const int q1 = A.ptr[r + 1];
+    for (int q = A.ptr[r]; q < q1; ++q) s += (double)A.val[q] * (double)it.xh[A.idx[q]];
+    epi(r, s, acc);
+  }
+  block_sum_store<4>(acc, lds, rec);
+}
+
+template <typename T>
+__device__ __forceinline__ void lam_rows_lds(int c0, int c1, const MatPtrs<T>& AT, const IterPtrs<T>& it,
+                                             const DataPtrs<T>& d, const Inst& I, double* rec) {
+  __shared__ double lds[kWavesPerBlock * 3];
+  if (I.status != kActive || I.last_acc == 0) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int j = c0 + (int)threadIdx.x; j < c1; j += kBlock) {
+    double s = 0.0;
+    const int q1 = AT.ptr[j + 1];
+    for (int q = AT.ptr[j]; q < q1; ++q) s += (double)AT.val[q] * (double)it.yh[AT.idx[q]];
+    lam_epilogue<T>(j, s, it, d, acc);
+  }
+  block_sum_store<3>(acc, lds, rec);
+}
+
 template <typename T>
 __device__ __forceinline__ void lds_copy(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
   for (int64_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
@@ -735,7 +774,7 @@ __device__ __forceinline__ void lds_copy(T* __restrict__ dst, const T* __restric
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_trials_lds(Ranges vcol, RowBlocks brow, RowBlocks bcol, MatPtrs<T> A,
                                                        MatPtrs<T> AT, IterPtrs<T> it, DataPtrs<T> d,
-                                                       Inst* __restrict__ inst, int prec, int K) {
+                                                       Inst* __restrict__ inst, int prec, int K, int rowwise) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   __shared__ Inst Ish;
   __shared__ int32_t iblk[6];
@@ -784,8 +823,8 @@ __global__ __launch_bounds__(kBlock) void k_trials_lds(Ranges vcol, RowBlocks br
   lds_copy(ri, AT.idx + t0, nnz);
   lds_copy(vt, AT.val + t0, nnz);
   double* recp = reinterpret_cast<double*>(dyn + L.rec);
-  double* recd = recp + 2 * np;
-  double* recl = recd + 4 * nd;
+  double* recd = recp + 2 * max(np, 1);
+  double* recl = recd + 4 * max(nd, 1);
   int32_t* bt = reinterpret_cast<int32_t*>(dyn + L.blk);
   lds_copy(bt, vcol.blk_start + p0, np);
   lds_copy(bt + np, vcol.blk_end + p0, np);
@@ -840,17 +879,59 @@ __global__ __launch_bounds__(kBlock) void k_trials_lds(Ranges vcol, RowBlocks br
   double* rp_ = recp - 2 * (size_t)p0;
   double* rd_ = recd - 4 * (size_t)d0;
   double* rl_ = recl - 3 * (size_t)l0;
+  // Row-wise instances take one range for the primal pass and the row-wise
+  // passes, each leaving one record (one[] is the per-instance block table of
+  // a single record); the others keep their blocks.
+  __shared__ int32_t one[2], rng[3];
+  __shared__ double pf[2];
+  if (threadIdx.x == 0) {
+    one[0] = 0;
+    one[1] = 1;
+    rng[0] = c0;
+    rng[1] = c0 + n;
+    rng[2] = iid;
+  }
+  if (threadIdx.x == kWave) {  // line-search factors of the first trial
+    const double kb = (double)Ish.kbar + 2.0;
+    pf[0] = pow(kb, -0.3);
+    pf[1] = pow(kb, -0.6);
+  }
+  __syncthreads();
+  Ranges l1 = vcol;
+  l1.blk_start = rng;
+  l1.blk_end = rng + 1;
+  l1.blk_inst = rng + 2;
   for (int s = 0; s < K; ++s) {
     if (Ish.status != kActive || Ish.precision != prec) break;
-    for (int b = p0; b < p0 + np; ++b) primal_body<T>(b, lv, li, ld, li_inst, prec, rp_);
-    __syncthreads();
-    for (int b = d0; b < d0 + nd; ++b) dual_body<T, T>(b, lr, LA, li, ld, li_inst, prec, rd_);
-    __syncthreads();
-    fin_ls_body(iid, lv.inst_blk0, rp_, lr.inst_blk0, rd_, li_inst);
-    __syncthreads();
-    for (int b = l0; b < l0 + nl; ++b) lam_body<T, T>(b, lc, LAT, li, ld, li_inst, prec, rl_);
-    __syncthreads();
-    fin_beta_body(iid, lc.inst_blk0, rl_, li_inst);
+    if (rowwise) {
+      primal_body<T>(0, l1, li, ld, li_inst, prec, recp);
+      __syncthreads();
+      dual_rows_lds<T>(r0, r0 + m, LA, li, ld, Ish, recd);
+      __syncthreads();
+      fin_ls_body(iid, one - iid, recp, one - iid, recd, li_inst, pf);
+      __syncthreads();
+      lam_rows_lds<T>(c0, c0 + n, LAT, li, ld, Ish, recl);
+      __syncthreads();
+      fin_beta_body(iid, one - iid, recl, li_inst);
+    } else {
+      for (int b = p0; b < p0 + np; ++b) primal_body<T>(b, lv, li, ld, li_inst, prec, rp_);
+      __syncthreads();
+      for (int b = d0; b < d0 + nd; ++b) dual_body<T, T>(b, lr, LA, li, ld, li_inst, prec, rd_);
+      __syncthreads();
+      fin_ls_body(iid, lv.inst_blk0, rp_, lr.inst_blk0, rd_, li_inst, pf);
+      __syncthreads();
+      for (int b = l0; b < l0 + nl; ++b) lam_body<T, T>(b, lc, LAT, li, ld, li_inst, prec, rl_);
+      __syncthreads();
+      fin_beta_body(iid, lc.inst_blk0, rl_, li_inst);
+    }
+    // every thread has passed the finalizer's reductions; thread 0 may still be
+    // in its scalar part (which does not touch kbar), while wave 1 forms the
+    // next trial's line-search factors
+    if (threadIdx.x == kWave) {
+      const double kb = (double)Ish.kbar + 2.0;
+      pf[0] = pow(kb, -0.3);
+      pf[1] = pow(kb, -0.6);
+    }
     __syncthreads();
   }
   // write back what trials change: x, x_hat, G^T y, G^T y_hat, S_x and the row
@@ -2313,7 +2394,7 @@ void launch_trials_wg(const KernelCtx& k, hipStream_t s, int mask, int K) {
   if (mask & 1) {
     if (k.lds_trials32 > 0)
       k_trials_lds<float><<<k.nb, kBlock, k.lds_trials32, s>>>(k.vcol, k.brow, k.bcol, k.A32, k.AT32, k.it32, k.d32,
-                                                              k.inst, kFP32, K);
+                                                              k.inst, kFP32, K, k.lds_rowwise);
     else
       k_trials_wg<float><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A32, k.AT32, k.it32, k.d32, k.inst, kFP32,
                                                  k.rec_primal, k.rec_dual, k.rec_lam, K);
@@ -2321,7 +2402,7 @@ void launch_trials_wg(const KernelCtx& k, hipStream_t s, int mask, int K) {
   if (mask & 2) {
     if (k.lds_trials64 > 0)
       k_trials_lds<double><<<k.nb, kBlock, k.lds_trials64, s>>>(k.vcol, k.brow, k.bcol, k.A64, k.AT64, k.it64,
-                                                               k.d64, k.inst, kFP64, K);
+                                                               k.d64, k.inst, kFP64, K, k.lds_rowwise);
     else
       k_trials_wg<double><<<k.nb, kBlock, 0, s>>>(k.vcol, k.brow, k.bcol, k.A64, k.AT64, k.it64, k.d64, k.inst, kFP64,
                                                   k.rec_primal, k.rec_dual, k.rec_lam, K);

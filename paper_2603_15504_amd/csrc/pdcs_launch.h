@@ -37,6 +37,9 @@ struct MatPtrs {
   const TM* val;
 };
 
+// Longest row or column for the row-wise passes of k_trials_lds.
+constexpr int kLdsRowMax = 64;
+
 // LDS footprint of one instance in k_trials_lds: the 14 iterate vectors the
 // trials touch, c, l, u, h, both CSR copies of the instance's part of G and
 // the three per-block record arrays.  Shared by the host (choice of kernel,
@@ -57,7 +60,9 @@ __host__ __device__ inline LdsLayout lds_layout(int64_t m, int64_t n, int64_t nn
   L.ri = L.cp + lds_align16((size_t)(n + 1) * 4);
   L.vt = L.ri + lds_align16((size_t)nnz * 4);
   L.rec = L.vt + lds_align16((size_t)nnz * s);
-  L.blk = L.rec + lds_align16((size_t)(2 * nb_p + 4 * nb_d + 3 * nb_l) * 8);
+  // one record per block, at least one per pass (the row-wise passes)
+  L.blk = L.rec + lds_align16((size_t)(2 * (nb_p > 1 ? nb_p : 1) + 4 * (nb_d > 1 ? nb_d : 1) +
+                                       3 * (nb_l > 1 ? nb_l : 1)) * 8);
   L.total = L.blk + lds_align16((size_t)(3 * nb_p + 3 * nb_d + 3 * nb_l) * 4);
   return L;
 }
@@ -111,6 +116,7 @@ struct KernelCtx {
   // k_trials_lds with this many bytes of dynamic LDS when nonzero
   int wg_trials;
   int lds_trials32, lds_trials64;
+  int lds_rowwise;  // every row of G and of G^T has at most kLdsRowMax entries: row-wise passes
 
   // the K1 (K2) product is split into partial sums plus an epilogue pass
   bool split1() const { return use_band || P1 > 1; }

@@ -410,27 +410,39 @@ def test_restart_variants_first_check_matches_oracle(variant):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("size", ["lds", "global"])
-def test_workgroup_layout_is_bit_identical_to_rows(precision, size):
-    # the single-workgroup chunk kernel runs the same passes over the same
-    # blocks as the row-block kernels, only separated by barriers instead of
-    # launches: every iterate agrees bit for bit, across restart checks too.
-    # C0 fits in LDS (the LDS-resident kernel); the m = 2000 instance does
-    # not (the kernel on global memory)
-    if size == "lds":
-        inst = lpgen.c0_instance(3)
-    else:
-        inst = lpgen.planted_lp(lpgen.rng_for(5, 0), 2000, 4000, per_col=8, m_zero=600)
+def test_workgroup_layout_on_global_memory_is_bit_identical_to_rows(precision):
+    # an instance too large for LDS: the chunk kernel runs the row-block passes
+    # over the same blocks, separated by barriers instead of launches, so every
+    # iterate agrees bit for bit, across restart checks too
+    inst = lpgen.planted_lp(lpgen.rng_for(5, 0), 2000, 4000, per_col=8, m_zero=600)
     states = {}
     for layout in ("rows", "workgroup"):
         prob = P.Problem.from_instance(inst)
         prob.set_layout(layout)
-        sol = prob.solve(precision=precision, max_iter=700, check_every=64, keep_state=True)
-        states[layout] = sol
+        states[layout] = prob.solve(precision=precision, max_iter=700, check_every=64, keep_state=True)
     a, b = states["rows"], states["workgroup"]
     assert a.info["iters"] == b.info["iters"] and a.info["restarts"] == b.info["restarts"]
     for key in ("x", "y", "x_hat", "y_hat", "x_a", "y_a"):
         assert np.array_equal(a.state[key], b.state[key]), key
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workgroup_layout_in_lds_matches_rows(precision):
+    # C0 runs out of LDS with one thread per row: the same arithmetic in another
+    # summation order, so before the first restart check the iterates agree to
+    # rounding (FP64 1e-12, FP32 storage 1e-5 of their scale)
+    inst = lpgen.c0_instance(3)
+    states = {}
+    for layout in ("rows", "workgroup"):
+        prob = P.Problem.from_instance(inst)
+        prob.set_layout(layout)
+        states[layout] = prob.solve(precision=precision, max_iter=63, check_every=1000, keep_state=True)
+    a, b = states["rows"], states["workgroup"]
+    assert a.info["iters"] == b.info["iters"] == 63
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for key in ("x", "y", "x_hat", "y_hat"):
+        scale = 1.0 + np.abs(a.state[key]).max()
+        assert np.max(np.abs(a.state[key] - b.state[key])) <= tol * scale, key
 
 
 def test_workgroup_layout_batch_matches_oracle():
