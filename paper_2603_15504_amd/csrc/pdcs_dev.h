@@ -252,6 +252,11 @@ __device__ __forceinline__ void reduce_records_wide(const double* rec, int b0, i
 template <int NV, int NS>
 __device__ __forceinline__ void reduce_records(const double* rec, int b0, int b1, double* lds,
                                                double (&res)[NV]) {
+  if (b1 - b0 == 1) {  // a single record (uniform across the workgroup): every thread reads it
+#pragma unroll
+    for (int i = 0; i < NV; ++i) res[i] = rec[(size_t)b0 * NV + i];
+    return;
+  }
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;

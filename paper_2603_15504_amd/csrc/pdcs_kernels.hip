@@ -728,6 +728,29 @@ __global__ __launch_bounds__(kBlock) void k_trials_wg(Ranges vcol, RowBlocks bro
 // columns hold at most kLdsRowMax entries): one thread per row of G (dual
 // step) or of G^T (dual slack), the dot product in FP64 in entry order, and one
 // record for the whole instance.
+// One thread's dot product of entries [q0, q1) with x, in entry order (FP64);
+// four entries' indices, values and gathers are requested before they are added.
+template <typename T>
+__device__ __forceinline__ double row_dot_seq(int q0, int q1, const int32_t* idx, const T* val, const T* x) {
+  double s = 0.0;
+  int q = q0;
+  for (; q + 4 <= q1; q += 4) {
+    int c[4];
+    double v[4], g[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = idx[q + u];
+      v[u] = (double)val[q + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[u] = (double)x[c[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u] * g[u];
+  }
+  for (; q < q1; ++q) s += (double)val[q] * (double)x[idx[q]];
+  return s;
+}
+
 template <typename T>
 __device__ __forceinline__ void dual_rows_lds(int r0, int r1, const MatPtrs<T>& A, const IterPtrs<T>& it,
                                               const DataPtrs<T>& d, const Inst& I, double* rec) {
@@ -736,9 +759,7 @@ __device__ __forceinline__ void dual_rows_lds(int r0, int r1, const MatPtrs<T>& 
   const DualEpilogue<T> epi = make_dual_epilogue(I, it, d);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
-    double s = 0.0;
-    const int q1 = A.ptr[r + 1];
-    for (int q = A.ptr[r]; q < q1; ++q) s += (double)A.val[q] * (double)it.xh[A.idx[q]];
+    const double s = row_dot_seq(A.ptr[r], A.ptr[r + 1], A.idx, A.val, it.xh);
     epi(r, s, acc);
   }
   block_sum_store<4>(acc, lds, rec);
@@ -751,9 +772,7 @@ __device__ __forceinline__ void lam_rows_lds(int c0, int c1, const MatPtrs<T>& A
   if (I.status != kActive || I.last_acc == 0) return;
   double acc[3] = {0.0, 0.0, 0.0};
   for (int j = c0 + (int)threadIdx.x; j < c1; j += kBlock) {
-    double s = 0.0;
-    const int q1 = AT.ptr[j + 1];
-    for (int q = AT.ptr[j]; q < q1; ++q) s += (double)AT.val[q] * (double)it.yh[AT.idx[q]];
+    const double s = row_dot_seq(AT.ptr[j], AT.ptr[j + 1], AT.idx, AT.val, it.yh);
     lam_epilogue<T>(j, s, it, d, acc);
   }
   block_sum_store<3>(acc, lds, rec);
@@ -1255,15 +1274,10 @@ __device__ __forceinline__ double probe_t(const CandState& C, int p) {
 // (eq. compute_zt_2).  Records: [candidate][workgroup][probe][2].
 constexpr int kProbeNV = kProbes * 2;
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_probe_cols(Ranges R, const T* __restrict__ x0,
-                                                       const T* __restrict__ x1,
-                                                       const double* __restrict__ g0,
-                                                       const double* __restrict__ g1,
-                                                       DataPtrs<double> d, const Inst* __restrict__ inst,
-                                                       int prec, double* __restrict__ rec) {
+__device__ __forceinline__ void probe_cols_body(int b, int q, const Ranges& R, const T* x0, const T* x1,
+                                                const double* g0, const double* g1, const DataPtrs<double>& d,
+                                                const Inst* inst, int prec, double* rec) {
   __shared__ double lds[kWavesPerBlock * kProbeNV];
-  const int b = blockIdx.x;
-  const int q = blockIdx.y;
   const Inst& I = inst[R.blk_inst[b]];
   if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;
   const CandState& C = I.cand[q];
@@ -1294,16 +1308,20 @@ __global__ __launch_bounds__(kBlock) void k_probe_cols(Ranges R, const T* __rest
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __restrict__ y0,
-                                                       const T* __restrict__ y1,
+__global__ __launch_bounds__(kBlock) void k_probe_cols(Ranges R, const T* __restrict__ x0,
+                                                       const T* __restrict__ x1,
                                                        const double* __restrict__ g0,
                                                        const double* __restrict__ g1,
-                                                       DataPtrs<double> d, const double* __restrict__ D1,
-                                                       const Inst* __restrict__ inst, int prec,
-                                                       double* __restrict__ rec) {
+                                                       DataPtrs<double> d, const Inst* __restrict__ inst,
+                                                       int prec, double* __restrict__ rec) {
+  probe_cols_body<T>(blockIdx.x, blockIdx.y, R, x0, x1, g0, g1, d, inst, prec, rec);
+}
+
+template <typename T>
+__device__ __forceinline__ void probe_rows_body(int b, int q, const Ranges& R, const T* y0, const T* y1,
+                                                const double* g0, const double* g1, const DataPtrs<double>& d,
+                                                const double* D1, const Inst* inst, int prec, double* rec) {
   __shared__ double lds[kWavesPerBlock * kProbeNV];
-  const int b = blockIdx.x;
-  const int q = blockIdx.y;
   const Inst& I = inst[R.blk_inst[b]];
   if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;
   const CandState& C = I.cand[q];
@@ -1355,17 +1373,26 @@ __global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __rest
   block_sum_store<kProbeNV>(acc, lds, rec + ((size_t)q * R.nblk + b) * kProbeNV);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_probe_rows(Ranges R, const T* __restrict__ y0,
+                                                       const T* __restrict__ y1,
+                                                       const double* __restrict__ g0,
+                                                       const double* __restrict__ g1,
+                                                       DataPtrs<double> d, const double* __restrict__ D1,
+                                                       const Inst* __restrict__ inst, int prec,
+                                                       double* __restrict__ rec) {
+  probe_rows_body<T>(blockIdx.x, blockIdx.y, R, y0, y1, g0, g1, d, D1, inst, prec, rec);
+}
+
 // Update every candidate's bracket from one multisection pass (Algorithm 3:
 // exponential search from t0, then bisection; here kProbes points per pass).
-__global__ __launch_bounds__(kBlock) void k_probe_fin(Ranges rc, const double* __restrict__ rec_c,
-                                                      Ranges rr, const double* __restrict__ rec_r,
-                                                      Inst* __restrict__ inst) {
+__device__ __forceinline__ void probe_fin_body(int iid, const Ranges& rc, const double* rec_c, const Ranges& rr,
+                                               const double* rec_r, Inst* inst) {
   __shared__ double red[kBlock];
   // the bracket update below indexes probes at run time: its inputs live in
   // LDS (registers indexed at run time would go to scratch memory)
   __shared__ double s_dist[kMaxCand][kProbes], s_val[kMaxCand][kProbes], s_t[kMaxCand][kProbes];
   __shared__ double s_cols[kProbeNV], s_rows[kProbeNV];
-  const int iid = blockIdx.x;
   Inst& I = inst[iid];
   if (I.status != kActive || I.check_due == 0) return;
   const bool s0 = I.cand[0].phase == kPhaseExp || I.cand[0].phase == kPhaseBisect;
@@ -1439,6 +1466,40 @@ __global__ __launch_bounds__(kBlock) void k_probe_fin(Ranges rc, const double* _
       C.t_hi = new_hi;
     }
     if (C.phase == kPhaseBisect && C.t_hi - C.t_lo <= eps * C.t_hi) C.phase = kPhaseDone;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_probe_fin(Ranges rc, const double* __restrict__ rec_c,
+                                                      Ranges rr, const double* __restrict__ rec_r,
+                                                      Inst* __restrict__ inst) {
+  probe_fin_body(blockIdx.x, rc, rec_c, rr, rec_r, inst);
+}
+
+// All multisection passes of a restart check in one launch, one workgroup per
+// instance of precision prec (the layouts that run trials in one workgroup per
+// instance): the passes of k_probe_cols, k_probe_rows and k_probe_fin over the
+// instance's blocks, separated by barriers, with the same records.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_probes_wg(Ranges ccol, Ranges crow, const T* x0, const T* x1,
+                                                      const T* y0, const T* y1, const double* gc0,
+                                                      const double* gc1, const double* gr0, const double* gr1,
+                                                      DataPtrs<double> d, const double* D1, Inst* inst, int prec,
+                                                      double* rec_c, double* rec_r, int passes) {
+  const int iid = blockIdx.x;
+  {
+    const Inst& I = inst[iid];
+    if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;  // uniform
+  }
+  const int c0 = ccol.inst_blk0[iid], c1 = ccol.inst_blk0[iid + 1];
+  const int r0 = crow.inst_blk0[iid], r1 = crow.inst_blk0[iid + 1];
+  for (int pass = 0; pass < passes; ++pass) {
+    for (int q = 0; q < kMaxCand; ++q)
+      for (int b = c0; b < c1; ++b) probe_cols_body<T>(b, q, ccol, x0, x1, gc0, gc1, d, inst, prec, rec_c);
+    for (int q = 0; q < kMaxCand; ++q)
+      for (int b = r0; b < r1; ++b) probe_rows_body<T>(b, q, crow, y0, y1, gr0, gr1, d, D1, inst, prec, rec_r);
+    __syncthreads();
+    probe_fin_body(iid, ccol, rec_c, crow, rec_r, inst);
+    __syncthreads();
   }
 }
 
@@ -2577,10 +2638,21 @@ void launch_check(const KernelCtx& k, hipStream_t s, int mask) {
   if (mask & 1) launch_check_pre_t<float>(k, s, kFP32, k.it32);
   if (mask & 2) launch_check_pre_t<double>(k, s, kFP64, k.it64);
   k_cand_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol, k.rec_cand_c, k.vrow, k.rec_cand_r, k.inst, kModeCheck);
-  for (int pass = 0; pass < k.probe_passes; ++pass) {
-    if (mask & 1) launch_probe_t<float>(k, s, kFP32, k.it32);
-    if (mask & 2) launch_probe_t<double>(k, s, kFP64, k.it64);
-    k_probe_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.ccol, k.rec_probe_c, k.crow, k.rec_probe_r, k.inst);
+  if (k.wg_trials && !k.use_band) {
+    if (mask & 1)
+      k_probes_wg<float><<<k.nb, kBlock, 0, s>>>(k.ccol, k.crow, k.it32.xh, k.it32.xbar, k.it32.yh, k.it32.ybar,
+                                                 k.cgty0, k.cgty1, k.cgx0, k.cgx1, k.d64, k.D1, k.inst, kFP32,
+                                                 k.rec_probe_c, k.rec_probe_r, k.probe_passes);
+    if (mask & 2)
+      k_probes_wg<double><<<k.nb, kBlock, 0, s>>>(k.ccol, k.crow, k.it64.xh, k.it64.xbar, k.it64.yh, k.it64.ybar,
+                                                  k.cgty0, k.cgty1, k.cgx0, k.cgx1, k.d64, k.D1, k.inst, kFP64,
+                                                  k.rec_probe_c, k.rec_probe_r, k.probe_passes);
+  } else {
+    for (int pass = 0; pass < k.probe_passes; ++pass) {
+      if (mask & 1) launch_probe_t<float>(k, s, kFP32, k.it32);
+      if (mask & 2) launch_probe_t<double>(k, s, kFP64, k.it64);
+      k_probe_fin<<<grid1(k.nb), kBlock, 0, s>>>(k.ccol, k.rec_probe_c, k.crow, k.rec_probe_r, k.inst);
+    }
   }
   k_decide<<<nbt, 64, 0, s>>>(k.inst, k.nb);
   if (k.infeas) launch_ray(k, s, mask);
