@@ -231,6 +231,41 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
+def run_c0(args, P, np):
+    """C0: the small LP (m=200, n=500, 5 rows per column) solved to relative
+    KKT 1e-6 in FP64; a step is one solve.  Reports solves/s and the time per
+    trial for each layout (one workgroup per instance, out of LDS, is the
+    automatic choice at this size)."""
+    import lpgen
+
+    inst = lpgen.c0_instance(0)
+    res = {}
+    for layout in ("workgroup", "rows"):
+        prob = P.Problem.from_instance(inst)
+        prob.set_layout(layout)
+        for _ in range(max(args.warmup, 1)):
+            prob.solve(precision="fp64", time_limit=60.0)
+        walls, s = [], None
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            s = prob.solve(precision="fp64", time_limit=60.0)
+            walls.append(time.perf_counter() - t0)
+        wall = float(np.median(walls))
+        res[layout] = {"solves_per_s": round(1.0 / wall, 3), "seconds": round(wall, 5), "trials": s.info["iters"],
+                       "us_per_trial": round(wall / s.info["iters"] * 1e6, 2), "status": s.info["status"]}
+        log(f"c0 {layout}: {wall * 1e3:.2f} ms per solve, {s.info['iters']} trials, "
+            f"{res[layout]['us_per_trial']} us per trial, {s.info['status']}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        sec = oracle_trial_seconds(inst, 200) * res["workgroup"]["trials"]
+        cpu = {"value": round(1.0 / sec, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "200 trials of the FP64 oracle (no rescaling), extrapolated to the GPU's trial count"}
+    w = res["workgroup"]
+    return common_fields(args, w["solves_per_s"], "solves/s", w["seconds"] * 1e3, "f64", {
+        "workload": "single LP m=200 n=500, 5 rows per column, box [0,10], rel. KKT 1e-6, FP64",
+        "layouts": res}, {"roofline": None, "cpu_baseline": cpu})
+
+
 def run_c4(args, P, np):
     """C4: the ill-conditioned LP to relative KKT 1e-6, mixed (FP32 with FP64
     polish) against plain FP64; a step is one solve."""
@@ -524,7 +559,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed chunks of 64 trials + restart check")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c1_nnz_matched", "c2", "c3", "c3_mlp", "c4"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1_nnz_matched", "c2", "c3", "c3_mlp", "c4"])
     ap.add_argument("--mlp-batch", type=int, default=256, help="c3_mlp: training batch")
     ap.add_argument("--c2-count", type=int, default=512)
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "bands"],
@@ -560,10 +595,10 @@ def main():
     if args.workload == "c3_mlp":
         print(json.dumps(run_c3_mlp(args, P, np)), flush=True)
         return
-    if args.workload in ("c2", "c3", "c4"):
+    if args.workload in ("c0", "c2", "c3", "c4"):
         if args.steps == 200 and args.warmup == 20:   # the C1 defaults: one step each here
-            args.steps, args.warmup = 1, 0
-        fn = {"c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload]
+            args.steps, args.warmup = (20, 2) if args.workload == "c0" else (1, 0)
+        fn = {"c0": run_c0, "c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload]
         print(json.dumps(fn(args, P, np)), flush=True)
         return
 

@@ -523,7 +523,7 @@ class Problem:
         pdcs_problem_set_panels(self.handle, px, py)
 
     def set_layout(self, layout="auto"):
-        """Matrix storage for the trial SpMVs: "auto", "rows" or "bands"."""
+        """Matrix storage for the trial SpMVs: "auto", "rows", "bands" or "workgroup"."""
         pdcs_problem_set_layout(self.handle, LAYOUTS[layout] if isinstance(layout, str) else layout)
 
     def set_band_schedule(self, rows=8192, min_tiles=384, entry_cap=32768):
@@ -678,7 +678,7 @@ class Batch:
         pdcs_batch_set_schedule(self.handle, iter_max, block_nnz, vec_per_block)
 
     def set_layout(self, layout="auto"):
-        """Matrix storage for the trial SpMVs of every instance: "auto", "rows" or "bands"."""
+        """Matrix storage for the trial SpMVs of every instance: "auto", "rows", "bands" or "workgroup"."""
         pdcs_batch_set_layout(self.handle, LAYOUTS[layout] if isinstance(layout, str) else layout)
 
     def set_band_schedule(self, rows=8192, min_tiles=384, entry_cap=32768):

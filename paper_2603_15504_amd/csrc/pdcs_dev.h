@@ -226,6 +226,11 @@ __device__ __forceinline__ void block_summax_store(double (&v)[NV], double* lds,
 template <int NV>
 __device__ __forceinline__ void reduce_records_wide(const double* rec, int b0, int b1, double* red, double* out) {
   static_assert(kBlock % NV == 0, "record width divides the block");
+  if (b1 - b0 == 1) {  // a single record (uniform across the workgroup)
+    if (threadIdx.x < NV) out[threadIdx.x] = rec[(size_t)b0 * NV + threadIdx.x];
+    __syncthreads();
+    return;
+  }
   constexpr int R = kBlock / NV;
   const int i = threadIdx.x % NV;
   int b = b0 + (int)threadIdx.x / NV;

@@ -1477,28 +1477,92 @@ __global__ __launch_bounds__(kBlock) void k_probe_fin(Ranges rc, const double* _
 
 // All multisection passes of a restart check in one launch, one workgroup per
 // instance of precision prec (the layouts that run trials in one workgroup per
-// instance): the passes of k_probe_cols, k_probe_rows and k_probe_fin over the
-// instance's blocks, separated by barriers, with the same records.
+// instance; no cone blocks there).  Wave w evaluates candidate w % 2 on the
+// columns (w < 2) or the rows (w >= 2) of the whole instance, with the
+// arithmetic of k_probe_cols / k_probe_rows, and leaves its sums in the record
+// of the instance's first block; k_probe_fin's update then reads that one
+// record per side.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_probes_wg(Ranges ccol, Ranges crow, const T* x0, const T* x1,
                                                       const T* y0, const T* y1, const double* gc0,
                                                       const double* gc1, const double* gr0, const double* gr1,
-                                                      DataPtrs<double> d, const double* D1, Inst* inst, int prec,
-                                                      double* rec_c, double* rec_r, int passes) {
+                                                      DataPtrs<double> d, Inst* inst, int prec, double* rec_c,
+                                                      double* rec_r, int passes) {
+  __shared__ int32_t first[4];
   const int iid = blockIdx.x;
   {
     const Inst& I = inst[iid];
     if (I.status != kActive || I.check_due == 0 || I.precision != prec) return;  // uniform
   }
-  const int c0 = ccol.inst_blk0[iid], c1 = ccol.inst_blk0[iid + 1];
-  const int r0 = crow.inst_blk0[iid], r1 = crow.inst_blk0[iid + 1];
+  if (threadIdx.x == 0) {
+    first[0] = ccol.inst_blk0[iid];
+    first[1] = first[0] + 1;
+    first[2] = crow.inst_blk0[iid];
+    first[3] = first[2] + 1;
+  }
+  __syncthreads();
+  Ranges rc1 = ccol, rr1 = crow;
+  rc1.inst_blk0 = first - iid;
+  rr1.inst_blk0 = first + 2 - iid;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int q = wave & 1;
+  const bool cols = wave < 2;
   for (int pass = 0; pass < passes; ++pass) {
-    for (int q = 0; q < kMaxCand; ++q)
-      for (int b = c0; b < c1; ++b) probe_cols_body<T>(b, q, ccol, x0, x1, gc0, gc1, d, inst, prec, rec_c);
-    for (int q = 0; q < kMaxCand; ++q)
-      for (int b = r0; b < r1; ++b) probe_rows_body<T>(b, q, crow, y0, y1, gr0, gr1, d, D1, inst, prec, rec_r);
+    const Inst& I = inst[iid];
+    const CandState& C = I.cand[q];
+    if (C.phase == kPhaseExp || C.phase == kPhaseBisect) {  // uniform within the wave
+      double acc[kProbeNV];
+#pragma unroll
+      for (int i = 0; i < kProbeNV; ++i) acc[i] = 0.0;
+      if (cols) {
+        const double tau = I.eta_hat / I.omega, inv_tau = 1.0 / tau;
+        double tq[kProbes];
+#pragma unroll
+        for (int p = 0; p < kProbes; ++p) tq[p] = probe_t(C, p) * tau;
+        const T* xs = q == 0 ? x0 : x1;
+        const double* gs = q == 0 ? gc0 : gc1;
+        for (int j = I.col0 + lane; j < I.col0 + I.cols; j += kWave) {
+          const double lo = d.l[j], hi = d.u[j];
+          const double xc = (double)xs[j];
+          const double b1 = gs[j] - d.c[j];
+#pragma unroll
+          for (int p = 0; p < kProbes; ++p) {
+            const double dx = clampd(xc + tq[p] * b1, lo, hi) - xc;
+            acc[p * 2 + 0] += dx * dx * inv_tau;
+            acc[p * 2 + 1] += b1 * dx;
+          }
+        }
+      } else {
+        const double sigma = I.eta_hat * I.omega, inv_sigma = 1.0 / sigma;
+        const int mz_end = I.row0 + I.m_zero;
+        double tq[kProbes];
+#pragma unroll
+        for (int p = 0; p < kProbes; ++p) tq[p] = probe_t(C, p) * sigma;
+        const T* ys = q == 0 ? y0 : y1;
+        const double* gs = q == 0 ? gr0 : gr1;
+        for (int i = I.row0 + lane; i < I.row0 + I.rows; i += kWave) {
+          const bool zero_row = i < mz_end;
+          const double yc = (double)ys[i];
+          const double b2 = d.h[i] - gs[i];
+#pragma unroll
+          for (int p = 0; p < kProbes; ++p) {
+            const double v = yc + tq[p] * b2;
+            const double dy = (zero_row ? v : fmax(v, 0.0)) - yc;
+            acc[p * 2 + 0] += dy * dy * inv_sigma;
+            acc[p * 2 + 1] += b2 * dy;
+          }
+        }
+      }
+      double* rec = cols ? rec_c + ((size_t)q * ccol.nblk + first[0]) * kProbeNV
+                         : rec_r + ((size_t)q * crow.nblk + first[2]) * kProbeNV;
+#pragma unroll
+      for (int i = 0; i < kProbeNV; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0) rec[i] = s;
+      }
+    }
     __syncthreads();
-    probe_fin_body(iid, ccol, rec_c, crow, rec_r, inst);
+    probe_fin_body(iid, rc1, rec_c, rr1, rec_r, inst);
     __syncthreads();
   }
 }
@@ -2641,11 +2705,11 @@ void launch_check(const KernelCtx& k, hipStream_t s, int mask) {
   if (k.wg_trials && !k.use_band) {
     if (mask & 1)
       k_probes_wg<float><<<k.nb, kBlock, 0, s>>>(k.ccol, k.crow, k.it32.xh, k.it32.xbar, k.it32.yh, k.it32.ybar,
-                                                 k.cgty0, k.cgty1, k.cgx0, k.cgx1, k.d64, k.D1, k.inst, kFP32,
+                                                 k.cgty0, k.cgty1, k.cgx0, k.cgx1, k.d64, k.inst, kFP32,
                                                  k.rec_probe_c, k.rec_probe_r, k.probe_passes);
     if (mask & 2)
       k_probes_wg<double><<<k.nb, kBlock, 0, s>>>(k.ccol, k.crow, k.it64.xh, k.it64.xbar, k.it64.yh, k.it64.ybar,
-                                                  k.cgty0, k.cgty1, k.cgx0, k.cgx1, k.d64, k.D1, k.inst, kFP64,
+                                                  k.cgty0, k.cgty1, k.cgx0, k.cgx1, k.d64, k.inst, kFP64,
                                                   k.rec_probe_c, k.rec_probe_r, k.probe_passes);
   } else {
     for (int pass = 0; pass < k.probe_passes; ++pass) {
