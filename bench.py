@@ -274,13 +274,15 @@ def run_c4(args, P, np):
     inst = lpgen.c4_instance(0)
     prob = P.Problem.from_instance(inst)
     res = {}
+    # --max-trials caps each solve (a bounded run for kernel traces)
+    cap = {"max_iter": args.max_trials} if args.max_trials > 0 else {}
     for prec in ("mixed", "fp64"):
         for _ in range(args.warmup):
-            prob.solve(precision=prec, time_limit=300.0)
+            prob.solve(precision=prec, time_limit=300.0, **cap)
         walls, s = [], None
         for _ in range(args.steps):
             t0 = time.perf_counter()
-            s = prob.solve(precision=prec, time_limit=300.0)
+            s = prob.solve(precision=prec, time_limit=300.0, **cap)
             walls.append(time.perf_counter() - t0)
         res[prec] = (float(np.median(walls)), s.info)
         log(f"c4 {prec}: {res[prec][0]:.2f}s, {s.info['iters']} trials ({s.info['fp64_iters']} FP64), "
@@ -355,26 +357,28 @@ def run_c3(args, P, np):
     zt = np.hstack([np.array([s.x for s in cold]), np.array([s.y for s in cold])])
     err = float(np.linalg.norm(np.hstack([xw, yw]) - zt) / np.linalg.norm(zt))
     err_mean = float(np.linalg.norm(Z.mean(0) - zt) / np.linalg.norm(zt))
-    # one training step of the network at this shape: 6 GEMMs of 2 x batch x
-    # (6e4 x 512 + 512 x 512 + 512 x 6e4) flops each pass (forward + 2 backward)
+    # one training step of the network at this shape (batch 256), timed with
+    # events around 10 asynchronous steps; bytes as in the c3_mlp workload
     import torch
 
     ub = torch.tensor(U[:256], device="cuda")
     zb = torch.tensor(Z[:256], device="cuda")
     net.net.train_step(ub, zb, 1e-9)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(10):
-        net.net.train_step(ub, zb, 1e-9)
+        net.net.train_step(ub, zb, 1e-9, wait=False)
+    e1.record()
     torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t0) / 10 * 1e3
+    ms_step = e0.elapsed_time(e1) / 10
     d = base.m + base.n
-    flops = 3 * 2 * 256 * (d * 512 + 512 * 512 + 512 * d)
-    tflops = flops / (ms_step * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
-            "frac": round(tflops / 2500.0, 5), "traffic": None,
-            "kernel": "MLP training step (k_gemm BF16 MFMA + epilogues + Adam), batch 256",
-            "ms_per_train_step": round(ms_step, 3)}
+    nbytes = mlp_step_bytes(256, d, 512, d)
+    gbs = nbytes / (ms_step * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(gbs / 8000.0, 4), "traffic": None,
+            "kernel": "MLP training step (BF16 MFMA products, loss and Adam in their epilogues), batch 256",
+            "ms_per_train_step": round(ms_step, 3), "bytes_per_step": int(nbytes)}
     return common_fields(args, round(len(held) / ww, 4), "solves/s", ww * 1e3, "f32+f64 (MLP bf16)", {
         "workload": f"LP family m=2e4 n=4e4 nnz=3e5, h and c perturbed by 10% N(0,1); {ntr} training and "
                     f"{nte} held-out members (the full family has 16000 and 4000)",
@@ -564,7 +568,7 @@ def main():
     ap.add_argument("--c2-count", type=int, default=512)
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "bands"],
                     help="c2: matrix layout of the batch (profiling)")
-    ap.add_argument("--max-trials", type=int, default=0, help="c2: cap on trials per instance (profiling)")
+    ap.add_argument("--max-trials", type=int, default=0, help="c2, c4: cap on trials per instance (profiling)")
     ap.add_argument("--c3-train", type=int, default=1024)
     ap.add_argument("--c3-test", type=int, default=256)
     ap.add_argument("--c3-epochs", type=int, default=200)

@@ -253,18 +253,9 @@ int  pdcs_problem_spmv(pdcs_problem p, int64_t transpose, int64_t precision,
 int  pdcs_problem_spmv_noalloc(pdcs_problem p, int64_t transpose, int64_t precision,
                                const void* in_dev, void* out_dev, void* stream);
 
-/* pdcs_problem_set_panels: column-panel split of the two SpMVs of a single
- * problem.  px panels split the columns gathered by G x, py the rows gathered
- * by G^T y; each panel's workgroups are routed to a fixed subset of the 8 XCDs
- * so that its slice of the gathered vector stays in that XCD's L2.
- * 0 = automatic (about 256 Ki entries per panel), 1 = off, 2/4/8 = forced.
- * Errors: PDCS_ERR_INVALID_ARG for other values. */
-int  pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py);
-
 /* pdcs_problem_set_layout: storage of the matrix for the two SpMVs of every
  * trial of a single problem.
- *   PDCS_LAYOUT_ROWS : CSR row blocks, fused with the dual / dual-slack steps
- *                      (with the column-panel split of pdcs_problem_set_panels);
+ *   PDCS_LAYOUT_ROWS : CSR row blocks, fused with the dual / dual-slack steps;
  *   PDCS_LAYOUT_BANDS: band tiles: row bands x gathered-index windows, entries
  *                      sorted by gathered index and summed per row in LDS, then
  *                      one partial sum per window combined by the epilogues;

@@ -82,7 +82,6 @@ PROTOTYPES = {
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
     "pdcs_problem_spmv_noalloc": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
-    "pdcs_problem_set_panels": (C.c_int, [_P, _I64, _I64]),
     "pdcs_problem_set_layout": (C.c_int, [_P, _I64]),
     "pdcs_problem_set_band_schedule": (C.c_int, [_P, _I64, _I64, _I64]),
     "pdcs_problem_band_schedule": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64),
@@ -253,10 +252,6 @@ def pdcs_problem_spmv_noalloc(p, transpose: int, precision: int, in_dev: int, ou
     _check(lib.pdcs_problem_spmv_noalloc(p, int(transpose), int(precision), C.c_void_p(in_dev),
                                          C.c_void_p(out_dev), C.c_void_p(stream) if stream else None),
            "pdcs_problem_spmv_noalloc")
-
-
-def pdcs_problem_set_panels(p, px: int, py: int):
-    _check(lib.pdcs_problem_set_panels(p, int(px), int(py)), "pdcs_problem_set_panels")
 
 
 LAYOUTS = {"auto": 0, "rows": 1, "bands": 2, "workgroup": 3}
@@ -518,9 +513,6 @@ class Problem:
                             device_out=device_out)
         finally:
             pdcs_result_destroy(r)
-
-    def set_panels(self, px=0, py=0):
-        pdcs_problem_set_panels(self.handle, px, py)
 
     def set_layout(self, layout="auto"):
         """Matrix storage for the trial SpMVs: "auto", "rows", "bands" or "workgroup"."""

@@ -101,23 +101,6 @@ struct RangeSet {
   Ranges view() const;
 };
 
-// Panel-major copy of a CSR-like structure whose gathered index range is split
-// into P panels: virtual row v = p * R + r holds the entries of row r whose
-// gathered index falls in panel p.  Used for single large instances so that
-// the gathered slice of each panel fits in one XCD's L2.
-struct PanelSet {
-  int P = 1;
-  int64_t R = 0;
-  std::vector<int32_t> h_ptr;
-  DBuf d_ptr, d_idx, d_val, val64, val32, part32, part64, part64b, slot;
-  int nslot = 0;
-  TileSet tiles;        // set-up passes
-  RowBlockSet blocks;   // iteration passes
-  void build(int P, int64_t R, int64_t G, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx,
-             const std::vector<double>& val, const Schedule& s);
-  void build_slots();
-};
-
 // Shape of the band tiles: the tallest band height (a power of two, at most
 // kBandRows), halved while fewer than min_tiles band-tiles would result; in a
 // batch, bands are further cut to at most about entry_cap entries per window.
@@ -199,11 +182,8 @@ struct Engine {
   SocTable soc;                // second-order-cone row blocks (absolute rows)
   RangeSet vrow, vcol;
   RangeSet crow, ccol;         // coarser blocks for the multisection passes
-  PanelSet prow, pcol;         // panel-major G (gathers x) and G^T (gathers y) when split
   std::vector<int32_t> h_ci, h_ri;
-  std::vector<double> h_v, h_vt;
   DBuf rec_dual_epi, rec_lam_epi;
-  int panels_x = 0, panels_y = 0;   // 0: automatic
   int layout = PDCS_LAYOUT_AUTO;
   bool use_band = false;
   bool wg_trials = false;           // chunks of trials by one workgroup per instance

@@ -371,68 +371,6 @@ Ranges RangeSet::view() const {
 }
 
 // ---------------------------------------------------------------------------
-// Panel split
-// ---------------------------------------------------------------------------
-void PanelSet::build(int P_, int64_t R_, int64_t G, const std::vector<int32_t>& ptr,
-                     const std::vector<int32_t>& idx, const std::vector<double>& val, const Schedule& s) {
-  P = P_;
-  R = R_;
-  const int64_t nnz = ptr[R];
-  if ((int64_t)P * R >= INT32_MAX) throw Error(PDCS_ERR_SIZE, "panel split too large");
-  const int64_t width = (G + P - 1) / P;
-  h_ptr.assign((size_t)P * R + 1, 0);
-  // counts per (panel, row)
-  for (int64_t r = 0; r < R; ++r)
-    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) h_ptr[(size_t)(idx[q] / width) * R + r + 1]++;
-  for (size_t v = 0; v < (size_t)P * R; ++v) h_ptr[v + 1] += h_ptr[v];
-  std::vector<int32_t> pidx(nnz);
-  std::vector<double> pval(nnz);
-  std::vector<int32_t> fill(h_ptr.begin(), h_ptr.end() - 1);
-  for (int64_t r = 0; r < R; ++r)
-    for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) {
-      const int32_t dst = fill[(size_t)(idx[q] / width) * R + r]++;
-      pidx[dst] = idx[q];
-      pval[dst] = val[q];
-    }
-  upload(d_ptr, h_ptr);
-  upload(d_idx, pidx);
-  upload(d_val, pval);
-  val64.alloc((size_t)nnz * 8);
-  val32.alloc((size_t)nnz * 4);
-  part32.alloc((size_t)P * R * 4);
-  part64.alloc((size_t)P * R * 8);
-  part64b.alloc((size_t)P * R * 8);
-  std::vector<int64_t> vr0(P + 1);
-  for (int p = 0; p <= P; ++p) vr0[p] = (int64_t)p * R;
-  tiles.build(h_ptr, vr0, s);
-  blocks.build(h_ptr, vr0, s.iter_max * 4);
-  build_slots();
-}
-
-// Launch slot s runs on XCD s % 8 (workgroups are dispatched to the XCDs in
-// round-robin order).  Panel p is served by the XCDs x with x % P == p, which
-// take its workgroups in interleaved order; slots without work hold -1.
-void PanelSet::build_slots() {
-  const int nx = 8;
-  const int share = nx / P;
-  std::vector<std::vector<int32_t>> per_xcd(nx);
-  std::vector<int> seen(P, 0);
-  for (int b = 0; b < blocks.nblk; ++b) {
-    const int p = blocks.h_binst[b];
-    const int k = seen[p]++;
-    per_xcd[p + P * (k % share)].push_back(b);
-  }
-  size_t S = 0;
-  for (auto& l : per_xcd) S = std::max(S, l.size());
-  std::vector<int32_t> sl(S * nx, -1);
-  for (size_t k = 0; k < S; ++k)
-    for (int x = 0; x < nx; ++x)
-      if (k < per_xcd[x].size()) sl[k * nx + x] = per_xcd[x][k];
-  nslot = (int)sl.size();
-  upload(slot, sl);
-}
-
-// ---------------------------------------------------------------------------
 // Band tiles
 // ---------------------------------------------------------------------------
 namespace {
@@ -767,14 +705,6 @@ BandTiles BandSet::view() const {
   return b;
 }
 
-static int auto_panels(int64_t gathered) {
-  // about 1 MiB of FP32 gathered values per panel, at most 8 (one per XCD)
-  const int64_t per = 256 * 1024;
-  int P = 1;
-  while (P < 8 && gathered > per * P) P *= 2;
-  return P;
-}
-
 // ---------------------------------------------------------------------------
 // Engine
 // ---------------------------------------------------------------------------
@@ -830,10 +760,6 @@ Engine::Engine(const std::vector<const HostProblem*>& probs) {
   h_cp[N] = (int32_t)NNZ;
   h_ci = ci;  // kept for the band tiles
   h_ri = ri;
-  if (B == 1) {  // kept for the panel split of single large instances
-    h_v = v;
-    h_vt = vt;
-  }
   upload(d_rp, h_rp);
   upload(d_ci, ci);
   upload(d_v, v);
@@ -917,20 +843,10 @@ void Engine::build_iteration_schedules(const std::vector<char>* active) {
 
 void Engine::build_schedule() {
   build_iteration_schedules(nullptr);
-  int P1 = 1, P2 = 1;
-  if (B == 1 && layout != PDCS_LAYOUT_WORKGROUP) {
-    P1 = panels_x > 0 ? panels_x : auto_panels(N);
-    P2 = panels_y > 0 ? panels_y : auto_panels(M);
-  }
   // cone blocks are projected in the row epilogues of the split dual pass,
   // which the band layout always takes
   const bool want_band = layout == PDCS_LAYOUT_BANDS || !soc.empty() ||
                          (layout == PDCS_LAYOUT_AUTO && NNZ >= ((int64_t)1 << 22));
-  prow.P = pcol.P = 1;
-  if (!want_band) {  // the panel-major CSR copies serve the row layout only
-    if (P1 > 1) prow.build(P1, M, N, h_rp, h_ci, h_v, sched);
-    if (P2 > 1) pcol.build(P2, N, M, h_cp, h_ri, h_vt, sched);
-  }
   if (want_band && !band1.nslot && !band2.nslot) {
     band1.build(row0, col0, h_rp, h_ci, bsched);
     band2.build(col0, row0, h_cp, h_ri, bsched);
@@ -939,9 +855,9 @@ void Engine::build_schedule() {
   // one workgroup per instance for whole chunks of trials: forced, or
   // automatically when every instance fits in LDS in FP64 (the workgroup then
   // runs its trials out of LDS; on global memory it would be slower than the
-  // row-block kernels), on row blocks without panels
+  // row-block kernels), on row blocks
   plan_lds_trials();
-  wg_trials = !want_band && prow.P == 1 && pcol.P == 1 &&
+  wg_trials = !want_band &&
               (layout == PDCS_LAYOUT_WORKGROUP || (layout == PDCS_LAYOUT_AUTO && lds_bytes[1] > 0));
   if (!wg_trials) lds_bytes[0] = lds_bytes[1] = 0;
   rec_dual_epi.alloc((size_t)std::max(vrow.nblk, 1) * 4 * 8);
@@ -1034,8 +950,6 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.rec_probe_c = rec_probe_c.as<double>();
   k.rec_probe_r = rec_probe_r.as<double>();
   k.probe_passes = probe_passes;
-  k.P1 = prow.P;
-  k.P2 = pcol.P;
   k.wg_trials = wg_trials ? 1 : 0;
   k.lds_trials32 = (int)lds_bytes[0];
   k.lds_trials64 = (int)lds_bytes[1];
@@ -1050,17 +964,6 @@ KernelCtx Engine::ctx(int probe_passes) const {
   k.ry = ry.as<double>();
   k.rgx = rgx.as<double>();
   k.rgty = rgty.as<double>();
-  if (prow.P > 1) {
-    k.prow = prow.tiles.view();
-    k.bprow = prow.blocks.view();
-    k.slot1 = prow.slot.as<int32_t>();
-    k.nslot1 = prow.nslot;
-    k.PA32 = MatPtrs<float>{prow.d_ptr.as<int32_t>(), prow.d_idx.as<int32_t>(), prow.val32.as<float>()};
-    k.PA64 = MatPtrs<double>{prow.d_ptr.as<int32_t>(), prow.d_idx.as<int32_t>(), prow.val64.as<double>()};
-    k.part32 = prow.part32.as<float>();
-    k.part64 = prow.part64.as<double>();
-    k.part64b = prow.part64b.as<double>();
-  }
   k.use_band = use_band && !band_suspended ? 1 : 0;
   if (k.use_band) {
     k.band1 = band1.view();
@@ -1075,17 +978,6 @@ KernelCtx Engine::ctx(int probe_passes) const {
     k.bpartT64 = band2.part64.as<double>();
     k.bpart64b = band1.part64b.as<double>();
     k.bpartT64b = band2.part64b.as<double>();
-  }
-  if (pcol.P > 1) {
-    k.pcol = pcol.tiles.view();
-    k.bpcol = pcol.blocks.view();
-    k.slot2 = pcol.slot.as<int32_t>();
-    k.nslot2 = pcol.nslot;
-    k.PAT32 = MatPtrs<float>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.val32.as<float>()};
-    k.PAT64 = MatPtrs<double>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.val64.as<double>()};
-    k.partT32 = pcol.part32.as<float>();
-    k.partT64 = pcol.part64.as<double>();
-    k.partT64b = pcol.part64b.as<double>();
   }
   return k;
 }
@@ -1322,16 +1214,6 @@ std::vector<pdcs_result> Engine::solve(const pdcs_options& o, const WarmStart& w
   su.rec_nm = rec_nm.as<double>();
   su.x0 = dx0;
   su.y0 = dy0;
-  if (prow.P > 1) {
-    su.PA = MatPtrs<double>{prow.d_ptr.as<int32_t>(), prow.d_idx.as<int32_t>(), prow.d_val.as<double>()};
-    su.pval64 = prow.val64.as<double>();
-    su.pval32 = prow.val32.as<float>();
-  }
-  if (pcol.P > 1) {
-    su.PAT = MatPtrs<double>{pcol.d_ptr.as<int32_t>(), pcol.d_idx.as<int32_t>(), pcol.d_val.as<double>()};
-    su.pvalT64 = pcol.val64.as<double>();
-    su.pvalT32 = pcol.val32.as<float>();
-  }
   if (use_band) {
     su.bsrc = band1.src.as<int32_t>();
     su.bsrcT = band2.src.as<int32_t>();
@@ -1802,18 +1684,6 @@ int pdcs_problem_set_layout(pdcs_problem p, int64_t layout) {
     p->eng->layout = (int)layout;
     p->eng->build_schedule();
     p->eng->prepare_plain();
-    return PDCS_OK;
-  });
-}
-
-int pdcs_problem_set_panels(pdcs_problem p, int64_t px, int64_t py) {
-  return guarded([&]() {
-    if (!p) throw Error(PDCS_ERR_INVALID_ARG, "problem is null");
-    auto ok = [](int64_t v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
-    if (!ok(px) || !ok(py)) throw Error(PDCS_ERR_INVALID_ARG, "panels must be 0, 1, 2, 4 or 8");
-    p->eng->panels_x = (int)px;
-    p->eng->panels_y = (int)py;
-    p->eng->build_schedule();
     return PDCS_OK;
   });
 }

@@ -257,29 +257,6 @@ __global__ __launch_bounds__(kBlock) void k_dual(RowBlocks rb, MatPtrs<TM> A, It
 }
 
 // ---------------------------------------------------------------------------
-// Column-panel SpMV for large instances.  The gathered index range is split
-// into P panels stored panel-major ("virtual rows" v = p * R + r), and the
-// slot table routes panel p's workgroups to the XCDs with blockIdx % 8 = p
-// (mod P), so that each XCD's L2 holds only its slice of the gathered vector.
-// Partial sums part[v] are combined, in panel order, by the epilogue passes.
-// ---------------------------------------------------------------------------
-// Split mode serves a single instance: inst[0] says whether this pass is needed
-// (need_acc: only after an accepted trial).
-template <typename T, typename TM>
-__global__ __launch_bounds__(kBlock) void k_spmv_part(RowBlocks rb, const int32_t* __restrict__ slot,
-                                                      MatPtrs<TM> A, const T* __restrict__ x,
-                                                      T* __restrict__ part, const Inst* __restrict__ inst,
-                                                      int need_acc) {
-  __shared__ double lds[kRowBlockCap + kWavesPerBlock];
-  const int b = slot[blockIdx.x];
-  if (b < 0) return;
-  if (inst[0].status != kActive || (need_acc && inst[0].last_acc == 0)) return;
-  const T* const xs[1] = {x};
-  block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
-                [&](int r, const double* s) { part[r] = (T)s[0]; });
-}
-
-// ---------------------------------------------------------------------------
 // Band-tile SpMV for single large instances (layout: BandTiles).  The gathers
 // of a band-tile stay inside one window of the gathered vector, held in the L2
 // of the XCDs that serve the window, and since the entries are sorted by
@@ -1029,51 +1006,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv2(RowBlocks rb, MatPtrs<double> 
     block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
                   [&](int r, const double* s) { out0[r] = s[0]; });
   }
-}
-
-// Split mode: two products with one pass over the panel-major FP64 values,
-// partial sums per panel, then combined in panel order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spmv2_part(RowBlocks rb, const int32_t* __restrict__ slot,
-                                                       MatPtrs<double> A, const T* __restrict__ in0,
-                                                       const T* __restrict__ in1, double* __restrict__ part0,
-                                                       double* __restrict__ part1, const Inst* __restrict__ inst,
-                                                       int prec, int mode) {
-  __shared__ double lds[2 * kRowBlockCap + kWavesPerBlock * 2];
-  const int b = slot[blockIdx.x];
-  if (b < 0) return;
-  const Inst& I = inst[0];
-  if (!mode_selects(I, mode) || !prec_selects(I, mode, prec)) return;
-  const bool two = (in1 != nullptr) && (mode != kModeCheck || I.use_avg != 0);
-  if (two) {
-    const T* const xs[2] = {in0, in1};
-    block_rows<2>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds, [&](int r, const double* s) {
-      part0[r] = s[0];
-      part1[r] = s[1];
-    });
-  } else {
-    const T* const xs[1] = {in0};
-    block_rows<1>(rb.blk_row0[b], rb.blk_row1[b], A.ptr, A.idx, A.val, xs, lds,
-                  [&](int r, const double* s) { part0[r] = s[0]; });
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_combine2(int64_t R, int P, const double* __restrict__ part0,
-                                                     const double* __restrict__ part1, double* __restrict__ out0,
-                                                     double* __restrict__ out1, const Inst* __restrict__ inst,
-                                                     int mode) {
-  const Inst& I = inst[0];
-  if (!mode_selects(I, mode)) return;
-  const bool two = part1 != nullptr && (mode != kModeCheck || I.use_avg != 0);
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r >= R) return;
-  double s0 = 0.0, s1 = 0.0;
-  for (int p = 0; p < P; ++p) {
-    s0 += part0[(size_t)p * R + r];
-    if (two) s1 += part1[(size_t)p * R + r];
-  }
-  out0[r] = s0;
-  if (two) out1[r] = s1;
 }
 
 // Candidate reductions over the columns.  Per candidate c (0: PDHG output or
@@ -2417,14 +2349,11 @@ const double* band_val<double>(const KernelCtx& k, int which) {
 
 template <typename T>
 static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
-                          const DataPtrs<T>& d, const MatPtrs<T>& A, const MatPtrs<T>& PA, T* part) {
+                          const DataPtrs<T>& d, const MatPtrs<T>& A, T* part) {
   if (k.use_band) {
     if (k.band1.nslot > 0)
       k_band_spmv<T><<<grid1(k.band1.nslot), kBandWaves * kWave, 0, s>>>(k.band1, band_val<T>(k, 0), it.xh, part,
                                                                          k.M, k.inst, prec, 0);
-  } else if (k.P1 > 1) {
-    if (k.nslot1 > 0)
-      k_spmv_part<T, T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, PA, it.xh, part, k.inst, 0);
   } else if (k.brow.nblk > 0) {
     k_dual<T, T><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, A, it, d, k.inst, prec, k.rec_dual);
   }
@@ -2433,55 +2362,49 @@ static void launch_dual_t(const KernelCtx& k, hipStream_t s, int prec, const Ite
 template <typename T>
 static void launch_dual_epi_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                               const DataPtrs<T>& d, const T* part) {
-  if (k.split1() && k.vrow.nblk > 0)
-    k_dual_epi<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, part, k.use_band ? k.band1.P : k.P1, k.M, it, d,
+  if (k.use_band && k.vrow.nblk > 0)
+    k_dual_epi<T><<<grid1(k.vrow.nblk), kBlock, 0, s>>>(k.vrow, part, k.band1.P, k.M, it, d,
                                                          k.D1, k.inst, prec, k.rec_dual_epi);
 }
 
 template <typename T>
 static void launch_lam_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
-                         const DataPtrs<T>& d, const MatPtrs<T>& AT, const MatPtrs<T>& PAT, T* part) {
-  if (k.split2()) {
-    if (k.use_band) {
-      if (k.band2.nslot > 0)
-        k_band_spmv<T><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, band_val<T>(k, 1), it.yh,
-                                                                           part, k.N, k.inst, prec, 1);
-    } else if (k.nslot2 > 0) {
-      k_spmv_part<T, T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, PAT, it.yh, part, k.inst, 1);
-    }
+                         const DataPtrs<T>& d, const MatPtrs<T>& AT, T* part) {
+  if (k.use_band) {
+    if (k.band2.nslot > 0)
+      k_band_spmv<T><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, band_val<T>(k, 1), it.yh, part,
+                                                                         k.N, k.inst, prec, 1);
     if (k.vcol.nblk > 0)
-      k_lam_epi<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, part, k.use_band ? k.band2.P : k.P2, k.N, it, d,
-                                                          k.inst, prec, k.rec_lam_epi);
+      k_lam_epi<T><<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, part, k.band2.P, k.N, it, d, k.inst, prec,
+                                                          k.rec_lam_epi);
   } else if (k.bcol.nblk > 0) {
     k_lam<T, T><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, AT, it, d, k.inst, prec, k.rec_lam);
   }
 }
 
-// part 0: primal pass; part 1: the SpMV G x_hat (fused with the dual step
-// unless the instance is split into panels); part 2: the rest of the trial.
+// part 0: primal pass; part 1: the SpMV G x_hat (fused with the dual step on
+// row blocks; band tiles write partial sums); part 2: the rest of the trial.
 void launch_trial_part(const KernelCtx& k, hipStream_t s, int mask, int part) {
   if (part == 0) {
     if (mask & 1) launch_primal_t<float>(k, s, kFP32, k.it32, k.d32);
     if (mask & 2) launch_primal_t<double>(k, s, kFP64, k.it64, k.d64);
     return;
   }
-  float* p32 = k.use_band ? k.bpart32 : k.part32;
-  double* p64 = k.use_band ? k.bpart64 : k.part64;
   if (part == 1) {
-    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, p32);
-    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, p64);
+    if (mask & 1) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.bpart32);
+    if (mask & 2) launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.bpart64);
     return;
   }
-  if (mask & 1) launch_dual_epi_t<float>(k, s, kFP32, k.it32, k.d32, p32);
-  if (mask & 2) launch_dual_epi_t<double>(k, s, kFP64, k.it64, k.d64, p64);
-  const bool s1 = k.split1(), s2 = k.split2();
+  if (mask & 1) launch_dual_epi_t<float>(k, s, kFP32, k.it32, k.d32, k.bpart32);
+  if (mask & 2) launch_dual_epi_t<double>(k, s, kFP64, k.it64, k.d64, k.bpart64);
+  const bool split = k.use_band != 0;
   k_fin_ls<<<grid1(k.nb), kBlock, 0, s>>>(k.vcol.inst_blk0, k.rec_primal,
-                                           s1 ? k.vrow.inst_blk0 : k.brow.inst_blk0,
-                                           s1 ? k.rec_dual_epi : k.rec_dual, k.inst);
-  if (mask & 1) launch_lam_t<float>(k, s, kFP32, k.it32, k.d32, k.AT32, k.PAT32, k.use_band ? k.bpartT32 : k.partT32);
-  if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.PAT64, k.use_band ? k.bpartT64 : k.partT64);
-  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(s2 ? k.vcol.inst_blk0 : k.bcol.inst_blk0,
-                                             s2 ? k.rec_lam_epi : k.rec_lam, k.inst);
+                                           split ? k.vrow.inst_blk0 : k.brow.inst_blk0,
+                                           split ? k.rec_dual_epi : k.rec_dual, k.inst);
+  if (mask & 1) launch_lam_t<float>(k, s, kFP32, k.it32, k.d32, k.AT32, k.bpartT32);
+  if (mask & 2) launch_lam_t<double>(k, s, kFP64, k.it64, k.d64, k.AT64, k.bpartT64);
+  k_fin_beta<<<grid1(k.nb), kBlock, 0, s>>>(split ? k.vcol.inst_blk0 : k.bcol.inst_blk0,
+                                             split ? k.rec_lam_epi : k.rec_lam, k.inst);
 }
 
 // Dynamic LDS the LDS-resident chunk kernel can take: the device's LDS per
@@ -2543,7 +2466,6 @@ void launch_trial(const KernelCtx& k, hipStream_t s, int mask) {
 template <typename T>
 static void launch_cand_t(const KernelCtx& k, hipStream_t s, int prec, const IterPtrs<T>& it,
                           const T* x0, const T* x1, const T* y0, const T* y1, int mode) {
-  auto blocks = [](int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
   if (k.use_band) {
     // band tiles with FP64 values: one pass per vector, then the window sums
     if (k.band1.nslot > 0) {
@@ -2567,26 +2489,10 @@ static void launch_cand_t(const KernelCtx& k, hipStream_t s, int prec, const Ite
       k_band_combine2<<<grid1(k.vcol.nblk), kBlock, 0, s>>>(k.vcol, k.band2.P, k.N, k.bpartT64,
                                                              y1 ? k.bpartT64b : nullptr, k.cgty0, k.cgty1, k.inst,
                                                              mode);
-  } else if (k.P1 > 1) {
-    if (k.nslot1 > 0)
-      k_spmv2_part<T><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, k.PA64, x0, x1, k.part64, k.part64b,
-                                                          k.inst, prec, mode);
-    if (k.M > 0)
-      k_combine2<<<blocks(k.M), kBlock, 0, s>>>(k.M, k.P1, k.part64, x1 ? k.part64b : nullptr, k.cgx0, k.cgx1,
-                                                 k.inst, mode);
   } else if (k.brow.nblk > 0) {
     k_spmv2<T><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, k.A64, x0, x1, k.cgx0, k.cgx1, k.inst, prec, mode);
   }
-  if (k.use_band) {
-    // done above
-  } else if (k.P2 > 1) {
-    if (k.nslot2 > 0)
-      k_spmv2_part<T><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, k.PAT64, y0, y1, k.partT64,
-                                                          k.partT64b, k.inst, prec, mode);
-    if (k.N > 0)
-      k_combine2<<<blocks(k.N), kBlock, 0, s>>>(k.N, k.P2, k.partT64, y1 ? k.partT64b : nullptr, k.cgty0,
-                                                 k.cgty1, k.inst, mode);
-  } else if (k.bcol.nblk > 0) {
+  if (!k.use_band && k.bcol.nblk > 0) {
     k_spmv2<T><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, k.AT64, y0, y1, k.cgty0, k.cgty1, k.inst, prec,
                                                       mode);
   }
@@ -2633,7 +2539,6 @@ static void launch_restart_t(const KernelCtx& k, hipStream_t s, int prec, const 
 // its precision): rgty = G_hat^T r_y, and rgx = G_hat r_x when some instance
 // has an unbounded column.
 static void launch_ray_products(const KernelCtx& k, hipStream_t s) {
-  auto blocks = [](int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
   if (k.use_band) {
     if (k.band2.nslot > 0)
       k_band_cand<double><<<grid1(k.band2.nslot), kBandWaves * kWave, 0, s>>>(k.band2, k.bvalT64, k.ry, k.bpartT64,
@@ -2651,24 +2556,12 @@ static void launch_ray_products(const KernelCtx& k, hipStream_t s) {
     }
     return;
   }
-  if (k.P2 > 1) {
-    if (k.nslot2 > 0)
-      k_spmv2_part<double><<<grid1(k.nslot2), kBlock, 0, s>>>(k.bpcol, k.slot2, k.PAT64, k.ry, nullptr, k.partT64,
-                                                               nullptr, k.inst, kFP64, kModeRay);
-    if (k.N > 0)
-      k_combine2<<<blocks(k.N), kBlock, 0, s>>>(k.N, k.P2, k.partT64, nullptr, k.rgty, nullptr, k.inst, kModeRay);
-  } else if (k.bcol.nblk > 0) {
+  if (k.bcol.nblk > 0) {
     k_spmv2<double><<<grid1(k.bcol.nblk), kBlock, 0, s>>>(k.bcol, k.AT64, k.ry, nullptr, k.rgty, nullptr, k.inst,
                                                            kFP64, kModeRay);
   }
   if (!k.ray_x) return;
-  if (k.P1 > 1) {
-    if (k.nslot1 > 0)
-      k_spmv2_part<double><<<grid1(k.nslot1), kBlock, 0, s>>>(k.bprow, k.slot1, k.PA64, k.rx, nullptr, k.part64,
-                                                               nullptr, k.inst, kFP64, kModeRay);
-    if (k.M > 0)
-      k_combine2<<<blocks(k.M), kBlock, 0, s>>>(k.M, k.P1, k.part64, nullptr, k.rgx, nullptr, k.inst, kModeRay);
-  } else if (k.brow.nblk > 0) {
+  if (k.brow.nblk > 0) {
     k_spmv2<double><<<grid1(k.brow.nblk), kBlock, 0, s>>>(k.brow, k.A64, k.rx, nullptr, k.rgx, nullptr, k.inst,
                                                            kFP64, kModeRay);
   }
@@ -2801,14 +2694,8 @@ void launch_setup(const KernelCtx& k, const SetupCtx& su, hipStream_t s, int mas
   }
   if (k.trow.nblk > 0)
     k_scale_vals<<<grid1(k.trow.nblk), kBlock, 0, s>>>(k.trow, su.A, k.D1, k.D2, 0, 0, su.val64, su.val32);
-  if (k.P1 > 1 && k.prow.nblk > 0)
-    k_scale_vals<<<grid1(k.prow.nblk), kBlock, 0, s>>>(k.prow, su.PA, k.D1, k.D2, 0, (int)k.M, su.pval64,
-                                                        su.pval32);
   if (k.tcol.nblk > 0)
     k_scale_vals<<<grid1(k.tcol.nblk), kBlock, 0, s>>>(k.tcol, su.AT, k.D1, k.D2, 1, 0, su.valT64, su.valT32);
-  if (k.P2 > 1 && k.pcol.nblk > 0)
-    k_scale_vals<<<grid1(k.pcol.nblk), kBlock, 0, s>>>(k.pcol, su.PAT, k.D1, k.D2, 1, (int)k.N, su.pvalT64,
-                                                        su.pvalT32);
   if (k.use_band) {
     if (su.bn > 0)
       k_band_vals<<<blocks(su.bn), tpb, 0, s>>>(su.bsrc, su.bn, su.val64, su.bval64, su.bval32);
@@ -2902,8 +2789,8 @@ void launch_pack_warm(const void* const* src, const int32_t* off, int B, int64_t
 }
 
 void launch_dual_only(const KernelCtx& k, hipStream_t s, int prec) {
-  if (prec == kFP32) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.PA32, k.use_band ? k.bpart32 : k.part32);
-  else launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.PA64, k.use_band ? k.bpart64 : k.part64);
+  if (prec == kFP32) launch_dual_t<float>(k, s, kFP32, k.it32, k.d32, k.A32, k.bpart32);
+  else launch_dual_t<double>(k, s, kFP64, k.it64, k.d64, k.A64, k.bpart64);
 }
 
 }  // namespace pdcs

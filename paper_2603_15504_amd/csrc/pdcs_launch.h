@@ -86,16 +86,6 @@ struct KernelCtx {
   double *xout, *yout, *lamout;
   double *rec_primal, *rec_dual, *rec_lam, *rec_cand_c, *rec_cand_r, *rec_probe_c, *rec_probe_r;
   int probe_passes;
-  // Column-panel split of large single instances (P1 panels for G x, P2 for G^T y).
-  int P1, P2;
-  Tiles prow, pcol;              // tiles over the panel-major structures ("virtual rows")
-  RowBlocks bprow, bpcol;        // row blocks over the panel-major structures
-  const int32_t *slot1, *slot2;  // launch slot -> workgroup of the panel schedule (-1: idle)
-  int nslot1, nslot2;
-  MatPtrs<float> PA32, PAT32;
-  MatPtrs<double> PA64, PAT64;
-  float *part32, *partT32;
-  double *part64, *partT64, *part64b, *partT64b;
   double *rec_dual_epi, *rec_lam_epi;
   // Infeasibility tests: projected start point (FP64, rescaled space), the
   // two rays and their products G_hat r_x (rows) and G_hat^T r_y (columns).
@@ -119,8 +109,8 @@ struct KernelCtx {
   int lds_rowwise;  // every row of G and of G^T has at most kLdsRowMax entries: row-wise passes
 
   // the K1 (K2) product is split into partial sums plus an epilogue pass
-  bool split1() const { return use_band || P1 > 1; }
-  bool split2() const { return use_band || P2 > 1; }
+  bool split1() const { return use_band != 0; }
+  bool split2() const { return use_band != 0; }
 };
 
 struct SetupCtx {
@@ -133,9 +123,6 @@ struct SetupCtx {
   DataMut32 d32m;
   double *stat_r, *stat_c, *rec_nc, *rec_nr, *rec_nm;
   const double *x0, *y0;          // device start point (unscaled) or null
-  MatPtrs<double> PA, PAT;        // panel-major unscaled values (when split)
-  double *pval64, *pvalT64;
-  float *pval32, *pvalT32;
   // band-tile values: entry e takes the scaled CSR (CSC) value at src[e] (-1: padding)
   const int32_t *bsrc, *bsrcT;
   int64_t bn, bnT;

@@ -164,31 +164,6 @@ def test_spmv_matches_scipy_power_law():
     assert np.all(np.abs(o32.cpu().numpy().astype(np.float64) - exact32) <= 6e-8 * (1 + np.abs(exact32)) + 1e-12 * bound_m)
 
 
-@pytest.mark.parametrize("panels", [(4, 2), (8, 8)])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_panel_split_matches_oracle(panels, precision):
-    # The XCD panel split changes only the summation order of the SpMVs.
-    inst = lpgen.c0_instance(3)
-    ref = O.solve(O.lpdata_from_instance(inst), O.Options())
-    prob = P.Problem.from_instance(inst)
-    prob.set_panels(*panels)
-    sol = prob.solve(precision=precision, time_limit=60.0)
-    _check_solution(inst, sol, ref.pobj)
-
-
-def test_panel_split_first_trials_elementwise():
-    inst = lpgen.planted_lp(lpgen.rng_for(77, 2), 150, 400, per_col=4, m_zero=70)
-    lp = O.lpdata_from_instance(inst)
-    N = 30
-    ref = O.solve(lp, O.Options(max_iter=N, check_every=1000))
-    prob = P.Problem.from_instance(inst)
-    prob.set_panels(8, 4)
-    sol = prob.solve(precision="fp64", max_iter=N, check_every=1000, keep_state=True)
-    for key, okey in (("x", "x"), ("y", "y"), ("x_hat", "x_hat"), ("y_hat", "y_hat")):
-        a, b = sol.state[key], ref.state[okey]
-        assert np.max(np.abs(a - b)) <= 1e-9 * (1.0 + np.abs(b).max()), key
-
-
 @pytest.mark.parametrize("seed,m", [(0, 300), (1, 1000)])
 def test_first_restart_check_matches_oracle(seed, m):
     # The trajectory is deterministic up to the first restart check, so the
@@ -226,8 +201,8 @@ def test_state_before_first_check_matches_oracle(seed, m):
         assert np.max(np.abs(a - b)) <= 1e-9 * (1.0 + np.abs(b).max()), key
 
 
-@pytest.mark.parametrize("seed,m,panels", [(0, 300, (1, 1)), (1, 1000, (1, 1)), (0, 300, (4, 2))])
-def test_first_trials_scalars_match_oracle(seed, m, panels):
+@pytest.mark.parametrize("seed,m,layout", [(0, 300, "rows"), (1, 1000, "rows"), (0, 300, "workgroup")])
+def test_first_trials_scalars_match_oracle(seed, m, layout):
     # Per-trial step sizes, acceptance and reflection parameters of the first
     # 64 trials (deterministic up to the first restart check) on a power-law
     # LP, whose SpMV schedules have many workgroups per instance.
@@ -235,7 +210,7 @@ def test_first_trials_scalars_match_oracle(seed, m, panels):
     lp = O.lpdata_from_instance(inst)
     ref = O.solve(lp, O.Options(max_iter=64, check_every=64), trace=True)
     prob = P.Problem.from_instance(inst)
-    prob.set_panels(*panels)
+    prob.set_layout(layout)
     sol = prob.solve(precision="fp64", max_iter=64, check_every=64, trace_trials=64)
     tr = sol.trace
     assert len(tr) == 64 == len(ref.trace)
