@@ -171,7 +171,7 @@ def c2_solves(P, np, count=512, sample_single=8, check_oracle=4):
     t_setup = time.perf_counter() - t
     log(f"solves: {len(insts)} LPs (sum nnz {sum(i.nnz for i in insts)}) generated and uploaded in {t_setup:.1f}s")
     t = time.perf_counter()
-    sched = batch.autotune(30000.0)
+    sched = batch.autotune(15000.0)
     t_tune = time.perf_counter() - t
     out = {"workload": f"{len(insts)} LPs m~logU[1e3,5e4], n=2m, 8 nnz/col, rel. KKT 1e-6",
            "sum_nnz": int(sum(i.nnz for i in insts)), "autotune_s": round(t_tune, 2),

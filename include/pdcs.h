@@ -93,7 +93,7 @@ typedef struct {
                                  trial whose trial count is a multiple of this         */
   int64_t precision;          /* PDCS_PRECISION_*                                     */
   int64_t stall_checks;       /* 16; mixed: switch to FP64 after this many checks
-                                 without a 2x improvement of the relative KKT error
+                                 without a 10% improvement of the relative KKT error
                                  once that error is below 100 * rel_tol, or after 8x
                                  this many checks without a new lowest error at any
                                  level (0: never)                                     */

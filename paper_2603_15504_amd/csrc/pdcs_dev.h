@@ -165,10 +165,33 @@ struct Ranges {
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
+// One DPP lane move of a double (both 32-bit halves with the same control):
+// lanes whose source is outside the pattern, or whose row is masked off,
+// receive +0.0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes, returned to every lane: data-parallel-primitive lane
+// moves inside the VALU instead of LDS-crossbar shuffles.  Pairs and quads
+// (quad permutes), then rows of 16 (row shifts by 4 and 8: lane 15 of a row
+// holds its row's sum), then rows 1 and 3 take lane 15 of the row before and
+// rows 2 and 3 take lane 31, so lane 63 holds the total, which is read back
+// as a uniform value.  Fixed order: deterministic.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_move<0x114>(v);       // row_shr:4
+  v += dpp_move<0x118>(v);       // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 __device__ __forceinline__ double wave_max(double v) {

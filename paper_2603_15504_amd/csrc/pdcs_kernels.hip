@@ -1562,11 +1562,13 @@ __global__ void k_decide(Inst* __restrict__ inst, int nb) {
   I.switch_fp64 = 0;
   if (!optimal && I.precision == kFP32) {
     // Two signs that FP32 storage limits the attainable error.  Near the
-    // tolerance (within 100x of rel_tol): stall_checks checks without halving
-    // the best error.  At any level: 8 x stall_checks checks without any new
-    // record low -- a steady (even slow) descent keeps setting records, while
-    // an error that fluctuates at a rounding floor sets them ever more rarely.
-    if (!(rmax >= 0.5 * I.best_rel) || rmax > 100.0 * I.rel_tol) {
+    // tolerance (within 100x of rel_tol): stall_checks checks without a 10%
+    // improvement of the best error (a slow linear descent still improves by
+    // that much within the window; an error at a rounding floor does not).  At
+    // any level: 8 x stall_checks checks without any new record low -- a
+    // steady (even slow) descent keeps setting records, while an error that
+    // fluctuates at a rounding floor sets them ever more rarely.
+    if (!(rmax >= 0.9 * I.best_rel) || rmax > 100.0 * I.rel_tol) {
       I.best_rel = rmax;
       I.stall = 0;
     } else {
