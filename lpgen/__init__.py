@@ -56,7 +56,9 @@ class LPInstance:
     name: str = "lp"
     x_planted: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
-    soc: tuple = ()  # dimensions of second-order-cone row blocks (the last rows)
+    soc: tuple = ()  # dimensions of second-order-cone row blocks (after the nonnegative rows)
+    n_exp: int = 0   # exponential-cone blocks of 3 rows (after the second-order-cone blocks)
+    n_dexp: int = 0  # dual-exponential-cone blocks of 3 rows (the last rows)
 
     @property
     def nnz(self) -> int:
@@ -315,6 +317,41 @@ def soc_instance(seed: int = 0, m_zero: int = 60, n: int = 300, blocks=(3, 5, 8,
     c = rng.uniform(0.0, 1.0, size=n)
     return LPInstance(m, n, m_zero, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, upper),
                       name=f"soc_{seed}", x_planted=x0, soc=blocks)
+
+def exp_instance(seed: int = 0, m_zero: int = 40, n: int = 200, m_nonneg: int = 20, n_exp: int = 12,
+                 n_dexp: int = 8, per_col: int = 3, upper: float = 10.0) -> LPInstance:
+    """Conic variant of the C0 recipe with exponential-cone rows (the expG and
+    dual_expG options): ``m_zero`` equality rows, ``m_nonneg`` >= rows, then
+    ``n_exp`` blocks (G x - h)_block = (x, y, z) in K_exp (y exp(x / y) <= z) and
+    ``n_dexp`` blocks in K_exp* (-u exp(v / u) <= e w).  Each column gets
+    ``per_col`` distinct uniform rows, values N(0,1); x0 ~ U[0,5] is planted
+    strictly feasible: h = G x0 on the equality rows, h = G x0 - s on the others
+    with s interior to the row's cone (>= rows: s ~ U[0.5, 1.5]; K_exp:
+    s = (a, b, (1.5 + U) b e^(a / b)), a ~ U[-2, 1], b ~ U[0.5, 2]; K_exp*:
+    s = (-a, b, (1.5 + U) a e^(-b / a) / e), a ~ U[0.5, 2], b ~ U[-1, 2]);
+    c ~ U[0,1]; 0 <= x <= upper."""
+    rng = rng_for(93, seed)
+    m = m_zero + m_nonneg + 3 * (n_exp + n_dexp)
+    row, col = _distinct_rows_per_column(rng, m, n, per_col)
+    val = rng.standard_normal(row.size)
+    row_ptr, col_idx, val = csr_from_columns(m, n, row, col, val)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    h = _csr_matvec(row_ptr, col_idx, val, x0)
+    r = m_zero
+    h[r:r + m_nonneg] -= rng.uniform(0.5, 1.5, size=m_nonneg)
+    r += m_nonneg
+    for _ in range(n_exp):
+        a, b = rng.uniform(-2.0, 1.0), rng.uniform(0.5, 2.0)
+        h[r:r + 3] -= np.array([a, b, (1.5 + rng.uniform()) * b * np.exp(a / b)])
+        r += 3
+    for _ in range(n_dexp):
+        a, b = rng.uniform(0.5, 2.0), rng.uniform(-1.0, 2.0)
+        h[r:r + 3] -= np.array([-a, b, (1.5 + rng.uniform()) * a * np.exp(-b / a) / np.e])
+        r += 3
+    c = rng.uniform(0.0, 1.0, size=n)
+    return LPInstance(m, n, m_zero, row_ptr, col_idx, val, h, c, np.zeros(n), np.full(n, upper),
+                      name=f"exp_{seed}", x_planted=x0, n_exp=n_exp, n_dexp=n_dexp)
+
 
 # ---------------------------------------------------------------------------
 # Infeasible and unbounded variants of the C0 recipe (tests of exit codes 2-5).

@@ -12,11 +12,13 @@ PDCS", arXiv 2603.15504):
 * the conic problem of Section 1.1 (eq. prob_cp) with every variable
   box-bounded (n2 = 0) and row cones in the paper's order: zero-cone
   (equality) rows, nonnegative-cone (>=) rows, then second-order-cone blocks
-  (the socG option of Section 3), so K_d* = {0}^m_zero x R+^m_nonneg x K_soc x
-  ... and K_d = R^m_zero x R+^m_nonneg x K_soc x ... (the second-order cone is
-  self-dual); after diagonal rescaling the blocks become rescaled cones
-  (Section 2.6), projected onto by a one-dimensional root find
-  (``proj_scaled_soc``);
+  (the socG option of Section 3), exponential-cone and dual-exponential-cone
+  blocks (expG, dual_expG), so K_d* = {0}^m_zero x R+^m_nonneg x K_soc x ... x
+  K_exp x ... x K_exp* x ... and K_d = R^m_zero x R+^m_nonneg x K_soc x ... x
+  K_exp* x ... x K_exp x ... (the second-order cone is self-dual); after
+  diagonal rescaling the blocks become rescaled cones (Section 2.6),
+  projected onto by one-dimensional root finds (``proj_scaled_soc``,
+  ``proj_scaled_exp``);
 * Algorithm "PDCS with preconditioning" (Section 2.6): diagonal rescaling, the
   PDCS loop of Algorithm 1 (Section 2) on the rescaled data, then unscaling;
 * inside it: OnePDHG (eq. PDHG, Section 1.2), AdaptiveStepPDHG (Function 2,
@@ -89,6 +91,8 @@ class LPData:
     m_zero: int
     soc: tuple = ()
     cone_scale: np.ndarray | None = None
+    n_exp: int = 0    # exponential-cone blocks (3 rows each) after the second-order-cone blocks
+    n_dexp: int = 0   # dual-exponential-cone blocks (3 rows each), the last rows
 
     @property
     def m(self) -> int:
@@ -99,25 +103,32 @@ class LPData:
         return self.G.shape[1]
 
     def proj_Kd(self, y):
-        return proj_Kd(y, self.m_zero, self.soc, self.cone_scale)
+        return proj_Kd(y, self.m_zero, self.soc, self.cone_scale, self.n_exp, self.n_dexp)
 
     def proj_Kd_star(self, v):
-        return proj_Kd_star(v, self.m_zero, self.soc, self.cone_scale)
+        return proj_Kd_star(v, self.m_zero, self.soc, self.cone_scale, self.n_exp, self.n_dexp)
+
+    @property
+    def has_cones(self) -> bool:
+        return bool(self.soc) or self.n_exp > 0 or self.n_dexp > 0
 
 
-def lpdata_from_arrays(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u, soc=()) -> LPData:
+def lpdata_from_arrays(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u, soc=(), n_exp=0, n_dexp=0) -> LPData:
     G = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col_idx), np.asarray(row_ptr)),
                       shape=(int(m), int(n)))
     soc = tuple(int(d) for d in soc)
-    if any(d < 1 for d in soc) or int(m_zero) + sum(soc) > int(m):
-        raise ValueError("second-order-cone blocks must have dimension >= 1 and fit after the zero rows")
+    n_exp, n_dexp = int(n_exp), int(n_dexp)
+    if (any(d < 1 for d in soc) or n_exp < 0 or n_dexp < 0 or
+            int(m_zero) + sum(soc) + 3 * (n_exp + n_dexp) > int(m)):
+        raise ValueError("cone blocks (second-order: dimension >= 1; exponential: 3 rows) must fit after the zero rows")
     return LPData(G, np.asarray(h, np.float64), np.asarray(c, np.float64),
-                  np.asarray(l, np.float64), np.asarray(u, np.float64), int(m_zero), soc)
+                  np.asarray(l, np.float64), np.asarray(u, np.float64), int(m_zero), soc, None, n_exp, n_dexp)
 
 
 def lpdata_from_instance(inst) -> LPData:
     return lpdata_from_arrays(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx,
-                              inst.val, inst.h, inst.c, inst.l, inst.u, getattr(inst, "soc", ()))
+                              inst.val, inst.h, inst.c, inst.l, inst.u, getattr(inst, "soc", ()),
+                              getattr(inst, "n_exp", 0), getattr(inst, "n_dexp", 0))
 
 
 # --------------------------------------------------------------------------
@@ -188,38 +199,143 @@ def proj_scaled_soc(v, e):
     return np.concatenate([[e0 * s], vb * e2 * s / (e2 * s + mu)])
 
 
-def _soc_blocks(m, soc):
-    """(start, end) row ranges of the second-order-cone blocks (the last rows)."""
-    r = m - sum(soc)
+# Exponential cones (the expG and dual_expG options of Section 3), in the
+# convention (x, y, z): K_exp = closure of {y > 0, y exp(x / y) <= z}, and its
+# dual K_exp* = closure of {(u, v, w): u < 0, -u exp(v / u) <= e w}.
+def in_exp_cone(q) -> bool:
+    """Membership in K_exp (exact comparisons; the boundary y = 0 is the face
+    {x <= 0, z >= 0})."""
+    x, y, z = (float(t) for t in q)
+    if y > 0.0:
+        return z > 0.0 and x <= y * np.log(z / y)
+    return y == 0.0 and x <= 0.0 and z >= 0.0
+
+
+def in_exp_dual(q) -> bool:
+    """Membership in K_exp* (the boundary u = 0 is the face {v >= 0, w >= 0})."""
+    u, v, w = (float(t) for t in q)
+    if u < 0.0:
+        return w > 0.0 and np.log(-u) + v / u <= 1.0 + np.log(w)
+    return u == 0.0 and v >= 0.0 and w >= 0.0
+
+
+def proj_scaled_exp(v, f):
+    """Projection onto the rescaled cone F K_exp = {F q : q in K_exp}, F = diag(f) > 0
+    (Section 2.6: after rescaling, a one-dimensional root find).
+
+    v itself if v / f lies in K_exp; 0 if v lies in the polar cone -F^{-1} K_exp*
+    (-f v in K_exp*).  Otherwise the projection lies on the boundary of F K_exp,
+    which is the face {(a, 0, b): a <= 0, b >= 0} (nearest point: clip) together
+    with the rays s F a(r), a(r) = (r, 1, e^r), s >= 0.  On the ray of r the best
+    s is <F a, v> / ||F a||^2, leaving the angle function
+    theta(r) = <F a(r), v> / ||F a(r)||, whose derivative has the sign of
+        h(r) = A be - B al r + C e^r (al r^2 - al r + be) + ga e^2r (A (1 - r) - B)
+    (A, B, C = f * v; al, be, ga = f^2).  Every local maximum of theta on
+    [-300, 300] is bracketed by a + to - sign change of h on a 0.05 grid and
+    bisected to the resolution of a float64; beyond that range the rays are
+    within e^-300 of the face's edges.  The nearest of all candidates wins.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    if in_exp_cone(v / f):
+        return v.copy()
+    if in_exp_dual(-f * v):
+        return np.zeros(3)
+    best = np.array([min(v[0], 0.0), 0.0, max(v[2], 0.0)])
+    bestd = float(np.linalg.norm(v - best))
+    A, B, C = f * v
+    al, be, ga = f * f
+
+    def h(r):
+        E = np.exp(r)
+        return A * be - B * al * r + C * E * (al * r * r - al * r + be) + ga * E * E * (A * (1.0 - r) - B)
+
+    grid = np.linspace(-300.0, 300.0, 12001)
+    hs = h(grid)
+    for i in np.nonzero((hs[:-1] > 0.0) & (hs[1:] <= 0.0))[0]:
+        lo, hi = float(grid[i]), float(grid[i + 1])
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if mid <= lo or mid >= hi:
+                break
+            if h(mid) > 0.0:
+                lo = mid
+            else:
+                hi = mid
+        r = 0.5 * (lo + hi)
+        a = f * np.array([r, 1.0, np.exp(r)])
+        s = float(a @ v) / float(a @ a)
+        if s > 0.0:
+            p = s * a
+            d = float(np.linalg.norm(v - p))
+            if d < bestd:
+                best, bestd = p, d
+    return best
+
+
+def proj_scaled_exp_dual(v, f):
+    """Projection onto F K_exp* (F = diag(f) > 0) by Moreau's decomposition:
+    F K_exp* is the dual cone of C = F^{-1} K_exp, so P(v) = v + P_C(-v)."""
+    v = np.asarray(v, dtype=np.float64)
+    return v + proj_scaled_exp(-v, 1.0 / np.asarray(f, dtype=np.float64))
+
+
+def _cone_blocks(m, soc, n_exp=0, n_dexp=0):
+    """(kind, start, end) row ranges of the cone blocks, the last rows in the
+    order second-order ("soc"), exponential ("exp"), dual exponential ("dexp")."""
+    r = m - sum(soc) - 3 * (n_exp + n_dexp)
     out = []
     for d in soc:
-        out.append((r, r + d))
+        out.append(("soc", r, r + d))
         r += d
+    for kind, cnt in (("exp", n_exp), ("dexp", n_dexp)):
+        for _ in range(cnt):
+            out.append((kind, r, r + 3))
+            r += 3
     return out
 
 
-def proj_Kd(y, m_zero, soc=(), scale=None):
-    """Projection onto K_d = R^m_zero x R+^m_nonneg x K_soc x ... (dual variables of
-    the rows); with row factors ``scale`` the blocks are diag(1/scale) K_soc."""
+def _soc_blocks(m, soc):
+    """(start, end) row ranges of the second-order-cone blocks when they are the last rows."""
+    return [(a, b) for _, a, b in _cone_blocks(m, soc)]
+
+
+def proj_Kd(y, m_zero, soc=(), scale=None, n_exp=0, n_dexp=0):
+    """Projection onto K_d = R^m_zero x R+^m_nonneg x K_soc x ... x K_exp* x ... x
+    K_exp x ... (dual variables of the rows: the dual of each row block's cone);
+    with row factors ``scale`` the blocks are diag(1/scale) of those cones."""
     out = np.array(y, dtype=np.float64, copy=True)
     m = out.size
-    m_cone = m - sum(soc)
+    m_cone = m - sum(soc) - 3 * (n_exp + n_dexp)
     out[m_zero:m_cone] = np.maximum(out[m_zero:m_cone], 0.0)
-    for a, b in _soc_blocks(m, soc):
-        out[a:b] = proj_soc(out[a:b]) if scale is None else proj_scaled_soc(out[a:b], 1.0 / scale[a:b])
+    for kind, a, b in _cone_blocks(m, soc, n_exp, n_dexp):
+        e = np.ones(b - a) if scale is None else 1.0 / scale[a:b]
+        if kind == "soc":
+            out[a:b] = proj_soc(out[a:b]) if scale is None else proj_scaled_soc(out[a:b], e)
+        elif kind == "exp":
+            out[a:b] = proj_scaled_exp_dual(out[a:b], e)
+        else:
+            out[a:b] = proj_scaled_exp(out[a:b], e)
     return out
 
 
-def proj_Kd_star(v, m_zero, soc=(), scale=None):
-    """Projection onto K_d* = {0}^m_zero x R+^m_nonneg x K_soc x ...; with row factors
-    ``scale`` the blocks are diag(scale) K_soc."""
+def proj_Kd_star(v, m_zero, soc=(), scale=None, n_exp=0, n_dexp=0):
+    """Projection onto K_d* = {0}^m_zero x R+^m_nonneg x K_soc x ... x K_exp x ... x
+    K_exp* x ... (the cones of G x - h); with row factors ``scale`` the blocks are
+    diag(scale) of those cones."""
     out = np.array(v, dtype=np.float64, copy=True)
     m = out.size
-    m_cone = m - sum(soc)
+    m_cone = m - sum(soc) - 3 * (n_exp + n_dexp)
     out[:m_zero] = 0.0
     out[m_zero:m_cone] = np.maximum(out[m_zero:m_cone], 0.0)
-    for a, b in _soc_blocks(m, soc):
-        out[a:b] = proj_soc(out[a:b]) if scale is None else proj_scaled_soc(out[a:b], scale[a:b])
+    for kind, a, b in _cone_blocks(m, soc, n_exp, n_dexp):
+        e = np.ones(b - a) if scale is None else scale[a:b]
+        if kind == "soc":
+            out[a:b] = proj_soc(out[a:b]) if scale is None else proj_scaled_soc(out[a:b], e)
+        elif kind == "exp":
+            out[a:b] = proj_scaled_exp(out[a:b], e)
+        else:
+            out[a:b] = proj_scaled_exp_dual(out[a:b], e)
     return out
 
 
@@ -287,7 +403,7 @@ def rescale(lp: LPData, D1, D2) -> LPData:
     Gs = (sp.diags(D1) @ lp.G @ sp.diags(D2)).tocsr()
     scale = D1 if lp.cone_scale is None else lp.cone_scale * D1
     return LPData(Gs, D1 * lp.h, D2 * lp.c, lp.l / D2, lp.u / D2, lp.m_zero, lp.soc,
-                  np.asarray(scale, np.float64) if lp.soc else None)
+                  np.asarray(scale, np.float64) if lp.has_cones else None, lp.n_exp, lp.n_dexp)
 
 
 # --------------------------------------------------------------------------
