@@ -633,18 +633,29 @@ __global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ g
   if (wave == 0 && c < cols) part[(size_t)blockIdx.y * cols + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// Adam step on FP32 parameters (the biases; weights are updated inside their gradient products).
-__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+// Adam step on FP32 parameters outside the weight matrices (whose updates run
+// inside their gradient products): three segments [o, o + n) in one launch,
+// the three bias vectors.
+__global__ void k_adam3(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                        float* __restrict__ v, int64_t o0, int64_t n0, int64_t o1, int64_t n1, int64_t o2,
+                        int64_t n2, float lr, float b1, float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t j;
+  if (i < n0) {
+    j = o0 + i;
+  } else if ((i -= n0) < n1) {
+    j = o1 + i;
+  } else if ((i -= n1) < n2) {
+    j = o2 + i;
+  } else {
+    return;
+  }
+  const float gi = g[j];
+  const float mi = b1 * m[j] + (1.0f - b1) * gi;
+  const float vi = b2 * v[j] + (1.0f - b2) * gi * gi;
+  m[j] = mi;
+  v[j] = vi;
+  p[j] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 inline dim3 lin(int64_t n, int t = 256) { return dim3((unsigned)((n + t - 1) / t)); }
@@ -714,7 +725,7 @@ struct pdcs_mlp_s {
     if (kind == EPI_ADAM) e.vec4 = adam_vec4(e, N);
     int splits = 1;
     if (kind == EPI_STORE || kind == EPI_ACT)
-      while (tiles * splits < 512 && K / (splits * 2) >= 256) splits *= 2;
+      while (tiles * splits < 512 && K / (splits * 2) >= 512) splits *= 2;
     int kchunk = (K + splits - 1) / splits;
     const int kt = kchunk >= 512 ? 128 : (kchunk >= 128 ? 64 : 32);
     kchunk = (kchunk + kt - 1) / kt * kt;
@@ -882,12 +893,11 @@ struct pdcs_mlp_s {
     // layer 1: dW1 = dZ1^T U
     gemm(adam ? EPI_ADAM : EPI_STORE, dz16b.as<bf16>(), w, 1, u16.as<bf16>(), din, 0, w, din, B,
          wgrad(adam, off_w1, W1(), lr), s);
-    if (adam) {  // the biases: FP32 only, one small pass each
+    if (adam) {  // the biases: FP32 only, one small pass
       const Epi e = wgrad(true, off_b1, nullptr, lr);
-      const int64_t offs[3] = {off_b1, off_b2, off_b3}, cnt[3] = {w, w, dout};
-      for (int q = 0; q < 3; ++q)
-        k_adam<<<lin(cnt[q]), 256, 0, s>>>(P(offs[q]), G(offs[q]), Mo(offs[q]), Vo(offs[q]), cnt[q], lr, e.b1, e.b2,
-                                           e.eps, e.c1, e.c2);
+      k_adam3<<<lin(2 * w + dout), 256, 0, s>>>(params.as<float>(), grads.as<float>(), adam_m.as<float>(),
+                                                 adam_v.as<float>(), off_b1, w, off_b2, w, off_b3, dout, lr, e.b1,
+                                                 e.b2, e.eps, e.c1, e.c2);
     }
   }
 };
