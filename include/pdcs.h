@@ -5,12 +5,15 @@
  *
  *     min  c^T x   s.t.  (G x - h)_i  = 0   for i <  m_zero      (zero cone)
  *                        (G x - h)_i >= 0   for the next rows     (nonnegative cone)
- *                        (G x - h)_B in K_soc for each second-order-cone block B
- *                                           of the last rows (pdcs_problem_create_conic)
+ *                        (G x - h)_B in K_soc for each second-order-cone block B,
+ *                                   then in K_exp and in K_exp* for the exponential
+ *                                   and dual-exponential blocks of 3 rows, the last
+ *                                   rows (pdcs_problem_create_conic / _cones)
  *                        l <= x <= u                            (box, +-inf allowed)
  *
  * with its dual (eq. dual_conic): max h^T y + l^T lam+ - u^T lam-, lam = c - G^T y,
- * y in K_d = R^m_zero x R+^... x K_soc x ... (the second-order cone is self-dual).
+ * y in K_d = R^m_zero x R+^... x K_soc x ... x K_exp* x ... x K_exp x ... (the dual
+ * cone of each row block; the second-order cone is self-dual).
  * The method is "PDCS with preconditioning" (Section 2.6): diagonal rescaling,
  * then the restarted, line-searched, reflected-Halpern PDHG loop of Algorithm 1
  * (Function 2 for the step size, Section 2.2 for the reflection parameter,
@@ -216,6 +219,31 @@ int  pdcs_problem_create_conic(int64_t m, int64_t n, int64_t m_zero, int64_t n_s
                                const int32_t* col_idx, const double* val,
                                const double* h, const double* c, const double* l,
                                const double* u, pdcs_problem* out);
+/* pdcs_problem_create_cones: as pdcs_problem_create_conic, with exponential-
+ * and dual-exponential-cone row blocks (the expG and dual_expG options of
+ * Section 3) after the second-order-cone blocks: n_exp blocks of 3 rows with
+ * (G x - h)_block = (x, y, z) in K_exp = closure {y > 0, y e^(x / y) <= z},
+ * then n_dexp blocks of 3 rows in the dual cone K_exp* = closure
+ * {(u, v, w): u < 0, -u e^(v / u) <= e w}, the last rows of the problem
+ * (Section 1.1, eq. prob_cp).  The dual rows y_block lie in the dual cone of
+ * each block (K_exp* for an exponential block, K_exp for a dual one); after
+ * the diagonal rescaling a block's cones are diag(D1) K and diag(1/D1) K*,
+ * projected onto by a one-dimensional root find (Section 2.6).  Needs
+ * m_zero + sum(soc_dims) + 3 (n_exp + n_dexp) <= m; n_soc = 0 with soc_dims
+ * null is allowed.  Errors: as pdcs_problem_create_conic. */
+int  pdcs_problem_create_cones(int64_t m, int64_t n, int64_t m_zero, int64_t n_soc,
+                               const int64_t* soc_dims, int64_t n_exp, int64_t n_dexp,
+                               const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                               const double* h, const double* c, const double* l,
+                               const double* u, pdcs_problem* out);
+/* pdcs_project_exp: the solver's projection onto a rescaled exponential cone
+ * (Section 2.6), for count 3-vectors: out_q = Proj onto diag(f_q) K_exp of
+ * v_q (dual = 0) or onto diag(f_q) K_exp* (dual = 1).  v, f and out are host
+ * arrays of 3 count doubles (vector q at [3q, 3q + 3)), f > 0 and v finite;
+ * the call copies them to the device, runs one wavefront per vector on the
+ * current device and copies the result back (synchronous).  count <= 2^26.
+ * Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_SIZE, PDCS_ERR_OOM, PDCS_ERR_HIP. */
+int  pdcs_project_exp(int64_t dual, int64_t count, const double* v, const double* f, double* out);
 void pdcs_problem_destroy(pdcs_problem p);
 int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
 

@@ -78,6 +78,9 @@ PROTOTYPES = {
     "pdcs_device_count": (C.c_int, []),
     "pdcs_problem_create": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
     "pdcs_problem_create_conic": (C.c_int, [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+    "pdcs_problem_create_cones": (C.c_int, [_I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P,
+                                            C.POINTER(_P)]),
+    "pdcs_project_exp": (C.c_int, [_I64, _I64, _P, _P, _P]),
     "pdcs_problem_destroy": (None, [_P]),
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
@@ -229,6 +232,34 @@ def pdcs_problem_create_conic(m, n, m_zero, soc_dims, row_ptr, col_idx, val, h, 
                                          _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(h), _ptr(c), _ptr(l),
                                          _ptr(u), C.byref(out)),
            "pdcs_problem_create_conic")
+    return out
+
+
+def pdcs_problem_create_cones(m, n, m_zero, soc_dims, n_exp, n_dexp, row_ptr, col_idx, val, h, c, l=None,
+                              u=None) -> C.c_void_p:
+    soc = np.ascontiguousarray(np.asarray(soc_dims, dtype=np.int64).reshape(-1))
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    val = _f64(val)
+    h = _f64(h, m) if m > 0 else np.zeros(1)
+    c = _f64(c, n)
+    l = _f64(l, n)
+    u = _f64(u, n)
+    out = C.c_void_p()
+    _check(lib.pdcs_problem_create_cones(int(m), int(n), int(m_zero), int(soc.size), _ptr(soc) if soc.size else None,
+                                         int(n_exp), int(n_dexp), _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(h),
+                                         _ptr(c), _ptr(l), _ptr(u), C.byref(out)),
+           "pdcs_problem_create_cones")
+    return out
+
+
+def pdcs_project_exp(dual, v, f) -> np.ndarray:
+    """Projections of the rows of v (count x 3) onto diag(f_q) K_exp (dual=0) or
+    diag(f_q) K_exp* (dual=1), on the current GPU."""
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 3))
+    f = np.ascontiguousarray(np.broadcast_to(np.asarray(f, dtype=np.float64), v.shape))
+    out = np.empty_like(v)
+    _check(lib.pdcs_project_exp(int(dual), int(v.shape[0]), _ptr(v), _ptr(f), _ptr(out)), "pdcs_project_exp")
     return out
 
 
@@ -483,10 +514,14 @@ def _info_dict(info: pdcs_info) -> dict:
 class Problem:
     """An LP uploaded to the GPU (pdcs_problem)."""
 
-    def __init__(self, m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=None, soc=()):
-        """soc: dimensions of second-order-cone row blocks (the last rows)."""
+    def __init__(self, m, n, m_zero, row_ptr, col_idx, val, h, c, l=None, u=None, soc=(), n_exp=0, n_dexp=0):
+        """soc: dimensions of second-order-cone row blocks, then n_exp exponential
+        and n_dexp dual-exponential blocks of 3 rows (the last rows)."""
         self.m, self.n = int(m), int(n)
-        if len(soc):
+        if n_exp or n_dexp:
+            self.handle = pdcs_problem_create_cones(m, n, m_zero, soc, n_exp, n_dexp, row_ptr, col_idx, val, h, c,
+                                                    l, u)
+        elif len(soc):
             self.handle = pdcs_problem_create_conic(m, n, m_zero, soc, row_ptr, col_idx, val, h, c, l, u)
         else:
             self.handle = pdcs_problem_create(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u)
@@ -494,7 +529,7 @@ class Problem:
     @classmethod
     def from_instance(cls, inst):
         return cls(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx, inst.val, inst.h, inst.c,
-                   inst.l, inst.u, getattr(inst, "soc", ()))
+                   inst.l, inst.u, getattr(inst, "soc", ()), getattr(inst, "n_exp", 0), getattr(inst, "n_dexp", 0))
 
     def solve(self, x0=None, y0=None, with_scaling=False, device_out=False, **opts) -> Solution:
         """Host warm start (arrays) or, for torch tensors on the GPU, the device

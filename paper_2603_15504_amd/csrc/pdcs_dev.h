@@ -147,9 +147,10 @@ struct BandTiles {
 };
 
 // Schedule of an elementwise pass: contiguous element ranges per workgroup.
-// Row ranges never split a second-order-cone block: the blocks inside range b
-// are [blk_soc0[b], blk_soc1[b]) of the table (soc_r0: first row, soc_dim:
-// dimension); all four are null when no instance has such blocks.
+// Row ranges never split a cone block: the blocks inside range b are
+// [blk_soc0[b], blk_soc1[b]) of the table (soc_r0: first row, soc_dim:
+// dimension, soc_kind: 0 second-order cone, 1 exponential cone, 2 dual
+// exponential cone); all five are null when no instance has cone blocks.
 struct Ranges {
   const int32_t* blk_start;
   const int32_t* blk_end;
@@ -159,6 +160,7 @@ struct Ranges {
   const int32_t* blk_soc1;
   const int32_t* soc_r0;
   const int32_t* soc_dim;
+  const int8_t* soc_kind;
   int32_t nblk;
 };
 

@@ -50,10 +50,12 @@ struct HostProblem {
   int64_t m = 0, n = 0, m_zero = 0, nnz = 0;
   std::vector<int32_t> rp, ci, cp, ri;
   std::vector<double> v, vt, h, c, l, u;
-  std::vector<int32_t> soc;  // second-order-cone block dimensions (the last rows)
+  std::vector<int32_t> soc;  // second-order-cone block dimensions (after the nonnegative rows)
+  int64_t n_exp = 0, n_dexp = 0;  // exponential / dual-exponential blocks of 3 rows (the last rows)
+  int64_t cone_rows() const;
   void build(int64_t m, int64_t n, int64_t mz, const int64_t* row_ptr, const int32_t* col_idx,
              const double* val, const double* h, const double* c, const double* l, const double* u,
-             int64_t n_soc = 0, const int64_t* soc_dims = nullptr);
+             int64_t n_soc = 0, const int64_t* soc_dims = nullptr, int64_t n_exp = 0, int64_t n_dexp = 0);
 };
 
 // Tile schedule parameters (chosen by pdcs_batch_autotune or set explicitly).
@@ -84,11 +86,12 @@ struct RowBlockSet {
   RowBlocks view() const;
 };
 
-// Second-order-cone row blocks of all instances: first (absolute) row and
-// dimension of each block, in row order.
+// Cone row blocks of all instances: first (absolute) row, dimension and kind
+// (0 second-order, 1 exponential, 2 dual exponential) of each block, in row order.
 struct SocTable {
   std::vector<int32_t> r0, dim;
-  DBuf r0_d, dim_d;
+  std::vector<int8_t> kind;
+  DBuf r0_d, dim_d, kind_d;
   bool empty() const { return r0.empty(); }
 };
 

@@ -60,12 +60,20 @@ static void upload(DBuf& d, const std::vector<T>& h) {
 // ---------------------------------------------------------------------------
 // Problem validation and transposition
 // ---------------------------------------------------------------------------
+int64_t HostProblem::cone_rows() const {
+  int64_t rows = 3 * (n_exp + n_dexp);
+  for (int32_t d : soc) rows += d;
+  return rows;
+}
+
 void HostProblem::build(int64_t m_, int64_t n_, int64_t mz, const int64_t* row_ptr, const int32_t* col_idx,
                         const double* val, const double* h_, const double* c_, const double* l_,
-                        const double* u_, int64_t n_soc, const int64_t* soc_dims) {
+                        const double* u_, int64_t n_soc, const int64_t* soc_dims, int64_t n_exp_,
+                        int64_t n_dexp_) {
   if (m_ < 0 || n_ < 1) throw Error(PDCS_ERR_INVALID_ARG, "need m >= 0 and n >= 1");
   if (mz < 0 || mz > m_) throw Error(PDCS_ERR_INVALID_ARG, "m_zero must lie in [0, m]");
   if (n_soc < 0 || (n_soc > 0 && !soc_dims)) throw Error(PDCS_ERR_INVALID_ARG, "bad second-order-cone list");
+  if (n_exp_ < 0 || n_dexp_ < 0) throw Error(PDCS_ERR_INVALID_ARG, "negative number of exponential-cone blocks");
   soc.clear();
   int64_t soc_rows = 0;
   for (int64_t q = 0; q < n_soc; ++q) {
@@ -74,6 +82,10 @@ void HostProblem::build(int64_t m_, int64_t n_, int64_t mz, const int64_t* row_p
     if (soc_rows > m_ - mz) throw Error(PDCS_ERR_INVALID_ARG, "second-order-cone rows exceed the rows after m_zero");
     soc.push_back((int32_t)soc_dims[q]);
   }
+  if (n_exp_ > (m_ - mz - soc_rows) / 3 || n_dexp_ > (m_ - mz - soc_rows) / 3 - n_exp_)
+    throw Error(PDCS_ERR_INVALID_ARG, "cone rows exceed the rows after m_zero");
+  n_exp = n_exp_;
+  n_dexp = n_dexp_;
   if (m_ >= INT32_MAX || n_ >= INT32_MAX) throw Error(PDCS_ERR_SIZE, "m and n must be < 2^31 - 1");
   if (!row_ptr) throw Error(PDCS_ERR_INVALID_ARG, "row_ptr is null");
   if (!c_) throw Error(PDCS_ERR_INVALID_ARG, "c is null");
@@ -366,6 +378,7 @@ Ranges RangeSet::view() const {
   r.blk_soc1 = cones ? soc1_d.as<int32_t>() : nullptr;
   r.soc_r0 = cones ? soc->r0_d.as<int32_t>() : nullptr;
   r.soc_dim = cones ? soc->dim_d.as<int32_t>() : nullptr;
+  r.soc_kind = cones ? soc->kind_d.as<int8_t>() : nullptr;
   r.nblk = nblk;
   return r;
 }
@@ -784,21 +797,26 @@ Engine::Engine(const std::vector<const HostProblem*>& probs) {
     upload(d_col0i, c0i);
   }
   for (int64_t j = 0; j < N && !any_unbounded; ++j) any_unbounded = !std::isfinite(l[j]) || !std::isfinite(u[j]);
-  // second-order-cone blocks: the last rows of each instance, in row order
+  // cone blocks: the last rows of each instance, in row order (second-order,
+  // then exponential, then dual exponential)
   for (int b = 0; b < B; ++b) {
-    int64_t rows = 0;
-    for (int32_t d : probs[b]->soc) rows += d;
-    int64_t r = row0[b + 1] - rows;
+    const HostProblem& P = *probs[b];
+    int64_t r = row0[b + 1] - P.cone_rows();
     socstart.push_back(r);
-    for (int32_t d : probs[b]->soc) {
+    auto add = [&](int32_t d, int8_t kind) {
       soc.r0.push_back((int32_t)r);
       soc.dim.push_back(d);
+      soc.kind.push_back(kind);
       r += d;
-    }
+    };
+    for (int32_t d : P.soc) add(d, 0);
+    for (int64_t q = 0; q < P.n_exp; ++q) add(3, 1);
+    for (int64_t q = 0; q < P.n_dexp; ++q) add(3, 2);
   }
   if (!soc.empty()) {
     upload(soc.r0_d, soc.r0);
     upload(soc.dim_d, soc.dim);
+    upload(soc.kind_d, soc.kind);
   }
   vrow.soc = &soc;
   crow.soc = &soc;
@@ -1552,6 +1570,48 @@ int pdcs_problem_create_conic(int64_t m, int64_t n, int64_t m_zero, int64_t n_so
     p->eng = std::make_unique<Engine>(v);
     p->eng->prepare_plain();
     *out = p.release();
+    return PDCS_OK;
+  });
+}
+
+int pdcs_problem_create_cones(int64_t m, int64_t n, int64_t m_zero, int64_t n_soc, const int64_t* soc_dims,
+                              int64_t n_exp, int64_t n_dexp, const int64_t* row_ptr, const int32_t* col_idx,
+                              const double* val, const double* h, const double* c, const double* l, const double* u,
+                              pdcs_problem* out) {
+  return guarded([&]() {
+    if (!out) throw Error(PDCS_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    auto p = std::make_unique<pdcs_problem_s>();
+    p->hp.build(m, n, m_zero, row_ptr, col_idx, val, h, c, l, u, n_soc, soc_dims, n_exp, n_dexp);
+    std::vector<const HostProblem*> v{&p->hp};
+    p->eng = std::make_unique<Engine>(v);
+    p->eng->prepare_plain();
+    *out = p.release();
+    return PDCS_OK;
+  });
+}
+
+int pdcs_project_exp(int64_t dual, int64_t count, const double* v, const double* f, double* out) {
+  return guarded([&]() {
+    if (dual != 0 && dual != 1) throw Error(PDCS_ERR_INVALID_ARG, "dual must be 0 or 1");
+    if (count < 0) throw Error(PDCS_ERR_INVALID_ARG, "count must be >= 0");
+    if (count == 0) return PDCS_OK;
+    if (!v || !f || !out) throw Error(PDCS_ERR_INVALID_ARG, "null array");
+    if (count > ((int64_t)1 << 26)) throw Error(PDCS_ERR_SIZE, "count must be <= 2^26");
+    for (int64_t i = 0; i < 3 * count; ++i) {
+      if (!(f[i] > 0.0) || !std::isfinite(f[i])) throw Error(PDCS_ERR_INVALID_ARG, "factors must be finite and > 0");
+      if (!std::isfinite(v[i])) throw Error(PDCS_ERR_INVALID_ARG, "points must be finite");
+    }
+    const size_t bytes = (size_t)count * 3 * sizeof(double);
+    DBuf dv, df, dout;
+    dv.alloc(bytes);
+    df.alloc(bytes);
+    dout.alloc(bytes);
+    HIP_OK(hipMemcpy(dv.p, v, bytes, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(df.p, f, bytes, hipMemcpyHostToDevice));
+    launch_proj_exp(dv.as<double>(), df.as<double>(), dout.as<double>(), count, (int)dual, nullptr);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpy(out, dout.p, bytes, hipMemcpyDeviceToHost));
     return PDCS_OK;
   });
 }

@@ -97,14 +97,159 @@ __device__ __forceinline__ void wave_proj_soc(int d, const LD& ld, const EF& ef,
   }
 }
 
+// ===========================================================================
+// Exponential-cone row blocks (expG and dual_expG options of Section 3)
+// ===========================================================================
+// K_exp = closure {(x, y, z): y > 0, y e^(x / y) <= z}; its dual cone
+// K_exp* = closure {(u, v, w): u < 0, -u e^(v / u) <= e w}.
+__device__ __forceinline__ bool exp_cone_has(double x, double y, double z) {
+  if (y > 0.0) return z > 0.0 && x <= y * log(z / y);
+  return y == 0.0 && x <= 0.0 && z >= 0.0;
+}
+
+__device__ __forceinline__ bool exp_dual_has(double u, double v, double w) {
+  if (u < 0.0) return w > 0.0 && log(-u) + v / u <= 1.0 + log(w);
+  return u == 0.0 && v >= 0.0 && w >= 0.0;
+}
+
+// Sign of the slope of the angle between v and the boundary ray of F K_exp
+// through F a(r), a(r) = (r, 1, e^r): the triple product
+// det[v, F a(r), F^-1 n(r)], n(r) = (-1, r - 1, e^-r) the element of K_exp*
+// normal to the cone along the ray (F a(r) x F^-1 n(r) points along the
+// derivative of the unit ray), times e^r, divided by e^2r for r > 0 so that
+// it stays finite.
+__device__ __forceinline__ double exp_ray_turn(double r, const double (&v)[3], const double (&f)[3]) {
+  double a0, a1, a2, m0, m1, m2;  // a = F a(r), m = e^r F^-1 n(r), both scaled by e^-r when r > 0
+  if (r <= 0.0) {
+    const double E = exp(r);
+    a0 = f[0] * r, a1 = f[1], a2 = f[2] * E;
+    m0 = -E / f[0], m1 = E * (r - 1.0) / f[1], m2 = 1.0 / f[2];
+  } else {
+    const double iE = exp(-r);
+    a0 = f[0] * r * iE, a1 = f[1] * iE, a2 = f[2];
+    m0 = -1.0 / f[0], m1 = (r - 1.0) / f[1], m2 = iE / f[2];
+  }
+  return v[0] * (a1 * m2 - a2 * m1) + v[1] * (a2 * m0 - a0 * m2) + v[2] * (a0 * m1 - a1 * m0);
+}
+
+// Projection of v onto F K_exp, F = diag(f) > 0, by one wave (every lane gets
+// the result).  v itself if v / f is in K_exp; 0 if -F v is in K_exp* (the
+// polar cone); otherwise the nearest of the clip onto the face
+// {(x, 0, z): x <= 0, z >= 0} and the best points of the rays: the local
+// maxima of the angle along the rays are the + to - sign changes of
+// exp_ray_turn, located on a grid of step kExpStep over |r| <= 64 kExpSteps
+// kExpStep / 2 (each lane scans kExpSteps cells) and bisected to full
+// precision; on the ray through F a the nearest point is s F a with
+// s = <F a, v> / |F a|^2 when positive.  Beyond the grid the rays lie within
+// e^-300 of the face's edges.
+constexpr int kExpSteps = 188;
+constexpr double kExpStep = 0.05;
+
+__device__ __noinline__ void exp_proj_wave(const double (&v)[3], const double (&f)[3], double (&p)[3]) {
+  if (exp_cone_has(v[0] / f[0], v[1] / f[1], v[2] / f[2])) {
+    p[0] = v[0], p[1] = v[1], p[2] = v[2];
+    return;
+  }
+  if (exp_dual_has(-f[0] * v[0], -f[1] * v[1], -f[2] * v[2])) {
+    p[0] = p[1] = p[2] = 0.0;
+    return;
+  }
+  double b0 = fmin(v[0], 0.0), b1 = 0.0, b2 = fmax(v[2], 0.0);
+  double bd = (v[0] - b0) * (v[0] - b0) + v[1] * v[1] + (v[2] - b2) * (v[2] - b2);
+  const int lane = threadIdx.x & (kWave - 1);
+  const double r_first = -0.5 * kWave * kExpSteps * kExpStep;
+  int k = lane * kExpSteps;
+  double lo = r_first + k * kExpStep;
+  double t_lo = exp_ray_turn(lo, v, f);
+  for (int c = 0; c < kExpSteps; ++c) {
+    ++k;
+    const double hi = r_first + k * kExpStep;
+    const double t_hi = exp_ray_turn(hi, v, f);
+    if (t_lo > 0.0 && t_hi <= 0.0) {
+      double a = lo, z = hi;
+      for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (a + z);
+        if (mid <= a || mid >= z) break;
+        if (exp_ray_turn(mid, v, f) > 0.0) a = mid;
+        else z = mid;
+      }
+      const double r = 0.5 * (a + z);
+      const double q0 = f[0] * r, q1 = f[1], q2 = f[2] * exp(r);
+      const double s = (q0 * v[0] + q1 * v[1] + q2 * v[2]) / (q0 * q0 + q1 * q1 + q2 * q2);
+      if (s > 0.0) {
+        const double c0 = s * q0, c1 = s * q1, c2 = s * q2;
+        const double d = (v[0] - c0) * (v[0] - c0) + (v[1] - c1) * (v[1] - c1) + (v[2] - c2) * (v[2] - c2);
+        if (d < bd) bd = d, b0 = c0, b1 = c1, b2 = c2;
+      }
+    }
+    lo = hi;
+    t_lo = t_hi;
+  }
+  // nearest candidate over the wave (ties: the lowest lane, i.e. the smallest r)
+  int who = lane;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double od = __shfl_xor(bd, off);
+    const int ow = __shfl_xor(who, off);
+    const double o0 = __shfl_xor(b0, off), o1 = __shfl_xor(b1, off), o2 = __shfl_xor(b2, off);
+    if (od < bd || (od == bd && ow < who)) bd = od, who = ow, b0 = o0, b1 = o1, b2 = o2;
+  }
+  p[0] = b0, p[1] = b1, p[2] = b2;
+}
+
+// Projection of a 3-row block onto F K_exp (dual = false) or onto F K_exp*
+// (dual = true: F K_exp* is the dual cone of F^-1 K_exp, so by Moreau's
+// decomposition P(v) = v + P_{F^-1 K_exp}(-v)), by one wave; ld, ef and st as
+// in wave_proj_soc (element i stored by lane i).
+template <class LD, class EF, class ST>
+__device__ __forceinline__ void wave_proj_exp(bool dual, const LD& ld, const EF& ef, const ST& st) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double v[3] = {ld(0), ld(1), ld(2)};
+  double p[3];
+  if (!dual) {
+    const double f[3] = {ef(0), ef(1), ef(2)};
+    exp_proj_wave(v, f, p);
+  } else {
+    const double w[3] = {-v[0], -v[1], -v[2]};
+    const double g[3] = {1.0 / ef(0), 1.0 / ef(1), 1.0 / ef(2)};
+    double q[3];
+    exp_proj_wave(w, g, q);
+    p[0] = v[0] + q[0], p[1] = v[1] + q[1], p[2] = v[2] + q[2];
+  }
+  if (lane < 3) st(lane, lane == 0 ? p[0] : (lane == 1 ? p[1] : p[2]));
+}
+
+// Cone block kinds of the block table.
+constexpr int kConeSoc = 0, kConeExp = 1, kConeDualExp = 2;
+
+// Projection of one cone block of kind `kind` at a primal site (the cone of
+// G x - h: K_soc, K_exp or K_exp*) or a dual site (the cone of y, its dual:
+// K_soc, K_exp* or K_exp), rescaled by diag(ef).
+template <class LD, class EF, class ST>
+__device__ __forceinline__ void wave_proj_cone(int kind, bool dual_site, int d, const LD& ld, const EF& ef,
+                                               const ST& st) {
+  if (kind == kConeSoc) wave_proj_soc(d, ld, ef, st);
+  else wave_proj_exp((kind == kConeExp) == dual_site, ld, ef, st);
+}
+
 // The cone blocks of row range b are handled by the waves of its workgroup,
-// block q by wave (q - first) mod kWavesPerBlock; fn(first row, dimension).
+// block q by wave (q - first) mod kWavesPerBlock; fn(first row, dimension, kind).
 template <class FN>
 __device__ __forceinline__ void for_cone_blocks(const Ranges& R, int b, const FN& fn) {
   if (!R.blk_soc0) return;
   const int wave = threadIdx.x / kWave;
   const int q0 = R.blk_soc0[b], q1 = R.blk_soc1[b];
-  for (int q = q0 + wave; q < q1; q += kWavesPerBlock) fn(R.soc_r0[q], R.soc_dim[q]);
+  for (int q = q0 + wave; q < q1; q += kWavesPerBlock) fn(R.soc_r0[q], R.soc_dim[q], (int)R.soc_kind[q]);
+}
+
+// Projection of count 3-vectors (v, f and out: 3 doubles each, contiguous)
+// onto diag(f) K_exp (dual = 0) or diag(f) K_exp* (dual = 1), one wave each.
+__global__ __launch_bounds__(kBlock) void k_proj_exp(const double* __restrict__ v, const double* __restrict__ f,
+                                                     double* __restrict__ out, int64_t count, int dual) {
+  const int64_t q = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (q >= count) return;
+  wave_proj_exp(
+      dual != 0, [&](int i) { return v[3 * q + i]; }, [&](int i) { return f[3 * q + i]; },
+      [&](int i, double p) { out[3 * q + i] = p; });
 }
 
 // ===========================================================================
@@ -470,10 +615,10 @@ __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restri
   }
   if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
     __syncthreads();  // the blocks' unprojected values and committed iterates are in memory
-    for_cone_blocks(R, b, [&](int r0, int dim) {
-      // y_hat = Proj onto diag(1/D1) K_soc of the stored value, with the line-search terms
-      wave_proj_soc(
-          dim, [&](int i) { return (double)it.yh[r0 + i]; }, [&](int i) { return 1.0 / D1[r0 + i]; },
+    for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+      // y_hat = Proj onto diag(1/D1) of the block's dual cone of the stored value, with the line-search terms
+      wave_proj_cone(
+          kind, true, dim, [&](int i) { return (double)it.yh[r0 + i]; }, [&](int i) { return 1.0 / D1[r0 + i]; },
           [&](int i, double p) {
             const int r = r0 + i;
             const double yn = (double)(T)p;
@@ -483,9 +628,9 @@ __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restri
             acc[1] += dy * ((double)it.gxh[r] - (double)it.gx[r]);
             acc[3] += (double)d.h[r] * yn;
           });
-      // primal residual of the reflection parameter: (G x_hat - h) against diag(D1) K_soc
-      wave_proj_soc(
-          dim, [&](int i) { return (double)it.gxh[r0 + i] - (double)d.h[r0 + i]; },
+      // primal residual of the reflection parameter: (G x_hat - h) against diag(D1) of the block's cone
+      wave_proj_cone(
+          kind, false, dim, [&](int i) { return (double)it.gxh[r0 + i] - (double)d.h[r0 + i]; },
           [&](int i) { return D1[r0 + i]; },
           [&](int i, double p) {
             const double pr = ((double)it.gxh[r0 + i] - (double)d.h[r0 + i]) - p;
@@ -1105,9 +1250,9 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
     }
   }
   // cone blocks: the same terms, with the residual r = G x - h projected onto
-  // diag(D1) K_soc for the scaled L2 term and, unscaled (r / D1), onto K_soc for
-  // the infinity-norm termination terms
-  for_cone_blocks(R, b, [&](int r0, int dim) {
+  // diag(D1) of the block's cone for the scaled L2 term and, unscaled (r / D1),
+  // onto the cone itself for the infinity-norm termination terms
+  for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
     for (int q = 0; q < nc; ++q) {
       const T* yq = q == 0 ? y0 : y1;
       const double* gq = q == 0 ? g0 : g1;
@@ -1120,14 +1265,14 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
         acc[q * 4 + 3] += h * yc;
         acc[8 + q * 3 + 1] = fmax(acc[8 + q * 3 + 1], fabs(gx) / D1[r]);
       }
-      wave_proj_soc(
-          dim, [&](int i) { return gq[r0 + i] - d.h[r0 + i]; }, [&](int i) { return D1[r0 + i]; },
+      wave_proj_cone(
+          kind, false, dim, [&](int i) { return gq[r0 + i] - d.h[r0 + i]; }, [&](int i) { return D1[r0 + i]; },
           [&](int i, double p) {
             const double pr = (gq[r0 + i] - d.h[r0 + i]) - p;
             acc[q * 4 + 2] += pr * pr;
           });
-      wave_proj_soc(
-          dim, [&](int i) { return (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; }, [](int) { return 1.0; },
+      wave_proj_cone(
+          kind, false, dim, [&](int i) { return (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; }, [](int) { return 1.0; },
           [&](int i, double p) {
             const double ru = (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i];
             acc[8 + q * 3 + 0] = fmax(acc[8 + q * 3 + 0], fabs(ru - p));
@@ -1283,14 +1428,14 @@ __device__ __forceinline__ void probe_rows_body(int b, int q, const Ranges& R, c
       acc[p * 2 + 1] += b2 * dy;
     }
   }
-  // cone blocks: y(t) = Proj onto diag(1/D1) K_soc of y + t sigma b2, per probe
-  for_cone_blocks(R, b, [&](int r0, int dim) {
+  // cone blocks: y(t) = Proj onto diag(1/D1) (dual cone) of y + t sigma b2, per probe
+  for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
 #pragma unroll
     for (int p = 0; p < kProbes; ++p) {
       const double tp = tq[p];
       double dd = 0.0, bd = 0.0;
-      wave_proj_soc(
-          dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
+      wave_proj_cone(
+          kind, true, dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
           [&](int i) { return 1.0 / D1[r0 + i]; },
           [&](int i, double pv) {
             const double yc = (double)ys[r0 + i];
@@ -1770,11 +1915,11 @@ __global__ __launch_bounds__(kBlock) void k_ray_vec_rows(Ranges R, const T* __re
     const double v = (double)yh[i] - ys0[i];
     ry[i] = i < mz_end ? v : fmax(v, 0.0);
   }
-  // cone blocks: the unscaled ray D1 (y_hat - y_start) projected onto K_soc,
+  // cone blocks: the unscaled ray D1 (y_hat - y_start) projected onto the dual cone,
   // stored scaled back by 1 / D1 like the other rows
-  for_cone_blocks(R, b, [&](int r0, int dim) {
-    wave_proj_soc(
-        dim, [&](int i) { return D1[r0 + i] * ((double)yh[r0 + i] - ys0[r0 + i]); }, [](int) { return 1.0; },
+  for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+    wave_proj_cone(
+        kind, true, dim, [&](int i) { return D1[r0 + i] * ((double)yh[r0 + i] - ys0[r0 + i]); }, [](int) { return 1.0; },
         [&](int i, double p) { ry[r0 + i] = p / D1[r0 + i]; });
   });
 }
@@ -1850,11 +1995,11 @@ __global__ __launch_bounds__(kBlock) void k_ray_rows(Ranges R, const double* __r
       acc[2] += res * res;
     }
   }
-  // cone blocks: the unscaled G r_x against K_soc
+  // cone blocks: the unscaled G r_x against the block's cone
   if (rgx)
-    for_cone_blocks(R, b, [&](int r0, int dim) {
-      wave_proj_soc(
-          dim, [&](int i) { return rgx[r0 + i] / D1[r0 + i]; }, [](int) { return 1.0; },
+    for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+      wave_proj_cone(
+          kind, false, dim, [&](int i) { return rgx[r0 + i] / D1[r0 + i]; }, [](int) { return 1.0; },
           [&](int i, double p) {
             const double res = rgx[r0 + i] / D1[r0 + i] - p;
             acc[2] += res * res;
@@ -2287,10 +2432,10 @@ __global__ __launch_bounds__(kBlock) void k_start_rows(Ranges R, const double* _
     it.yh[i] = y;
     it.sy[i] = (T)0;
   }
-  // cone blocks: y0 / D1 projected onto diag(1/D1) K_soc
-  for_cone_blocks(R, b, [&](int r0, int dim) {
-    wave_proj_soc(
-        dim, [&](int i) { return y0 ? y0[r0 + i] / D1[r0 + i] : 0.0; }, [&](int i) { return 1.0 / D1[r0 + i]; },
+  // cone blocks: y0 / D1 projected onto diag(1/D1) (dual cone)
+  for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+    wave_proj_cone(
+        kind, true, dim, [&](int i) { return y0 ? y0[r0 + i] / D1[r0 + i] : 0.0; }, [&](int i) { return 1.0 / D1[r0 + i]; },
         [&](int i, double p) {
           const int r = r0 + i;
           const T y = (T)p;
@@ -2780,6 +2925,11 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
 
 void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n > 0) k_to_f32<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, s>>>(in, out, n);
+}
+
+void launch_proj_exp(const double* v, const double* f, double* out, int64_t count, int dual, hipStream_t s) {
+  if (count > 0)
+    k_proj_exp<<<(unsigned)((count + kWavesPerBlock - 1) / kWavesPerBlock), kBlock, 0, s>>>(v, f, out, count, dual);
 }
 
 void launch_pack_warm(const void* const* src, const int32_t* off, int B, int64_t maxlen, int dtype, double* out,
