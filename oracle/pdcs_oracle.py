@@ -232,8 +232,13 @@ def proj_scaled_exp(v, f):
         h(r) = A be - B al r + C e^r (al r^2 - al r + be) + ga e^2r (A (1 - r) - B)
     (A, B, C = f * v; al, be, ga = f^2).  Every local maximum of theta on
     [-300, 300] is bracketed by a + to - sign change of h on a 0.05 grid and
-    bisected to the resolution of a float64; beyond that range the rays are
-    within e^-300 of the face's edges.  The nearest of all candidates wins.
+    bisected to the resolution of a float64.  Above the grid the rays lie within
+    e^-300 of the face's edge (0, 0, 1).  Below it they approach the edge
+    (-1, 0, 0) only like 1 / |r|, but their third coordinate is below e^-300
+    of the others: there h(r) is A be - B al r up to that relative size, whose
+    root r = (v_1 / f_1) / (v_2 / f_2) (x / y of v / f, when v_1 < 0 < v_2) is
+    one more candidate if it lies below the grid.  The nearest of all
+    candidates wins.
     """
     v = np.asarray(v, dtype=np.float64)
     f = np.asarray(f, dtype=np.float64)
@@ -252,6 +257,7 @@ def proj_scaled_exp(v, f):
 
     grid = np.linspace(-300.0, 300.0, 12001)
     hs = h(grid)
+    roots = []
     for i in np.nonzero((hs[:-1] > 0.0) & (hs[1:] <= 0.0))[0]:
         lo, hi = float(grid[i]), float(grid[i + 1])
         for _ in range(200):
@@ -262,7 +268,10 @@ def proj_scaled_exp(v, f):
                 lo = mid
             else:
                 hi = mid
-        r = 0.5 * (lo + hi)
+        roots.append(0.5 * (lo + hi))
+    if v[0] < 0.0 < v[1] and (v[0] / f[0]) / (v[1] / f[1]) < grid[0]:
+        roots.append((v[0] / f[0]) / (v[1] / f[1]))
+    for r in roots:
         a = f * np.array([r, 1.0, np.exp(r)])
         s = float(a @ v) / float(a @ a)
         if s > 0.0:

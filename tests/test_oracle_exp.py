@@ -72,15 +72,33 @@ def test_memberships_by_hand():
 def test_projection_of_ray_plus_normal_is_the_ray_point(seed):
     # p = s F a(r) lies on the boundary of F K_exp and w = -t F^-1 n(r) in its
     # polar (-F w = t n(r) in K_exp*) with <p, w> = s t <a, n> = 0: P(p + w) = p
+    # (the normal taken times min(1, e^r), to keep it finite for r << 0)
     rng = np.random.default_rng(seed)
-    for _ in range(60):
+    for k in range(60):
         f = np.exp(rng.uniform(-2, 2, size=3)) if seed else np.ones(3)
-        r = rng.uniform(-6, 4)
+        r = rng.uniform(-6, 4) if k % 2 else rng.uniform(-60, 40)
         s, t = rng.uniform(0.05, 5.0), rng.uniform(0.0, 5.0)
         p = s * f * ray(r)
-        v = p - t * normal(r) / f
+        v = p - t * normal(r) * min(1.0, math.exp(r)) / f
         got = O.proj_scaled_exp(v, f)
         assert np.allclose(got, p, rtol=0, atol=1e-9 * (1 + np.abs(v).max())), (f, r, s, t)
+
+
+@pytest.mark.parametrize("r", [-300.5, -400.0, -700.0, -2000.0])
+def test_projection_onto_far_negative_rays(r):
+    # the rays (r, 1, e^r) approach the face edge (-1, 0, 0) only like 1 / |r|:
+    # with e^r F^-1 n(r) = F^-1 (-e^r, (r - 1) e^r, 1) as the normal, the point
+    # s F a(r) - t F^-1 (-e^r, (r - 1) e^r, 1) projects onto s F a(r), which is
+    # s f1 away from the face's clip
+    rng = np.random.default_rng(int(-r))
+    for _ in range(20):
+        f = np.exp(rng.uniform(-2, 2, size=3))
+        s, t = rng.uniform(0.05, 5.0), rng.uniform(0.1, 5.0)
+        E = math.exp(r)
+        p = s * f * np.array([r, 1.0, E])
+        v = p - t * np.array([-E, (r - 1.0) * E, 1.0]) / f
+        got = O.proj_scaled_exp(v, f)
+        assert np.allclose(got, p, rtol=0, atol=1e-9 * (1 + np.abs(v).max())), (f, s, t, got, p)
 
 
 def test_textbook_case_both_leading_coordinates_nonpositive():
