@@ -31,7 +31,8 @@ same run and reported under config.solves: one batched mixed-precision solve,
 one batched FP64 solve, and a sample of unbatched FP64 solves extrapolated to
 the batch (labelled as such); the FP64 oracle's termination test re-checks a
 random sample of the returned (x, y).  --no-solves skips it.  The other
-workloads run alone with --workload c2 | c3 | c4 (one JSON line each).
+workloads run alone with --workload c0 | c2 | c3 | c3_mlp | c4 | cones (one
+JSON line each).
 
 Prints one JSON line.
 """
@@ -440,6 +441,67 @@ def run_c3_mlp(args, P, np):
         {"roofline": roof, "cpu_baseline": None})
 
 
+# FP64 operations of one evaluation of the ray-angle slope on the coarse scan
+# (the running e^r and e^-r, the two scaled vectors, their cross product and
+# its dot product with v), times the 64 x 24 evaluations of that scan: the
+# work every projection off the closed-form cases does at least.
+EXP_FLOPS_PER_PROJECTION = 64 * 24 * 22
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def run_cones(args, P, np):
+    """Conic rows: an LP with exponential and dual-exponential cone blocks and
+    one with second-order-cone blocks, each solved to relative KKT 1e-6 in
+    FP64 and in mixed precision (a step is one solve of each); the
+    exponential-cone projection kernel timed with HIP events on 2^18 random
+    points and rescaling factors (its FP64 rate against the vector peak)."""
+    import lpgen
+
+    insts = {"exp": lpgen.exp_instance(0, m_zero=2000, n=10000, m_nonneg=1000, n_exp=600, n_dexp=400),
+             "soc": lpgen.soc_instance(0, m_zero=2000, n=10000, blocks=(3,) * 600 + (9,) * 100 + (50,) * 10)}
+    res = {}
+    for name, inst in insts.items():
+        prob = P.Problem.from_instance(inst)
+        for prec in ("fp64", "mixed"):
+            for _ in range(args.warmup):
+                prob.solve(precision=prec, time_limit=120.0)
+            walls, s = [], None
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                s = prob.solve(precision=prec, time_limit=120.0)
+                walls.append(time.perf_counter() - t0)
+            wall = float(np.median(walls))
+            res[f"{name}_{prec}"] = {"seconds": round(wall, 4), "solves_per_s": round(1.0 / wall, 3),
+                                     "trials": s.info["iters"], "us_per_trial": round(wall / s.info["iters"] * 1e6, 2),
+                                     "status": s.info["status"]}
+            log(f"cones {name} {prec}: m={inst.m} n={inst.n}: {wall * 1e3:.1f} ms per solve, {s.info['iters']} trials, "
+                f"{res[f'{name}_{prec}']['us_per_trial']} us per trial, {s.info['status']}")
+    rng = np.random.default_rng(0)
+    cnt = 1 << 18
+    v = rng.standard_normal((cnt, 3)) * rng.uniform(0.1, 10, size=(cnt, 1))
+    f = np.exp(rng.uniform(-2, 2, size=(cnt, 3)))
+    P.pdcs_project_exp(0, v[:4096], f[:4096])
+    times = sorted(P.pdcs_project_exp(0, v, f, timed=True)[1] for _ in range(5))
+    ms = times[len(times) // 2]
+    tflops = EXP_FLOPS_PER_PROJECTION * cnt / (ms * 1e-3) / 1e12
+    log(f"exp projection: {cnt} points in {ms:.3f} ms ({cnt / ms / 1e3:.1f} M/s), {tflops:.2f} TFLOP/s FP64")
+    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_proj_exp: projection onto diag(f) K_exp, one wave per point, random points and factors",
+            "flops_per_projection": EXP_FLOPS_PER_PROJECTION, "points": cnt, "kernel_ms": round(ms, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        sec = oracle_trial_seconds(insts["exp"], 20) * res["exp_fp64"]["trials"]
+        cpu = {"value": round(1.0 / sec, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "20 trials of the FP64 oracle (no rescaling) on the exponential-cone LP, extrapolated to "
+                         "the GPU's FP64 trial count"}
+    e = res["exp_fp64"]
+    return common_fields(args, e["solves_per_s"], "solves/s", e["seconds"] * 1e3, "f64", {
+        "workload": "conic LPs to rel. KKT 1e-6: m=6000 n=1e4 with 600 exponential and 400 dual-exponential "
+                    "3-row blocks (value: FP64 solves/s); m=5200 n=1e4 with 710 second-order-cone blocks",
+        "solves": res}, {"roofline": roof, "cpu_baseline": cpu})
+
+
 def workload(name: str):
     import lpgen
 
@@ -563,7 +625,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed chunks of 64 trials + restart check")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1_nnz_matched", "c2", "c3", "c3_mlp", "c4"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1_nnz_matched", "c2", "c3", "c3_mlp", "c4", "cones"])
     ap.add_argument("--mlp-batch", type=int, default=256, help="c3_mlp: training batch")
     ap.add_argument("--c2-count", type=int, default=512)
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "bands"],
@@ -599,10 +661,10 @@ def main():
     if args.workload == "c3_mlp":
         print(json.dumps(run_c3_mlp(args, P, np)), flush=True)
         return
-    if args.workload in ("c0", "c2", "c3", "c4"):
+    if args.workload in ("c0", "c2", "c3", "c4", "cones"):
         if args.steps == 200 and args.warmup == 20:   # the C1 defaults: one step each here
-            args.steps, args.warmup = (20, 2) if args.workload == "c0" else (1, 0)
-        fn = {"c0": run_c0, "c2": run_c2, "c3": run_c3, "c4": run_c4}[args.workload]
+            args.steps, args.warmup = {"c0": (20, 2), "cones": (3, 1)}.get(args.workload, (1, 0))
+        fn = {"c0": run_c0, "c2": run_c2, "c3": run_c3, "c4": run_c4, "cones": run_cones}[args.workload]
         print(json.dumps(fn(args, P, np)), flush=True)
         return
 

@@ -236,14 +236,19 @@ int  pdcs_problem_create_cones(int64_t m, int64_t n, int64_t m_zero, int64_t n_s
                                const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                                const double* h, const double* c, const double* l,
                                const double* u, pdcs_problem* out);
-/* pdcs_project_exp: the solver's projection onto a rescaled exponential cone
- * (Section 2.6), for count 3-vectors: out_q = Proj onto diag(f_q) K_exp of
- * v_q (dual = 0) or onto diag(f_q) K_exp* (dual = 1).  v, f and out are host
- * arrays of 3 count doubles (vector q at [3q, 3q + 3)), f > 0 and v finite;
+/* pdcs_project_cone: the solver's projection onto a rescaled cone (Section
+ * 2.6), for count vectors of dimension dim: out_q = Proj onto diag(f_q) K of
+ * v_q, with K = K_soc = {(t, w): ||w|| <= t} (cone 0, any dim >= 1), K_exp
+ * (cone 1, dim 3) or K_exp* (cone 2, dim 3).  v, f and out are host arrays of
+ * dim * count doubles (vector q at [q dim, q dim + dim)), f > 0 and v finite;
  * the call copies them to the device, runs one wavefront per vector on the
- * current device and copies the result back (synchronous).  count <= 2^26.
- * Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_SIZE, PDCS_ERR_OOM, PDCS_ERR_HIP. */
-int  pdcs_project_exp(int64_t dual, int64_t count, const double* v, const double* f, double* out);
+ * current device (the device function the solver calls at its cone rows)
+ * and copies the result back (synchronous).  count * dim <= 2^28.  kernel_ms
+ * (host, may be null) receives the kernel's duration from HIP events around
+ * its launch.  Errors: PDCS_ERR_INVALID_ARG, PDCS_ERR_SIZE, PDCS_ERR_OOM,
+ * PDCS_ERR_HIP. */
+int  pdcs_project_cone(int64_t cone, int64_t dim, int64_t count, const double* v, const double* f,
+                       double* out, double* kernel_ms);
 void pdcs_problem_destroy(pdcs_problem p);
 int  pdcs_problem_dims(pdcs_problem p, int64_t* m, int64_t* n, int64_t* nnz);
 

@@ -80,7 +80,7 @@ PROTOTYPES = {
     "pdcs_problem_create_conic": (C.c_int, [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
     "pdcs_problem_create_cones": (C.c_int, [_I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P,
                                             C.POINTER(_P)]),
-    "pdcs_project_exp": (C.c_int, [_I64, _I64, _P, _P, _P]),
+    "pdcs_project_cone": (C.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
     "pdcs_problem_destroy": (None, [_P]),
     "pdcs_problem_dims": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
     "pdcs_problem_spmv": (C.c_int, [_P, _I64, _I64, _P, _P, _P]),
@@ -253,14 +253,27 @@ def pdcs_problem_create_cones(m, n, m_zero, soc_dims, n_exp, n_dexp, row_ptr, co
     return out
 
 
-def pdcs_project_exp(dual, v, f) -> np.ndarray:
-    """Projections of the rows of v (count x 3) onto diag(f_q) K_exp (dual=0) or
-    diag(f_q) K_exp* (dual=1), on the current GPU."""
-    v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 3))
+CONES = {"soc": 0, "exp": 1, "exp_dual": 2}
+
+
+def pdcs_project_cone(cone, v, f, timed=False):
+    """Projections of the rows of v (count x dim) onto diag(f_q) K, K named by
+    cone ("soc", "exp" or "exp_dual"; dim 3 for the exponential cones), on the
+    current GPU; with timed, also the kernel's duration in ms."""
+    v = np.asarray(v, dtype=np.float64)
+    v = np.ascontiguousarray(v.reshape(-1, v.shape[-1] if v.ndim > 1 else v.size))
     f = np.ascontiguousarray(np.broadcast_to(np.asarray(f, dtype=np.float64), v.shape))
     out = np.empty_like(v)
-    _check(lib.pdcs_project_exp(int(dual), int(v.shape[0]), _ptr(v), _ptr(f), _ptr(out)), "pdcs_project_exp")
-    return out
+    ms = C.c_double(0.0)
+    _check(lib.pdcs_project_cone(CONES[cone], int(v.shape[1]), int(v.shape[0]), _ptr(v), _ptr(f), _ptr(out),
+                                 C.byref(ms) if timed else None), "pdcs_project_cone")
+    return (out, ms.value) if timed else out
+
+
+def pdcs_project_exp(dual, v, f, timed=False):
+    """pdcs_project_cone onto diag(f) K_exp (dual=0) or diag(f) K_exp* (dual=1)."""
+    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    return pdcs_project_cone("exp_dual" if dual else "exp", v, f, timed)
 
 
 def pdcs_problem_destroy(p):

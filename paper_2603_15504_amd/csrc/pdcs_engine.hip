@@ -335,8 +335,14 @@ void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block, const 
       const size_t q0 = q;
       if (cones) {
         // a range ends at a cone block boundary: blocks starting inside it are
-        // taken whole, and a range that reaches a block's rows takes the block
+        // taken whole, and a range that reaches a block's rows takes the block;
+        // a range holds at most kConeBlocksPerRange blocks (each wave of its
+        // workgroup projects one), so that the blocks spread over workgroups
         while (q < soc->r0.size() && soc->r0[q] < e && soc->r0[q] < stop) {
+          if (q - q0 == (size_t)kConeBlocksPerRange) {
+            e = soc->r0[q];
+            break;
+          }
           e = std::max<int64_t>(e, (int64_t)soc->r0[q] + soc->dim[q]);
           ++q;
         }
@@ -1591,26 +1597,46 @@ int pdcs_problem_create_cones(int64_t m, int64_t n, int64_t m_zero, int64_t n_so
   });
 }
 
-int pdcs_project_exp(int64_t dual, int64_t count, const double* v, const double* f, double* out) {
+int pdcs_project_cone(int64_t cone, int64_t dim, int64_t count, const double* v, const double* f, double* out,
+                      double* kernel_ms) {
   return guarded([&]() {
-    if (dual != 0 && dual != 1) throw Error(PDCS_ERR_INVALID_ARG, "dual must be 0 or 1");
+    if (cone < 0 || cone > 2) throw Error(PDCS_ERR_INVALID_ARG, "cone must be 0, 1 or 2");
+    if (dim < 1 || (cone != 0 && dim != 3)) throw Error(PDCS_ERR_INVALID_ARG, "bad cone dimension");
     if (count < 0) throw Error(PDCS_ERR_INVALID_ARG, "count must be >= 0");
     if (count == 0) return PDCS_OK;
     if (!v || !f || !out) throw Error(PDCS_ERR_INVALID_ARG, "null array");
-    if (count > ((int64_t)1 << 26)) throw Error(PDCS_ERR_SIZE, "count must be <= 2^26");
-    for (int64_t i = 0; i < 3 * count; ++i) {
+    if (dim > ((int64_t)1 << 24) || count > ((int64_t)1 << 28) / dim)
+      throw Error(PDCS_ERR_SIZE, "count * dim must be <= 2^28");
+    for (int64_t i = 0; i < dim * count; ++i) {
       if (!(f[i] > 0.0) || !std::isfinite(f[i])) throw Error(PDCS_ERR_INVALID_ARG, "factors must be finite and > 0");
       if (!std::isfinite(v[i])) throw Error(PDCS_ERR_INVALID_ARG, "points must be finite");
     }
-    const size_t bytes = (size_t)count * 3 * sizeof(double);
+    const size_t bytes = (size_t)count * dim * sizeof(double);
     DBuf dv, df, dout;
     dv.alloc(bytes);
     df.alloc(bytes);
     dout.alloc(bytes);
     HIP_OK(hipMemcpy(dv.p, v, bytes, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(df.p, f, bytes, hipMemcpyHostToDevice));
-    launch_proj_exp(dv.as<double>(), df.as<double>(), dout.as<double>(), count, (int)dual, nullptr);
-    HIP_OK(hipGetLastError());
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (kernel_ms) {
+      HIP_OK(hipEventCreate(&ev[0]));
+      HIP_OK(hipEventCreate(&ev[1]));
+      HIP_OK(hipEventRecord(ev[0], nullptr));
+    }
+    launch_proj_cone((int)cone, (int)dim, dv.as<double>(), df.as<double>(), dout.as<double>(), count, nullptr);
+    hipError_t le = hipGetLastError();
+    if (kernel_ms) {
+      float ms = 0.0f;
+      hipError_t e1 = hipEventRecord(ev[1], nullptr);
+      hipError_t e2 = e1 == hipSuccess ? hipEventSynchronize(ev[1]) : e1;
+      hipError_t e3 = e2 == hipSuccess ? hipEventElapsedTime(&ms, ev[0], ev[1]) : e2;
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+      HIP_OK(e3);
+      *kernel_ms = ms;
+    }
+    HIP_OK(le);
     HIP_OK(hipMemcpy(out, dout.p, bytes, hipMemcpyDeviceToHost));
     return PDCS_OK;
   });

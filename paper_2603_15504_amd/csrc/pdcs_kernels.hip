@@ -70,8 +70,10 @@ __device__ __forceinline__ void wave_proj_soc(int d, const LD& ld, const EF& ef,
     for (int i = 1 + lane; i < d; i += kWave) {
       const double v = ld(i), e = ef(i), e2 = e * e;
       const double den = e2 * sv + mu, q = v * v * e2;
-      f += q / (den * den);
-      df -= 2.0 * q * (e2 * ie02 + 1.0) / (den * den * den);
+      if (q > 0.0) {  // (a zero term stays zero at den = 0, which mu = 0 with v_0 = 0 gives)
+        f += q / (den * den);
+        df -= 2.0 * q * (e2 * ie02 + 1.0) / (den * den * den);
+      }
     }
     f = wave_sum(f) - 1.0;
     df = wave_sum(df);
@@ -112,40 +114,136 @@ __device__ __forceinline__ bool exp_dual_has(double u, double v, double w) {
   return u == 0.0 && v >= 0.0 && w >= 0.0;
 }
 
+// A point to project onto F K_exp: v, f and 1 / f.
+struct ExpPoint {
+  double v[3], f[3], fi[3];
+};
+
 // Sign of the slope of the angle between v and the boundary ray of F K_exp
 // through F a(r), a(r) = (r, 1, e^r): the triple product
 // det[v, F a(r), F^-1 n(r)], n(r) = (-1, r - 1, e^-r) the element of K_exp*
 // normal to the cone along the ray (F a(r) x F^-1 n(r) points along the
 // derivative of the unit ray), times e^r, divided by e^2r for r > 0 so that
-// it stays finite.
-__device__ __forceinline__ double exp_ray_turn(double r, const double (&v)[3], const double (&f)[3]) {
-  double a0, a1, a2, m0, m1, m2;  // a = F a(r), m = e^r F^-1 n(r), both scaled by e^-r when r > 0
+// it stays finite.  E = e^r and iE = e^-r are passed in.
+__device__ __forceinline__ double exp_ray_turn(double r, double E, double iE, const ExpPoint& P) {
+  double a0, a1, a2, m0, m1, m2;  // a = F a(r), m = e^r F^-1 n(r), both times e^-r when r > 0
   if (r <= 0.0) {
-    const double E = exp(r);
-    a0 = f[0] * r, a1 = f[1], a2 = f[2] * E;
-    m0 = -E / f[0], m1 = E * (r - 1.0) / f[1], m2 = 1.0 / f[2];
+    a0 = P.f[0] * r, a1 = P.f[1], a2 = P.f[2] * E;
+    m0 = -E * P.fi[0], m1 = E * (r - 1.0) * P.fi[1], m2 = P.fi[2];
   } else {
-    const double iE = exp(-r);
-    a0 = f[0] * r * iE, a1 = f[1] * iE, a2 = f[2];
-    m0 = -1.0 / f[0], m1 = (r - 1.0) / f[1], m2 = iE / f[2];
+    a0 = P.f[0] * r * iE, a1 = P.f[1] * iE, a2 = P.f[2];
+    m0 = -P.fi[0], m1 = (r - 1.0) * P.fi[1], m2 = iE * P.fi[2];
   }
-  return v[0] * (a1 * m2 - a2 * m1) + v[1] * (a2 * m0 - a0 * m2) + v[2] * (a0 * m1 - a1 * m0);
+  return P.v[0] * (a1 * m2 - a2 * m1) + P.v[1] * (a2 * m0 - a0 * m2) + P.v[2] * (a0 * m1 - a1 * m0);
+}
+
+__device__ __forceinline__ double exp_ray_turn(double r, const ExpPoint& P) {
+  return exp_ray_turn(r, exp(r), exp(-r), P);
+}
+
+// Candidate on the ray of r: the nearest point s F a(r), s = <F a, v> / |F a|^2,
+// kept in (bd, b) when s > 0 and it is nearer than bd; cert is set when it is
+// nearer and v - p is a nonpositive multiple of F^-1 n(r) (at a root of the
+// slope v - p is parallel to it): then -F (v - p) lies in K_exp*, p in F K_exp
+// and <p, v - p> = 0, which makes p the projection.
+__device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, double& bd, double (&b)[3],
+                                                  bool& cert) {
+  const double E = exp(r);
+  const double q0 = P.f[0] * r, q1 = P.f[1], q2 = P.f[2] * E;
+  const double s = (q0 * P.v[0] + q1 * P.v[1] + q2 * P.v[2]) / (q0 * q0 + q1 * q1 + q2 * q2);
+  if (!(s > 0.0)) return;
+  const double c0 = s * q0, c1 = s * q1, c2 = s * q2;
+  const double d0 = P.v[0] - c0, d1 = P.v[1] - c1, d2 = P.v[2] - c2;
+  const double d = d0 * d0 + d1 * d1 + d2 * d2;
+  if (!(d < bd)) return;
+  bd = d, b[0] = c0, b[1] = c1, b[2] = c2;
+  // <v - p, F^-1 n(r) min(1, e^r)>
+  const double w = r <= 0.0 ? -d0 * E * P.fi[0] + d1 * (r - 1.0) * E * P.fi[1] + d2 * P.fi[2]
+                            : -d0 * P.fi[0] + d1 * (r - 1.0) * P.fi[1] + d2 * exp(-r) * P.fi[2];
+  cert = w <= 0.0;
+}
+
+// One scan of the rays by the wave: lane l takes cells [l C, l C + C) of
+// width h from r = -32 C h, every + to - sign change of the slope is refined
+// to full precision and its candidate kept (exp_ray_candidate).  e^r runs by
+// multiplication along a lane's cells (the refinement uses exp itself).
+template <int C>
+__device__ __forceinline__ void exp_scan(double h, const ExpPoint& P, double& bd, double (&b)[3], bool& cert) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double r_first = -0.5 * kWave * C * h;
+  const double g = exp(h), ig = exp(-h);
+  int k = lane * C;
+  double lo = r_first + k * h;
+  double E = exp(lo), iE = exp(-lo);
+  double t_lo = exp_ray_turn(lo, E, iE, P);
+  for (int c = 0; c < C; ++c) {
+    ++k;
+    const double hi = r_first + k * h;
+    E *= g, iE *= ig;
+    const double t_hi = exp_ray_turn(hi, E, iE, P);
+    if (t_lo > 0.0 && t_hi <= 0.0) {
+      // the bracket [x, z] (slope > 0 at x, <= 0 at z) shrunk to adjacent
+      // doubles: regula falsi with the Illinois halving of a stale end, every
+      // fourth step a bisection
+      double x = lo, z = hi, tx = t_lo, tz = t_hi;
+      int side = 0;
+      for (int it = 0; it < 160 && tz != 0.0; ++it) {
+        double m = (it & 3) == 3 ? 0.5 * (x + z) : (x * tz - z * tx) / (tz - tx);
+        if (!(m > x && m < z)) m = 0.5 * (x + z);
+        if (!(m > x && m < z)) break;
+        const double tm = exp_ray_turn(m, P);
+        if (tm > 0.0) {
+          x = m, tx = tm;
+          if (side == 1) tz *= 0.5;
+          side = 1;
+        } else {
+          z = m, tz = tm;
+          if (side == -1) tx *= 0.5;
+          side = -1;
+        }
+      }
+      exp_ray_candidate(tz == 0.0 ? z : 0.5 * (x + z), P, bd, b, cert);
+    }
+    lo = hi;
+    t_lo = t_hi;
+  }
+}
+
+// Nearest candidate over the wave (ties: the lowest lane); with `certified`,
+// only lanes holding a certified candidate take part.  Returns whether any did.
+__device__ __forceinline__ bool exp_wave_pick(double bd, const double (&b)[3], bool eligible, double (&p)[3]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double d = eligible ? bd : INFINITY;
+  double b0 = b[0], b1 = b[1], b2 = b[2];
+  int who = eligible ? lane : kWave;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double od = __shfl_xor(d, off);
+    const int ow = __shfl_xor(who, off);
+    const double o0 = __shfl_xor(b0, off), o1 = __shfl_xor(b1, off), o2 = __shfl_xor(b2, off);
+    if (ow < kWave && (who == kWave || od < d || (od == d && ow < who))) d = od, who = ow, b0 = o0, b1 = o1, b2 = o2;
+  }
+  if (who == kWave) return false;
+  p[0] = b0, p[1] = b1, p[2] = b2;
+  return true;
 }
 
 // Projection of v onto F K_exp, F = diag(f) > 0, by one wave (every lane gets
 // the result).  v itself if v / f is in K_exp; 0 if -F v is in K_exp* (the
-// polar cone); otherwise the nearest of the clip onto the face
-// {(x, 0, z): x <= 0, z >= 0} and the best points of the rays: the local
-// maxima of the angle along the rays are the + to - sign changes of
-// exp_ray_turn, located on a grid of step kExpStep over |r| <= 64 kExpSteps
-// kExpStep / 2 (each lane scans kExpSteps cells) and bisected to full
-// precision; on the ray through F a the nearest point is s F a with
-// s = <F a, v> / |F a|^2 when positive.  Beyond the grid the rays lie within
-// e^-300 of the face's edges.
-constexpr int kExpSteps = 188;
-constexpr double kExpStep = 0.05;
+// polar cone); the clip onto the face {(x, 0, z): x <= 0, z >= 0} if -F times
+// its residual is in K_exp*; otherwise the nearest of the face's clip and the
+// best points of the rays s F a(r): the local maxima of the angle along the
+// rays (+ to - sign changes of exp_ray_turn) and, for rays below the scanned
+// range, whose third coordinate is then below e^-300 of the others, the ray
+// through v's own x / y, r = (v_1 / f_1) / (v_2 / f_2).  A first scan on a
+// coarse grid (step 0.4 over |r| <= 307.2) ends the search when a candidate
+// carries the projection's certificate; else a scan on a fine grid (step
+// 0.05 over |r| <= 300.8) takes the nearest of all candidates.  Above the
+// scanned range the rays lie within e^-300 of the face's edge (0, 0, 1).
+constexpr double kExpTail = -300.0;
 
 __device__ __noinline__ void exp_proj_wave(const double (&v)[3], const double (&f)[3], double (&p)[3]) {
+  ExpPoint P;
+  for (int i = 0; i < 3; ++i) P.v[i] = v[i], P.f[i] = f[i], P.fi[i] = 1.0 / f[i];
   if (exp_cone_has(v[0] / f[0], v[1] / f[1], v[2] / f[2])) {
     p[0] = v[0], p[1] = v[1], p[2] = v[2];
     return;
@@ -154,46 +252,23 @@ __device__ __noinline__ void exp_proj_wave(const double (&v)[3], const double (&
     p[0] = p[1] = p[2] = 0.0;
     return;
   }
-  double b0 = fmin(v[0], 0.0), b1 = 0.0, b2 = fmax(v[2], 0.0);
-  double bd = (v[0] - b0) * (v[0] - b0) + v[1] * v[1] + (v[2] - b2) * (v[2] - b2);
+  const double face[3] = {fmin(v[0], 0.0), 0.0, fmax(v[2], 0.0)};
+  if (exp_dual_has(-f[0] * (v[0] - face[0]), -f[1] * v[1], -f[2] * (v[2] - face[2]))) {
+    p[0] = face[0], p[1] = face[1], p[2] = face[2];
+    return;
+  }
+  const double face_d = (v[0] - face[0]) * (v[0] - face[0]) + v[1] * v[1] + (v[2] - face[2]) * (v[2] - face[2]);
+  const bool tail = v[0] < 0.0 && v[1] > 0.0 && (v[0] * P.fi[0]) / (v[1] * P.fi[1]) < kExpTail;
   const int lane = threadIdx.x & (kWave - 1);
-  const double r_first = -0.5 * kWave * kExpSteps * kExpStep;
-  int k = lane * kExpSteps;
-  double lo = r_first + k * kExpStep;
-  double t_lo = exp_ray_turn(lo, v, f);
-  for (int c = 0; c < kExpSteps; ++c) {
-    ++k;
-    const double hi = r_first + k * kExpStep;
-    const double t_hi = exp_ray_turn(hi, v, f);
-    if (t_lo > 0.0 && t_hi <= 0.0) {
-      double a = lo, z = hi;
-      for (int it = 0; it < 64; ++it) {
-        const double mid = 0.5 * (a + z);
-        if (mid <= a || mid >= z) break;
-        if (exp_ray_turn(mid, v, f) > 0.0) a = mid;
-        else z = mid;
-      }
-      const double r = 0.5 * (a + z);
-      const double q0 = f[0] * r, q1 = f[1], q2 = f[2] * exp(r);
-      const double s = (q0 * v[0] + q1 * v[1] + q2 * v[2]) / (q0 * q0 + q1 * q1 + q2 * q2);
-      if (s > 0.0) {
-        const double c0 = s * q0, c1 = s * q1, c2 = s * q2;
-        const double d = (v[0] - c0) * (v[0] - c0) + (v[1] - c1) * (v[1] - c1) + (v[2] - c2) * (v[2] - c2);
-        if (d < bd) bd = d, b0 = c0, b1 = c1, b2 = c2;
-      }
-    }
-    lo = hi;
-    t_lo = t_hi;
-  }
-  // nearest candidate over the wave (ties: the lowest lane, i.e. the smallest r)
-  int who = lane;
-  for (int off = 1; off < kWave; off <<= 1) {
-    const double od = __shfl_xor(bd, off);
-    const int ow = __shfl_xor(who, off);
-    const double o0 = __shfl_xor(b0, off), o1 = __shfl_xor(b1, off), o2 = __shfl_xor(b2, off);
-    if (od < bd || (od == bd && ow < who)) bd = od, who = ow, b0 = o0, b1 = o1, b2 = o2;
-  }
-  p[0] = b0, p[1] = b1, p[2] = b2;
+  double bd = face_d, b[3] = {face[0], face[1], face[2]};
+  bool cert = false;
+  if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b, cert);
+  exp_scan<24>(0.4, P, bd, b, cert);
+  if (exp_wave_pick(bd, b, cert, p)) return;
+  bd = face_d, b[0] = face[0], b[1] = face[1], b[2] = face[2];
+  if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b, cert);
+  exp_scan<188>(0.05, P, bd, b, cert);
+  exp_wave_pick(bd, b, true, p);
 }
 
 // Projection of a 3-row block onto F K_exp (dual = false) or onto F K_exp*
@@ -241,15 +316,20 @@ __device__ __forceinline__ void for_cone_blocks(const Ranges& R, int b, const FN
   for (int q = q0 + wave; q < q1; q += kWavesPerBlock) fn(R.soc_r0[q], R.soc_dim[q], (int)R.soc_kind[q]);
 }
 
-// Projection of count 3-vectors (v, f and out: 3 doubles each, contiguous)
-// onto diag(f) K_exp (dual = 0) or diag(f) K_exp* (dual = 1), one wave each.
-__global__ __launch_bounds__(kBlock) void k_proj_exp(const double* __restrict__ v, const double* __restrict__ f,
-                                                     double* __restrict__ out, int64_t count, int dual) {
+// Projection of count vectors of dimension dim (v, f and out: dim doubles
+// each, contiguous) onto diag(f) K, K = K_soc (cone 0), K_exp (cone 1) or
+// K_exp* (cone 2, dim 3), one wave each.
+__global__ __launch_bounds__(kBlock) void k_proj_cone(int cone, int dim, const double* __restrict__ v,
+                                                      const double* __restrict__ f, double* __restrict__ out,
+                                                      int64_t count) {
   const int64_t q = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (q >= count) return;
-  wave_proj_exp(
-      dual != 0, [&](int i) { return v[3 * q + i]; }, [&](int i) { return f[3 * q + i]; },
-      [&](int i, double p) { out[3 * q + i] = p; });
+  const size_t o = (size_t)q * dim;
+  const auto ld = [&](int i) { return v[o + i]; };
+  const auto ef = [&](int i) { return f[o + i]; };
+  const auto st = [&](int i, double p) { out[o + i] = p; };
+  if (cone == 0) wave_proj_soc(dim, ld, ef, st);
+  else wave_proj_exp(cone == 2, ld, ef, st);
 }
 
 // ===========================================================================
@@ -687,13 +767,8 @@ __device__ __forceinline__ void fin_ls_body(int iid, const int32_t* iblk_p, cons
   const double kb1 = (double)I.kbar + 1.0;
   const double p3 = pf ? pf[0] : pow(kb1, -0.3), p6 = pf ? pf[1] : pow(kb1, -0.6);
   const double eta_next = fmin((1.0 - p3) * etabar, (1.0 + p6) * eta);
-  if (!isfinite(num) || isnan(etabar) || isnan(q[2]) || isnan(q[3]) || isnan(p[1]) ||
-      !(eta_next > 0.0) || !isfinite(eta_next)) {
-    I.status = kDone;
-    I.exit_code = 8;
-    I.last_acc = 0;
-    return;
-  }
+  const bool bad = !isfinite(num) || isnan(etabar) || isnan(q[2]) || isnan(q[3]) || isnan(p[1]) ||
+                   !(eta_next > 0.0) || !isfinite(eta_next);
   if (I.trace && I.kbar <= I.trace_cap) {
     double* tr = I.trace + (I.kbar - 1) * kTraceStride;
     tr[0] = (double)I.kbar;
@@ -706,6 +781,17 @@ __device__ __forceinline__ void fin_ls_body(int iid, const int32_t* iblk_p, cons
     tr[7] = eta_next;
     for (int f = 8; f < kTraceStride; ++f) tr[f] = NAN;
     tr[9] = (double)I.k;
+    if (bad) {  // the failing trial's reductions, for diagnosis
+      tr[10] = p[1];
+      tr[11] = q[3];
+      tr[14] = q[2];
+    }
+  }
+  if (bad) {
+    I.status = kDone;
+    I.exit_code = 8;
+    I.last_acc = 0;
+    return;
   }
   if (eta < etabar) {
     I.last_acc = 1;
@@ -2927,9 +3013,11 @@ void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n > 0) k_to_f32<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, s>>>(in, out, n);
 }
 
-void launch_proj_exp(const double* v, const double* f, double* out, int64_t count, int dual, hipStream_t s) {
+void launch_proj_cone(int cone, int dim, const double* v, const double* f, double* out, int64_t count,
+                      hipStream_t s) {
   if (count > 0)
-    k_proj_exp<<<(unsigned)((count + kWavesPerBlock - 1) / kWavesPerBlock), kBlock, 0, s>>>(v, f, out, count, dual);
+    k_proj_cone<<<(unsigned)((count + kWavesPerBlock - 1) / kWavesPerBlock), kBlock, 0, s>>>(cone, dim, v, f, out,
+                                                                                           count);
 }
 
 void launch_pack_warm(const void* const* src, const int32_t* off, int B, int64_t maxlen, int dtype, double* out,

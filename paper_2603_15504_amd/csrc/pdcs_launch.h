@@ -40,6 +40,9 @@ struct MatPtrs {
 // Longest row or column for the row-wise passes of k_trials_lds.
 constexpr int kLdsRowMax = 64;
 
+// Cone blocks per row range of the elementwise passes: one per wave.
+constexpr int kConeBlocksPerRange = kWavesPerBlock;
+
 // LDS footprint of one instance in k_trials_lds: the 14 iterate vectors the
 // trials touch, c, l, u, h, both CSR copies of the instance's part of G and
 // the three per-block record arrays.  Shared by the host (choice of kernel,
@@ -150,9 +153,10 @@ void launch_band_plain(const BandTiles& bt, int prec, const void* val, const voi
 void launch_band_vals(const int32_t* src, int64_t n, const double* v64, double* o64, float* o32, hipStream_t s);
 // out[i] = (float)in[i], i < n
 void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
-// count 3-vectors (contiguous in v, f, out) projected onto diag(f) K_exp
-// (dual = 0) or diag(f) K_exp* (dual = 1).
-void launch_proj_exp(const double* v, const double* f, double* out, int64_t count, int dual, hipStream_t s);
+// count vectors of dimension dim (contiguous in v, f, out) projected onto
+// diag(f) K, K = K_soc (cone 0), K_exp (1) or K_exp* (2, dim 3).
+void launch_proj_cone(int cone, int dim, const double* v, const double* f, double* out, int64_t count,
+                      hipStream_t s);
 // Warm starts from device pointers: out[off[b] + e] = src[b][e] (FP64 or FP32
 // source, dtype 0 / 1; a null src[b] gives zeros), e < off[b + 1] - off[b];
 // *nan_flag is set to 1 when a value is NaN.

@@ -2,7 +2,7 @@
 Section 3; the rescaled-cone projection of Section 2.6) against the FP64
 oracle, through the C ABI.
 
-The projection itself (pdcs_project_exp, the device function the solver
+The projection itself (pdcs_project_cone, the device function the solver
 calls) is compared element by element with the oracle's on random points and
 factors, and with points whose projection is known by construction.  Before
 the first restart check an FP64 solve follows the oracle trial by trial (step
@@ -68,6 +68,26 @@ def test_projection_of_ray_plus_normal_is_the_ray_point():
     assert np.all(np.abs(got_d - (-v + p)) <= 1e-9 * (1 + np.abs(v).max(axis=1, keepdims=True)))
 
 
+def test_projection_onto_far_negative_and_far_positive_rays():
+    # rays below the scanned range (r < -300) and near its ends; the normal
+    # taken times min(1, e^r) to stay finite
+    rng = np.random.default_rng(4)
+    r = np.concatenate([-rng.uniform(290, 2000, size=200), rng.uniform(-60, 40, size=200)])
+    n = r.size
+    s, t = rng.uniform(0.05, 5.0, size=n), rng.uniform(0.1, 5.0, size=n)
+    f = np.exp(rng.uniform(-2, 2, size=(n, 3)))
+    E = np.exp(r)
+    a = np.stack([r, np.ones(n), E], axis=1)
+    sc = np.minimum(1.0, E)
+    nr = np.stack([-sc, (r - 1.0) * sc, np.where(r < 0, 1.0, np.exp(-np.maximum(r, 0.0)))], axis=1)
+    p = s[:, None] * f * a
+    v = p - t[:, None] * nr / f
+    got = P.pdcs_project_exp(0, v, f)
+    tol = 1e-9 * (1 + np.abs(v).max(axis=1))
+    bad = np.nonzero(np.abs(got - p).max(axis=1) > tol)[0]
+    assert bad.size == 0, (r[bad[:5]], got[bad[:5]], p[bad[:5]])
+
+
 def test_projection_special_cases():
     f = np.ones(3)
     v = np.array([[0.2, 1.0, 2.0],        # inside K_exp: itself
@@ -85,7 +105,7 @@ def test_projection_special_cases():
     with pytest.raises(P.PdcsError):
         P.pdcs_project_exp(0, v, np.array([1.0, 0.0, 1.0]))
     with pytest.raises(P.PdcsError):
-        P.pdcs_project_exp(2, v, f)
+        P.pdcs_project_cone("exp", np.ones((2, 4)), np.ones(4))   # exponential cones have dimension 3
 
 
 def _with_soc(inst, k):

@@ -146,3 +146,23 @@ def test_conic_create_rejects_bad_blocks():
         with pytest.raises(P.PdcsError):
             P.Problem(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx, inst.val, inst.h, inst.c,
                       inst.l, inst.u, soc=soc)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 9, 50, 64, 65, 200])
+def test_soc_projection_matches_oracle_elementwise(d):
+    # the device projection onto diag(e) K_soc against the oracle's, on random
+    # points and factors, with zero leading entries and zero entries of w
+    # among them (v_0 = 0 starts the multiplier search at a zero denominator)
+    rng = np.random.default_rng(d)
+    cnt = 300
+    v = rng.standard_normal((cnt, d)) * rng.uniform(0.1, 10, size=(cnt, 1))
+    e = np.exp(rng.uniform(-3, 3, size=(cnt, d)))
+    v[::3, 0] = 0.0
+    if d > 2:
+        v[::2, 1] = 0.0
+    e[::4] = 1.0
+    got = P.pdcs_project_cone("soc", v, e)
+    for q in range(cnt):
+        want = O.proj_scaled_soc(v[q], e[q])
+        assert np.all(np.isfinite(got[q]))
+        assert np.max(np.abs(got[q] - want)) <= 1e-10 * (1 + np.abs(v[q]).max()), (q, v[q], got[q], want)
