@@ -460,15 +460,16 @@ def run_cones(args, P, np):
     insts = {"exp": lpgen.exp_instance(0, m_zero=2000, n=10000, m_nonneg=1000, n_exp=600, n_dexp=400),
              "soc": lpgen.soc_instance(0, m_zero=2000, n=10000, blocks=(3,) * 600 + (9,) * 100 + (50,) * 10)}
     res = {}
+    cap = {"max_iter": args.max_trials} if args.max_trials > 0 else {}  # bounded runs for kernel traces
     for name, inst in insts.items():
         prob = P.Problem.from_instance(inst)
         for prec in ("fp64", "mixed"):
             for _ in range(args.warmup):
-                prob.solve(precision=prec, time_limit=120.0)
+                prob.solve(precision=prec, time_limit=120.0, **cap)
             walls, s = [], None
             for _ in range(args.steps):
                 t0 = time.perf_counter()
-                s = prob.solve(precision=prec, time_limit=120.0)
+                s = prob.solve(precision=prec, time_limit=120.0, **cap)
                 walls.append(time.perf_counter() - t0)
             wall = float(np.median(walls))
             res[f"{name}_{prec}"] = {"seconds": round(wall, 4), "solves_per_s": round(1.0 / wall, 3),
@@ -630,7 +631,7 @@ def main():
     ap.add_argument("--c2-count", type=int, default=512)
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "bands"],
                     help="c2: matrix layout of the batch (profiling)")
-    ap.add_argument("--max-trials", type=int, default=0, help="c2, c4: cap on trials per instance (profiling)")
+    ap.add_argument("--max-trials", type=int, default=0, help="c2, c4, cones: cap on trials per instance (profiling)")
     ap.add_argument("--c3-train", type=int, default=1024)
     ap.add_argument("--c3-test", type=int, default=256)
     ap.add_argument("--c3-epochs", type=int, default=200)

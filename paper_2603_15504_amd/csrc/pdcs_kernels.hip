@@ -36,52 +36,90 @@ namespace pdcs {
 // result goes to st(i, p_i), each by the lane that read v_i.  From the KKT
 // conditions: v itself inside the cone; 0 inside the polar cone -diag(1/e)
 // K_soc (||w e_w|| <= -t e_t); otherwise the multiplier mu > 0 is the root of
-//   f(mu) = sum_i v_i^2 e_i^2 / (e_i^2 s + mu)^2 - 1,  s = v_0 / e_0 + mu / e_0^2
-// (sum over i >= 1), which is convex and decreasing, positive at
-// max(0, -v_0 e_0) and non-positive at ||w e_w||: Newton steps kept inside the
-// bracket (bisection when a step leaves it), then p_0 = e_0 s and
-// p_i = v_i e_i^2 s / (e_i^2 s + mu).  FP64 throughout.
+//   F(mu) = sum_i v_i^2 e_i^2 / (e_i^2 s + mu)^2 = 1,  s = v_0 / e_0 + mu / e_0^2
+// (sum over i >= 1), F decreasing, F > 1 at max(0, -v_0 e_0) and F <= 1 at
+// ||w e_w||: Newton steps on 1 - F^-1/2 (linear in mu when one term
+// dominates), kept inside the bracket, then p_0 = e_0 s and
+// p_i = v_i e_i^2 s / (e_i^2 s + mu).  FP64 throughout; the
+// first kSocCache elements of each lane stay in registers.
+constexpr int kSocCache = 4;
+
 template <class LD, class EF, class ST>
 __device__ __forceinline__ void wave_proj_soc(int d, const LD& ld, const EF& ef, const ST& st) {
   const int lane = threadIdx.x & (kWave - 1);
   const double v0 = ld(0), e0 = ef(0);
+  double vr[kSocCache], er[kSocCache];
+#pragma unroll
+  for (int k = 0; k < kSocCache; ++k) {
+    const int i = lane + k * kWave;
+    vr[k] = i < d ? ld(i) : 0.0;
+    er[k] = i < d ? ef(i) : 1.0;
+  }
+  // fn(i, v_i, e_i) over this lane's elements i >= 1
+  const auto each = [&](auto&& fn) {
+#pragma unroll
+    for (int k = 0; k < kSocCache; ++k) {
+      const int i = lane + k * kWave;
+      if (i >= 1 && i < d) fn(i, vr[k], er[k]);
+    }
+    for (int i = lane + kSocCache * kWave; i < d; i += kWave) fn(i, ld(i), ef(i));
+  };
   double in_w = 0.0, po_w = 0.0;
-  for (int i = 1 + lane; i < d; i += kWave) {
-    const double v = ld(i), e = ef(i);
+  each([&](int, double v, double e) {
     in_w += (v / e) * (v / e);
     po_w += (v * e) * (v * e);
-  }
+  });
   in_w = wave_sum(in_w);
   po_w = wave_sum(po_w);
   if (sqrt(in_w) <= v0 / e0) {
-    for (int i = lane; i < d; i += kWave) st(i, ld(i));
+    if (lane == 0) st(0, v0);
+    each([&](int i, double v, double) { st(i, v); });
     return;
   }
   if (sqrt(po_w) <= -v0 * e0) {
-    for (int i = lane; i < d; i += kWave) st(i, 0.0);
+    if (lane == 0) st(0, 0.0);
+    each([&](int i, double, double) { st(i, 0.0); });
     return;
   }
   const double ie02 = 1.0 / (e0 * e0);
   double lo = fmax(0.0, -v0 * e0), hi = fmax(lo, sqrt(po_w));
-  double mu = lo;
+  // phi = 1 - F^-1/2 is < 0 at lo and >= 0 at hi; a Newton step that leaves
+  // the bracket is replaced by the secant step of phi over it (bisection while
+  // phi is unknown at an end), and one that lands within rounding of an end
+  // (the root sits at that end) ends the search there
+  double mu = lo, flo = NAN, fhi = NAN;
+#pragma unroll 1
   for (int it = 0; it < 200; ++it) {
     const double sv = v0 / e0 + mu * ie02;
-    double f = 0.0, df = 0.0;
-    for (int i = 1 + lane; i < d; i += kWave) {
-      const double v = ld(i), e = ef(i), e2 = e * e;
+    double F = 0.0, dF = 0.0;
+    each([&](int, double v, double e) {
+      const double e2 = e * e;
       const double den = e2 * sv + mu, q = v * v * e2;
       if (q > 0.0) {  // (a zero term stays zero at den = 0, which mu = 0 with v_0 = 0 gives)
-        f += q / (den * den);
-        df -= 2.0 * q * (e2 * ie02 + 1.0) / (den * den * den);
+        F += q / (den * den);
+        dF -= 2.0 * q * (e2 * ie02 + 1.0) / (den * den * den);
       }
+    });
+    F = wave_sum(F);
+    dF = wave_sum(dF);
+    const double rs = 1.0 / sqrt(F);
+    const double phi = 1.0 - rs;
+    if (F > 1.0) lo = mu, flo = phi;
+    else hi = mu, fhi = phi;
+    if (F == 1.0 || !(hi > lo) || hi - lo <= 4e-16 * hi) break;
+    double next = mu - 2.0 * phi / (rs * rs * rs * dF);
+    if (!(next > lo && next < hi)) {
+      if (fabs(next - lo) <= 4e-16 * lo) {
+        mu = lo;
+        break;
+      }
+      if (fabs(next - hi) <= 4e-16 * hi) {
+        mu = hi;
+        break;
+      }
+      next = (flo == flo && fhi == fhi) ? lo - flo * (hi - lo) / (fhi - flo) : 0.5 * (lo + hi);
+      if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
     }
-    f = wave_sum(f) - 1.0;
-    df = wave_sum(df);
-    if (f > 0.0) lo = mu;
-    else hi = mu;
-    if (f == 0.0 || !(hi > lo)) break;
-    double next = mu - f / df;
-    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
     if (fabs(next - mu) <= 4e-16 * next) {
       mu = next;
       break;
@@ -89,14 +127,11 @@ __device__ __forceinline__ void wave_proj_soc(int d, const LD& ld, const EF& ef,
     mu = next;
   }
   const double sv = v0 / e0 + mu * ie02;
-  for (int i = lane; i < d; i += kWave) {
-    if (i == 0) {
-      st(0, e0 * sv);
-    } else {
-      const double v = ld(i), e = ef(i), e2 = e * e;
-      st(i, v * e2 * sv / (e2 * sv + mu));
-    }
-  }
+  if (lane == 0) st(0, e0 * sv);
+  each([&](int i, double v, double e) {
+    const double e2 = e * e;
+    st(i, v * e2 * sv / (e2 * sv + mu));
+  });
 }
 
 // ===========================================================================
@@ -112,6 +147,13 @@ __device__ __forceinline__ bool exp_cone_has(double x, double y, double z) {
 __device__ __forceinline__ bool exp_dual_has(double u, double v, double w) {
   if (u < 0.0) return w > 0.0 && log(-u) + v / u <= 1.0 + log(w);
   return u == 0.0 && v >= 0.0 && w >= 0.0;
+}
+
+// (u, v, w) in K_exp* up to 1e-15 of its size (rounding).
+__device__ __forceinline__ bool exp_dual_near(double u, double v, double w) {
+  const double sc = 1e-15 * (fabs(u) + fabs(v) + fabs(w));
+  if (u < -sc) return -u * exp(v / u) <= M_E * w + sc;
+  return v >= -sc && w >= -sc;
 }
 
 // A point to project onto F K_exp: v, f and 1 / f.
@@ -137,8 +179,29 @@ __device__ __forceinline__ double exp_ray_turn(double r, double E, double iE, co
   return P.v[0] * (a1 * m2 - a2 * m1) + P.v[1] * (a2 * m0 - a0 * m2) + P.v[2] * (a0 * m1 - a1 * m0);
 }
 
-__device__ __forceinline__ double exp_ray_turn(double r, const ExpPoint& P) {
-  return exp_ray_turn(r, exp(r), exp(-r), P);
+// The slope t at r (one exp), its derivative dt and the size sc of the terms
+// summed into t (|t| <= 1e-15 sc is rounding noise: r is a root).
+__device__ __forceinline__ void exp_ray_turn_d(double r, const ExpPoint& P, double& t, double& dt, double& sc) {
+  double a0, a1, a2, m0, m1, m2, da0, da1, da2, dm0, dm1, dm2;
+  if (r <= 0.0) {
+    const double E = exp(r);
+    a0 = P.f[0] * r, a1 = P.f[1], a2 = P.f[2] * E;
+    m0 = -E * P.fi[0], m1 = E * (r - 1.0) * P.fi[1], m2 = P.fi[2];
+    da0 = P.f[0], da1 = 0.0, da2 = a2;
+    dm0 = m0, dm1 = E * r * P.fi[1], dm2 = 0.0;
+  } else {  // both vectors times e^-r: the derivative of t e^-2r, whose sign change is the same
+    const double iE = exp(-r);
+    a0 = P.f[0] * r * iE, a1 = P.f[1] * iE, a2 = P.f[2];
+    m0 = -P.fi[0], m1 = (r - 1.0) * P.fi[1], m2 = iE * P.fi[2];
+    da0 = P.f[0] * (1.0 - r) * iE, da1 = -a1, da2 = 0.0;
+    dm0 = 0.0, dm1 = P.fi[1], dm2 = -m2;
+  }
+  const double c0 = a1 * m2 - a2 * m1, c1 = a2 * m0 - a0 * m2, c2 = a0 * m1 - a1 * m0;
+  t = P.v[0] * c0 + P.v[1] * c1 + P.v[2] * c2;
+  sc = fabs(P.v[0]) * (fabs(a1 * m2) + fabs(a2 * m1)) + fabs(P.v[1]) * (fabs(a2 * m0) + fabs(a0 * m2)) +
+       fabs(P.v[2]) * (fabs(a0 * m1) + fabs(a1 * m0));
+  dt = P.v[0] * (da1 * m2 - da2 * m1 + a1 * dm2 - a2 * dm1) + P.v[1] * (da2 * m0 - da0 * m2 + a2 * dm0 - a0 * dm2) +
+       P.v[2] * (da0 * m1 - da1 * m0 + a0 * dm1 - a1 * dm0);
 }
 
 // Candidate on the ray of r: the nearest point s F a(r), s = <F a, v> / |F a|^2,
@@ -167,8 +230,10 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
 // width h from r = -32 C h, every + to - sign change of the slope is refined
 // to full precision and its candidate kept (exp_ray_candidate).  e^r runs by
 // multiplication along a lane's cells (the refinement uses exp itself).
-template <int C>
-__device__ __forceinline__ void exp_scan(double h, const ExpPoint& P, double& bd, double (&b)[3], bool& cert) {
+// (Loops are kept rolled throughout: the projection's code is fetched into
+// the instruction cache at every launch that uses it.)
+__device__ __forceinline__ void exp_scan(int C, double h, const ExpPoint& P, double& bd, double (&b)[3],
+                                         bool& cert) {
   const int lane = threadIdx.x & (kWave - 1);
   const double r_first = -0.5 * kWave * C * h;
   const double g = exp(h), ig = exp(-h);
@@ -176,33 +241,32 @@ __device__ __forceinline__ void exp_scan(double h, const ExpPoint& P, double& bd
   double lo = r_first + k * h;
   double E = exp(lo), iE = exp(-lo);
   double t_lo = exp_ray_turn(lo, E, iE, P);
+#pragma unroll 1
   for (int c = 0; c < C; ++c) {
     ++k;
     const double hi = r_first + k * h;
     E *= g, iE *= ig;
     const double t_hi = exp_ray_turn(hi, E, iE, P);
     if (t_lo > 0.0 && t_hi <= 0.0) {
-      // the bracket [x, z] (slope > 0 at x, <= 0 at z) shrunk to adjacent
-      // doubles: regula falsi with the Illinois halving of a stale end, every
-      // fourth step a bisection
-      double x = lo, z = hi, tx = t_lo, tz = t_hi;
-      int side = 0;
-      for (int it = 0; it < 160 && tz != 0.0; ++it) {
-        double m = (it & 3) == 3 ? 0.5 * (x + z) : (x * tz - z * tx) / (tz - tx);
-        if (!(m > x && m < z)) m = 0.5 * (x + z);
-        if (!(m > x && m < z)) break;
-        const double tm = exp_ray_turn(m, P);
-        if (tm > 0.0) {
-          x = m, tx = tm;
-          if (side == 1) tz *= 0.5;
-          side = 1;
-        } else {
-          z = m, tz = tm;
-          if (side == -1) tx *= 0.5;
-          side = -1;
-        }
+      // Newton steps from the secant point of the cell, kept inside the
+      // bracket [x, z] (slope > 0 at x, <= 0 at z; bisection when a step
+      // leaves it), until the slope is rounding noise
+      double x = lo, z = hi;
+      double r = (lo * t_hi - hi * t_lo) / (t_hi - t_lo);
+      if (!(r > x && r < z)) r = 0.5 * (x + z);
+#pragma unroll 1
+      for (int it = 0; it < 100; ++it) {
+        double t, dt, sc;
+        exp_ray_turn_d(r, P, t, dt, sc);
+        if (fabs(t) <= 1e-15 * sc) break;
+        if (t > 0.0) x = r;
+        else z = r;
+        double nr = r - t / dt;
+        if (!(nr > x && nr < z)) nr = 0.5 * (x + z);
+        if (!(nr > x && nr < z)) break;
+        r = nr;
       }
-      exp_ray_candidate(tz == 0.0 ? z : 0.5 * (x + z), P, bd, b, cert);
+      exp_ray_candidate(r, P, bd, b, cert);
     }
     lo = hi;
     t_lo = t_hi;
@@ -230,7 +294,9 @@ __device__ __forceinline__ bool exp_wave_pick(double bd, const double (&b)[3], b
 // Projection of v onto F K_exp, F = diag(f) > 0, by one wave (every lane gets
 // the result).  v itself if v / f is in K_exp; 0 if -F v is in K_exp* (the
 // polar cone); the clip onto the face {(x, 0, z): x <= 0, z >= 0} if -F times
-// its residual is in K_exp*; otherwise the nearest of the face's clip and the
+// its residual is in K_exp* up to rounding (then the clip is within rounding
+// of the projection: this takes the points whose projection lies on a ray
+// so far out that it meets the face's edge to working precision); otherwise the nearest of the face's clip and the
 // best points of the rays s F a(r): the local maxima of the angle along the
 // rays (+ to - sign changes of exp_ray_turn) and, for rays below the scanned
 // range, whose third coordinate is then below e^-300 of the others, the ray
@@ -241,7 +307,7 @@ __device__ __forceinline__ bool exp_wave_pick(double bd, const double (&b)[3], b
 // scanned range the rays lie within e^-300 of the face's edge (0, 0, 1).
 constexpr double kExpTail = -300.0;
 
-__device__ __noinline__ void exp_proj_wave(const double (&v)[3], const double (&f)[3], double (&p)[3]) {
+__device__ __forceinline__ void exp_proj_wave(const double (&v)[3], const double (&f)[3], double (&p)[3]) {
   ExpPoint P;
   for (int i = 0; i < 3; ++i) P.v[i] = v[i], P.f[i] = f[i], P.fi[i] = 1.0 / f[i];
   if (exp_cone_has(v[0] / f[0], v[1] / f[1], v[2] / f[2])) {
@@ -253,22 +319,21 @@ __device__ __noinline__ void exp_proj_wave(const double (&v)[3], const double (&
     return;
   }
   const double face[3] = {fmin(v[0], 0.0), 0.0, fmax(v[2], 0.0)};
-  if (exp_dual_has(-f[0] * (v[0] - face[0]), -f[1] * v[1], -f[2] * (v[2] - face[2]))) {
+  if (exp_dual_near(-f[0] * (v[0] - face[0]), -f[1] * v[1], -f[2] * (v[2] - face[2]))) {
     p[0] = face[0], p[1] = face[1], p[2] = face[2];
     return;
   }
   const double face_d = (v[0] - face[0]) * (v[0] - face[0]) + v[1] * v[1] + (v[2] - face[2]) * (v[2] - face[2]);
   const bool tail = v[0] < 0.0 && v[1] > 0.0 && (v[0] * P.fi[0]) / (v[1] * P.fi[1]) < kExpTail;
   const int lane = threadIdx.x & (kWave - 1);
-  double bd = face_d, b[3] = {face[0], face[1], face[2]};
-  bool cert = false;
-  if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b, cert);
-  exp_scan<24>(0.4, P, bd, b, cert);
-  if (exp_wave_pick(bd, b, cert, p)) return;
-  bd = face_d, b[0] = face[0], b[1] = face[1], b[2] = face[2];
-  if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b, cert);
-  exp_scan<188>(0.05, P, bd, b, cert);
-  exp_wave_pick(bd, b, true, p);
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {  // coarse, then fine
+    double bd = face_d, b[3] = {face[0], face[1], face[2]};
+    bool cert = false;
+    if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b, cert);
+    exp_scan(pass == 0 ? 24 : 188, pass == 0 ? 0.4 : 0.05, P, bd, b, cert);
+    if (exp_wave_pick(bd, b, pass == 0 ? cert : true, p)) return;
+  }
 }
 
 // Projection of a 3-row block onto F K_exp (dual = false) or onto F K_exp*
@@ -279,17 +344,12 @@ template <class LD, class EF, class ST>
 __device__ __forceinline__ void wave_proj_exp(bool dual, const LD& ld, const EF& ef, const ST& st) {
   const int lane = threadIdx.x & (kWave - 1);
   const double v[3] = {ld(0), ld(1), ld(2)};
-  double p[3];
-  if (!dual) {
-    const double f[3] = {ef(0), ef(1), ef(2)};
-    exp_proj_wave(v, f, p);
-  } else {
-    const double w[3] = {-v[0], -v[1], -v[2]};
-    const double g[3] = {1.0 / ef(0), 1.0 / ef(1), 1.0 / ef(2)};
-    double q[3];
-    exp_proj_wave(w, g, q);
-    p[0] = v[0] + q[0], p[1] = v[1] + q[1], p[2] = v[2] + q[2];
-  }
+  const double f[3] = {ef(0), ef(1), ef(2)};
+  const double w[3] = {dual ? -v[0] : v[0], dual ? -v[1] : v[1], dual ? -v[2] : v[2]};
+  const double g[3] = {dual ? 1.0 / f[0] : f[0], dual ? 1.0 / f[1] : f[1], dual ? 1.0 / f[2] : f[2]};
+  double q[3];
+  exp_proj_wave(w, g, q);
+  const double p[3] = {dual ? v[0] + q[0] : q[0], dual ? v[1] + q[1] : q[1], dual ? v[2] + q[2] : q[2]};
   if (lane < 3) st(lane, lane == 0 ? p[0] : (lane == 1 ? p[1] : p[2]));
 }
 
@@ -696,26 +756,34 @@ __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restri
   if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
     __syncthreads();  // the blocks' unprojected values and committed iterates are in memory
     for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
-      // y_hat = Proj onto diag(1/D1) of the block's dual cone of the stored value, with the line-search terms
-      wave_proj_cone(
-          kind, true, dim, [&](int i) { return (double)it.yh[r0 + i]; }, [&](int i) { return 1.0 / D1[r0 + i]; },
-          [&](int i, double p) {
-            const int r = r0 + i;
-            const double yn = (double)(T)p;
-            it.yh[r] = (T)yn;
-            const double dy = yn - (double)it.y[r];
-            acc[0] += dy * dy;
-            acc[1] += dy * ((double)it.gxh[r] - (double)it.gx[r]);
-            acc[3] += (double)d.h[r] * yn;
-          });
-      // primal residual of the reflection parameter: (G x_hat - h) against diag(D1) of the block's cone
-      wave_proj_cone(
-          kind, false, dim, [&](int i) { return (double)it.gxh[r0 + i] - (double)d.h[r0 + i]; },
-          [&](int i) { return D1[r0 + i]; },
-          [&](int i, double p) {
-            const double pr = ((double)it.gxh[r0 + i] - (double)d.h[r0 + i]) - p;
-            acc[2] += pr * pr;
-          });
+      // pass 0: y_hat = Proj onto diag(1/D1) of the block's dual cone of the
+      // stored value, with the line-search terms; pass 1: the primal residual
+      // of the reflection parameter, (G x_hat - h) against diag(D1) of the
+      // block's cone (one inlined projection for both)
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool dual = pass == 0;
+        wave_proj_cone(
+            kind, dual, dim,
+            [&](int i) {
+              return dual ? (double)it.yh[r0 + i] : (double)it.gxh[r0 + i] - (double)d.h[r0 + i];
+            },
+            [&](int i) { return dual ? 1.0 / D1[r0 + i] : D1[r0 + i]; },
+            [&](int i, double p) {
+              const int r = r0 + i;
+              if (dual) {
+                const double yn = (double)(T)p;
+                it.yh[r] = (T)yn;
+                const double dy = yn - (double)it.y[r];
+                acc[0] += dy * dy;
+                acc[1] += dy * ((double)it.gxh[r] - (double)it.gx[r]);
+                acc[3] += (double)d.h[r] * yn;
+              } else {
+                const double pr = ((double)it.gxh[r] - (double)d.h[r]) - p;
+                acc[2] += pr * pr;
+              }
+            });
+      }
     });
   }
   block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
@@ -1338,32 +1406,49 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
   // cone blocks: the same terms, with the residual r = G x - h projected onto
   // diag(D1) of the block's cone for the scaled L2 term and, unscaled (r / D1),
   // onto the cone itself for the infinity-norm termination terms
+  // (candidate q and the scaled / unscaled projection run at run time, with
+  // one inlined projection; the terms go to acc through compile-time indices)
   for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+#pragma unroll 1
     for (int q = 0; q < nc; ++q) {
       const T* yq = q == 0 ? y0 : y1;
       const double* gq = q == 0 ? g0 : g1;
+      double t[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // sums 0..3 as acc[q*4+i], maxima 4..6 as acc[8+q*3+i-4]
       for (int i = (int)(threadIdx.x & (kWave - 1)); i < dim; i += kWave) {
         const int r = r0 + i;
         const double yc = (double)yq[r], gx = gq[r], h = d.h[r];
         const double dya = yc - (double)ya[r], res = gx - h;
-        acc[q * 4 + 0] += dya * dya;
-        acc[q * 4 + 1] += res * res;
-        acc[q * 4 + 3] += h * yc;
-        acc[8 + q * 3 + 1] = fmax(acc[8 + q * 3 + 1], fabs(gx) / D1[r]);
+        t[0] += dya * dya;
+        t[1] += res * res;
+        t[3] += h * yc;
+        t[5] = fmax(t[5], fabs(gx) / D1[r]);
       }
-      wave_proj_cone(
-          kind, false, dim, [&](int i) { return gq[r0 + i] - d.h[r0 + i]; }, [&](int i) { return D1[r0 + i]; },
-          [&](int i, double p) {
-            const double pr = (gq[r0 + i] - d.h[r0 + i]) - p;
-            acc[q * 4 + 2] += pr * pr;
-          });
-      wave_proj_cone(
-          kind, false, dim, [&](int i) { return (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; }, [](int) { return 1.0; },
-          [&](int i, double p) {
-            const double ru = (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i];
-            acc[8 + q * 3 + 0] = fmax(acc[8 + q * 3 + 0], fabs(ru - p));
-            acc[8 + q * 3 + 2] = fmax(acc[8 + q * 3 + 2], fabs(p));
-          });
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool scaled = pass == 0;
+        wave_proj_cone(
+            kind, false, dim,
+            [&](int i) { return scaled ? gq[r0 + i] - d.h[r0 + i] : (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; },
+            [&](int i) { return scaled ? D1[r0 + i] : 1.0; },
+            [&](int i, double p) {
+              if (scaled) {
+                const double pr = (gq[r0 + i] - d.h[r0 + i]) - p;
+                t[2] += pr * pr;
+              } else {
+                const double ru = (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i];
+                t[4] = fmax(t[4], fabs(ru - p));
+                t[6] = fmax(t[6], fabs(p));
+              }
+            });
+      }
+#pragma unroll
+      for (int qq = 0; qq < kMaxCand; ++qq) {
+        if (qq != q) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[qq * 4 + i] += t[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[8 + qq * 3 + i] = fmax(acc[8 + qq * 3 + i], t[4 + i]);
+      }
     }
   });
   block_summax_store<kCandRowsNV, kCandRowsNS>(acc, lds, rec + (size_t)b * kCandRowsNV);
@@ -1514,25 +1599,39 @@ __device__ __forceinline__ void probe_rows_body(int b, int q, const Ranges& R, c
       acc[p * 2 + 1] += b2 * dy;
     }
   }
-  // cone blocks: y(t) = Proj onto diag(1/D1) (dual cone) of y + t sigma b2, per probe
-  for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+  // cone blocks: y(t) = Proj onto diag(1/D1) (dual cone) of y + t sigma b2, per
+  // probe.  The probe index runs at run time here (one inlined projection);
+  // each wave's sums go to its own LDS slots and join acc in its lane 0.
+  if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
+    __shared__ double cone_acc[kWavesPerBlock][kProbeNV];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (int i = lane; i < kProbeNV; i += kWave) cone_acc[wave][i] = 0.0;
+    for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
+      for (int p = 0; p < kProbes; ++p) {
+        const double tp = probe_t(C, p) * sigma;
+        double dd = 0.0, bd = 0.0;
+        wave_proj_cone(
+            kind, true, dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
+            [&](int i) { return 1.0 / D1[r0 + i]; },
+            [&](int i, double pv) {
+              const double yc = (double)ys[r0 + i];
+              const double dy = pv - yc;
+              dd += dy * dy;
+              bd += (d.h[r0 + i] - gs[r0 + i]) * dy;
+            });
+        dd = wave_sum(dd);
+        bd = wave_sum(bd);
+        if (lane == 0) {
+          cone_acc[wave][p * 2 + 0] += dd * inv_sigma;
+          cone_acc[wave][p * 2 + 1] += bd;
+        }
+      }
+    });
+    if (lane == 0) {
 #pragma unroll
-    for (int p = 0; p < kProbes; ++p) {
-      const double tp = tq[p];
-      double dd = 0.0, bd = 0.0;
-      wave_proj_cone(
-          kind, true, dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
-          [&](int i) { return 1.0 / D1[r0 + i]; },
-          [&](int i, double pv) {
-            const double yc = (double)ys[r0 + i];
-            const double dy = pv - yc;
-            dd += dy * dy;
-            bd += (d.h[r0 + i] - gs[r0 + i]) * dy;
-          });
-      acc[p * 2 + 0] += dd * inv_sigma;
-      acc[p * 2 + 1] += bd;
+      for (int i = 0; i < kProbeNV; ++i) acc[i] += cone_acc[wave][i];
     }
-  });
+  }
   block_sum_store<kProbeNV>(acc, lds, rec + ((size_t)q * R.nblk + b) * kProbeNV);
 }
 
