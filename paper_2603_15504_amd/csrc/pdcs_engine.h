@@ -100,6 +100,7 @@ struct RangeSet {
   int nblk = 0;
   std::vector<int32_t> h_iblk0;  // host copy: instance -> first block
   const SocTable* soc = nullptr;  // set for row ranges that must not split cone blocks
+  int cone_cap = 1;               // at most this many cone blocks per range
   void build(const std::vector<int64_t>& inst_off, int per_block, const std::vector<char>* active = nullptr);
   Ranges view() const;
 };

@@ -336,10 +336,10 @@ void RangeSet::build(const std::vector<int64_t>& inst_off, int per_block, const 
       if (cones) {
         // a range ends at a cone block boundary: blocks starting inside it are
         // taken whole, and a range that reaches a block's rows takes the block;
-        // a range holds at most kConeBlocksPerRange blocks (each wave of its
-        // workgroup projects one), so that the blocks spread over workgroups
+        // a range holds at most cone_cap blocks, so that the blocks' tasks
+        // spread over the waves of many workgroups
         while (q < soc->r0.size() && soc->r0[q] < e && soc->r0[q] < stop) {
-          if (q - q0 == (size_t)kConeBlocksPerRange) {
+          if (q - q0 == (size_t)cone_cap) {
             e = soc->r0[q];
             break;
           }
@@ -848,6 +848,7 @@ void Engine::build_iteration_schedules(const std::vector<char>* active) {
   tcol.build(h_cp, col0, sched, active);
   brow.build(h_rp, row0, sched.iter_max * 4, active);
   bcol.build(h_cp, col0, sched.iter_max * 4, active);
+  vrow.cone_cap = kConeBlocksPerRange;
   vrow.build(row0, sched.vec_per_block, active);
   vcol.build(col0, sched.vec_per_block, active);
   // The multisection passes reduce 32 values per element into per-workgroup
@@ -861,6 +862,7 @@ void Engine::build_iteration_schedules(const std::vector<char>* active) {
     const int64_t f = std::max<int64_t>(1, std::min<int64_t>(kCheckCoarsen, total / (256 * (int64_t)sched.vec_per_block)));
     return (int)(sched.vec_per_block * f);
   };
+  crow.cone_cap = kConeBlocksPerCheckRange;
   crow.build(row0, check_block(row0), active);
   ccol.build(col0, check_block(col0), active);
 }

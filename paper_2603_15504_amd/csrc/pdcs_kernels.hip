@@ -366,14 +366,25 @@ __device__ __forceinline__ void wave_proj_cone(int kind, bool dual_site, int d, 
   else wave_proj_exp((kind == kConeExp) == dual_site, ld, ef, st);
 }
 
-// The cone blocks of row range b are handled by the waves of its workgroup,
-// block q by wave (q - first) mod kWavesPerBlock; fn(first row, dimension, kind).
-template <class FN>
-__device__ __forceinline__ void for_cone_blocks(const Ranges& R, int b, const FN& fn) {
+// The cone blocks of row range b, each with S independent tasks (sub = 0 ..
+// S - 1), are handled by the waves of its workgroup: task j of the range
+// (block j / S, sub j mod S) by wave j mod kWavesPerBlock;
+// fn(first row, dimension, kind, sub).
+template <int S, class FN>
+__device__ __forceinline__ void for_cone_tasks(const Ranges& R, int b, const FN& fn) {
   if (!R.blk_soc0) return;
   const int wave = threadIdx.x / kWave;
-  const int q0 = R.blk_soc0[b], q1 = R.blk_soc1[b];
-  for (int q = q0 + wave; q < q1; q += kWavesPerBlock) fn(R.soc_r0[q], R.soc_dim[q], (int)R.soc_kind[q]);
+  const int q0 = R.blk_soc0[b], n = (R.blk_soc1[b] - q0) * S;
+#pragma unroll 1
+  for (int j = wave; j < n; j += kWavesPerBlock) {
+    const int q = q0 + j / S;
+    fn(R.soc_r0[q], R.soc_dim[q], (int)R.soc_kind[q], j % S);
+  }
+}
+
+template <class FN>
+__device__ __forceinline__ void for_cone_blocks(const Ranges& R, int b, const FN& fn) {
+  for_cone_tasks<1>(R, b, [&](int r0, int dim, int kind, int) { fn(r0, dim, kind); });
 }
 
 // Projection of count vectors of dimension dim (v, f and out: dim doubles
@@ -755,13 +766,12 @@ __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restri
   }
   if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
     __syncthreads();  // the blocks' unprojected values and committed iterates are in memory
-    for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
-      // pass 0: y_hat = Proj onto diag(1/D1) of the block's dual cone of the
-      // stored value, with the line-search terms; pass 1: the primal residual
-      // of the reflection parameter, (G x_hat - h) against diag(D1) of the
-      // block's cone (one inlined projection for both)
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
+    // task 0: y_hat = Proj onto diag(1/D1) of the block's dual cone of the
+    // stored value, with the line-search terms; task 1: the primal residual
+    // of the reflection parameter, (G x_hat - h) against diag(D1) of the
+    // block's cone (independent: task 1 reads neither y nor y_hat)
+    for_cone_tasks<2>(R, b, [&](int r0, int dim, int kind, int pass) {
+      {
         const bool dual = pass == 0;
         wave_proj_cone(
             kind, dual, dim,
@@ -1406,25 +1416,27 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
   // cone blocks: the same terms, with the residual r = G x - h projected onto
   // diag(D1) of the block's cone for the scaled L2 term and, unscaled (r / D1),
   // onto the cone itself for the infinity-norm termination terms
-  // (candidate q and the scaled / unscaled projection run at run time, with
-  // one inlined projection; the terms go to acc through compile-time indices)
-  for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
-#pragma unroll 1
-    for (int q = 0; q < nc; ++q) {
+  // (one task per block, candidate q and scaled / unscaled projection, spread
+  // over the waves, with one inlined projection; the terms go to acc through
+  // compile-time indices)
+  for_cone_tasks<2 * kMaxCand>(R, b, [&](int r0, int dim, int kind, int task) {
+    const int q = task >> 1, pass = task & 1;
+    if (q < nc) {
       const T* yq = q == 0 ? y0 : y1;
       const double* gq = q == 0 ? g0 : g1;
       double t[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // sums 0..3 as acc[q*4+i], maxima 4..6 as acc[8+q*3+i-4]
-      for (int i = (int)(threadIdx.x & (kWave - 1)); i < dim; i += kWave) {
-        const int r = r0 + i;
-        const double yc = (double)yq[r], gx = gq[r], h = d.h[r];
-        const double dya = yc - (double)ya[r], res = gx - h;
-        t[0] += dya * dya;
-        t[1] += res * res;
-        t[3] += h * yc;
-        t[5] = fmax(t[5], fabs(gx) / D1[r]);
+      if (pass == 0) {
+        for (int i = (int)(threadIdx.x & (kWave - 1)); i < dim; i += kWave) {
+          const int r = r0 + i;
+          const double yc = (double)yq[r], gx = gq[r], h = d.h[r];
+          const double dya = yc - (double)ya[r], res = gx - h;
+          t[0] += dya * dya;
+          t[1] += res * res;
+          t[3] += h * yc;
+          t[5] = fmax(t[5], fabs(gx) / D1[r]);
+        }
       }
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
+      {
         const bool scaled = pass == 0;
         wave_proj_cone(
             kind, false, dim,
@@ -1599,15 +1611,15 @@ __device__ __forceinline__ void probe_rows_body(int b, int q, const Ranges& R, c
       acc[p * 2 + 1] += b2 * dy;
     }
   }
-  // cone blocks: y(t) = Proj onto diag(1/D1) (dual cone) of y + t sigma b2, per
-  // probe.  The probe index runs at run time here (one inlined projection);
+  // cone blocks: y(t) = Proj onto diag(1/D1) (dual cone) of y + t sigma b2, one
+  // task per block and probe spread over the waves (one inlined projection);
   // each wave's sums go to its own LDS slots and join acc in its lane 0.
   if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
     __shared__ double cone_acc[kWavesPerBlock][kProbeNV];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     for (int i = lane; i < kProbeNV; i += kWave) cone_acc[wave][i] = 0.0;
-    for_cone_blocks(R, b, [&](int r0, int dim, int kind) {
-      for (int p = 0; p < kProbes; ++p) {
+    for_cone_tasks<kProbes>(R, b, [&](int r0, int dim, int kind, int p) {
+      {
         const double tp = probe_t(C, p) * sigma;
         double dd = 0.0, bd = 0.0;
         wave_proj_cone(

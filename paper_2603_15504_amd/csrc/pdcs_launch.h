@@ -40,8 +40,11 @@ struct MatPtrs {
 // Longest row or column for the row-wise passes of k_trials_lds.
 constexpr int kLdsRowMax = 64;
 
-// Cone blocks per row range of the elementwise passes: one per wave.
-constexpr int kConeBlocksPerRange = kWavesPerBlock;
+// Cone blocks per row range: in the elementwise passes (two projections per
+// block in the dual epilogue: one per wave), and in the restart checks (one
+// block, its multisection probes or candidate terms spread over the waves).
+constexpr int kConeBlocksPerRange = kWavesPerBlock / 2;
+constexpr int kConeBlocksPerCheckRange = 1;
 
 // LDS footprint of one instance in k_trials_lds: the 14 iterate vectors the
 // trials touch, c, l, u, h, both CSR copies of the instance's part of G and
