@@ -723,9 +723,12 @@ struct pdcs_mlp_s {
     const int gx = (N + TN - 1) / TN, gy = (M + TM - 1) / TM;
     const int tiles = gx * gy;
     if (kind == EPI_ADAM) e.vec4 = adam_vec4(e, N);
+    // (products of a few tiles split down to K-ranges of 128: a handful of
+    // workgroups walking the whole K serially would leave the chip idle)
     int splits = 1;
+    const int min_range = tiles < 64 ? 128 : 512;
     if (kind == EPI_STORE || kind == EPI_ACT)
-      while (tiles * splits < 512 && K / (splits * 2) >= 512) splits *= 2;
+      while (tiles * splits < 512 && K / (splits * 2) >= min_range) splits *= 2;
     int kchunk = (K + splits - 1) / splits;
     const int kt = kchunk >= 512 ? 128 : (kchunk >= 128 ? 64 : 32);
     kchunk = (kchunk + kt - 1) / kt * kt;
