@@ -716,8 +716,9 @@ struct pdcs_mlp_s {
   // op(A)[M x K] op(B)[K x N] with epilogue `kind`.  Products whose output tiles
   // alone cannot fill the chip are split along K (EPI_STORE / EPI_ACT only);
   // the partials are then summed in a fixed order.  EPI_STORE writes e.out32.
-  // The tile depth grows with the K-range of a workgroup: each step of the
-  // K-loop costs about one memory latency, so long ranges take deep steps.
+  // The tile depth is 64 for K-ranges of 128 or more (128-deep tiles halve the
+  // steps of long ranges but double the LDS, and measured 2% slower per step
+  // at batch 256), 32 below.
   void gemm(int kind, const bf16* A, int lda, int ta, const bf16* Bm, int ldb, int tb, int M, int N, int K,
             Epi e, hipStream_t s) {
     const int gx = (N + TN - 1) / TN, gy = (M + TM - 1) / TM;
@@ -730,7 +731,7 @@ struct pdcs_mlp_s {
     if (kind == EPI_STORE || kind == EPI_ACT)
       while (tiles * splits < 512 && K / (splits * 2) >= min_range) splits *= 2;
     int kchunk = (K + splits - 1) / splits;
-    const int kt = kchunk >= 512 ? 128 : (kchunk >= 128 ? 64 : 32);
+    const int kt = kchunk >= 128 ? 64 : 32;
     kchunk = (kchunk + kt - 1) / kt * kt;
     splits = (K + kchunk - 1) / kchunk;
     if (splits < 1) splits = 1;
@@ -751,9 +752,7 @@ struct pdcs_mlp_s {
   static void launch_kt(int kt, dim3 grid, const bf16* A, int lda, int ta, int veca, const bf16* Bm, int ldb, int tb,
                         int vecb, float* C, int M, int N, int K, int gx, int gy, const Epi& e,
                         hipStream_t s) {
-    if (kt == 128)
-      k_gemm<KIND, 128><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e);
-    else if (kt == 64)
+    if (kt == 64)
       k_gemm<KIND, 64><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e);
     else
       k_gemm<KIND, 32><<<grid, 256, 0, s>>>(A, lda, ta, veca, Bm, ldb, tb, vecb, C, M, N, K, gx, gy, e);
