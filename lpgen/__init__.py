@@ -401,6 +401,15 @@ def infeasible_free_columns(seed: int = 0, m: int = 200, n: int = 500, free: int
     return inst
 
 
+def infeasible_exp_sum_row(seed: int = 0, **kw) -> LPInstance:
+    """exp_instance(seed, **kw) plus the equality row sum_j x_j = 100 n: beyond
+    reach of the box 0 <= x <= upper (the cone blocks stay the last rows)."""
+    base = exp_instance(seed, **kw)
+    inst = _with_rows(base, np.ones((1, base.n)), np.array([100.0 * base.n]), True, f"infeas_exp_s{seed}")
+    inst.soc, inst.n_exp, inst.n_dexp = base.soc, base.n_exp, base.n_dexp
+    return inst
+
+
 def infeasible_geq_pair(seed: int = 0, m: int = 200, n: int = 500) -> LPInstance:
     """C0 plus two ">=" rows a^T x >= 1 and -a^T x >= 1 (a ~ N(0,1)): contradictory."""
     base = c0_instance(seed, m, n)

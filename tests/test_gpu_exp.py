@@ -245,3 +245,22 @@ def test_cones_create_rejects_bad_blocks():
         with pytest.raises(P.PdcsError):
             P.Problem(inst.m, inst.n, inst.m_zero, inst.row_ptr, inst.col_idx, inst.val, inst.h, inst.c,
                       inst.l, inst.u, n_exp=n_exp, n_dexp=n_dexp)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_infeasible_exp_lp_exit_code_and_ratios_match_oracle(precision):
+    # an exponential-cone LP with an equality row beyond the box: the
+    # infeasibility rays cross the cone rows (projections onto K_exp and K_exp*)
+    inst = lpgen.infeasible_exp_sum_row(1)
+    ref = O.solve(O.lpdata_from_instance(inst), O.Options(max_iter=20000))
+    assert ref.exit_code == O.EXIT_PRIMAL_INFEASIBLE_HIGH_ACC and ref.iters == 64
+    sol = P.Problem.from_instance(inst).solve(precision=precision, max_iter=20000, time_limit=60.0, keep_state=True)
+    assert sol.info["exit_code"] == ref.exit_code and sol.info["iters"] == 64
+    if precision == "fp64":
+        c = ref.checks_log[0]
+        for key in ("ratio_p", "ratio_d"):
+            want, got = c[key], sol.state[key]
+            if math.isinf(want):
+                assert math.isinf(got), (key, got)
+            else:
+                assert got == pytest.approx(want, rel=1e-9, abs=1e-300), key
