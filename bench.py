@@ -30,7 +30,11 @@ Solves per second at relative KKT 1e-6 are measured on the batched workload
 same run and reported under config.solves: one batched mixed-precision solve,
 one batched FP64 solve, and a sample of unbatched FP64 solves extrapolated to
 the batch (labelled as such); the FP64 oracle's termination test re-checks a
-random sample of the returned (x, y).  --no-solves skips it.  The other
+random sample of the returned (x, y).  --no-solves skips it.  config.cones
+holds the conic LPs of the cones workload (exponential / dual-exponential
+and second-order cone rows) solved to 1e-6 in FP64 and mixed precision, each
+answer re-checked by the oracle's termination test; --no-cones skips it.  The
+other
 workloads run alone with --workload c0 | c2 | c3 | c3_mlp | c4 | cones (one
 JSON line each).
 
@@ -449,46 +453,70 @@ EXP_FLOPS_PER_PROJECTION = 64 * 24 * 22
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+def cone_instances():
+    import lpgen
+
+    return {"exp": lpgen.exp_instance(0, m_zero=2000, n=10000, m_nonneg=1000, n_exp=600, n_dexp=400),
+            "soc": lpgen.soc_instance(0, m_zero=2000, n=10000, blocks=(3,) * 600 + (9,) * 100 + (50,) * 10)}
+
+
+def cone_solves(P, np, insts, steps=1, warmup=0, cap=None, check=False):
+    """Each conic LP solved to relative KKT 1e-6 in FP64 and in mixed precision
+    (median wall time of `steps` solves after `warmup`); with `check`, the FP64
+    oracle's termination test of each returned (x, y)."""
+    res = {}
+    for name, inst in insts.items():
+        prob = P.Problem.from_instance(inst)
+        lp = None
+        for prec in ("fp64", "mixed"):
+            for _ in range(warmup):
+                prob.solve(precision=prec, time_limit=120.0, **(cap or {}))
+            walls, s = [], None
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                s = prob.solve(precision=prec, time_limit=120.0, **(cap or {}))
+                walls.append(time.perf_counter() - t0)
+            wall = float(np.median(walls))
+            r = {"seconds": round(wall, 4), "solves_per_s": round(1.0 / wall, 3), "trials": s.info["iters"],
+                 "us_per_trial": round(wall / s.info["iters"] * 1e6, 2), "status": s.info["status"]}
+            if check:
+                from oracle import pdcs_oracle as O
+
+                lp = lp or O.lpdata_from_instance(inst)
+                err = O.termination_errors(lp, s.x, s.y)
+                r["oracle_rel_kkt"] = float(max(err["rel_p"], err["rel_d"], err["rel_gap"]))
+            res[f"{name}_{prec}"] = r
+            log(f"cones {name} {prec}: m={inst.m} n={inst.n}: {wall * 1e3:.1f} ms per solve, {s.info['iters']} trials, "
+                f"{r['us_per_trial']} us per trial, {s.info['status']}"
+                + (f", oracle rel KKT {r['oracle_rel_kkt']:.2e}" if check else ""))
+    return res
+
+
+CONES_DESC = ("conic LPs to rel. KKT 1e-6: m=6000 n=1e4 with 600 exponential and 400 dual-exponential 3-row "
+              "blocks; m=5200 n=1e4 with 710 second-order-cone blocks")
+
+
 def run_cones(args, P, np):
     """Conic rows: an LP with exponential and dual-exponential cone blocks and
     one with second-order-cone blocks, each solved to relative KKT 1e-6 in
     FP64 and in mixed precision (a step is one solve of each); the
     exponential-cone projection kernel timed with HIP events on 2^18 random
     points and rescaling factors (its FP64 rate against the vector peak)."""
-    import lpgen
-
-    insts = {"exp": lpgen.exp_instance(0, m_zero=2000, n=10000, m_nonneg=1000, n_exp=600, n_dexp=400),
-             "soc": lpgen.soc_instance(0, m_zero=2000, n=10000, blocks=(3,) * 600 + (9,) * 100 + (50,) * 10)}
-    res = {}
+    insts = cone_instances()
     cap = {"max_iter": args.max_trials} if args.max_trials > 0 else {}  # bounded runs for kernel traces
-    for name, inst in insts.items():
-        prob = P.Problem.from_instance(inst)
-        for prec in ("fp64", "mixed"):
-            for _ in range(args.warmup):
-                prob.solve(precision=prec, time_limit=120.0, **cap)
-            walls, s = [], None
-            for _ in range(args.steps):
-                t0 = time.perf_counter()
-                s = prob.solve(precision=prec, time_limit=120.0, **cap)
-                walls.append(time.perf_counter() - t0)
-            wall = float(np.median(walls))
-            res[f"{name}_{prec}"] = {"seconds": round(wall, 4), "solves_per_s": round(1.0 / wall, 3),
-                                     "trials": s.info["iters"], "us_per_trial": round(wall / s.info["iters"] * 1e6, 2),
-                                     "status": s.info["status"]}
-            log(f"cones {name} {prec}: m={inst.m} n={inst.n}: {wall * 1e3:.1f} ms per solve, {s.info['iters']} trials, "
-                f"{res[f'{name}_{prec}']['us_per_trial']} us per trial, {s.info['status']}")
+    res = cone_solves(P, np, insts, args.steps, args.warmup, cap)
     rng = np.random.default_rng(0)
     cnt = 1 << 18
     v = rng.standard_normal((cnt, 3)) * rng.uniform(0.1, 10, size=(cnt, 1))
     f = np.exp(rng.uniform(-2, 2, size=(cnt, 3)))
-    P.pdcs_project_exp(0, v[:4096], f[:4096])
-    times = sorted(P.pdcs_project_exp(0, v, f, timed=True)[1] for _ in range(5))
+    P.pdcs_project_cone("exp", v[:4096], f[:4096])
+    times = sorted(P.pdcs_project_cone("exp", v, f, timed=True)[1] for _ in range(5))
     ms = times[len(times) // 2]
     tflops = EXP_FLOPS_PER_PROJECTION * cnt / (ms * 1e-3) / 1e12
     log(f"exp projection: {cnt} points in {ms:.3f} ms ({cnt / ms / 1e3:.1f} M/s), {tflops:.2f} TFLOP/s FP64")
     roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-            "kernel": "k_proj_exp: projection onto diag(f) K_exp, one wave per point, random points and factors",
+            "kernel": "k_proj_cone: projection onto diag(f) K_exp, one wave per point, random points and factors",
             "flops_per_projection": EXP_FLOPS_PER_PROJECTION, "points": cnt, "kernel_ms": round(ms, 4)}
     cpu = None
     if not args.no_cpu_baseline:
@@ -498,9 +526,8 @@ def run_cones(args, P, np):
                          "the GPU's FP64 trial count"}
     e = res["exp_fp64"]
     return common_fields(args, e["solves_per_s"], "solves/s", e["seconds"] * 1e3, "f64", {
-        "workload": "conic LPs to rel. KKT 1e-6: m=6000 n=1e4 with 600 exponential and 400 dual-exponential "
-                    "3-row blocks (value: FP64 solves/s); m=5200 n=1e4 with 710 second-order-cone blocks",
-        "solves": res}, {"roofline": roof, "cpu_baseline": cpu})
+        "workload": CONES_DESC + " (value: the exponential-cone LP's FP64 solves/s)", "solves": res},
+        {"roofline": roof, "cpu_baseline": cpu})
 
 
 def workload(name: str):
@@ -642,6 +669,7 @@ def main():
                     help="c1: launch the timed chunks eagerly with kernel events (default: hipGraph replay, "
                          "kernel events from a second solve)")
     ap.add_argument("--no-solves", action="store_true", help="c1: skip the batched solves/s record")
+    ap.add_argument("--no-cones", action="store_true", help="c1: skip the conic-LP solves record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build solves on one GPU only (the multi-GPU sharding is a design note); "
@@ -721,6 +749,8 @@ def main():
 
     if not args.no_solves:
         extras["solves"] = c2_solves(P, np)
+    if not args.no_cones:
+        extras["cones"] = {"workload": CONES_DESC, **cone_solves(P, np, cone_instances(), check=True)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -270,12 +270,6 @@ def pdcs_project_cone(cone, v, f, timed=False):
     return (out, ms.value) if timed else out
 
 
-def pdcs_project_exp(dual, v, f, timed=False):
-    """pdcs_project_cone onto diag(f) K_exp (dual=0) or diag(f) K_exp* (dual=1)."""
-    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
-    return pdcs_project_cone("exp_dual" if dual else "exp", v, f, timed)
-
-
 def pdcs_problem_destroy(p):
     lib.pdcs_problem_destroy(p)
 

@@ -209,8 +209,8 @@ __device__ __forceinline__ void exp_ray_turn_d(double r, const ExpPoint& P, doub
 // nearer and v - p is a nonpositive multiple of F^-1 n(r) (at a root of the
 // slope v - p is parallel to it): then -F (v - p) lies in K_exp*, p in F K_exp
 // and <p, v - p> = 0, which makes p the projection.
-__device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, double& bd, double (&b)[3],
-                                                  bool& cert) {
+__device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, double& bd, double& b0, double& b1,
+                                                  double& b2, bool& cert) {
   const double E = exp(r);
   const double q0 = P.f[0] * r, q1 = P.f[1], q2 = P.f[2] * E;
   const double s = (q0 * P.v[0] + q1 * P.v[1] + q2 * P.v[2]) / (q0 * q0 + q1 * q1 + q2 * q2);
@@ -219,7 +219,7 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
   const double d0 = P.v[0] - c0, d1 = P.v[1] - c1, d2 = P.v[2] - c2;
   const double d = d0 * d0 + d1 * d1 + d2 * d2;
   if (!(d < bd)) return;
-  bd = d, b[0] = c0, b[1] = c1, b[2] = c2;
+  bd = d, b0 = c0, b1 = c1, b2 = c2;
   // <v - p, F^-1 n(r) min(1, e^r)>
   const double w = r <= 0.0 ? -d0 * E * P.fi[0] + d1 * (r - 1.0) * E * P.fi[1] + d2 * P.fi[2]
                             : -d0 * P.fi[0] + d1 * (r - 1.0) * P.fi[1] + d2 * exp(-r) * P.fi[2];
@@ -232,8 +232,8 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
 // multiplication along a lane's cells (the refinement uses exp itself).
 // (Loops are kept rolled throughout: the projection's code is fetched into
 // the instruction cache at every launch that uses it.)
-__device__ __forceinline__ void exp_scan(int C, double h, const ExpPoint& P, double& bd, double (&b)[3],
-                                         bool& cert) {
+__device__ __forceinline__ void exp_scan(int C, double h, const ExpPoint& P, double& bd, double& b0, double& b1,
+                                         double& b2, bool& cert) {
   const int lane = threadIdx.x & (kWave - 1);
   const double r_first = -0.5 * kWave * C * h;
   const double g = exp(h), ig = exp(-h);
@@ -266,19 +266,19 @@ __device__ __forceinline__ void exp_scan(int C, double h, const ExpPoint& P, dou
         if (!(nr > x && nr < z)) break;
         r = nr;
       }
-      exp_ray_candidate(r, P, bd, b, cert);
+      exp_ray_candidate(r, P, bd, b0, b1, b2, cert);
     }
     lo = hi;
     t_lo = t_hi;
   }
 }
 
-// Nearest candidate over the wave (ties: the lowest lane); with `certified`,
-// only lanes holding a certified candidate take part.  Returns whether any did.
-__device__ __forceinline__ bool exp_wave_pick(double bd, const double (&b)[3], bool eligible, double (&p)[3]) {
+// Nearest candidate over the wave (ties: the lowest lane) among the lanes with
+// `eligible` set.  Returns whether any lane was eligible.
+__device__ __forceinline__ bool exp_wave_pick(double bd, double b0, double b1, double b2, bool eligible,
+                                              double (&p)[3]) {
   const int lane = threadIdx.x & (kWave - 1);
   double d = eligible ? bd : INFINITY;
-  double b0 = b[0], b1 = b[1], b2 = b[2];
   int who = eligible ? lane : kWave;
   for (int off = 1; off < kWave; off <<= 1) {
     const double od = __shfl_xor(d, off);
@@ -328,11 +328,11 @@ __device__ __forceinline__ void exp_proj_wave(const double (&v)[3], const double
   const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {  // coarse, then fine
-    double bd = face_d, b[3] = {face[0], face[1], face[2]};
+    double bd = face_d, b0 = face[0], b1 = face[1], b2 = face[2];
     bool cert = false;
-    if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b, cert);
-    exp_scan(pass == 0 ? 24 : 188, pass == 0 ? 0.4 : 0.05, P, bd, b, cert);
-    if (exp_wave_pick(bd, b, pass == 0 ? cert : true, p)) return;
+    if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b0, b1, b2, cert);
+    exp_scan(pass == 0 ? 24 : 188, pass == 0 ? 0.4 : 0.05, P, bd, b0, b1, b2, cert);
+    if (exp_wave_pick(bd, b0, b1, b2, pass == 0 ? cert : true, p)) return;
   }
 }
 
@@ -770,31 +770,34 @@ __global__ __launch_bounds__(kBlock) void k_dual_epi(Ranges R, const T* __restri
     // stored value, with the line-search terms; task 1: the primal residual
     // of the reflection parameter, (G x_hat - h) against diag(D1) of the
     // block's cone (independent: task 1 reads neither y nor y_hat)
+    // (the terms go through scalars: acc itself, written from the lambdas,
+    // would be kept in scratch memory)
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
     for_cone_tasks<2>(R, b, [&](int r0, int dim, int kind, int pass) {
-      {
-        const bool dual = pass == 0;
-        wave_proj_cone(
-            kind, dual, dim,
-            [&](int i) {
-              return dual ? (double)it.yh[r0 + i] : (double)it.gxh[r0 + i] - (double)d.h[r0 + i];
-            },
-            [&](int i) { return dual ? 1.0 / D1[r0 + i] : D1[r0 + i]; },
-            [&](int i, double p) {
-              const int r = r0 + i;
-              if (dual) {
-                const double yn = (double)(T)p;
-                it.yh[r] = (T)yn;
-                const double dy = yn - (double)it.y[r];
-                acc[0] += dy * dy;
-                acc[1] += dy * ((double)it.gxh[r] - (double)it.gx[r]);
-                acc[3] += (double)d.h[r] * yn;
-              } else {
-                const double pr = ((double)it.gxh[r] - (double)d.h[r]) - p;
-                acc[2] += pr * pr;
-              }
-            });
-      }
+      const bool dual = pass == 0;
+      wave_proj_cone(
+          kind, dual, dim,
+          [&](int i) { return dual ? (double)it.yh[r0 + i] : (double)it.gxh[r0 + i] - (double)d.h[r0 + i]; },
+          [&](int i) { return dual ? 1.0 / D1[r0 + i] : D1[r0 + i]; },
+          [&](int i, double p) {
+            const int r = r0 + i;
+            if (dual) {
+              const double yn = (double)(T)p;
+              it.yh[r] = (T)yn;
+              const double dy = yn - (double)it.y[r];
+              t0 += dy * dy;
+              t1 += dy * ((double)it.gxh[r] - (double)it.gx[r]);
+              t3 += (double)d.h[r] * yn;
+            } else {
+              const double pr = ((double)it.gxh[r] - (double)d.h[r]) - p;
+              t2 += pr * pr;
+            }
+          });
     });
+    acc[0] += t0;
+    acc[1] += t1;
+    acc[2] += t2;
+    acc[3] += t3;
   }
   block_sum_store<4>(acc, lds, rec + (size_t)b * 4);
 }
@@ -1417,52 +1420,56 @@ __global__ __launch_bounds__(kBlock) void k_cand_rows(Ranges R, const T* __restr
   // diag(D1) of the block's cone for the scaled L2 term and, unscaled (r / D1),
   // onto the cone itself for the infinity-norm termination terms
   // (one task per block, candidate q and scaled / unscaled projection, spread
-  // over the waves, with one inlined projection; the terms go to acc through
-  // compile-time indices)
+  // over the waves, with one inlined projection; the terms go through scalars
+  // to acc)
+  // per candidate: sums c[q][0..3] for acc[q*4 + i], maxima c[q][4..6] for acc[8 + q*3 + i - 4]
+  double c00 = 0.0, c01 = 0.0, c02 = 0.0, c03 = 0.0, c04 = 0.0, c05 = 0.0, c06 = 0.0;
+  double c10 = 0.0, c11 = 0.0, c12 = 0.0, c13 = 0.0, c14 = 0.0, c15 = 0.0, c16 = 0.0;
   for_cone_tasks<2 * kMaxCand>(R, b, [&](int r0, int dim, int kind, int task) {
     const int q = task >> 1, pass = task & 1;
     if (q < nc) {
       const T* yq = q == 0 ? y0 : y1;
       const double* gq = q == 0 ? g0 : g1;
-      double t[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // sums 0..3 as acc[q*4+i], maxima 4..6 as acc[8+q*3+i-4]
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0;
       if (pass == 0) {
         for (int i = (int)(threadIdx.x & (kWave - 1)); i < dim; i += kWave) {
           const int r = r0 + i;
           const double yc = (double)yq[r], gx = gq[r], h = d.h[r];
           const double dya = yc - (double)ya[r], res = gx - h;
-          t[0] += dya * dya;
-          t[1] += res * res;
-          t[3] += h * yc;
-          t[5] = fmax(t[5], fabs(gx) / D1[r]);
+          t0 += dya * dya;
+          t1 += res * res;
+          t3 += h * yc;
+          t5 = fmax(t5, fabs(gx) / D1[r]);
         }
       }
-      {
-        const bool scaled = pass == 0;
-        wave_proj_cone(
-            kind, false, dim,
-            [&](int i) { return scaled ? gq[r0 + i] - d.h[r0 + i] : (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; },
-            [&](int i) { return scaled ? D1[r0 + i] : 1.0; },
-            [&](int i, double p) {
-              if (scaled) {
-                const double pr = (gq[r0 + i] - d.h[r0 + i]) - p;
-                t[2] += pr * pr;
-              } else {
-                const double ru = (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i];
-                t[4] = fmax(t[4], fabs(ru - p));
-                t[6] = fmax(t[6], fabs(p));
-              }
-            });
-      }
-#pragma unroll
-      for (int qq = 0; qq < kMaxCand; ++qq) {
-        if (qq != q) continue;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[qq * 4 + i] += t[i];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) acc[8 + qq * 3 + i] = fmax(acc[8 + qq * 3 + i], t[4 + i]);
+      const bool scaled = pass == 0;
+      wave_proj_cone(
+          kind, false, dim,
+          [&](int i) { return scaled ? gq[r0 + i] - d.h[r0 + i] : (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i]; },
+          [&](int i) { return scaled ? D1[r0 + i] : 1.0; },
+          [&](int i, double p) {
+            if (scaled) {
+              const double pr = (gq[r0 + i] - d.h[r0 + i]) - p;
+              t2 += pr * pr;
+            } else {
+              const double ru = (gq[r0 + i] - d.h[r0 + i]) / D1[r0 + i];
+              t4 = fmax(t4, fabs(ru - p));
+              t6 = fmax(t6, fabs(p));
+            }
+          });
+      if (q == 0) {
+        c00 += t0, c01 += t1, c02 += t2, c03 += t3;
+        c04 = fmax(c04, t4), c05 = fmax(c05, t5), c06 = fmax(c06, t6);
+      } else {
+        c10 += t0, c11 += t1, c12 += t2, c13 += t3;
+        c14 = fmax(c14, t4), c15 = fmax(c15, t5), c16 = fmax(c16, t6);
       }
     }
   });
+  acc[0] += c00, acc[1] += c01, acc[2] += c02, acc[3] += c03;
+  acc[4] += c10, acc[5] += c11, acc[6] += c12, acc[7] += c13;
+  acc[8] = fmax(acc[8], c04), acc[9] = fmax(acc[9], c05), acc[10] = fmax(acc[10], c06);
+  acc[11] = fmax(acc[11], c14), acc[12] = fmax(acc[12], c15), acc[13] = fmax(acc[13], c16);
   block_summax_store<kCandRowsNV, kCandRowsNS>(acc, lds, rec + (size_t)b * kCandRowsNV);
 }
 
@@ -1588,18 +1595,48 @@ __device__ __forceinline__ void probe_rows_body(int b, int q, const Ranges& R, c
   if (C.phase != kPhaseExp && C.phase != kPhaseBisect) return;
   const double sigma = I.eta_hat * I.omega;
   const int mz_end = I.row0 + I.m_zero;
+  const double inv_sigma = 1.0 / sigma;
+  const T* ys = q == 0 ? y0 : y1;
+  const double* gs = q == 0 ? g0 : g1;
+  // cone blocks first: y(t) = Proj onto diag(1/D1) (dual cone) of
+  // y + t sigma b2, one task per block and probe spread over the waves (one
+  // inlined projection); each wave's sums go to its own LDS slots.  (Done
+  // before the element loop below, whose 48 per-probe values are then not
+  // live across the projection: the kernel keeps more waves per SIMD.)
+  __shared__ double cone_acc[kWavesPerBlock][kProbeNV];
+  const bool cones = R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (cones) {
+    for (int i = lane; i < kProbeNV; i += kWave) cone_acc[wave][i] = 0.0;
+    for_cone_tasks<kProbes>(R, b, [&](int r0, int dim, int kind, int p) {
+      const double tp = probe_t(C, p) * sigma;
+      double dd = 0.0, bd = 0.0;
+      wave_proj_cone(
+          kind, true, dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
+          [&](int i) { return 1.0 / D1[r0 + i]; },
+          [&](int i, double pv) {
+            const double yc = (double)ys[r0 + i];
+            const double dy = pv - yc;
+            dd += dy * dy;
+            bd += (d.h[r0 + i] - gs[r0 + i]) * dy;
+          });
+      dd = wave_sum(dd);
+      bd = wave_sum(bd);
+      if (lane == 0) {
+        cone_acc[wave][p * 2 + 0] += dd * inv_sigma;
+        cone_acc[wave][p * 2 + 1] += bd;
+      }
+    });
+  }
   double tq[kProbes];
 #pragma unroll
   for (int p = 0; p < kProbes; ++p) tq[p] = probe_t(C, p) * sigma;
   double acc[kProbeNV];
 #pragma unroll
   for (int i = 0; i < kProbeNV; ++i) acc[i] = 0.0;
-  const double inv_sigma = 1.0 / sigma;
-  const T* ys = q == 0 ? y0 : y1;
-  const double* gs = q == 0 ? g0 : g1;
   const int i1 = R.blk_end[b];
   for (int i = R.blk_start[b] + (int)threadIdx.x; i < i1; i += kBlock) {
-    if (i >= I.soc_start) continue;  // cone block rows: below
+    if (i >= I.soc_start) continue;  // cone block rows: above
     const bool zero_row = i < mz_end;
     const double yc = (double)ys[i];
     const double b2 = d.h[i] - gs[i];
@@ -1611,38 +1648,9 @@ __device__ __forceinline__ void probe_rows_body(int b, int q, const Ranges& R, c
       acc[p * 2 + 1] += b2 * dy;
     }
   }
-  // cone blocks: y(t) = Proj onto diag(1/D1) (dual cone) of y + t sigma b2, one
-  // task per block and probe spread over the waves (one inlined projection);
-  // each wave's sums go to its own LDS slots and join acc in its lane 0.
-  if (R.blk_soc0 && R.blk_soc1[b] > R.blk_soc0[b]) {
-    __shared__ double cone_acc[kWavesPerBlock][kProbeNV];
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int i = lane; i < kProbeNV; i += kWave) cone_acc[wave][i] = 0.0;
-    for_cone_tasks<kProbes>(R, b, [&](int r0, int dim, int kind, int p) {
-      {
-        const double tp = probe_t(C, p) * sigma;
-        double dd = 0.0, bd = 0.0;
-        wave_proj_cone(
-            kind, true, dim, [&](int i) { return (double)ys[r0 + i] + tp * (d.h[r0 + i] - gs[r0 + i]); },
-            [&](int i) { return 1.0 / D1[r0 + i]; },
-            [&](int i, double pv) {
-              const double yc = (double)ys[r0 + i];
-              const double dy = pv - yc;
-              dd += dy * dy;
-              bd += (d.h[r0 + i] - gs[r0 + i]) * dy;
-            });
-        dd = wave_sum(dd);
-        bd = wave_sum(bd);
-        if (lane == 0) {
-          cone_acc[wave][p * 2 + 0] += dd * inv_sigma;
-          cone_acc[wave][p * 2 + 1] += bd;
-        }
-      }
-    });
-    if (lane == 0) {
+  if (cones && lane == 0) {  // the wave's cone sums join acc in its lane 0
 #pragma unroll
-      for (int i = 0; i < kProbeNV; ++i) acc[i] += cone_acc[wave][i];
-    }
+    for (int i = 0; i < kProbeNV; ++i) acc[i] += cone_acc[wave][i];
   }
   block_sum_store<kProbeNV>(acc, lds, rec + ((size_t)q * R.nblk + b) * kProbeNV);
 }

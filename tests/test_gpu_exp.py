@@ -43,7 +43,7 @@ def _points(seed, count, scaled):
 @pytest.mark.parametrize("scaled", [False, True])
 def test_projection_matches_oracle_elementwise(dual, scaled):
     v, f = _points(10 + dual + 2 * scaled, 700, scaled)
-    got = P.pdcs_project_exp(dual, v, f)
+    got = P.pdcs_project_cone("exp_dual" if dual else "exp", v, f)
     ref = O.proj_scaled_exp_dual if dual else O.proj_scaled_exp
     for q in range(v.shape[0]):
         want = ref(v[q], f[q])
@@ -61,10 +61,10 @@ def test_projection_of_ray_plus_normal_is_the_ray_point():
     nr = np.stack([-np.ones(n), r - 1.0, np.exp(-r)], axis=1)
     p = s[:, None] * f * a
     v = p - t[:, None] * nr / f
-    got = P.pdcs_project_exp(0, v, f)
+    got = P.pdcs_project_cone("exp", v, f)
     assert np.all(np.abs(got - p) <= 1e-9 * (1 + np.abs(v).max(axis=1, keepdims=True)))
     # Moreau: the dual cone of F K_exp is F^-1 K_exp*, and P_{F^-1 K_exp*}(-v) = P_{F K_exp}(v) - v
-    got_d = P.pdcs_project_exp(1, -v, 1.0 / f)
+    got_d = P.pdcs_project_cone("exp_dual", -v, 1.0 / f)
     assert np.all(np.abs(got_d - (-v + p)) <= 1e-9 * (1 + np.abs(v).max(axis=1, keepdims=True)))
 
 
@@ -82,7 +82,7 @@ def test_projection_onto_far_negative_and_far_positive_rays():
     nr = np.stack([-sc, (r - 1.0) * sc, np.where(r < 0, 1.0, np.exp(-np.maximum(r, 0.0)))], axis=1)
     p = s[:, None] * f * a
     v = p - t[:, None] * nr / f
-    got = P.pdcs_project_exp(0, v, f)
+    got = P.pdcs_project_cone("exp", v, f)
     tol = 1e-9 * (1 + np.abs(v).max(axis=1))
     bad = np.nonzero(np.abs(got - p).max(axis=1) > tol)[0]
     assert bad.size == 0, (r[bad[:5]], got[bad[:5]], p[bad[:5]])
@@ -95,15 +95,15 @@ def test_projection_special_cases():
                   [-1.0, -2.0, 0.5],      # x, y <= 0: (x, 0, max(z, 0))
                   [-1.0, -2.0, -0.5],
                   [0.0, 0.0, 0.0]])
-    got = P.pdcs_project_exp(0, v, f)
+    got = P.pdcs_project_cone("exp", v, f)
     assert np.array_equal(got[0], v[0])
     assert np.array_equal(got[1], np.zeros(3))
     assert np.allclose(got[2], [-1.0, 0.0, 0.5], rtol=0, atol=1e-15)
     assert np.allclose(got[3], [-1.0, 0.0, 0.0], rtol=0, atol=1e-15)
     assert np.array_equal(got[4], np.zeros(3))
-    assert P.pdcs_project_exp(0, np.zeros((0, 3)), f).shape == (0, 3)
+    assert P.pdcs_project_cone("exp", np.zeros((0, 3)), f).shape == (0, 3)
     with pytest.raises(P.PdcsError):
-        P.pdcs_project_exp(0, v, np.array([1.0, 0.0, 1.0]))
+        P.pdcs_project_cone("exp", v, np.array([1.0, 0.0, 1.0]))
     with pytest.raises(P.PdcsError):
         P.pdcs_project_cone("exp", np.ones((2, 4)), np.ones(4))   # exponential cones have dimension 3
 
