@@ -80,9 +80,10 @@ def test_feasible_lps_with_unbounded_columns_stay_optimal(layout, precision):
     # the tests are on by default: feasible LPs with free, one-sided and boxed
     # columns and >= rows must still end optimal.  The objective is compared
     # with HiGHS's optimum.  A relative KKT error of eps bounds |pobj - dobj|
-    # by eps (1 + max(|pobj|, |dobj|)), and the free columns let an eps-feasible
-    # point move the objective by as much again, so two 1e-6 answers can differ
-    # by about 2e-6 relative; solving to 1e-7 puts the objective within 1e-6.
+    # by eps (1 + max(|pobj|, |dobj|)), but the primal residual is relative to
+    # max(|h|, |Gx|), and with free columns |Gx| can be large: a 1e-7 answer
+    # has been seen 2e-6 (relative) from the optimum.  The objective is compared
+    # after a 1e-8 solve, where even 100 times that amplification stays within 1e-6.
     from scipy.optimize import linprog
 
     inst = lpgen.planted_lp(lpgen.rng_for(91, 1), 200, 500, per_col=5, m_zero=100)
@@ -97,7 +98,7 @@ def test_feasible_lps_with_unbounded_columns_stay_optimal(layout, precision):
     assert hi.status == 0
     prob = P.Problem.from_instance(inst)
     prob.set_layout(layout)
-    for tol in (1e-6, 1e-7):
+    for tol in (1e-6, 1e-7, 1e-8):
         sol = prob.solve(precision=precision, time_limit=60.0, rel_tol=tol, abs_tol=tol)
         assert sol.info["exit_code"] == 0, (tol, sol.info)
         err = O.termination_errors(lp, sol.x, sol.y)
