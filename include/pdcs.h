@@ -95,7 +95,7 @@ typedef struct {
   int64_t check_every;        /* 64: restart/termination check after every accepted
                                  trial whose trial count is a multiple of this         */
   int64_t precision;          /* PDCS_PRECISION_*                                     */
-  int64_t stall_checks;       /* 128; mixed: switch to FP64 after this many checks
+  int64_t stall_checks;       /* 512; mixed: switch to FP64 after this many checks
                                  without a 10% improvement of the relative KKT error
                                  once that error is below 100 * rel_tol, or after 8x
                                  this many checks without a new lowest error at any

@@ -1505,7 +1505,7 @@ void pdcs_options_default(pdcs_options* o) {
   o->method = PDCS_METHOD_AUTO;
   o->check_every = 64;
   o->precision = PDCS_PRECISION_FP64;
-  o->stall_checks = 128;
+  o->stall_checks = 512;
   o->polish_switch_tol = 0.0;
   o->bisect_rel_eps = 1e-6;
   o->use_graph = 1;

@@ -36,7 +36,7 @@ def test_options_defaults_follow_the_paper():
     assert P.pdcs_status_string(0) == "optimal" and P.pdcs_status_string(8) == "numerical_error"
     assert P.pdcs_status_string(6) == "time_limit"
     # engineering defaults of the added options
-    assert o.check_every == 64 and o.stall_checks == 128 and o.probe_passes == 7
+    assert o.check_every == 64 and o.stall_checks == 512 and o.probe_passes == 7
     assert o.use_graph == 1 and o.compact == 1 and o.precision == 0
 
 
