@@ -526,12 +526,28 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int ld
 }
 
 // Split products: out = sum_z part[z] in a fixed order, then the EPI_ACT use.
+// The split partials of 4 consecutive elements per thread (16-byte loads, 8
+// splits' loads in flight), summed in split order.
 __global__ void k_epilogue(const float* __restrict__ part, int splits, int64_t MN, int N, Epi e) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= MN) return;
-  float s = 0.0f;
-  for (int z = 0; z < splits; ++z) s += part[(size_t)z * MN + i];
-  epi_act(e, (size_t)i, (int)(i % N), s);
+  if (MN % 4 == 0) {
+    float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll 8
+    for (int z = 0; z < splits; ++z) {
+      const float4 p = *reinterpret_cast<const float4*>(part + (size_t)z * MN + i);
+      s.x += p.x, s.y += p.y, s.z += p.z, s.w += p.w;
+    }
+    const float sv[4] = {s.x, s.y, s.z, s.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) epi_act(e, (size_t)(i + k), (int)((i + k) % N), sv[k]);
+    return;
+  }
+  for (int64_t j = i; j < i + 4 && j < MN; ++j) {
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[(size_t)z * MN + j];
+    epi_act(e, (size_t)j, (int)(j % N), s);
+  }
 }
 
 __global__ void k_to_bf16(const float* __restrict__ in, bf16* __restrict__ out, int64_t n) {
@@ -742,7 +758,7 @@ struct pdcs_mlp_s {
         part_bytes = need;
       }
       launch(EPI_STORE, kt, A, lda, ta, Bm, ldb, tb, part.as<float>(), M, N, K, gx, gy, splits, e, s);
-      k_epilogue<<<lin((int64_t)M * N), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, e);
+      k_epilogue<<<lin(((int64_t)M * N + 3) / 4), 256, 0, s>>>(part.as<float>(), splits, (int64_t)M * N, N, e);
       return;
     }
     launch(kind, kt, A, lda, ta, Bm, ldb, tb, kind == EPI_STORE ? e.out32 : nullptr, M, N, K, gx, gy, 1, e, s);
