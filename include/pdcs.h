@@ -230,7 +230,9 @@ int  pdcs_problem_create_conic(int64_t m, int64_t n, int64_t m_zero, int64_t n_s
  * the diagonal rescaling a block's cones are diag(D1) K and diag(1/D1) K*,
  * projected onto by a one-dimensional root find (Section 2.6).  Needs
  * m_zero + sum(soc_dims) + 3 (n_exp + n_dexp) <= m; n_soc = 0 with soc_dims
- * null is allowed.  Errors: as pdcs_problem_create_conic. */
+ * null is allowed.  Problems with cone blocks always take the band layout
+ * (pdcs_problem_set_layout does not change that).  Errors: as
+ * pdcs_problem_create_conic. */
 int  pdcs_problem_create_cones(int64_t m, int64_t n, int64_t m_zero, int64_t n_soc,
                                const int64_t* soc_dims, int64_t n_exp, int64_t n_dexp,
                                const int64_t* row_ptr, const int32_t* col_idx, const double* val,
