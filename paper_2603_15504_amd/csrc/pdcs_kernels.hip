@@ -183,14 +183,15 @@ __device__ __forceinline__ double exp_ray_turn(double r, double E, double iE, co
 // summed into t (|t| <= 1e-15 sc is rounding noise: r is a root).
 __device__ __forceinline__ void exp_ray_turn_d(double r, const ExpPoint& P, double& t, double& dt, double& sc) {
   double a0, a1, a2, m0, m1, m2, da0, da1, da2, dm0, dm1, dm2;
+  const double q = exp(-fabs(r));  // e^r for r <= 0, e^-r above
   if (r <= 0.0) {
-    const double E = exp(r);
+    const double E = q;
     a0 = P.f[0] * r, a1 = P.f[1], a2 = P.f[2] * E;
     m0 = -E * P.fi[0], m1 = E * (r - 1.0) * P.fi[1], m2 = P.fi[2];
     da0 = P.f[0], da1 = 0.0, da2 = a2;
     dm0 = m0, dm1 = E * r * P.fi[1], dm2 = 0.0;
   } else {  // both vectors times e^-r: the derivative of t e^-2r, whose sign change is the same
-    const double iE = exp(-r);
+    const double iE = q;
     a0 = P.f[0] * r * iE, a1 = P.f[1] * iE, a2 = P.f[2];
     m0 = -P.fi[0], m1 = (r - 1.0) * P.fi[1], m2 = iE * P.fi[2];
     da0 = P.f[0] * (1.0 - r) * iE, da1 = -a1, da2 = 0.0;
@@ -211,7 +212,8 @@ __device__ __forceinline__ void exp_ray_turn_d(double r, const ExpPoint& P, doub
 // and <p, v - p> = 0, which makes p the projection.
 __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, double& bd, double& b0, double& b1,
                                                   double& b2, bool& cert) {
-  const double E = exp(r);
+  const double q = exp(-fabs(r));  // e^r for r <= 0, e^-r above
+  const double E = r <= 0.0 ? q : 1.0 / q;
   const double q0 = P.f[0] * r, q1 = P.f[1], q2 = P.f[2] * E;
   const double s = (q0 * P.v[0] + q1 * P.v[1] + q2 * P.v[2]) / (q0 * q0 + q1 * q1 + q2 * q2);
   if (!(s > 0.0)) return;
@@ -222,24 +224,25 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
   bd = d, b0 = c0, b1 = c1, b2 = c2;
   // <v - p, F^-1 n(r) min(1, e^r)>
   const double w = r <= 0.0 ? -d0 * E * P.fi[0] + d1 * (r - 1.0) * E * P.fi[1] + d2 * P.fi[2]
-                            : -d0 * P.fi[0] + d1 * (r - 1.0) * P.fi[1] + d2 * exp(-r) * P.fi[2];
+                            : -d0 * P.fi[0] + d1 * (r - 1.0) * P.fi[1] + d2 * q * P.fi[2];
   cert = w <= 0.0;
 }
 
 // One scan of the rays by the wave: lane l takes cells [l C, l C + C) of
 // width h from r = -32 C h, every + to - sign change of the slope is refined
 // to full precision and its candidate kept (exp_ray_candidate).  e^r runs by
-// multiplication along a lane's cells (the refinement uses exp itself).
+// multiplication with g = e^h (ig = e^-h) along a lane's cells (the
+// refinement uses exp itself).
 // (Loops are kept rolled throughout: the projection's code is fetched into
 // the instruction cache at every launch that uses it.)
-__device__ __forceinline__ void exp_scan(int C, double h, const ExpPoint& P, double& bd, double& b0, double& b1,
-                                         double& b2, bool& cert) {
+__device__ __forceinline__ void exp_scan(int C, double h, double g, double ig, const ExpPoint& P, double& bd,
+                                         double& b0, double& b1, double& b2, bool& cert) {
   const int lane = threadIdx.x & (kWave - 1);
   const double r_first = -0.5 * kWave * C * h;
-  const double g = exp(h), ig = exp(-h);
   int k = lane * C;
   double lo = r_first + k * h;
-  double E = exp(lo), iE = exp(-lo);
+  const double q = exp(-fabs(lo));
+  double E = lo <= 0.0 ? q : 1.0 / q, iE = lo <= 0.0 ? 1.0 / q : q;
   double t_lo = exp_ray_turn(lo, E, iE, P);
 #pragma unroll 1
   for (int c = 0; c < C; ++c) {
@@ -331,7 +334,9 @@ __device__ __forceinline__ void exp_proj_wave(const double (&v)[3], const double
     double bd = face_d, b0 = face[0], b1 = face[1], b2 = face[2];
     bool cert = false;
     if (tail && lane == 0) exp_ray_candidate((v[0] * P.fi[0]) / (v[1] * P.fi[1]), P, bd, b0, b1, b2, cert);
-    exp_scan(pass == 0 ? 24 : 188, pass == 0 ? 0.4 : 0.05, P, bd, b0, b1, b2, cert);
+    // e^0.4, e^-0.4, e^0.05, e^-0.05 to double precision
+    exp_scan(pass == 0 ? 24 : 188, pass == 0 ? 0.4 : 0.05, pass == 0 ? 1.4918246976412703 : 1.0512710963760241,
+             pass == 0 ? 0.6703200460356393 : 0.951229424500714, P, bd, b0, b1, b2, cert);
     if (exp_wave_pick(bd, b0, b1, b2, pass == 0 ? cert : true, p)) return;
   }
 }
