@@ -233,8 +233,8 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
 // to full precision and its candidate kept (exp_ray_candidate).  e^r runs by
 // multiplication with g = e^h (ig = e^-h) along a lane's cells (the
 // refinement uses exp itself).
-// (Loops are kept rolled throughout: the projection's code is fetched into
-// the instruction cache at every launch that uses it.)
+// (Loops are kept rolled throughout, so that each kernel holds one compact
+// copy of the projection.)
 __device__ __forceinline__ void exp_scan(int C, double h, double g, double ig, const ExpPoint& P, double& bd,
                                          double& b0, double& b1, double& b2, bool& cert) {
   const int lane = threadIdx.x & (kWave - 1);
