@@ -672,7 +672,7 @@ def main():
     ap.add_argument("--no-cones", action="store_true", help="c1: skip the conic-LP solves record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build solves on one GPU only (the multi-GPU sharding is a design note); "
+        print("bench.py: the solver runs on one GPU (sharding across GPUs is described, not built); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
