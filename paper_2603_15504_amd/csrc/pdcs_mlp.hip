@@ -877,8 +877,9 @@ struct pdcs_mlp_s {
   // stored in `grads`, or, when `adam`, applied as an Adam step inside the
   // weight-gradient products (each layer's BF16 weights are read by the
   // backward product before its own update rewrites them).  Bias gradients go
-  // to `grads` either way; the loss stays on the device (lossv).
-  void train(const float* in, const float* target, int64_t B, bool adam, float lr, hipStream_t s) {
+  // to `grads` either way; the loss stays on the device (lossv), summed from
+  // its partials only when `need_loss`.
+  void train(const float* in, const float* target, int64_t B, bool adam, float lr, bool need_loss, hipStream_t s) {
     hidden(in, B, s);
     have_grad_acts = true;
     const int64_t n = B * dout;
@@ -894,7 +895,7 @@ struct pdcs_mlp_s {
     mse.colpart = colpart.as<float>();
     mse.lossp = lossp.as<double>();
     gemm(EPI_MSE, h2_16.as<bf16>(), w, 0, W3(), w, 1, B, dout, w, mse, s);
-    k_sum_parts<<<1, 256, 0, s>>>(lossp.as<double>(), rt * ct, 1.0 / (double)n, lossv.as<float>());
+    if (need_loss) k_sum_parts<<<1, 256, 0, s>>>(lossp.as<double>(), rt * ct, 1.0 / (double)n, lossv.as<float>());
     colsum(colpart.as<float>(), rt, dout, G(off_b3), s);
     // layer 3: dZ2 = (dV W3) * (h2 > 0) before W3 changes, then dW3 = dV^T H2
     gemm(EPI_ACT, dv16.as<bf16>(), dout, 0, W3(), w, 0, B, w, dout,
@@ -999,11 +1000,11 @@ int pdcs_mlp_gradients(pdcs_mlp net, const float* in_dev, const float* target_de
   try {
     if (!net || !in_dev || !target_dev || batch < 1) throw Error(PDCS_ERR_INVALID_ARG, "bad gradient arguments");
     hipStream_t s = pick(net, stream);
-    net->train(in_dev, target_dev, batch, false, 0.0f, s);
+    net->train(in_dev, target_dev, batch, false, 0.0f, loss_out != nullptr, s);
     if (grad_dev) HIP_OK(hipMemcpyAsync(grad_dev, net->grads.p, net->np * 4, hipMemcpyDeviceToDevice, s));
     HIP_OK(hipGetLastError());
     float loss = 0.0f;
-    HIP_OK(hipMemcpyAsync(&loss, net->lossv.p, 4, hipMemcpyDeviceToHost, s));
+    if (loss_out) HIP_OK(hipMemcpyAsync(&loss, net->lossv.p, 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     if (loss_out) *loss_out = loss;
     return PDCS_OK;
@@ -1020,7 +1021,7 @@ int pdcs_mlp_train_step(pdcs_mlp net, const float* in_dev, const float* target_d
       throw Error(PDCS_ERR_INVALID_ARG, "bad train arguments");
     hipStream_t s = pick(net, stream);
     net->step += 1;
-    net->train(in_dev, target_dev, batch, true, lr, s);
+    net->train(in_dev, target_dev, batch, true, lr, loss_out != nullptr, s);
     HIP_OK(hipGetLastError());
     if (loss_out) {  // without a loss pointer the step stays asynchronous on `stream`
       float loss = 0.0f;
