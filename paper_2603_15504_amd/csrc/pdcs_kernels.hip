@@ -222,10 +222,16 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
   const double d = d0 * d0 + d1 * d1 + d2 * d2;
   if (!(d < bd)) return;
   bd = d, b0 = c0, b1 = c1, b2 = c2;
-  // <v - p, F^-1 n(r) min(1, e^r)>
-  const double w = r <= 0.0 ? -d0 * E * P.fi[0] + d1 * (r - 1.0) * E * P.fi[1] + d2 * P.fi[2]
-                            : -d0 * P.fi[0] + d1 * (r - 1.0) * P.fi[1] + d2 * q * P.fi[2];
-  cert = w <= 0.0;
+  // m = F^-1 n(r) min(1, e^r); at a root v - p is parallel to m, so the cosine
+  // of their angle is -1 (the projection) or +1 (not): the test takes the
+  // sign with room for rounding, and a residual at the rounding level of v
+  // (v on the boundary: p is then within that level of the projection)
+  const double m0 = r <= 0.0 ? -E * P.fi[0] : -P.fi[0];
+  const double m1 = r <= 0.0 ? (r - 1.0) * E * P.fi[1] : (r - 1.0) * P.fi[1];
+  const double m2 = r <= 0.0 ? P.fi[2] : q * P.fi[2];
+  const double w = d0 * m0 + d1 * m1 + d2 * m2;
+  const double vv = P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2];
+  cert = w <= 0.5 * sqrt(d * (m0 * m0 + m1 * m1 + m2 * m2)) || d <= 1e-24 * vv;
 }
 
 // One scan of the rays by the wave: lane l takes cells [l C, l C + C) of
