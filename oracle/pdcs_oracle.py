@@ -237,8 +237,15 @@ def proj_scaled_exp(v, f):
     (-1, 0, 0) only like 1 / |r|, but their third coordinate is below e^-300
     of the others: there h(r) is A be - B al r up to that relative size, whose
     root r = (v_1 / f_1) / (v_2 / f_2) (x / y of v / f, when v_1 < 0 < v_2) is
-    one more candidate if it lies below the grid.  The nearest of all
-    candidates wins.
+    one more candidate if it lies below the grid.  A candidate meets the
+    optimality conditions of the projection (Moreau: p in the cone, v - p in its
+    polar cone -F^{-1} K_exp*, <p, v - p> = 0) when its residual v - p is a
+    nonpositive multiple of F^{-1} n(r), n(r) = (-1, r - 1, e^-r) the normal of
+    K_exp along the ray (the face clip: when -F (v - p) lies in K_exp*); such a
+    candidate is the projection, so the nearest of these wins, and the nearest
+    of all candidates only when none qualifies.  (Near the apex a ray candidate
+    and the face clip can lie within rounding of the same distance from v while
+    the points themselves differ by the square root of that rounding.)
     """
     v = np.asarray(v, dtype=np.float64)
     f = np.asarray(f, dtype=np.float64)
@@ -248,6 +255,7 @@ def proj_scaled_exp(v, f):
         return np.zeros(3)
     best = np.array([min(v[0], 0.0), 0.0, max(v[2], 0.0)])
     bestd = float(np.linalg.norm(v - best))
+    best_ok = in_exp_dual(-f * (v - best))
     A, B, C = f * v
     al, be, ga = f * f
 
@@ -277,8 +285,11 @@ def proj_scaled_exp(v, f):
         if s > 0.0:
             p = s * a
             d = float(np.linalg.norm(v - p))
-            if d < bestd:
-                best, bestd = p, d
+            # n(r) times min(1, e^r), which stays finite at both ends
+            n = np.array([-np.exp(r), (r - 1.0) * np.exp(r), 1.0]) if r <= 0.0 else np.array([-1.0, r - 1.0, np.exp(-r)])
+            ok = float((v - p) @ (n / f)) <= 0.0
+            if (ok and not best_ok) or (ok == best_ok and d < bestd):
+                best, bestd, best_ok = p, d, ok
     return best
 
 

@@ -220,8 +220,6 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
   const double c0 = s * q0, c1 = s * q1, c2 = s * q2;
   const double d0 = P.v[0] - c0, d1 = P.v[1] - c1, d2 = P.v[2] - c2;
   const double d = d0 * d0 + d1 * d1 + d2 * d2;
-  if (!(d < bd)) return;
-  bd = d, b0 = c0, b1 = c1, b2 = c2;
   // m = F^-1 n(r) min(1, e^r); at a root v - p is parallel to m, so the cosine
   // of their angle is -1 (the projection) or +1 (not): the test takes the
   // sign with room for rounding, and a residual at the rounding level of v
@@ -231,7 +229,13 @@ __device__ __forceinline__ void exp_ray_candidate(double r, const ExpPoint& P, d
   const double m2 = r <= 0.0 ? P.fi[2] : q * P.fi[2];
   const double w = d0 * m0 + d1 * m1 + d2 * m2;
   const double vv = P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2];
-  cert = w <= 0.5 * sqrt(d * (m0 * m0 + m1 * m1 + m2 * m2)) || d <= 1e-24 * vv;
+  const bool ok = w <= 0.5 * sqrt(d * (m0 * m0 + m1 * m1 + m2 * m2)) || d <= 1e-24 * vv;
+  // a certified candidate is the projection: it replaces an uncertified one
+  // even when rounding makes it look no nearer (near the apex the face clip
+  // and the projection can be within rounding of the same distance from v
+  // while the points differ by the square root of that rounding)
+  if (!((ok && !cert) || (ok == cert && d < bd))) return;
+  bd = d, b0 = c0, b1 = c1, b2 = c2, cert = ok;
 }
 
 // One scan of the rays by the wave: lane l takes cells [l C, l C + C) of
@@ -282,18 +286,23 @@ __device__ __forceinline__ void exp_scan(int C, double h, double g, double ig, c
   }
 }
 
-// Nearest candidate over the wave (ties: the lowest lane) among the lanes with
-// `eligible` set.  Returns whether any lane was eligible.
-__device__ __forceinline__ bool exp_wave_pick(double bd, double b0, double b1, double b2, bool eligible,
+// Best candidate over the wave: certified before uncertified, then the nearest
+// (ties: the lowest lane), among the lanes that hold a certified candidate or,
+// when need_cert is false, among all.  Returns whether any lane took part.
+__device__ __forceinline__ bool exp_wave_pick(double bd, double b0, double b1, double b2, bool cert, bool need_cert,
                                               double (&p)[3]) {
   const int lane = threadIdx.x & (kWave - 1);
+  const bool eligible = cert || !need_cert;
   double d = eligible ? bd : INFINITY;
   int who = eligible ? lane : kWave;
+  int rank = cert ? 0 : 1;
   for (int off = 1; off < kWave; off <<= 1) {
     const double od = __shfl_xor(d, off);
-    const int ow = __shfl_xor(who, off);
+    const int ow = __shfl_xor(who, off), orank = __shfl_xor(rank, off);
     const double o0 = __shfl_xor(b0, off), o1 = __shfl_xor(b1, off), o2 = __shfl_xor(b2, off);
-    if (ow < kWave && (who == kWave || od < d || (od == d && ow < who))) d = od, who = ow, b0 = o0, b1 = o1, b2 = o2;
+    if (ow < kWave &&
+        (who == kWave || orank < rank || (orank == rank && (od < d || (od == d && ow < who)))))
+      d = od, who = ow, rank = orank, b0 = o0, b1 = o1, b2 = o2;
   }
   if (who == kWave) return false;
   p[0] = b0, p[1] = b1, p[2] = b2;
@@ -305,14 +314,16 @@ __device__ __forceinline__ bool exp_wave_pick(double bd, double b0, double b1, d
 // polar cone); the clip onto the face {(x, 0, z): x <= 0, z >= 0} if -F times
 // its residual is in K_exp* up to rounding (then the clip is within rounding
 // of the projection: this takes the points whose projection lies on a ray
-// so far out that it meets the face's edge to working precision); otherwise the nearest of the face's clip and the
+// so far out that it meets the face's edge to working precision); otherwise,
+// among the face's clip and the
 // best points of the rays s F a(r): the local maxima of the angle along the
 // rays (+ to - sign changes of exp_ray_turn) and, for rays below the scanned
 // range, whose third coordinate is then below e^-300 of the others, the ray
 // through v's own x / y, r = (v_1 / f_1) / (v_2 / f_2).  A first scan on a
 // coarse grid (step 0.4 over |r| <= 307.2) ends the search when a candidate
 // carries the projection's certificate; else a scan on a fine grid (step
-// 0.05 over |r| <= 300.8) takes the nearest of all candidates.  Above the
+// 0.05 over |r| <= 300.8) takes a certified candidate if one turns up, else
+// the nearest of all candidates.  Above the
 // scanned range the rays lie within e^-300 of the face's edge (0, 0, 1).
 constexpr double kExpTail = -300.0;
 
@@ -343,7 +354,7 @@ __device__ __forceinline__ void exp_proj_wave(const double (&v)[3], const double
     // e^0.4, e^-0.4, e^0.05, e^-0.05 to double precision
     exp_scan(pass == 0 ? 24 : 188, pass == 0 ? 0.4 : 0.05, pass == 0 ? 1.4918246976412703 : 1.0512710963760241,
              pass == 0 ? 0.6703200460356393 : 0.951229424500714, P, bd, b0, b1, b2, cert);
-    if (exp_wave_pick(bd, b0, b1, b2, pass == 0 ? cert : true, p)) return;
+    if (exp_wave_pick(bd, b0, b1, b2, cert, pass == 0, p)) return;
   }
 }
 

@@ -68,6 +68,30 @@ def test_projection_of_ray_plus_normal_is_the_ray_point():
     assert np.all(np.abs(got_d - (-v + p)) <= 1e-9 * (1 + np.abs(v).max(axis=1, keepdims=True)))
 
 
+def test_projection_near_the_apex_is_the_ray_point():
+    # the same construction with s a billionth of t: p is within 1e-7 |v| of
+    # the apex, where its distance from v and the face clip's agree to
+    # rounding; the certificate, not the distance, must pick p
+    rng = np.random.default_rng(11)
+    n = 400
+    r = rng.uniform(-8, 5, size=n)
+    t = rng.uniform(0.1, 10.0, size=n)
+    s = t * 10.0 ** rng.uniform(-10, -7, size=n)
+    f = np.exp(rng.uniform(-2, 2, size=(n, 3)))
+    a = np.stack([r, np.ones(n), np.exp(r)], axis=1)
+    nr = np.stack([-np.minimum(1.0, np.exp(r)), (r - 1.0) * np.minimum(1.0, np.exp(r)),
+                   np.minimum(1.0, np.exp(r)) * np.exp(-r)], axis=1)
+    p = s[:, None] * f * a
+    v = p - t[:, None] * nr / f
+    scale = np.abs(v).max(axis=1, keepdims=True)
+    got = P.pdcs_project_cone("exp", v, f)
+    assert np.all(np.abs(got - p) <= 1e-12 * scale)
+    want = np.array([O.proj_scaled_exp(v[i], f[i]) for i in range(n)])
+    assert np.all(np.abs(got - want) <= 1e-12 * scale)
+    got_d = P.pdcs_project_cone("exp_dual", -v, 1.0 / f)
+    assert np.all(np.abs(got_d - (-v + p)) <= 1e-12 * scale)
+
+
 def test_projection_onto_far_negative_and_far_positive_rays():
     # rays below the scanned range (r < -300) and near its ends; the normal
     # taken times min(1, e^r) to stay finite

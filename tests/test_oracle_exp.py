@@ -84,6 +84,25 @@ def test_projection_of_ray_plus_normal_is_the_ray_point(seed):
         assert np.allclose(got, p, rtol=0, atol=1e-9 * (1 + np.abs(v).max())), (f, r, s, t)
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_projection_near_the_apex_is_the_ray_point(seed):
+    # the same construction with s a billionth of t: the projection p is
+    # within 1e-7 |v| of the apex, so its distance from v and that of the face
+    # clip 0 agree to rounding (|v|^2 - |v - p|^2 = |p|^2), while the points
+    # differ by |p|; the optimality conditions, not the distances, single p
+    # out, and the projection is 1-Lipschitz, so rounding v moves it by as much
+    rng = np.random.default_rng(100 + seed)
+    for k in range(40):
+        f = np.exp(rng.uniform(-2, 2, size=3)) if seed else np.ones(3)
+        r = rng.uniform(-8, 5)
+        t = rng.uniform(0.1, 10.0)
+        s = t * 10.0 ** rng.uniform(-10, -7)
+        p = s * f * ray(r)
+        v = p - t * normal(r) * min(1.0, math.exp(r)) / f
+        got = O.proj_scaled_exp(v, f)
+        assert np.abs(got - p).max() <= 1e-13 * np.abs(v).max(), (f, r, s, t, got, p)
+
+
 @pytest.mark.parametrize("r", [-300.5, -400.0, -700.0, -2000.0])
 def test_projection_onto_far_negative_rays(r):
     # the rays (r, 1, e^r) approach the face edge (-1, 0, 0) only like 1 / |r|:
